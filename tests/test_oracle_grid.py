@@ -1,0 +1,328 @@
+"""Pins for the oracle's grid (Section 2, Fig. 3, Eqs. 2-5).
+
+Each test checks the oracle against something other than itself: a library
+routine, 30-digit arithmetic, a closed form, brute force, a hand-worked
+example or a statement the paper prints.
+"""
+import itertools
+import math
+import os
+import random
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.special as ss
+
+from oracle import grid as G
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --- Gauss-Legendre rings (Section 2.1, Eq. 2) ------------------------------
+
+@pytest.mark.parametrize("n", [2, 4, 10, 16, 50, 80, 128, 200])
+def test_gl_nodes_match_numpy_leggauss(n):
+    theta, s, c, w = G.gauss_legendre_theta(n)
+    x_ref, w_ref = np.polynomial.legendre.leggauss(n)
+    order = np.argsort(c)
+    assert np.max(np.abs(c[order] - x_ref)) < 1e-14
+    # leggauss's own end weights carry up to ~3e-11 relative error at N = 128-200
+    # (its polish is one Newton step in x); the 40-digit test below is the tight pin.
+    assert np.max(np.abs(w[order] - w_ref) / w_ref) < 1e-10
+
+
+@pytest.mark.parametrize("n", [16, 80, 528])
+def test_gl_quadrature_is_exact_for_polynomials(n):
+    """Eq. 2: the rule integrates P_l exactly for l <= 2N-1 (int P_l = 2 delta_l0)."""
+    theta, s, c, w = G.gauss_legendre_theta(n)
+    assert abs(w.sum() - 2.0) < 1e-13
+    for l in range(1, 2 * n, max(1, (2 * n) // 37)):
+        assert abs(np.sum(w * ss.eval_legendre(l, c))) < 1e-12
+
+
+def test_gl_mirror_symmetry_exact():
+    theta, s, c, w = G.gauss_legendre_theta(272)
+    assert np.array_equal(c, -c[::-1])
+    assert np.array_equal(s, s[::-1])
+    assert np.array_equal(w, w[::-1])
+    assert np.all(np.diff(theta) > 0)
+
+
+@pytest.mark.parametrize("n,idx", [(3008, [0, 1, 2, 700, 1503]), (1040, [0, 1, 519])])
+def test_gl_theta_and_weight_against_30_digit_newton(n, idx):
+    """Near the pole theta must be accurate relative to itself (pairs there are
+    a fraction of a milliradian apart); checked against an mpmath Newton
+    iteration at 40 digits using the three-term recurrence in x."""
+    theta, s, c, w = G.gauss_legendre_theta(n)
+    mpmath.mp.dps = 40
+
+    def pn_pair(x):
+        p0, p1 = mpmath.mpf(1), x
+        for l in range(1, n):
+            p0, p1 = p1, ((2 * l + 1) * x * p1 - l * p0) / (l + 1)
+        return p1, p0
+
+    for j in idx:
+        th = mpmath.mpf(float(theta[j]))
+        for _ in range(3):
+            x = mpmath.cos(th)
+            pn, pn1 = pn_pair(x)
+            th = th + pn * mpmath.sin(th) / (n * (pn1 - x * pn))
+        x = mpmath.cos(th)
+        _, pn1 = pn_pair(x)
+        w_ref = 2 * mpmath.sin(th) ** 2 / (n * pn1) ** 2
+        assert abs(float((mpmath.mpf(float(theta[j])) - th) / th)) < 1e-15      # ~4 ulp
+        assert abs(float((mpmath.mpf(float(w[j])) - w_ref) / w_ref)) < 1e-11
+
+
+# --- polar cut (Eq. 3) --------------------------------------------------------
+
+def _m_closed_form(lmax, s, c, thr):
+    """Smallest integer m with sqrt(m^2 - 2 m c) > A = lmax s + thr, from the
+    roots of m^2 - 2 c m - A^2 = 0 (valid for A >= 0, where the radicand at
+    the answer is positive)."""
+    A = lmax * s + thr
+    root = c + math.sqrt(c * c + A * A)
+    m = math.floor(root) + 1
+    return m if m <= lmax else None
+
+
+def test_min_m_matches_quadratic_root():
+    rng = random.Random(3)
+    for _ in range(400):
+        lmax = rng.randint(10, 3000)
+        th = rng.uniform(1e-4, 0.5 * math.pi)
+        thr = rng.choice([0.0, 3.5, 100.0, G.polar_threshold(lmax)])
+        s, c = math.sin(th), math.cos(th)
+        assert G.min_m_eq3(lmax, s, c, thr) == _m_closed_form(lmax, s, c, thr)
+
+
+def test_c1_closed_form_layout():
+    """lmax = 64, k = 8, margin 100: Eq. 3 never holds (sqrt(...) <= 64 < 100),
+    so every band needs 2*64+1 = 129 pixels, alpha = 17, T_0 = 18 (smallest
+    5-smooth >= 17) and every band keeps 18 tiles: 80 rings of 144 pixels."""
+    g = G.make_grid(64, 8)
+    assert g.nrings == 80 and g.nbands_hemi == 5
+    assert g.alpha == [17] * 5
+    assert g.tiles_north == [18] * 5
+    assert g.npix == 11520 and g.ntiles == 180
+    assert set(g.ring_npix().tolist()) == {144}
+
+
+# --- tile-count optimisation (Fig. 3, Eqs. 4-5) --------------------------------
+
+def _brute(alpha, runs):
+    n = len(alpha)
+    t0 = G.smallest_5_smooth(alpha[0], False)
+    best = [math.inf, None]
+
+    def rec(seq, cost):
+        i = len(seq)
+        if i == n:
+            if cost < best[0]:
+                best[0], best[1] = cost, list(seq)
+            return
+        a, tp = alpha[i], seq[-1]
+        for num in (1, 2, 3, 4, 5, 6):
+            for den in (1, 3, 4, 5):
+                if (num, den) not in ((3, 1), (2, 1), (1, 1), (4, 3), (5, 4), (6, 5)):
+                    continue
+                if (num * tp) % den:
+                    continue
+                t = num * tp // den
+                if not (a <= t <= 3 * a):
+                    continue
+                if runs and num != den and i >= 2 and seq[-1] != seq[-2]:
+                    continue
+                seq.append(t)
+                rec(seq, cost + (a - t) ** 2)
+                seq.pop()
+
+    rec([t0], (t0 - alpha[0]) ** 2)
+    return best
+
+
+def _cost(T, alpha):
+    return sum((t - a) ** 2 for t, a in zip(T, alpha))
+
+
+def test_dp_without_run_rule_is_exact_optimum():
+    """With the run rule off the programme is an exact DP: its cost must equal
+    the minimum over all sequences obeying Eq. 5 and alpha <= T <= 3 alpha."""
+    rng = random.Random(11)
+    for _ in range(600):
+        n = rng.randint(1, 6)
+        alpha = sorted(rng.randint(1, 45) for _ in range(n))
+        T = G.optimal_tiles(alpha, enforce_runs=False)
+        bc, bs = _brute(alpha, runs=False)
+        assert (T is None) == (bs is None)
+        if T is not None:
+            assert _cost(T, alpha) == bc
+
+
+def test_dp_with_run_rule_is_feasible_and_never_beats_brute_force():
+    rng = random.Random(12)
+    for _ in range(600):
+        n = rng.randint(1, 6)
+        alpha = sorted(rng.randint(1, 45) for _ in range(n))
+        T = G.optimal_tiles(alpha)
+        bc, bs = _brute(alpha, runs=True)
+        if T is None:
+            continue
+        assert bs is not None and _cost(T, alpha) >= bc
+        _assert_rules(T, alpha)
+
+
+def _assert_rules(T, alpha):
+    assert G.is_5_smooth(T[0]) and T[0] == G.smallest_5_smooth(alpha[0], False)
+    ok = {(3, 1), (2, 1), (1, 1), (4, 3), (5, 4), (6, 5)}
+    for i in range(1, len(T)):
+        assert alpha[i] <= T[i] <= 3 * alpha[i]
+        r = (T[i] // math.gcd(T[i], T[i - 1]), T[i - 1] // math.gcd(T[i], T[i - 1]))
+        assert r in ok
+        if i >= 2 and T[i] != T[i - 1]:
+            assert T[i - 1] == T[i - 2]          # runs of at least two after a change
+
+
+def test_dp_hand_worked_example():
+    """tests/golden/dp_hand_example.txt works this case through by hand."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "dp_hand_example.txt"))
+            if l.strip() and not l.startswith("#")]
+    alpha = [int(v) for v in rows[0][1:]]
+    T_expected = [int(v) for v in rows[1][1:]]
+    cost_expected = int(rows[2][1])
+    T = G.optimal_tiles(alpha)
+    assert T == T_expected
+    assert _cost(T, alpha) == cost_expected
+
+
+@pytest.mark.parametrize("lmax,k", [(64, 8), (100, 8), (256, 8), (512, 8), (1500, 8), (3000, 8), (2000, 4), (30, 2)])
+def test_grid_structural_rules(lmax, k):
+    g = G.make_grid(lmax, k)
+    assert g.nrings % (2 * k) == 0 and g.nrings >= lmax + 1 and g.nrings - (lmax + 1) < 2 * k
+    _assert_rules(g.tiles_north, g.alpha)
+    assert g.npix == 2 * k * k * sum(g.tiles_north)
+    nj = g.ring_npix()
+    for j in range(g.nrings):     # every ring length is 5-smooth when k is
+        if G.is_5_smooth(k):
+            assert G.is_5_smooth(int(nj[j]))
+
+
+def test_table1_pixel_counts_are_recorded_not_matched():
+    """Table 1 prints SymPix counts that no reading of Fig. 3 reproduces (see the
+    golden file); the build's values are recorded there and must not drift."""
+    lines = [l.split() for l in open(os.path.join(GOLDEN, "table1_npix.txt"))
+             if l.strip() and not l.startswith("#")]
+    paper = {int(l[0]): int(l[1]) for l in lines if len(l) == 3}
+    build = {int(l[0]): int(l[1]) for l in lines if len(l) == 2}
+    for lmax, npix in build.items():
+        g = G.make_grid(lmax, 8)
+        assert g.npix == npix
+        assert 1.0 < g.npix / paper[lmax] < 1.15        # soft: within 15% of print
+        gl = (lmax + 1) * 2 * (lmax + 1)
+        assert int([l for l in lines if len(l) == 3 and int(l[0]) == lmax][0][2]) == gl
+
+
+def test_geometric_efficiency_statements():
+    """Section 3.1 at lmax = 2000, k = 4: ring length at most 1.35x the reduced
+    Gauss-Legendre count, about 11% oversampling overall, pixel areas within
+    +20% of 4 pi / Npix and mostly within 0.9-1.1 (soft checks)."""
+    g = G.make_grid(2000, 4)
+    assert 5.0e6 < g.npix < 6.5e6                     # paper: 5.6e6
+    nj = g.ring_npix()
+    thr = G.polar_threshold(2000)
+    red = np.array([2 * (G.min_m_eq3(2000, g.sin_theta[j], g.cos_theta[j], thr) or 2000) + 1
+                    for j in range(g.nrings)])
+    assert np.max(nj / red) <= 1.35
+    assert 1.05 < g.npix / red.sum() < 1.15
+    area = np.repeat(2 * np.pi * g.weight / nj / (4 * np.pi / g.npix), nj)
+    assert area.max() < 1.2
+    assert np.mean((area > 0.9) & (area < 1.1)) > 0.85
+
+
+# --- layout (Section 2.4) ----------------------------------------------------
+
+@pytest.mark.parametrize("lmax,k", [(64, 8), (256, 8), (30, 2)])
+def test_layout_rules(lmax, k):
+    g = G.make_grid(lmax, k)
+    n = g.nbands_hemi
+    # bands interleaved N0, S0, N1, S1, ...
+    for b in range(2 * n):
+        i, south = divmod(b, 2)
+        rings = g.band_rings[b]
+        assert len(rings) == k
+        th = g.theta[rings]
+        assert np.all(np.diff(th) > 0)                       # theta increasing
+        assert (th[0] < 0.5 * np.pi) == (not south)
+        assert g.band_tiles[b] == g.tiles_north[i]
+    ring, pin, nr, phi = g.pixel_coords()
+    # bijection pixel -> (ring, index on ring)
+    key = ring * 100000 + pin
+    assert len(np.unique(key)) == g.npix
+    assert np.all(np.bincount(ring) == g.ring_npix())
+    # first pixel of each ring at half a pixel step
+    first = g.ring_first_pix()
+    assert np.allclose(phi[first], np.pi / g.ring_npix(), rtol=0, atol=1e-15)
+    # theta fastest inside a tile, then column; consecutive along a ring
+    for b in (0, 1, 2 * n - 1):
+        p0 = g.band_pix0[b]
+        assert ring[p0 + 1] == g.band_rings[b][1] and pin[p0 + 1] == 0
+        assert ring[p0 + k] == g.band_rings[b][0] and pin[p0 + k] == 1
+
+
+# --- tile adjacency (Section 2.2, reading of "neighbouring tiles") ------------
+
+def _float_adjacent(g, I, J):
+    """Independent check: neighbouring bands (or the same band) and closed phi
+    intervals overlapping on the circle, in floating point with a tolerance far
+    below the smallest non-zero gap 1/(T T')."""
+    bI, bJ = g.tile_band(I), g.tile_band(J)
+    iI, sI = divmod(bI, 2)
+    iJ, sJ = divmod(bJ, 2)
+    n = g.nbands_hemi
+    if bI == bJ:
+        pass
+    elif sI == sJ and abs(iI - iJ) == 1:
+        pass
+    elif iI == iJ == n - 1 and sI != sJ:
+        pass
+    else:
+        return False
+    TI, TJ = g.band_tiles[bI], g.band_tiles[bJ]
+    a0, a1 = (I - g.band_tile0[bI]) / TI, (I - g.band_tile0[bI] + 1) / TI
+    b0, b1 = (J - g.band_tile0[bJ]) / TJ, (J - g.band_tile0[bJ] + 1) / TJ
+    if bI == bJ:
+        d = (J - I) % TI
+        return d in (0, 1, TI - 1)
+    eps = 1e-9
+    return any(a0 <= b1 + s + eps and b0 + s <= a1 + eps for s in (-1.0, 0.0, 1.0))
+
+
+@pytest.mark.parametrize("lmax,k", [(64, 8), (256, 8), (30, 2), (40, 4)])
+def test_adjacency_matches_float_interval_test(lmax, k):
+    g = G.make_grid(lmax, k)
+    rp, col = g.adjacency()
+    for I in range(g.ntiles):
+        nb = set(col[rp[I]:rp[I + 1]].tolist())
+        assert I in nb
+        ref = {J for J in range(g.ntiles) if _float_adjacent(g, I, J)}
+        assert nb == ref, I
+
+
+def test_adjacency_symmetric_and_counts():
+    g = G.make_grid(512, 8)
+    rp, col = g.adjacency()
+    pairs = {(I, int(J)) for I in range(g.ntiles) for J in col[rp[I]:rp[I + 1]]}
+    assert all((J, I) in pairs for I, J in pairs)
+    # interior tile of a band between two bands of equal count: 3 x 3 neighbours
+    T = g.tiles_north
+    i = next(i for i in range(1, len(T) - 1) if T[i - 1] == T[i] == T[i + 1])
+    b = 2 * i
+    assert rp[g.band_tile0[b] + 1] - rp[g.band_tile0[b]] == 9
+    # a coarse tile above a ratio-2 step sees 4 fine tiles; a fine tile sees 2 coarse
+    i2 = next(i for i in range(len(T) - 1) if T[i + 1] == 2 * T[i])
+    coarse = g.band_tile0[2 * i2] + 1
+    fine_band = 2 * (i2 + 1)
+    nb = col[rp[coarse]:rp[coarse + 1]]
+    assert sum(1 for J in nb if g.tile_band(int(J)) == fine_band) == 4
