@@ -1,0 +1,181 @@
+/*
+ * sympix.h -- C ABI of the SymPix local-operator sampling library (gfx950).
+ *
+ * What it computes (Seljebotn & Eriksen, "SymPix: A spherical grid for
+ * efficient sampling of rotationally invariant operators"):
+ *   - the SymPix grid for a band limit lmax and tile size k (Section 2, Fig. 3);
+ *   - the kernel b(x) = sum_l (2l+1)/(4 pi) b_l P_l(x) of a rotationally
+ *     invariant operator with transfer function b_l (Eq. 10);
+ *   - the local part of D-hat = Y D Y^T and B-hat = Y B Y^T (Eq. 16): elements
+ *     between pixels in the same or in neighbouring tiles (Section 4.2);
+ *   - the matching blocks of B-hat^T N^-1 B-hat for a diagonal pixel-space N^-1
+ *     (Eq. 15).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status: every call returns a sympix_status; on failure a thread-local
+ *   message is available from sympix_last_error().  No C++ exception crosses
+ *   this boundary.  Argument checks are synchronous.  Device work is queued on
+ *   the caller's stream (a hipStream_t passed as void*, NULL = default stream)
+ *   and is asynchronous: a device fault surfaces as SYMPIX_EHIP on a later
+ *   call, or on the call itself when the environment variable SYMPIX_SYNC=1.
+ * Ownership: the caller owns every buffer it passes.  "host" buffers are
+ *   ordinary host memory of the stated length; "device" buffers are device
+ *   pointers on the current HIP device.  The library owns the opaque handles
+ *   and the device tables behind them; handles are immutable once created, so
+ *   concurrent sample calls on different streams are safe.
+ * Pixel layout (Section 2.4): bands in the order N0, S0, N1, S1, ...; inside a
+ *   band tiles by increasing phi; inside a tile the ring index r (rings by
+ *   increasing theta) runs fastest, then the column c.  Pixel index =
+ *   tile * k^2 + c*k + r, so tile J owns pixels [J k^2, (J+1) k^2).
+ * Block layout: a block (J, K) is k^2 x k^2 float64, row-major, row a = local
+ *   pixel c*k + r of tile J, column b = local pixel of tile K.  Stored blocks
+ *   are the pairs with K a neighbour of J and K >= J, ordered by J then K (the
+ *   CSR of sympix_grid_blocks); lower blocks are the transposes.
+ */
+#ifndef SYMPIX_H
+#define SYMPIX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SYMPIX_OK = 0,
+    SYMPIX_EINVAL = -1,      /* bad argument: NULL handle/pointer, lmax < 1, k < 1, ... */
+    SYMPIX_EINFEASIBLE = -2, /* the tile-count programme of Fig. 3 has no solution */
+    SYMPIX_ENOMEM = -3,      /* host or device allocation failed */
+    SYMPIX_EHIP = -4,        /* a HIP runtime call or kernel launch failed */
+    SYMPIX_ESIZE = -5,       /* an output or input length does not match the grid */
+    SYMPIX_EUNSUPPORTED = -6 /* valid request this build does not implement (see message) */
+} sympix_status;
+
+typedef enum {
+    SYMPIX_FP64 = 0,   /* FP64 MFMA, FP64 accumulation */
+    SYMPIX_FP32 = 1,   /* FP32 MFMA per term, FP64 accumulation across terms */
+    SYMPIX_BF16X3 = 2, /* operands split in two BF16 parts, 3 products, FP32 MFMA accumulation
+                          per term, FP64 across terms */
+    SYMPIX_BF16X6 = 3  /* operands split in three BF16 parts, 6 products, otherwise as BF16X3 */
+} sympix_precision;
+
+typedef struct sympix_grid sympix_grid;     /* opaque, library-owned */
+typedef struct sympix_kernel sympix_kernel; /* opaque, library-owned, bound to one grid */
+
+typedef struct {
+    int32_t lmax;            /* band limit given at creation */
+    int32_t k;               /* tile size (k x k pixels per tile, k rings per band) */
+    int32_t nrings;          /* lmax+1 rounded up to a multiple of 2k (Fig. 3) */
+    int32_t nbands_hemi;     /* n = nrings / 2k bands per hemisphere */
+    int64_t npix;            /* 2 k^2 sum_i T_i */
+    int64_t ntiles;          /* npix / k^2 */
+    int64_t nadjacency;      /* entries of the full tile adjacency (itself included) */
+    int64_t nblocks;         /* stored blocks (J, K), K >= J */
+    int64_t nterms;          /* sum over stored blocks of |nbr(J) & nbr(K)| */
+    int64_t nunique;         /* distinct (band_I, band_J, phi offset) keys */
+    double polar_margin;     /* right-hand side of Eq. 3 actually used */
+    double y_pattern_max;    /* largest 1 - cos(gamma) between pixels of neighbouring tiles */
+} sympix_dims;
+
+/* Build the SymPix grid for (lmax, k): Gauss-Legendre rings (Section 2.1),
+ * alpha_i from Eq. 3 at the pole-most ring of each band, tile counts from the
+ * dynamic programme of Fig. 3 (band 1 may differ from band 0, as the caption
+ * of Fig. 3 allows), the Section 2.4 layout, the neighbouring-tile relation and
+ * the symmetry keys of Section 2.3.  Host only: no device is touched.
+ *   polar_margin: right-hand side of Eq. 3; NaN selects the paper's
+ *                 max(100, lmax/100).
+ *   out:          receives the new handle (destroy with sympix_grid_destroy).
+ * Errors: EINVAL (lmax < 1, k < 1, k > 64, lmax > 100000, out NULL),
+ *         EINFEASIBLE (no tile layout), ENOMEM. */
+sympix_status sympix_grid_create(int32_t lmax, int32_t k, double polar_margin, sympix_grid **out);
+
+/* Free a grid and its device tables. NULL is ignored.  All kernels made from
+ * the grid must be destroyed first and no call using it may be in flight. */
+void sympix_grid_destroy(sympix_grid *g);
+
+/* Sizes of the grid (host struct). Errors: EINVAL. */
+sympix_status sympix_grid_dims(const sympix_grid *g, sympix_dims *out);
+
+/* Ring tables, host buffers of length nrings, ring j counted from the north
+ * pole: colatitude theta_j (zeros of P_nrings(cos theta)), Gauss-Legendre weight
+ * w_j (Eq. 2), pixels on the ring n_j = k T, and the pixel index of the ring's
+ * first pixel (phi = pi / n_j).  Any pointer may be NULL to skip it. */
+sympix_status sympix_grid_rings(const sympix_grid *g, double *theta, double *weight,
+                                int32_t *npix_ring, int64_t *first_pix);
+
+/* Band tables in storage order (length 2 n): tiles T and alpha (Fig. 3), and
+ * the index of the band's first (smallest-theta) ring.  NULL skips. */
+sympix_status sympix_grid_bands(const sympix_grid *g, int32_t *tiles, int32_t *alpha,
+                                int32_t *first_ring);
+
+/* Full tile adjacency as CSR: row_ptr[ntiles+1] (int64), col[nadjacency]
+ * (int32, ascending, the tile itself included).  Same band: t-1, t, t+1 mod T;
+ * neighbouring band (N_i-N_i+1, S_i-S_i+1, N_{n-1}-S_{n-1}): closed phi
+ * intervals that meet.  Host buffers. */
+sympix_status sympix_grid_neighbours(const sympix_grid *g, int64_t *row_ptr, int32_t *col);
+
+/* Stored blocks as CSR over J: row_ptr[ntiles+1], col[nblocks] = K >= J. */
+sympix_status sympix_grid_blocks(const sympix_grid *g, int64_t *row_ptr, int32_t *col);
+
+/* Symmetry keys (Section 2.3): for every adjacency entry (I, J) in CSR order
+ * its unique-block id uid[nadjacency]; and for every id its key
+ * (band_I, band_J, delta = (t_J T_I - t_I T_J) mod T_I T_J), arrays of length
+ * nunique.  A block B-hat_IJ depends on (I, J) only through this key.  NULL skips. */
+sympix_status sympix_grid_unique(const sympix_grid *g, int32_t *uid, int32_t *key_band_i,
+                                 int32_t *key_band_j, int64_t *key_delta);
+
+/* Tabulate the kernel of Eq. 10 for transfer function coef_l[0..ncoef-1]
+ * (host, ncoef = lmax + 1 of the grid; entries beyond are ignored, missing
+ * ones are zero) and evaluate every unique local block of the grid with it.
+ *   radius:  truncation radius in radians (pairs with gamma > radius give 0);
+ *            <= 0 means no radial cut (only the tile pattern truncates).
+ *   n_nodes: table size, >= 64 (65536 recommended; 0 selects 65536).  Nodes
+ *            are uniform in s = sqrt(1 - cos gamma) over the pattern's range
+ *            (or the radius, if smaller); lookups use 4-point Lagrange
+ *            interpolation in s, mirrored at s = 0 where the kernel is even.
+ *   stream:  hipStream_t for the device work.
+ * The FP64 recurrence in y = 1 - cos gamma runs on the device; the unique
+ * blocks are stored in FP64 and in the split forms the precision modes read.
+ * Errors: EINVAL, ESIZE (ncoef < 1), ENOMEM, EHIP. */
+sympix_status sympix_kernel_tabulate(const sympix_grid *g, const double *coef_l, int32_t ncoef,
+                                     double radius, int32_t n_nodes, void *stream,
+                                     sympix_kernel **out);
+
+/* Free a kernel. NULL is ignored.  No call using it may be in flight. */
+void sympix_kernel_destroy(sympix_kernel *kr);
+
+/* Evaluate the tabulated kernel (with its radial cut) at n arguments
+ * y = 1 - cos gamma (device buffers y_dev[n] in, out_dev[n] out).  For tests of
+ * the interpolation; y beyond the table domain is clamped to its end. */
+sympix_status sympix_kernel_eval(const sympix_kernel *kr, const double *y_dev, double *out_dev,
+                                 int64_t n, void *stream);
+
+/* Local blocks of D-hat (Eq. 16 with Section 4.2's truncation) for the kernel
+ * d: out_dev (device, float64) receives nblocks * k^4 values in stored-block
+ * order.  Called with the beam kernel it returns the local blocks of B-hat.
+ * Errors: EINVAL (NULL, kernel of another grid), ESIZE (out_len !=
+ * nblocks k^4), EUNSUPPORTED (k != 8), EHIP. */
+sympix_status sympix_sample_D(const sympix_grid *g, const sympix_kernel *d, double *out_dev,
+                              int64_t out_len, void *stream);
+
+/* Stored blocks of B-hat^T N^-1 B-hat (Eq. 15):
+ *   C_JK = sum_{I in nbr(J) & nbr(K)} B_IJ^T diag(ninv_I) B_IK,
+ * with ninv_dev (device, float64, npix values in pixel order, >= 0; negative or
+ * NaN values are not checked and give undefined results) and out_dev (device,
+ * float64, nblocks k^4 values, stored-block order).
+ *   prec: a sympix_precision.  FP64 is bitwise reproducible run to run.
+ * Errors: EINVAL, ESIZE (ninv_len != npix or out_len != nblocks k^4),
+ *         EUNSUPPORTED (k != 8), EHIP. */
+sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
+                                 int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
+                                 void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sympix_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYMPIX_H */

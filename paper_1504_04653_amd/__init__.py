@@ -1,0 +1,249 @@
+"""Python binding of libsympix (SymPix local-operator sampling on gfx950).
+
+Argument marshalling only: every step of the computation runs in the C++ host
+library and its HIP kernels.  Device buffers are passed as torch CUDA tensors
+(or raw integer addresses) and streams as torch streams (or raw handles).
+Importing this package fails loudly if the shared library has not been built.
+
+Precision modes: FP64, FP32, BF16X3, BF16X6 (see include/sympix.h).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsympix.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with paper_1504_04653_amd.build.build() "
+                      "(or __graft_entry__.build()); there is no fallback path")
+
+_lib = ctypes.CDLL(_LIB_PATH)
+
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "EINFEASIBLE", -3: "ENOMEM", -4: "EHIP", -5: "ESIZE",
+           -6: "EUNSUPPORTED"}
+
+
+class SympixError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.code = _STATUS.get(status, str(status))
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("lmax", ctypes.c_int32), ("k", ctypes.c_int32), ("nrings", ctypes.c_int32),
+                ("nbands_hemi", ctypes.c_int32), ("npix", ctypes.c_int64), ("ntiles", ctypes.c_int64),
+                ("nadjacency", ctypes.c_int64), ("nblocks", ctypes.c_int64), ("nterms", ctypes.c_int64),
+                ("nunique", ctypes.c_int64), ("polar_margin", ctypes.c_double),
+                ("y_pattern_max", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_f64 = ctypes.c_double
+
+
+def _sig(name, args, res=ctypes.c_int):
+    fn = getattr(_lib, name)
+    fn.argtypes = args
+    fn.restype = res
+    return fn
+
+
+_grid_create = _sig("sympix_grid_create", [_i32, _i32, _f64, ctypes.POINTER(_vp)])
+_grid_destroy = _sig("sympix_grid_destroy", [_vp], None)
+_grid_dims = _sig("sympix_grid_dims", [_vp, ctypes.POINTER(Dims)])
+_grid_rings = _sig("sympix_grid_rings", [_vp, _vp, _vp, _vp, _vp])
+_grid_bands = _sig("sympix_grid_bands", [_vp, _vp, _vp, _vp])
+_grid_neighbours = _sig("sympix_grid_neighbours", [_vp, _vp, _vp])
+_grid_blocks = _sig("sympix_grid_blocks", [_vp, _vp, _vp])
+_grid_unique = _sig("sympix_grid_unique", [_vp, _vp, _vp, _vp, _vp])
+_kernel_tabulate = _sig("sympix_kernel_tabulate", [_vp, _vp, _i32, _f64, _i32, _vp, ctypes.POINTER(_vp)])
+_kernel_destroy = _sig("sympix_kernel_destroy", [_vp], None)
+_kernel_eval = _sig("sympix_kernel_eval", [_vp, _vp, _vp, _i64, _vp])
+_sample_D = _sig("sympix_sample_D", [_vp, _vp, _vp, _i64, _vp])
+_sample_BtNB = _sig("sympix_sample_BtNB", [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp])
+_last_error = _sig("sympix_last_error", [], ctypes.c_char_p)
+
+EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sympix_grid_rings",
+            "sympix_grid_bands", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_unique",
+            "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
+            "sympix_sample_BtNB", "sympix_last_error")
+
+
+def _check(status):
+    if status != 0:
+        raise SympixError(status, (_last_error() or b"").decode())
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor, numpy array or integer."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _numel(x):
+    if hasattr(x, "numel"):
+        return int(x.numel())
+    return int(np.asarray(x).size)
+
+
+def _require_f64_device(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+
+
+class Grid:
+    """SymPix grid (host object; device tables are created on first use)."""
+
+    def __init__(self, lmax: int, k: int = 8, polar_margin: float | None = None):
+        h = _vp()
+        _check(_grid_create(int(lmax), int(k), math.nan if polar_margin is None else float(polar_margin),
+                            ctypes.byref(h)))
+        self._h = h
+        d = Dims()
+        _check(_grid_dims(self._h, ctypes.byref(d)))
+        self.dims = d
+        for f, _ in Dims._fields_:
+            setattr(self, f, getattr(d, f))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _grid_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def rings(self):
+        n = self.nrings
+        theta = np.zeros(n)
+        weight = np.zeros(n)
+        npix = np.zeros(n, dtype=np.int32)
+        first = np.zeros(n, dtype=np.int64)
+        _check(_grid_rings(self._h, _ptr(theta), _ptr(weight), _ptr(npix), _ptr(first)))
+        return theta, weight, npix, first
+
+    def bands(self):
+        nb = 2 * self.nbands_hemi
+        tiles = np.zeros(nb, dtype=np.int32)
+        alpha = np.zeros(nb, dtype=np.int32)
+        ring0 = np.zeros(nb, dtype=np.int32)
+        _check(_grid_bands(self._h, _ptr(tiles), _ptr(alpha), _ptr(ring0)))
+        return tiles, alpha, ring0
+
+    def neighbours(self):
+        rp = np.zeros(self.ntiles + 1, dtype=np.int64)
+        col = np.zeros(self.nadjacency, dtype=np.int32)
+        _check(_grid_neighbours(self._h, _ptr(rp), _ptr(col)))
+        return rp, col
+
+    def blocks(self):
+        rp = np.zeros(self.ntiles + 1, dtype=np.int64)
+        col = np.zeros(self.nblocks, dtype=np.int32)
+        _check(_grid_blocks(self._h, _ptr(rp), _ptr(col)))
+        return rp, col
+
+    def unique(self):
+        uid = np.zeros(self.nadjacency, dtype=np.int32)
+        bi = np.zeros(self.nunique, dtype=np.int32)
+        bj = np.zeros(self.nunique, dtype=np.int32)
+        de = np.zeros(self.nunique, dtype=np.int64)
+        _check(_grid_unique(self._h, _ptr(uid), _ptr(bi), _ptr(bj), _ptr(de)))
+        return uid, bi, bj, de
+
+    def pixel_theta_phi(self):
+        """Colatitude and longitude of every pixel in pixel order (host arrays),
+        from the ring tables and the Section 2.4 layout."""
+        theta, _, npix_ring, first = self.rings()
+        k = self.k
+        th = np.empty(self.npix)
+        ph = np.empty(self.npix)
+        for j in range(self.nrings):
+            n = int(npix_ring[j])
+            p = np.arange(n)
+            idx = first[j] + (p // k) * k * k + (p % k) * k
+            th[idx] = theta[j]
+            ph[idx] = 2.0 * np.pi * (p + 0.5) / n
+        return th, ph
+
+    @property
+    def out_len(self):
+        return self.nblocks * self.k ** 4
+
+
+class Kernel:
+    """Tabulated Eq. 10 kernel plus all unique local blocks of a grid."""
+
+    def __init__(self, grid: Grid, coef_l, radius: float = 0.0, n_nodes: int = 65536, stream=None):
+        coef = np.ascontiguousarray(coef_l, dtype=np.float64)
+        h = _vp()
+        self.grid = grid
+        _check(_kernel_tabulate(grid.handle, _ptr(coef), int(coef.size), float(radius), int(n_nodes),
+                                _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _kernel_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def eval(self, y, out, stream=None):
+        _require_f64_device(y, "y")
+        _require_f64_device(out, "out")
+        if _numel(out) != _numel(y):
+            raise ValueError("y and out differ in length")
+        _check(_kernel_eval(self._h, _ptr(y), _ptr(out), _numel(y), _stream(stream)))
+        return out
+
+
+def sample_D(grid: Grid, kernel: Kernel, out, stream=None):
+    _require_f64_device(out, "out")
+    _check(_sample_D(grid.handle, kernel.handle, _ptr(out), _numel(out), _stream(stream)))
+    return out
+
+
+def sample_BtNB(grid: Grid, kernel: Kernel, ninv, out, prec=FP64, stream=None):
+    if isinstance(prec, str):
+        prec = PRECISIONS[prec]
+    _require_f64_device(ninv, "ninv")
+    _require_f64_device(out, "out")
+    _check(_sample_BtNB(grid.handle, kernel.handle, _ptr(ninv), _numel(ninv), int(prec), _ptr(out),
+                        _numel(out), _stream(stream)))
+    return out
+
+
+def raw_call(name):
+    """The ctypes function of an exported symbol (for ABI-level tests)."""
+    return getattr(_lib, name)

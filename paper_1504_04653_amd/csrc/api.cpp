@@ -1,0 +1,395 @@
+// C ABI of the SymPix library: argument checks, handle lifetimes, device
+// tables and launches.  Declarations and contracts are in include/sympix.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sympix.h"
+#include "device.hpp"
+#include "geometry.hpp"
+
+using sympix::DevTerm;
+using sympix::Geometry;
+using sympix::UInfo;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sympix_status fail(sympix_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+sympix_status hip_fail(hipError_t e, const char *what) {
+    return fail(SYMPIX_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool sync_mode() {
+    const char *v = std::getenv("SYMPIX_SYNC");
+    return v && v[0] == '1';
+}
+
+// Device copies of the grid tables, one set per device that used the grid.
+struct DevGrid {
+    double *ring_theta = nullptr;
+    double *ring_sin = nullptr;
+    UInfo *uinfo = nullptr;
+    int32_t *blk_uid = nullptr;
+    int64_t *term_ptr = nullptr;
+    DevTerm *terms = nullptr;
+};
+
+template <class T>
+hipError_t upload(T **dst, const T *src, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void **)dst, n * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_dev(DevGrid &d) {
+    hipFree(d.ring_theta);
+    hipFree(d.ring_sin);
+    hipFree(d.uinfo);
+    hipFree(d.blk_uid);
+    hipFree(d.term_ptr);
+    hipFree(d.terms);
+    d = DevGrid();
+}
+
+}  // namespace
+
+struct sympix_grid {
+    Geometry geo;
+    mutable std::mutex mu;
+    mutable std::map<int, DevGrid> dev;
+};
+
+struct sympix_kernel {
+    const sympix_grid *g = nullptr;
+    int device = 0;
+    int32_t n_nodes = 0;
+    double h = 0.0, inv_h = 0.0, y_cut = 0.0;
+    double *coef = nullptr;
+    double *table = nullptr;
+    double *u64 = nullptr;
+    float *ut32 = nullptr;
+    uint16_t *bf[3] = {nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+// Upload the grid's tables to the current device once (blocking copies, so
+// every stream sees them afterwards).
+sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **out) {
+    std::lock_guard<std::mutex> lock(g->mu);
+    auto it = g->dev.find(device);
+    if (it != g->dev.end()) {
+        *out = &it->second;
+        return SYMPIX_OK;
+    }
+    const Geometry &geo = g->geo;
+    std::vector<UInfo> uinfo(geo.nunique());
+    for (int64_t u = 0; u < geo.nunique(); ++u) {
+        const int64_t I = geo.rep_i[u], J = geo.rep_j[u];
+        const int bI = geo.tile_band[I], bJ = geo.tile_band[J];
+        UInfo x;
+        x.ring0_i = geo.band_ring0[bI];
+        x.ring0_j = geo.band_ring0[bJ];
+        x.n_i = geo.k * geo.band_tiles[bI];
+        x.n_j = geo.k * geo.band_tiles[bJ];
+        x.p0_i = (int32_t)((I - geo.band_tile0[bI]) * geo.k);
+        x.p0_j = (int32_t)((J - geo.band_tile0[bJ]) * geo.k);
+        x.pad0 = x.pad1 = 0;
+        uinfo[u] = x;
+    }
+    std::vector<DevTerm> terms(geo.terms.size());
+    for (size_t t = 0; t < geo.terms.size(); ++t)
+        terms[t] = DevTerm{geo.terms[t].uid_a, geo.terms[t].uid_b, geo.terms[t].tile, 0};
+    DevGrid d;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = upload(&d.ring_theta, geo.theta.data(), geo.theta.size());
+    if (e == hipSuccess) e = upload(&d.ring_sin, geo.sin_theta.data(), geo.sin_theta.size());
+    if (e == hipSuccess) e = upload(&d.uinfo, uinfo.data(), uinfo.size());
+    if (e == hipSuccess) e = upload(&d.blk_uid, geo.blk_uid.data(), geo.blk_uid.size());
+    if (e == hipSuccess) e = upload(&d.term_ptr, geo.term_ptr.data(), geo.term_ptr.size());
+    if (e == hipSuccess) e = upload(&d.terms, terms.data(), terms.size());
+    if (e != hipSuccess) {
+        free_dev(d);
+        return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for grid tables failed")
+                                        : hip_fail(e, "uploading grid tables");
+    }
+    auto res = g->dev.emplace(device, d);
+    *out = &res.first->second;
+    return SYMPIX_OK;
+}
+
+sympix_status after_launch(hipError_t e, hipStream_t st, const char *what) {
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (sync_mode()) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
+    return SYMPIX_OK;
+}
+
+sympix::KTable ktable(const sympix_kernel *kr) {
+    sympix::KTable kt;
+    kt.table = kr->table;
+    kt.n_nodes = kr->n_nodes;
+    kt.inv_h = kr->inv_h;
+    kt.y_cut = kr->y_cut;
+    return kt;
+}
+
+void free_kernel(sympix_kernel *kr) {
+    hipFree(kr->coef);
+    hipFree(kr->table);
+    hipFree(kr->u64);
+    hipFree(kr->ut32);
+    for (auto &p : kr->bf) hipFree(p);
+    delete kr;
+}
+
+sympix_status check_kernel_use(const sympix_grid *g, const sympix_kernel *kr) {
+    if (!g || !kr) return fail(SYMPIX_EINVAL, "NULL grid or kernel");
+    if (kr->g != g) return fail(SYMPIX_EINVAL, "kernel was tabulated for another grid");
+    if (g->geo.k != 8) return fail(SYMPIX_EUNSUPPORTED, "device sampling is implemented for k = 8 only");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != kr->device) return fail(SYMPIX_EINVAL, "kernel lives on another device than the current one");
+    return SYMPIX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sympix_last_error(void) { return g_last_error.c_str(); }
+
+sympix_status sympix_grid_create(int32_t lmax, int32_t k, double polar_margin, sympix_grid **out) {
+    if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
+    *out = nullptr;
+    sympix_grid *g = new (std::nothrow) sympix_grid();
+    if (!g) return fail(SYMPIX_ENOMEM, "host allocation failed");
+    std::string err;
+    int rc = sympix::build_geometry(lmax, k, polar_margin, g->geo, err);
+    if (rc != 0) {
+        delete g;
+        return fail((sympix_status)rc, err);
+    }
+    *out = g;
+    g_last_error.clear();
+    return SYMPIX_OK;
+}
+
+void sympix_grid_destroy(sympix_grid *g) {
+    if (!g) return;
+    for (auto &kv : g->dev) free_dev(kv.second);
+    delete g;
+}
+
+sympix_status sympix_grid_dims(const sympix_grid *g, sympix_dims *out) {
+    if (!g || !out) return fail(SYMPIX_EINVAL, "NULL argument");
+    const Geometry &s = g->geo;
+    out->lmax = s.lmax;
+    out->k = s.k;
+    out->nrings = s.nrings;
+    out->nbands_hemi = s.nbands_hemi;
+    out->npix = s.npix;
+    out->ntiles = s.ntiles;
+    out->nadjacency = (int64_t)s.adj_col.size();
+    out->nblocks = s.nblocks();
+    out->nterms = (int64_t)s.terms.size();
+    out->nunique = s.nunique();
+    out->polar_margin = s.margin;
+    out->y_pattern_max = s.y_pattern_max;
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_grid_rings(const sympix_grid *g, double *theta, double *weight,
+                                int32_t *npix_ring, int64_t *first_pix) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const Geometry &s = g->geo;
+    const size_t n = (size_t)s.nrings;
+    if (theta) std::memcpy(theta, s.theta.data(), n * sizeof(double));
+    if (weight) std::memcpy(weight, s.weight.data(), n * sizeof(double));
+    if (npix_ring) std::memcpy(npix_ring, s.ring_npix.data(), n * sizeof(int32_t));
+    if (first_pix) std::memcpy(first_pix, s.ring_first_pix.data(), n * sizeof(int64_t));
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_grid_bands(const sympix_grid *g, int32_t *tiles, int32_t *alpha,
+                                int32_t *first_ring) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const Geometry &s = g->geo;
+    const size_t n = s.band_tiles.size();
+    if (tiles) std::memcpy(tiles, s.band_tiles.data(), n * sizeof(int32_t));
+    if (alpha) std::memcpy(alpha, s.band_alpha.data(), n * sizeof(int32_t));
+    if (first_ring) std::memcpy(first_ring, s.band_ring0.data(), n * sizeof(int32_t));
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_grid_neighbours(const sympix_grid *g, int64_t *row_ptr, int32_t *col) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const Geometry &s = g->geo;
+    if (row_ptr) std::memcpy(row_ptr, s.adj_ptr.data(), s.adj_ptr.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, s.adj_col.data(), s.adj_col.size() * sizeof(int32_t));
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_grid_blocks(const sympix_grid *g, int64_t *row_ptr, int32_t *col) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const Geometry &s = g->geo;
+    if (row_ptr) std::memcpy(row_ptr, s.blk_ptr.data(), s.blk_ptr.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, s.blk_col.data(), s.blk_col.size() * sizeof(int32_t));
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_grid_unique(const sympix_grid *g, int32_t *uid, int32_t *key_band_i,
+                                 int32_t *key_band_j, int64_t *key_delta) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const Geometry &s = g->geo;
+    if (uid) std::memcpy(uid, s.adj_uid.data(), s.adj_uid.size() * sizeof(int32_t));
+    if (key_band_i) std::memcpy(key_band_i, s.key_band_i.data(), s.key_band_i.size() * sizeof(int32_t));
+    if (key_band_j) std::memcpy(key_band_j, s.key_band_j.data(), s.key_band_j.size() * sizeof(int32_t));
+    if (key_delta) std::memcpy(key_delta, s.key_delta.data(), s.key_delta.size() * sizeof(int64_t));
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_kernel_tabulate(const sympix_grid *g, const double *coef_l, int32_t ncoef,
+                                     double radius, int32_t n_nodes, void *stream,
+                                     sympix_kernel **out) {
+    if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g || !coef_l) return fail(SYMPIX_EINVAL, "NULL grid or coefficients");
+    if (ncoef < 1) return fail(SYMPIX_ESIZE, "ncoef must be >= 1");
+    if (n_nodes == 0) n_nodes = 65536;
+    if (n_nodes < 64) return fail(SYMPIX_EINVAL, "n_nodes must be >= 64");
+    if (!(radius == radius)) return fail(SYMPIX_EINVAL, "radius is NaN");
+    for (int32_t l = 0; l < ncoef; ++l)
+        if (!std::isfinite(coef_l[l])) return fail(SYMPIX_EINVAL, "coefficients must be finite");
+    const Geometry &geo = g->geo;
+    hipStream_t st = (hipStream_t)stream;
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const DevGrid *dg = nullptr;
+    sympix_status s = device_tables(g, device, &dg);
+    if (s != SYMPIX_OK) return s;
+
+    sympix_kernel *kr = new (std::nothrow) sympix_kernel();
+    if (!kr) return fail(SYMPIX_ENOMEM, "host allocation failed");
+    kr->g = g;
+    kr->device = device;
+    kr->n_nodes = n_nodes;
+    double y_dom = geo.y_pattern_max;
+    kr->y_cut = INFINITY;
+    if (radius > 0) {
+        const double sr = std::sin(0.5 * radius);
+        kr->y_cut = 2.0 * sr * sr;
+        if (kr->y_cut < y_dom) y_dom = kr->y_cut;
+    }
+    // nodes uniform in s = sqrt(y) up to the domain end plus a little slack for
+    // device rounding of y; the last interval keeps one spare node
+    const double s_top = std::fmax(std::sqrt(y_dom) * (1.0 + 1e-6), 1e-300);
+    kr->h = s_top / (double)(n_nodes - 5);
+    kr->inv_h = 1.0 / kr->h;
+
+    const int32_t lmax = geo.lmax;
+    std::vector<double> coef(lmax + 1, 0.0);
+    for (int32_t l = 0; l <= lmax && l < ncoef; ++l) coef[l] = coef_l[l];
+    const size_t nu = (size_t)geo.nunique() * sympix::kBlockElems;
+    e = hipMalloc((void **)&kr->coef, coef.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&kr->table, (size_t)n_nodes * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&kr->u64, nu * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&kr->ut32, nu * sizeof(float));
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipMalloc((void **)&kr->bf[q], nu * sizeof(uint16_t));
+    if (e != hipSuccess) {
+        free_kernel(kr);
+        return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the kernel failed")
+                                        : hip_fail(e, "hipMalloc");
+    }
+    e = hipMemcpy(kr->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_kernel(kr);
+        return hip_fail(e, "copying coefficients");
+    }
+    e = sympix::launch_tabulate(kr->coef, lmax, kr->h, kr->table, n_nodes, st);
+    if (e == hipSuccess)
+        e = sympix::launch_unique_eval(ktable(kr), dg->uinfo, geo.nunique(), geo.k, dg->ring_theta,
+                                       dg->ring_sin, kr->u64, kr->ut32, kr->bf[0], kr->bf[1],
+                                       kr->bf[2], st);
+    s = after_launch(e, st, "tabulate / unique-block evaluation");
+    if (s != SYMPIX_OK) {
+        hipStreamSynchronize(st);
+        free_kernel(kr);
+        return s;
+    }
+    *out = kr;
+    return SYMPIX_OK;
+}
+
+void sympix_kernel_destroy(sympix_kernel *kr) {
+    if (kr) free_kernel(kr);
+}
+
+sympix_status sympix_kernel_eval(const sympix_kernel *kr, const double *y_dev, double *out_dev,
+                                 int64_t n, void *stream) {
+    if (!kr || (n > 0 && (!y_dev || !out_dev))) return fail(SYMPIX_EINVAL, "NULL argument");
+    if (n < 0) return fail(SYMPIX_ESIZE, "n < 0");
+    hipStream_t st = (hipStream_t)stream;
+    return after_launch(sympix::launch_eval(ktable(kr), y_dev, out_dev, n, st), st, "kernel_eval");
+}
+
+sympix_status sympix_sample_D(const sympix_grid *g, const sympix_kernel *d, double *out_dev,
+                              int64_t out_len, void *stream) {
+    sympix_status s = check_kernel_use(g, d);
+    if (s != SYMPIX_OK) return s;
+    const Geometry &geo = g->geo;
+    if (out_len != geo.nblocks() * sympix::kBlockElems)
+        return fail(SYMPIX_ESIZE, "out_len must be nblocks * k^4");
+    if (out_len > 0 && !out_dev) return fail(SYMPIX_EINVAL, "out_dev is NULL");
+    if (((uintptr_t)out_dev) % 16) return fail(SYMPIX_EINVAL, "out_dev must be 16-byte aligned");
+    const DevGrid *dg = nullptr;
+    s = device_tables(g, d->device, &dg);
+    if (s != SYMPIX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    return after_launch(sympix::launch_expand(d->u64, dg->blk_uid, geo.nblocks(), out_dev, st), st,
+                        "sample_D");
+}
+
+sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
+                                 int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
+                                 void *stream) {
+    sympix_status s = check_kernel_use(g, b);
+    if (s != SYMPIX_OK) return s;
+    const Geometry &geo = g->geo;
+    if (prec < SYMPIX_FP64 || prec > SYMPIX_BF16X6) return fail(SYMPIX_EINVAL, "unknown precision mode");
+    if (ninv_len != geo.npix) return fail(SYMPIX_ESIZE, "ninv_len must be npix");
+    if (out_len != geo.nblocks() * sympix::kBlockElems)
+        return fail(SYMPIX_ESIZE, "out_len must be nblocks * k^4");
+    if ((geo.npix > 0 && !ninv_dev) || (out_len > 0 && !out_dev))
+        return fail(SYMPIX_EINVAL, "NULL device buffer");
+    if (((uintptr_t)out_dev) % 16 || ((uintptr_t)ninv_dev) % 8)
+        return fail(SYMPIX_EINVAL, "out_dev must be 16-byte and ninv_dev 8-byte aligned");
+    const DevGrid *dg = nullptr;
+    s = device_tables(g, b->device, &dg);
+    if (s != SYMPIX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = sympix::launch_btnb(prec, b->u64, b->ut32, b->bf[0], b->bf[1], b->bf[2],
+                                       dg->term_ptr, dg->terms, ninv_dev, geo.nblocks(), out_dev, st);
+    return after_launch(e, st, "sample_BtNB");
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Device-side data layouts and launch functions (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sympix {
+
+// Geometry of one unique block: rows are the k^2 pixels of a representative
+// tile I, columns those of tile J.  Ring of local pixel (c, r) is ring0 + r,
+// its index on the ring is p0 + c, the ring holds n pixels.
+struct UInfo {
+    int32_t ring0_i, ring0_j;
+    int32_t n_i, n_j;
+    int32_t p0_i, p0_j;
+    int32_t pad0, pad1;
+};
+
+struct DevTerm {
+    int32_t uid_a, uid_b, tile, pad;
+};
+
+// Tabulated kernel as seen by device code.
+struct KTable {
+    const double *table;  // n_nodes values, node i at s = |i - 1| h
+    int32_t n_nodes;
+    double inv_h;
+    double y_cut;         // values at y > y_cut are 0 (+inf: no cut)
+};
+
+constexpr int kBlockDim = 64;              // k^2 for k = 8
+constexpr int kBlockElems = 64 * 64;
+
+// a6: table of sum_l c_l P_l(1 - s^2), c_l = (2l+1) coef_l / 4 pi
+hipError_t launch_tabulate(const double *coef, int32_t lmax, double h, double *table,
+                           int32_t n_nodes, hipStream_t st);
+// evaluation of the table at arbitrary y (tests of the interpolation)
+hipError_t launch_eval(KTable kt, const double *y, double *out, int64_t n, hipStream_t st);
+// a7: every unique block, FP64 row-major + FP32 and BF16 (3 parts) transposed
+hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, int32_t k,
+                              const double *ring_theta, const double *ring_sin,
+                              double *u64, float *ut32, uint16_t *ubf_hi, uint16_t *ubf_mid,
+                              uint16_t *ubf_lo, hipStream_t st);
+// a8: D-hat expansion, out[blk] = u64[blk_uid[blk]]
+hipError_t launch_expand(const double *u64, const int32_t *blk_uid, int64_t nblocks, double *out,
+                         hipStream_t st);
+// a9: B-hat^T N^-1 B-hat contraction
+hipError_t launch_btnb(int prec, const double *u64, const float *ut32, const uint16_t *ubf_hi,
+                       const uint16_t *ubf_mid, const uint16_t *ubf_lo, const int64_t *term_ptr,
+                       const DevTerm *terms, const double *ninv, int64_t nblocks, double *out,
+                       hipStream_t st);
+
+}  // namespace sympix

@@ -1,0 +1,356 @@
+// Host-side SymPix geometry (Section 2 of Seljebotn & Eriksen, Fig. 3).
+//
+// Compiled with -ffp-contract=off: the ring latitudes feed integer decisions
+// (the polar cut of Eq. 3), so every floating-point expression is evaluated
+// exactly as written, one rounding per operation.
+#include "geometry.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <map>
+#include <new>
+#include <tuple>
+
+namespace sympix {
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+
+// P_n(1-y) and P_{n-1}(1-y) for n >= 1, by the Legendre recurrence written in
+// y = 1 - x with D_l = P_l - P_{l-1}: D_1 = -y,
+// (l+1) D_{l+1} = l D_l - (2l+1) y P_l, P_{l+1} = P_l + D_{l+1}.
+void legendre_pair_y(int n, double y, double &pn, double &pn1) {
+    double p_prev = 1.0;
+    double d = -y;
+    double p = p_prev + d;
+    for (int l = 1; l < n; ++l) {
+        d = ((double)l * d - (double)(2 * l + 1) * y * p) / (double)(l + 1);
+        p_prev = p;
+        p = p + d;
+    }
+    pn = p;
+    pn1 = p_prev;
+}
+
+double half_angle_y(double th) {
+    double s = std::sin(0.5 * th);
+    return 2.0 * (s * s);
+}
+
+double newton_step(int n, double th) {
+    double y = half_angle_y(th);
+    double x = std::cos(th);
+    double pn, pn1;
+    legendre_pair_y(n, y, pn, pn1);
+    return pn * std::sin(th) / ((double)n * (pn1 - x * pn));
+}
+
+// Gauss-Legendre colatitudes and weights (Section 2.1, Eq. 2): Newton in
+// theta on P_N(cos theta) for the northern half, mirrored to the south.
+void gauss_legendre(int n, Geometry &g) {
+    const int half = n / 2;
+    std::vector<double> th(half);
+    for (int j = 0; j < half; ++j)
+        th[j] = kPi * (4.0 * (double)j + 3.0) / (4.0 * (double)n + 2.0);
+    const double eps = std::numeric_limits<double>::epsilon();
+    std::vector<double> step(half);
+    for (int it = 0; it < 100; ++it) {
+        bool done = true;
+        for (int j = 0; j < half; ++j) step[j] = newton_step(n, th[j]);
+        for (int j = 0; j < half; ++j) {
+            th[j] = th[j] + step[j];
+            if (!(std::fabs(step[j]) <= 4.0 * eps * th[j])) done = false;
+        }
+        if (done) break;
+    }
+    for (int j = 0; j < half; ++j) th[j] = th[j] + newton_step(n, th[j]);
+
+    g.theta.assign(n, 0.0);
+    g.sin_theta.assign(n, 0.0);
+    g.cos_theta.assign(n, 0.0);
+    g.weight.assign(n, 0.0);
+    for (int j = 0; j < half; ++j) {
+        double pn, pn1;
+        legendre_pair_y(n, half_angle_y(th[j]), pn, pn1);
+        double s = std::sin(th[j]);
+        double c = std::cos(th[j]);
+        double np1 = (double)n * pn1;
+        double w = 2.0 * s * s / (np1 * np1);
+        g.theta[j] = th[j];
+        g.sin_theta[j] = s;
+        g.cos_theta[j] = c;
+        g.weight[j] = w;
+        g.theta[n - 1 - j] = kPi - th[j];
+        g.sin_theta[n - 1 - j] = s;
+        g.cos_theta[n - 1 - j] = -c;
+        g.weight[n - 1 - j] = w;
+    }
+}
+
+// Smallest m in [0, lmax] with sqrt(m^2 - 2 m cos(theta)) - lmax sin(theta) > thr
+// (Eq. 3); a negative radicand does not satisfy it.  -1 if none does.
+int min_m_eq3(int lmax, double s, double c, double thr) {
+    for (int m = 0; m <= lmax; ++m) {
+        double rad = (double)((int64_t)m * m) - 2.0 * (double)m * c;
+        if (rad < 0.0) continue;
+        if (std::sqrt(rad) - (double)lmax * s > thr) return m;
+    }
+    return -1;
+}
+
+bool five_smooth(int64_t t) {
+    for (int p : {2, 3, 5})
+        while (t % p == 0) t /= p;
+    return t == 1;
+}
+
+// Fig. 3: minimise sum (T_i - alpha_i)^2 with T_0 the smallest 5-smooth number
+// >= alpha_0, T_i / T_{i-1} in {3, 2, 1, 4/3, 5/4, 6/5} (Eq. 5), alpha_i <= T_i
+// <= 3 alpha_i, and a change only after a band that did not change (band 1 is
+// exempt).  Ties: t_prev ascending, ratios in the listed order, strict <, and
+// the final argmin takes the smallest t.  Returns false if infeasible.
+bool tile_programme(const std::vector<int32_t> &alpha, std::vector<int32_t> &tiles) {
+    static const int ratio[6][2] = {{3, 1}, {2, 1}, {1, 1}, {4, 3}, {5, 4}, {6, 5}};
+    const int n = (int)alpha.size();
+    int64_t t0 = std::max<int64_t>(alpha[0], 1);
+    while (!five_smooth(t0)) ++t0;
+    std::vector<std::map<int64_t, int64_t>> C(n);
+    std::vector<std::map<int64_t, int64_t>> P(n);
+    C[0][t0] = (t0 - alpha[0]) * (t0 - alpha[0]);
+    P[0][t0] = -1;
+    for (int i = 1; i < n; ++i) {
+        const int64_t a = alpha[i];
+        for (const auto &cp : C[i - 1]) {
+            const int64_t tp = cp.first;
+            const int64_t prev_ptr = P[i - 1][tp];
+            for (const auto &r : ratio) {
+                if ((r[0] * tp) % r[1]) continue;
+                const int64_t t = r[0] * tp / r[1];
+                if (t < a || t > 3 * a) continue;
+                const bool steady = prev_ptr == tp || r[0] == r[1] || i == 1;
+                if (!steady) continue;
+                const int64_t cand = cp.second + (a - t) * (a - t);
+                auto it = C[i].find(t);
+                if (it == C[i].end() || cand < it->second) {
+                    C[i][t] = cand;
+                    P[i][t] = tp;
+                }
+            }
+        }
+    }
+    if (C[n - 1].empty()) return false;
+    int64_t best = std::numeric_limits<int64_t>::max(), tbest = 0;
+    for (const auto &c : C[n - 1])   // ascending t: first minimiser is the smallest t
+        if (c.second < best) { best = c.second; tbest = c.first; }
+    tiles.assign(n, 0);
+    tiles[n - 1] = (int32_t)tbest;
+    for (int i = n - 1; i > 0; --i) tiles[i - 1] = (int32_t)P[i][tiles[i]];
+    return true;
+}
+
+int64_t floor_div(int64_t a, int64_t b) {   // b > 0
+    int64_t q = a / b;
+    if ((a % b) != 0 && (a < 0)) --q;
+    return q;
+}
+
+int64_t pos_mod(int64_t a, int64_t m) {
+    int64_t r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+}  // namespace
+
+int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::string &err) {
+    try {
+        if (lmax < 1 || k < 1 || k > 64 || lmax > 100000) {
+            err = "lmax must be in [1, 100000] and k in [1, 64]";
+            return -1;
+        }
+        g = Geometry();
+        g.lmax = lmax;
+        g.k = k;
+        g.nrings = (int32_t)(((int64_t)lmax + 1 + 2 * k - 1) / (2 * k) * (2 * k));
+        g.nbands_hemi = g.nrings / (2 * k);
+        g.margin = std::isnan(margin) ? std::max(100.0, 0.01 * (double)lmax) : margin;
+        if (!std::isfinite(g.margin)) {
+            err = "polar_margin must be finite (or NaN for the default)";
+            return -1;
+        }
+        const int n = g.nbands_hemi;
+        gauss_legendre(g.nrings, g);
+
+        // alpha_i at the pole-most ring of each northern band (Fig. 3)
+        g.alpha_north.resize(n);
+        for (int i = 0; i < n; ++i) {
+            const int j = i * k;
+            int m = min_m_eq3(lmax, g.sin_theta[j], g.cos_theta[j], g.margin);
+            if (m < 0) m = lmax;
+            g.alpha_north[i] = (int32_t)((2 * (int64_t)m + 1 + k - 1) / k);
+        }
+        if (!tile_programme(g.alpha_north, g.tiles_north)) {
+            err = "no tile layout satisfies the rules of Fig. 3 for this lmax, k and margin";
+            return -2;
+        }
+
+        // bands in storage order N0, S0, N1, S1, ... (Section 2.4), rings by increasing theta
+        int64_t tile = 0;
+        for (int i = 0; i < n; ++i) {
+            for (int south = 0; south < 2; ++south) {
+                g.band_tiles.push_back(g.tiles_north[i]);
+                g.band_alpha.push_back(g.alpha_north[i]);
+                g.band_ring0.push_back(south ? g.nrings - i * k - k : i * k);
+                g.band_tile0.push_back(tile);
+                tile += g.tiles_north[i];
+            }
+        }
+        g.ntiles = tile;
+        g.npix = tile * (int64_t)k * k;
+        const int nb = 2 * n;
+        g.tile_band.resize(g.ntiles);
+        for (int b = 0; b < nb; ++b)
+            for (int64_t t = 0; t < g.band_tiles[b]; ++t) g.tile_band[g.band_tile0[b] + t] = b;
+        g.ring_npix.assign(g.nrings, 0);
+        g.ring_first_pix.assign(g.nrings, 0);
+        for (int b = 0; b < nb; ++b)
+            for (int r = 0; r < k; ++r) {
+                g.ring_npix[g.band_ring0[b] + r] = k * g.band_tiles[b];
+                g.ring_first_pix[g.band_ring0[b] + r] = g.band_tile0[b] * k * k + r;
+            }
+
+        // tile adjacency (Section 2.2): same band t-1, t, t+1 mod T; neighbouring
+        // bands by closed phi-interval intersection, in integers scaled by T T'
+        g.adj_ptr.assign(g.ntiles + 1, 0);
+        std::vector<int32_t> row;
+        for (int64_t I = 0; I < g.ntiles; ++I) {
+            const int b = g.tile_band[I];
+            const int64_t T = g.band_tiles[b];
+            const int64_t t = I - g.band_tile0[b];
+            row.clear();
+            for (int d = -1; d <= 1; ++d) row.push_back((int32_t)(g.band_tile0[b] + pos_mod(t + d, T)));
+            const int i = b / 2, south = b % 2;
+            int nbrs[2], nn = 0;
+            if (i > 0) nbrs[nn++] = 2 * (i - 1) + south;
+            if (i < n - 1) nbrs[nn++] = 2 * (i + 1) + south;
+            else nbrs[nn++] = 2 * i + (1 - south);
+            for (int q = 0; q < nn; ++q) {
+                const int b2 = nbrs[q];
+                const int64_t T2 = g.band_tiles[b2];
+                const int64_t M = T * T2;
+                const int64_t lo1 = t * T2, hi1 = (t + 1) * T2;
+                int64_t u0 = 0, u1 = T2 - 1;
+                if (T2 > 8) { u0 = floor_div(t * T2, T) - 1; u1 = floor_div((t + 1) * T2, T) + 1; }
+                for (int64_t u = u0; u <= u1; ++u) {
+                    const int64_t t2 = pos_mod(u, T2);
+                    const int64_t lo2 = t2 * T, hi2 = (t2 + 1) * T;
+                    for (int64_t shift : {-M, (int64_t)0, M}) {
+                        if (lo1 <= hi2 + shift && lo2 + shift <= hi1) {
+                            row.push_back((int32_t)(g.band_tile0[b2] + t2));
+                            break;
+                        }
+                    }
+                }
+            }
+            std::sort(row.begin(), row.end());
+            row.erase(std::unique(row.begin(), row.end()), row.end());
+            g.adj_col.insert(g.adj_col.end(), row.begin(), row.end());
+            g.adj_ptr[I + 1] = (int64_t)g.adj_col.size();
+        }
+
+        // symmetry keys (band_I, band_J, (t_J T_I - t_I T_J) mod T_I T_J)
+        std::map<std::tuple<int32_t, int32_t, int64_t>, int32_t> keys;
+        g.adj_uid.resize(g.adj_col.size());
+        for (int64_t I = 0; I < g.ntiles; ++I) {
+            const int bI = g.tile_band[I];
+            const int64_t TI = g.band_tiles[bI], tI = I - g.band_tile0[bI];
+            for (int64_t e = g.adj_ptr[I]; e < g.adj_ptr[I + 1]; ++e) {
+                const int64_t J = g.adj_col[e];
+                const int bJ = g.tile_band[J];
+                const int64_t TJ = g.band_tiles[bJ], tJ = J - g.band_tile0[bJ];
+                const int64_t delta = pos_mod(tJ * TI - tI * TJ, TI * TJ);
+                auto key = std::make_tuple((int32_t)bI, (int32_t)bJ, delta);
+                auto it = keys.find(key);
+                int32_t uid;
+                if (it == keys.end()) {
+                    uid = (int32_t)g.key_delta.size();
+                    keys.emplace(key, uid);
+                    g.key_band_i.push_back(bI);
+                    g.key_band_j.push_back(bJ);
+                    g.key_delta.push_back(delta);
+                    g.rep_i.push_back((int32_t)I);
+                    g.rep_j.push_back((int32_t)J);
+                } else {
+                    uid = it->second;
+                }
+                g.adj_uid[e] = uid;
+            }
+        }
+
+        auto uid_of = [&](int64_t I, int64_t J) -> int32_t {
+            auto first = g.adj_col.begin() + g.adj_ptr[I], last = g.adj_col.begin() + g.adj_ptr[I + 1];
+            auto it = std::lower_bound(first, last, (int32_t)J);
+            return g.adj_uid[it - g.adj_col.begin()];
+        };
+
+        // stored blocks (J, K >= J) and their contraction terms I in nbr(J) & nbr(K)
+        g.blk_ptr.assign(g.ntiles + 1, 0);
+        g.term_ptr.push_back(0);
+        for (int64_t J = 0; J < g.ntiles; ++J) {
+            for (int64_t e = g.adj_ptr[J]; e < g.adj_ptr[J + 1]; ++e) {
+                const int64_t K = g.adj_col[e];
+                if (K < J) continue;
+                g.blk_col.push_back((int32_t)K);
+                g.blk_uid.push_back(g.adj_uid[e]);
+                auto a = g.adj_col.begin() + g.adj_ptr[J], ae = g.adj_col.begin() + g.adj_ptr[J + 1];
+                auto b = g.adj_col.begin() + g.adj_ptr[K], be = g.adj_col.begin() + g.adj_ptr[K + 1];
+                while (a != ae && b != be) {
+                    if (*a < *b) ++a;
+                    else if (*b < *a) ++b;
+                    else {
+                        const int64_t I = *a;
+                        g.terms.push_back(Term{uid_of(I, J), uid_of(I, K), (int32_t)I, 0});
+                        ++a;
+                        ++b;
+                    }
+                }
+                g.term_ptr.push_back((int64_t)g.terms.size());
+            }
+            g.blk_ptr[J + 1] = (int64_t)g.blk_col.size();
+        }
+
+        // largest y = 1 - cos(gamma) over every pattern pair: per unique block the
+        // largest |phi offset| over the k x k column pairs, then every ring pair
+        double ymax = 0.0;
+        for (int64_t u = 0; u < g.nunique(); ++u) {
+            const int64_t I = g.rep_i[u], J = g.rep_j[u];
+            const int bI = g.tile_band[I], bJ = g.tile_band[J];
+            const int64_t nI = (int64_t)k * g.band_tiles[bI], nJ = (int64_t)k * g.band_tiles[bJ];
+            const int64_t pI0 = (I - g.band_tile0[bI]) * k, pJ0 = (J - g.band_tile0[bJ]) * k;
+            const int64_t M = nI * nJ;
+            int64_t nmax = 0;
+            for (int c = 0; c < k; ++c)
+                for (int c2 = 0; c2 < k; ++c2) {
+                    int64_t N = pos_mod((2 * (pJ0 + c2) + 1) * nI - (2 * (pI0 + c) + 1) * nJ, 2 * M);
+                    if (N > M) N -= 2 * M;
+                    nmax = std::max(nmax, N < 0 ? -N : N);
+                }
+            const double sh = std::sin(0.5 * (kPi * (double)nmax / (double)M));
+            const double hmax = sh * sh;
+            for (int r = 0; r < k; ++r)
+                for (int r2 = 0; r2 < k; ++r2) {
+                    const int j1 = g.band_ring0[bI] + r, j2 = g.band_ring0[bJ] + r2;
+                    const double sd = std::sin(0.5 * (g.theta[j1] - g.theta[j2]));
+                    const double y = 2.0 * (sd * sd + g.sin_theta[j1] * g.sin_theta[j2] * hmax);
+                    ymax = std::max(ymax, y);
+                }
+        }
+        g.y_pattern_max = ymax;
+        return 0;
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed while building the grid";
+        return -3;
+    }
+}
+
+}  // namespace sympix

@@ -1,0 +1,66 @@
+// Host-side SymPix geometry: rings, tile counts, layout, tile adjacency,
+// symmetry keys and the contraction term lists.  Pure C++17, no device code.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sympix {
+
+// One contraction term of an output block (J, K): C_JK += B_IJ^T diag(w_I) B_IK.
+struct Term {
+    int32_t uid_a;  // unique block of (I -> J)
+    int32_t uid_b;  // unique block of (I -> K)
+    int32_t tile;   // I (its N^-1 values are pixels [I k^2, (I+1) k^2))
+    int32_t pad;
+};
+
+struct Geometry {
+    int32_t lmax = 0, k = 0, nrings = 0, nbands_hemi = 0;
+    double margin = 0.0;
+
+    // rings, j = 0 at the north pole
+    std::vector<double> theta, sin_theta, cos_theta, weight;
+    std::vector<int32_t> ring_npix;
+    std::vector<int64_t> ring_first_pix;
+
+    // per northern band i (Fig. 3)
+    std::vector<int32_t> alpha_north, tiles_north;
+
+    // bands in storage order N0, S0, N1, S1, ...
+    std::vector<int32_t> band_tiles, band_alpha, band_ring0;
+    std::vector<int64_t> band_tile0;
+
+    int64_t npix = 0, ntiles = 0;
+    std::vector<int32_t> tile_band;   // band of every tile
+
+    // full tile adjacency (CSR, itself included, ascending)
+    std::vector<int64_t> adj_ptr;
+    std::vector<int32_t> adj_col;
+    std::vector<int32_t> adj_uid;     // unique-block id of each (I, J) entry
+
+    // symmetry keys, one per unique block, and a representative tile pair
+    std::vector<int32_t> key_band_i, key_band_j;
+    std::vector<int64_t> key_delta;
+    std::vector<int32_t> rep_i, rep_j;
+
+    // stored blocks (J, K >= J) as CSR over J, and per block its D-hat uid
+    std::vector<int64_t> blk_ptr;
+    std::vector<int32_t> blk_col;
+    std::vector<int32_t> blk_uid;
+
+    // contraction terms per stored block (CSR, I ascending)
+    std::vector<int64_t> term_ptr;
+    std::vector<Term> terms;
+
+    double y_pattern_max = 0.0;   // max 1 - cos(gamma) over all pattern pairs
+
+    int64_t nblocks() const { return (int64_t)blk_col.size(); }
+    int64_t nunique() const { return (int64_t)key_delta.size(); }
+};
+
+// Status codes follow sympix_status. On failure err holds a message.
+int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::string &err);
+
+}  // namespace sympix

@@ -1,0 +1,132 @@
+"""Host-side tests of the C ABI (no GPU): exported symbols, grid layout and
+symmetry keys against the oracle bit for bit, and error paths."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1504_04653_amd as sp
+from oracle import grid as G
+from oracle import operators as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    header = open(os.path.join(ROOT, "include", "sympix.h")).read()
+    declared = set(re.findall(r"\b(sympix_[a-z_A-Z]+)\s*\(", header))
+    assert declared == set(sp.EXPORTED)
+    for name in declared:
+        assert sp.raw_call(name) is not None
+
+
+LAYOUT_CASES = [(64, 8, None), (100, 8, None), (256, 8, None), (512, 8, None),
+                (20, 2, 0.0), (34, 2, 2.0), (40, 4, None)]
+
+
+@pytest.mark.parametrize("lmax,k,margin", LAYOUT_CASES)
+def test_layout_bit_exact_against_oracle(lmax, k, margin):
+    og = G.make_grid(lmax, k, polar_margin=margin)
+    g = sp.Grid(lmax, k, margin)
+    assert (g.nrings, g.nbands_hemi, g.npix, g.ntiles) == (og.nrings, og.nbands_hemi, og.npix, og.ntiles)
+    theta, weight, npix_ring, first = g.rings()
+    # independent Newton codes: within 4 ulp (identical on this host's libm)
+    assert np.all(np.abs(theta - og.theta) <= 4 * np.spacing(og.theta))
+    assert np.max(np.abs(weight - og.weight) / og.weight) < 1e-13
+    assert np.array_equal(npix_ring, og.ring_npix())
+    assert np.array_equal(first, og.ring_first_pix())
+    tiles, alpha, ring0 = g.bands()
+    assert tiles.tolist() == og.band_tiles
+    assert alpha.tolist() == og.band_alpha
+    assert ring0.tolist() == [r[0] for r in og.band_rings]
+    rp, col = g.neighbours()
+    orp, ocol = og.adjacency()
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    brp, bcol = g.blocks()
+    obrp, obcol = og.stored_blocks()
+    assert np.array_equal(brp, obrp) and np.array_equal(bcol, obcol)
+    uid, bi, bj, de = g.unique()
+    keys = set()
+    for I in range(g.ntiles):
+        for e in range(rp[I], rp[I + 1]):
+            J = int(col[e])
+            u = uid[e]
+            key = O.unique_key(og, I, J)
+            assert (bi[u], bj[u], de[u]) == key
+            keys.add(key)
+    assert len(keys) == g.nunique
+    # contraction terms: sum over stored blocks of |nbr(J) & nbr(K)|
+    nterms = 0
+    for J in range(g.ntiles):
+        for K in bcol[brp[J]:brp[J + 1]]:
+            nterms += len(set(col[rp[J]:rp[J + 1]]) & set(col[rp[K]:rp[K + 1]]))
+    assert g.nterms == nterms
+
+
+@pytest.mark.parametrize("lmax,k,margin", [(64, 8, None), (34, 2, 2.0), (100, 8, None)])
+def test_pattern_max_separation(lmax, k, margin):
+    """The table domain: max y over all pairs in neighbouring tiles."""
+    og = G.make_grid(lmax, k, polar_margin=margin)
+    g = sp.Grid(lmax, k, margin)
+    rp, col = og.adjacency()
+    ymax = 0.0
+    for I in range(og.ntiles):
+        for J in col[rp[I]:rp[I + 1]]:
+            ymax = max(ymax, O.block_y(og, I, int(J)).max())
+    assert abs(g.y_pattern_max - ymax) <= 1e-13 * ymax
+
+
+def test_pixel_coordinates_match_oracle():
+    og = G.make_grid(100, 8)
+    g = sp.Grid(100, 8)
+    th, ph = g.pixel_theta_phi()
+    ring, pin, nr, phi = og.pixel_coords()
+    assert np.array_equal(th, og.theta[ring])
+    assert np.allclose(ph, phi, rtol=0, atol=1e-15)
+
+
+def test_default_margin_and_dims():
+    g = sp.Grid(3000, 8)
+    assert g.polar_margin == 100.0
+    g2 = sp.Grid(10400, 8)
+    assert g2.polar_margin == 0.01 * 10400
+    assert g.nblocks > 0 and g.nterms > g.nblocks and g.nunique > 0
+    assert g.out_len == g.nblocks * 8 ** 4
+
+
+@pytest.mark.parametrize("lmax,k", [(0, 8), (-3, 8), (64, 0), (64, 65), (200000, 8)])
+def test_create_rejects_bad_arguments(lmax, k):
+    with pytest.raises(sp.SympixError) as e:
+        sp.Grid(lmax, k)
+    assert e.value.code == "EINVAL"
+    assert "lmax" in str(e.value)
+
+
+def test_create_reports_infeasible_layout():
+    """lmax 64, k 8, margin 0: alpha = 2, 6, 11, ... and no ratio sequence from
+    T_0 = 2 can follow alpha with runs of two (the oracle agrees)."""
+    with pytest.raises(G.InfeasibleGrid):
+        G.make_grid(64, 8, polar_margin=0.0)
+    with pytest.raises(sp.SympixError) as e:
+        sp.Grid(64, 8, 0.0)
+    assert e.value.code == "EINFEASIBLE"
+
+
+def test_null_handles_are_rejected():
+    dims = sp.Dims()
+    assert sp.raw_call("sympix_grid_dims")(None, None) == -1
+    assert sp.raw_call("sympix_grid_rings")(None, None, None, None, None) == -1
+    assert b"NULL" in sp.raw_call("sympix_last_error")()
+    # destroy accepts NULL
+    sp.raw_call("sympix_grid_destroy")(None)
+    sp.raw_call("sympix_kernel_destroy")(None)
+    del dims
+
+
+def test_grid_handles_are_independent():
+    a = sp.Grid(64, 8)
+    b = sp.Grid(100, 8)
+    del a
+    assert b.rings()[0].shape == (112,)
