@@ -1,0 +1,231 @@
+"""Benchmark: B-hat^T N^-1 B-hat elements/s on one MI355X.
+
+A step is one pass of the whole device path on one synthetic problem:
+tabulate the beam and prior kernels (each with its unique-block evaluation),
+expand D-hat, and contract B-hat^T N^-1 B-hat.  Grid construction is host work
+done once per resolution and is timed separately (setup_s).  Inputs are
+resident in device memory before the timed region.
+
+Default workload: lmax = 3000, k = 8 (13.0M pixels, 1,013,648 stored 64x64
+blocks), Gaussian beam FWHM 3 pixels cut at 3 FWHM, prior d_l = (l+1)^2,
+N^-1 = log-normal scan-stripe pattern with 20% of the sky masked.
+
+value = stored B^T N^-1 B elements / step time in the headline precision mode
+(split BF16, 6 products); FP64 and the other modes are timed the same way and
+reported side by side under "modes".
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4]
+                       [--modes bf16x6,fp64,bf16x3] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "B^T N^-1 B elements/s at lmax=3000: FP64 vs split-BF16 MFMA at <=1e-6 rel err"
+HEADLINE = "bf16x6"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}     # TFLOP/s, dense
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}                   # MFMA products per term
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAME = {"fp64": "k_btnb_f64", "fp32": "k_btnb_f32", "bf16x3": "k_btnb_bf16<2>",
+               "bf16x6": "k_btnb_bf16<3>"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c4")
+    ap.add_argument("--modes", default="bf16x6,fp64,bf16x3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def kernels_hash():
+    src = os.path.join(ROOT, "paper_1504_04653_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def recorded_traffic(mode, config):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
+    if not os.path.exists(path):
+        return None
+    h = kernels_hash()
+    for line in open(path):
+        m = re.match(r"\|\s*(\S+)\s*\|\s*(\S+)\s*\|\s*(\S+)\s*\|\s*([0-9.eE+]+)\s*\|\s*([0-9.eE+]+)\s*\|", line)
+        if m and m.group(1) == mode and m.group(2) == config and m.group(3) == h:
+            return float(m.group(4)) + float(m.group(5))
+    return None
+
+
+def cpu_baseline(cfg, budget_s):
+    """The oracle as it stands, on a bounded sample of the same workload: whole
+    block-rows of B^T N^-1 B at random tiles until the time budget is spent."""
+    from oracle import grid as G
+    from oracle import operators as O
+    from workloads import synth as S
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    og = G.make_grid(cfg.lmax, cfg.k)
+    ring, pin, nr, phi = og.pixel_coords()
+    ninv = S.ninv_for(cfg, og.theta[ring], phi)
+    b_l, R = S.gaussian_beam(cfg.lmax, og.npix, cfg.fwhm_pix)
+    op = O.LocalOperator(og, b_l, R)
+    rng = np.random.default_rng(7)
+    t0 = time.perf_counter()
+    nblk = 0
+    nrows = 0
+    while time.perf_counter() - t0 < budget_s:
+        J = int(rng.integers(og.ntiles))
+        for K in og.tile_neighbours(J):
+            if K >= J:
+                O.btnb_block(op, ninv, J, K)
+                nblk += 1
+        nrows += 1
+    dt = time.perf_counter() - t0
+    return {"value": nblk * 4096 / dt, "unit": "elements/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{nrows} random block-rows ({nblk} stored 64x64 blocks of B^T N^-1 B, "
+                      f"unique blocks evaluated on first use) of the lmax={cfg.lmax} workload, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1504_04653_amd as sp
+    from workloads import synth as S
+
+    cfg = S.CONFIGS[args.config]
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    torch.cuda.set_device(0)
+
+    t0 = time.perf_counter()
+    g = sp.Grid(cfg.lmax, cfg.k)
+    setup_grid = time.perf_counter() - t0
+    th, ph = g.pixel_theta_phi()
+    ninv = S.ninv_for(cfg, th, ph)
+    b_l, R = S.gaussian_beam(cfg.lmax, g.npix, cfg.fwhm_pix)
+    d_l = S.prior(cfg.lmax)
+    ninv_dev = torch.as_tensor(ninv).cuda()
+    out_C = torch.empty(g.out_len, dtype=torch.float64, device="cuda")
+    out_D = torch.empty(g.out_len, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    nelem = g.nblocks * 4096
+    alg_flop = 2.0 * 64 ** 3 * g.nterms
+    print(f"# workload {args.config}: lmax={cfg.lmax} npix={g.npix} nblocks={g.nblocks} "
+          f"nterms={g.nterms} nunique={g.nunique} grid_setup={setup_grid:.2f}s", file=sys.stderr, flush=True)
+
+    def step(prec, ev):
+        ev[0].record(stream)
+        kb = sp.Kernel(g, b_l, R, stream=stream)
+        ev[1].record(stream)
+        kd = sp.Kernel(g, d_l, 0.0, stream=stream)
+        ev[2].record(stream)
+        sp.sample_D(g, kd, out_D, stream=stream)
+        ev[3].record(stream)
+        sp.sample_BtNB(g, kb, ninv_dev, out_C, prec, stream=stream)
+        ev[4].record(stream)
+        return kb, kd
+
+    results = {}
+    for prec in modes:
+        for _ in range(args.warmup):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            keep = step(prec, ev)
+            torch.cuda.synchronize()
+            del keep
+        evs = []
+        keeps = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            keeps.append(step(prec, ev))
+            evs.append(ev)
+            if len(keeps) > 2:          # free kernel handles of finished steps
+                keeps.pop(0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        keeps.clear()
+        seg = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])   # ms
+        tab_b, tab_d, t_D, t_C = seg.mean(axis=0)
+        ms_step = wall * 1000.0 / args.steps
+        r = {
+            "elements_per_s": nelem / (ms_step * 1e-3),
+            "ms_per_step": ms_step,
+            "btnb_ms": t_C,
+            "btnb_elements_per_s": nelem / (t_C * 1e-3),
+            "D_ms": t_D,
+            "D_elements_per_s": nelem / (t_D * 1e-3),
+            "tabulate_beam_ms": tab_b,
+            "tabulate_prior_ms": tab_d,
+            "btnb_tflops_algorithmic": alg_flop / (t_C * 1e-3) / 1e12,
+            "btnb_roofline": {
+                "bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec],
+                "achieved": PRODUCTS[prec] * alg_flop / (t_C * 1e-3) / 1e12,
+                "frac": PRODUCTS[prec] * alg_flop / (t_C * 1e-3) / 1e12 / PEAK[prec],
+            },
+            "D_hbm_GBs": nelem * 8 / (t_D * 1e-3) / 1e9,
+        }
+        results[prec] = r
+        print(f"# {prec}: step {ms_step:.2f} ms, btnb {t_C:.2f} ms "
+              f"({r['btnb_roofline']['frac'] * 100:.1f}% of {PEAK[prec]} TFLOP/s), D {t_D:.2f} ms "
+              f"({r['D_hbm_GBs']:.0f} GB/s), tabulate {tab_b:.2f}+{tab_d:.2f} ms",
+              file=sys.stderr, flush=True)
+
+    head = HEADLINE if HEADLINE in results else modes[0]
+    hr = results[head]
+    traffic = recorded_traffic(head, args.config)
+    roof = dict(hr["btnb_roofline"])
+    roof["kernel"] = KERNEL_NAME[head]
+    roof["traffic"] = traffic
+    line = {
+        "metric": METRIC,
+        "value": hr["elements_per_s"],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hr["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if head.startswith("bf16") else ("f64" if head == "fp64" else "f32"),
+        "data": "synthetic",
+        "config": {"workload": f"sympix lmax={cfg.lmax} k={cfg.k} beam FWHM {cfg.fwhm_pix:g} px "
+                               f"cut 3 FWHM, prior (l+1)^2, N^-1 {cfg.ninv_kind} seed {cfg.seed}",
+                   "lmax": cfg.lmax, "k": cfg.k, "npix": g.npix, "nblocks": g.nblocks,
+                   "nterms": g.nterms, "nunique": g.nunique, "precision": head,
+                   "grid_setup_s": round(setup_grid, 3)},
+        "roofline": roof,
+        "modes": results,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

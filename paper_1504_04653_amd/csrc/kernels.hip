@@ -152,7 +152,8 @@ __global__ __launch_bounds__(256) void k_expand(const double *__restrict__ u64,
 // per wave.  For a term I: A = B_IJ (rows p in I, cols a in J), B = B_IK, and
 // C[a][b] += sum_p A[p][a] w_p B[p][b].  MFMA operand lanes: A fragment holds
 // (row a = 16 i + lane%16, k = p), B fragment (k = p, col b = 16 j + lane%16),
-// with p = 4 ks + lane/16; the result lane holds rows 4 (lane/16) + v.
+// with p = 4 ks + lane/16.  The FP64 result interleaves rows: lane holds rows
+// lane/16 + 4 v of column lane%16 (the FP32/BF16 16x16 forms hold 4 (lane/16) + v).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_btnb_f64(const double *__restrict__ u64,
                                                   const int64_t *__restrict__ term_ptr,
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_btnb_f64(const double *__restrict__ u64
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                __builtin_nontemporal_store(acc[i][j][v], &o[(16 * i + 4 * lk + v) * 64 + 16 * j]);
+                __builtin_nontemporal_store(acc[i][j][v], &o[(16 * i + lk + 4 * v) * 64 + 16 * j]);
 }
 
 // ---------------------------------------------------------------------------
