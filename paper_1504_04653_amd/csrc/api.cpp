@@ -45,6 +45,11 @@ struct DevGrid {
     int32_t *blk_uid = nullptr;
     int64_t *term_ptr = nullptr;
     DevTerm *terms = nullptr;
+    sympix::DevClass *classes = nullptr;
+    int32_t *class_terms = nullptr;
+    int32_t *class_blk = nullptr;
+    int32_t *class_itab = nullptr;
+    int32_t *mtiles = nullptr;
 };
 
 template <class T>
@@ -63,6 +68,11 @@ void free_dev(DevGrid &d) {
     hipFree(d.blk_uid);
     hipFree(d.term_ptr);
     hipFree(d.terms);
+    hipFree(d.classes);
+    hipFree(d.class_terms);
+    hipFree(d.class_blk);
+    hipFree(d.class_itab);
+    hipFree(d.mtiles);
     d = DevGrid();
 }
 
@@ -115,6 +125,7 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     std::vector<DevTerm> terms(geo.terms.size());
     for (size_t t = 0; t < geo.terms.size(); ++t)
         terms[t] = DevTerm{geo.terms[t].uid_a, geo.terms[t].uid_b, geo.terms[t].tile, 0};
+    static_assert(sizeof(sympix::DevClass) == sizeof(sympix::BlockClass), "class layout");
     DevGrid d;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(&d.ring_theta, geo.theta.data(), geo.theta.size());
@@ -123,6 +134,13 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.blk_uid, geo.blk_uid.data(), geo.blk_uid.size());
     if (e == hipSuccess) e = upload(&d.term_ptr, geo.term_ptr.data(), geo.term_ptr.size());
     if (e == hipSuccess) e = upload(&d.terms, terms.data(), terms.size());
+    if (e == hipSuccess)
+        e = upload(&d.classes, reinterpret_cast<const sympix::DevClass *>(geo.classes.data()),
+                   geo.classes.size());
+    if (e == hipSuccess) e = upload(&d.class_terms, geo.class_terms.data(), geo.class_terms.size());
+    if (e == hipSuccess) e = upload(&d.class_blk, geo.class_blk.data(), geo.class_blk.size());
+    if (e == hipSuccess) e = upload(&d.class_itab, geo.class_itab.data(), geo.class_itab.size());
+    if (e == hipSuccess) e = upload(&d.mtiles, geo.mtiles.data(), geo.mtiles.size());
     if (e != hipSuccess) {
         free_dev(d);
         return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for grid tables failed")
@@ -387,8 +405,40 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
     s = device_tables(g, b->device, &dg);
     if (s != SYMPIX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = sympix::launch_btnb(prec, b->u64, b->ut32, b->bf[0], b->bf[1], b->bf[2],
-                                       dg->term_ptr, dg->terms, ninv_dev, geo.nblocks(), out_dev, st);
+    sympix::BtnbArgs a;
+    a.u64 = b->u64;
+    a.ut32 = b->ut32;
+    for (int q = 0; q < 3; ++q) a.ubf[q] = b->bf[q];
+    a.term_ptr = dg->term_ptr;
+    a.terms = dg->terms;
+    a.classes = dg->classes;
+    a.class_terms = dg->class_terms;
+    a.class_blk = dg->class_blk;
+    a.class_itab = dg->class_itab;
+    a.mtiles = dg->mtiles;
+    a.nmtiles = (int64_t)geo.mtiles.size() / 2;
+    a.nblocks = geo.nblocks();
+    a.npix = geo.npix;
+    a.ninv = ninv_dev;
+    a.out = out_dev;
+    a.wsplit[0] = a.wsplit[1] = a.wsplit[2] = nullptr;
+    hipError_t e = hipSuccess;
+    if (prec >= SYMPIX_BF16X3 && geo.max_class_terms > sympix::kMaxClassTerms)
+        return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
+    if (prec >= SYMPIX_BF16X3) {
+        // stream-ordered scratch for the split N^-1: concurrent calls stay independent
+        e = hipMallocAsync((void **)&a.wsplit[0], (size_t)geo.npix * 3 * sizeof(uint16_t), st);
+        if (e != hipSuccess)
+            return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 split")
+                                            : hip_fail(e, "hipMallocAsync");
+        a.wsplit[1] = a.wsplit[0] + geo.npix;
+        a.wsplit[2] = a.wsplit[1] + geo.npix;
+    }
+    e = sympix::launch_btnb(prec, a, st);
+    if (a.wsplit[0]) {
+        hipError_t ef = hipFreeAsync(a.wsplit[0], st);
+        if (e == hipSuccess) e = ef;
+    }
     return after_launch(e, st, "sample_BtNB");
 }
 

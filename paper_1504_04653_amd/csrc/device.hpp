@@ -21,6 +21,12 @@ struct DevTerm {
     int32_t uid_a, uid_b, tile, pad;
 };
 
+// A class of stored blocks sharing their contraction pattern (see geometry.hpp).
+struct DevClass {
+    int32_t nterms, nblocks, term0, blk0;
+    int64_t itab0;
+};
+
 // Tabulated kernel as seen by device code.
 struct KTable {
     const double *table;  // n_nodes values, node i at s = |i - 1| h
@@ -31,6 +37,7 @@ struct KTable {
 
 constexpr int kBlockDim = 64;              // k^2 for k = 8
 constexpr int kBlockElems = 64 * 64;
+constexpr int kMaxClassTerms = 16;      // member-tile table width in the class GEMM
 
 // a6: table of sum_l c_l P_l(1 - s^2), c_l = (2l+1) coef_l / 4 pi
 hipError_t launch_tabulate(const double *coef, int32_t lmax, double h, double *table,
@@ -46,9 +53,21 @@ hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, in
 hipError_t launch_expand(const double *u64, const int32_t *blk_uid, int64_t nblocks, double *out,
                          hipStream_t st);
 // a9: B-hat^T N^-1 B-hat contraction
-hipError_t launch_btnb(int prec, const double *u64, const float *ut32, const uint16_t *ubf_hi,
-                       const uint16_t *ubf_mid, const uint16_t *ubf_lo, const int64_t *term_ptr,
-                       const DevTerm *terms, const double *ninv, int64_t nblocks, double *out,
-                       hipStream_t st);
+struct BtnbArgs {
+    const double *u64;
+    const float *ut32;
+    const uint16_t *ubf[3];
+    const int64_t *term_ptr;
+    const DevTerm *terms;
+    const DevClass *classes;
+    const int32_t *class_terms, *class_blk, *class_itab, *mtiles;
+    int64_t nmtiles;
+    uint16_t *wsplit[3];      // scratch: N^-1 split into BF16 parts, npix each
+    int64_t npix;
+    int64_t nblocks;
+    const double *ninv;
+    double *out;
+};
+hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st);
 
 }  // namespace sympix

@@ -11,6 +11,7 @@
 #include <map>
 #include <new>
 #include <tuple>
+#include <unordered_map>
 
 namespace sympix {
 namespace {
@@ -317,6 +318,64 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
                 g.term_ptr.push_back((int64_t)g.terms.size());
             }
             g.blk_ptr[J + 1] = (int64_t)g.blk_col.size();
+        }
+
+        // block classes: key = sorted (uid_a, uid_b) pairs of the block's terms
+        {
+            struct VecHash {
+                size_t operator()(const std::vector<int32_t> &v) const {
+                    uint64_t h = 1469598103934665603ull;
+                    for (int32_t x : v) h = (h ^ (uint32_t)x) * 1099511628211ull;
+                    return (size_t)h;
+                }
+            };
+            std::unordered_map<std::vector<int32_t>, int32_t, VecHash> index;
+            std::vector<std::vector<int32_t>> members;     // per class: block indices
+            std::vector<std::vector<int32_t>> tiles_of;    // per class: I per (member, term)
+            std::vector<std::vector<int32_t>> keys;
+            std::vector<std::tuple<int32_t, int32_t, int32_t>> tt;
+            std::vector<int32_t> key;
+            for (int64_t n = 0; n < g.nblocks(); ++n) {
+                tt.clear();
+                for (int64_t t = g.term_ptr[n]; t < g.term_ptr[n + 1]; ++t)
+                    tt.emplace_back(g.terms[t].uid_a, g.terms[t].uid_b, g.terms[t].tile);
+                std::sort(tt.begin(), tt.end());
+                key.clear();
+                for (auto &x : tt) {
+                    key.push_back(std::get<0>(x));
+                    key.push_back(std::get<1>(x));
+                }
+                auto it = index.find(key);
+                int32_t c;
+                if (it == index.end()) {
+                    c = (int32_t)keys.size();
+                    index.emplace(key, c);
+                    keys.push_back(key);
+                    members.emplace_back();
+                    tiles_of.emplace_back();
+                } else {
+                    c = it->second;
+                }
+                members[c].push_back((int32_t)n);
+                for (auto &x : tt) tiles_of[c].push_back(std::get<2>(x));
+            }
+            for (size_t c = 0; c < keys.size(); ++c) {
+                BlockClass bc;
+                bc.nterms = (int32_t)(keys[c].size() / 2);
+                g.max_class_terms = std::max(g.max_class_terms, bc.nterms);
+                bc.nblocks = (int32_t)members[c].size();
+                bc.term0 = (int32_t)(g.class_terms.size() / 2);
+                bc.blk0 = (int32_t)g.class_blk.size();
+                bc.itab0 = (int64_t)g.class_itab.size();
+                g.class_terms.insert(g.class_terms.end(), keys[c].begin(), keys[c].end());
+                g.class_blk.insert(g.class_blk.end(), members[c].begin(), members[c].end());
+                g.class_itab.insert(g.class_itab.end(), tiles_of[c].begin(), tiles_of[c].end());
+                for (int32_t m0 = 0; m0 < bc.nblocks; m0 += 128) {
+                    g.mtiles.push_back((int32_t)c);
+                    g.mtiles.push_back(m0);
+                }
+                g.classes.push_back(bc);
+            }
         }
 
         // largest y = 1 - cos(gamma) over every pattern pair: per unique block the

@@ -16,6 +16,16 @@ struct Term {
     int32_t pad;
 };
 
+// Stored blocks whose contraction tiles carry the same multiset of
+// (unique B_IJ, unique B_IK) pairs: C_m = sum_(e,p) w[I_e(m)*k^2 + p] * M_e[p][ab]
+// with M_e[p][(a,b)] = B_IJ[p][a] B_IK[p][b] shared by every block m.
+struct BlockClass {
+    int32_t nterms, nblocks;
+    int32_t term0;   // first (uid_a, uid_b) pair in class_terms (pairs)
+    int32_t blk0;    // first block in class_blk
+    int64_t itab0;   // first entry in class_itab (nblocks * nterms, block-major)
+};
+
 struct Geometry {
     int32_t lmax = 0, k = 0, nrings = 0, nbands_hemi = 0;
     double margin = 0.0;
@@ -53,6 +63,14 @@ struct Geometry {
     // contraction terms per stored block (CSR, I ascending)
     std::vector<int64_t> term_ptr;
     std::vector<Term> terms;
+
+    // block classes for the GEMM form of the contraction, and its m-tiles
+    std::vector<BlockClass> classes;
+    std::vector<int32_t> class_terms;   // 2 per term: uid_a, uid_b
+    std::vector<int32_t> class_blk;     // stored-block index of each class member
+    std::vector<int32_t> class_itab;    // tile I of each (member, term)
+    std::vector<int32_t> mtiles;        // 2 per m-tile: class, first member
+    int32_t max_class_terms = 0;
 
     double y_pattern_max = 0.0;   // max 1 - cos(gamma) over all pattern pairs
 

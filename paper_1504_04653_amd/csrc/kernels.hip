@@ -6,9 +6,12 @@
 //                  pair geometry, table lookup, radial cut; writes FP64
 //                  row-major and FP32 / BF16-split copies transposed via LDS
 //   k_expand       D-hat: streams each stored block from its unique block
-//   k_btnb_*       B-hat^T N^-1 B-hat (Eq. 15): one output block per wave (FP64)
-//                  or per wave pair (FP32, split BF16), MFMA over the 64 pixels
-//                  of each contraction tile, FP64 accumulation across tiles.
+//   k_btnb_f64/f32 B-hat^T N^-1 B-hat (Eq. 15): one output block per wave (FP64)
+//                  or per wave pair (FP32), MFMA over the 64 pixels of each
+//                  contraction tile, FP64 accumulation across tiles
+//   k_split_ninv   N^-1 split into BF16 parts
+//   k_class_bf16   split-BF16 contraction as one GEMM per class of blocks that
+//                  share their contraction pattern
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -267,107 +270,239 @@ __global__ __launch_bounds__(256) void k_btnb_f32(const double *__restrict__ u64
 }
 
 // ---------------------------------------------------------------------------
-// a9, split BF16: two waves per output block.  A = B_IJ comes pre-split (FP64
-// value into 3 BF16 parts, transposed so a lane's 8 consecutive p are one
-// 16-byte load); B = w_p B_IK is formed in FP32 from the FP32 copy and split
-// on the fly (three BF16 parts of an FP32 value are exact).  MFMA 16x16x32
-// BF16 with FP32 accumulation per term, FP64 across terms.  NPARTS = 2 uses
-// hi*hi + hi*mid + mid*hi; NPARTS = 3 adds hi*lo + lo*hi + mid*mid.
+// a9, split BF16.  A value is split into NP BF16 parts, each rounded to nearest
+// even from the exact FP32 remainder of the previous ones: three parts
+// represent an FP32 value exactly, two parts to 2^-17 relative, and every
+// part has a sign independent of the value's, so the products left out
+// (NP = 3: ml, lm, ll; NP = 2: mm) are unbiased.  Products kept: NP = 3: mm,
+// lh, hl, mh, hm, hh (all of order >= 2^-16); NP = 2: mh, hm, hh.  FP32 MFMA
+// accumulation over the 64 pixels of one contraction tile, FP64 across tiles.
 // ---------------------------------------------------------------------------
-template <int NPARTS>
-__global__ __launch_bounds__(256) void k_btnb_bf16(const uint16_t *__restrict__ ubf_hi,
-                                                   const uint16_t *__restrict__ ubf_mid,
-                                                   const uint16_t *__restrict__ ubf_lo,
-                                                   const float *__restrict__ ut32,
-                                                   const int64_t *__restrict__ term_ptr,
-                                                   const DevTerm *__restrict__ terms,
-                                                   const double *__restrict__ ninv,
-                                                   int64_t nblocks, double *__restrict__ out) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int64_t blk = (int64_t)blockIdx.x * 2 + (wave >> 1);
-    const int half = wave & 1;
-    if (blk >= nblocks) return;
-    const int lr = lane & 15, lk = lane >> 4;
-    doublex4 acc[4][2];
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {   // round to nearest even
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){a, b}, bf16x2));
+}
+
+template <int NP>
+__device__ __forceinline__ void split_pair(float y0, float y1, uint32_t *out) {
+    const uint32_t h = pack_bf16(y0, y1);
+    out[0] = h;
+    const float r0 = y0 - __uint_as_float(h << 16);
+    const float r1 = y1 - __uint_as_float(h & 0xffff0000u);
+    const uint32_t m = pack_bf16(r0, r1);
+    out[1] = m;
+    if constexpr (NP == 3) {
+        const float l0 = r0 - __uint_as_float(m << 16);
+        const float l1 = r1 - __uint_as_float(m & 0xffff0000u);
+        out[2] = pack_bf16(l0, l1);
+    }
+}
+
+// part += a * b over the kept products (smallest first).
+template <int NP>
+__device__ __forceinline__ floatx4 split_mfma(const bf16x8 *a, const bf16x8 *b, floatx4 c) {
+    if constexpr (NP == 3) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], c, 0, 0, 0);
+    }
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], c, 0, 0, 0);
+    return c;
+}
+
+__device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p) {
+    return __builtin_bit_cast(bf16x8, *(const u16x8 *)p);
+}
+
+// N^-1 split into three BF16 parts (hi, mid, lo) from FP64, read directly as
+// MFMA operands by the class GEMM.
+__global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ ninv, int64_t n,
+                                                    uint16_t *__restrict__ w0, uint16_t *__restrict__ w1,
+                                                    uint16_t *__restrict__ w2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = ninv[i];
+    const uint16_t h = bf16_bits((float)v);
+    const double r1 = v - (double)bf16_value(h);
+    const uint16_t m = bf16_bits((float)r1);
+    w0[i] = h;
+    w1[i] = m;
+    w2[i] = bf16_bits((float)(r1 - (double)bf16_value(m)));
+}
+
+// Class GEMM, split BF16.  For a class of blocks sharing the multiset of
+// (B_IJ, B_IK) unique pairs, C[m][(a,b)] = sum_(e,p) W[m][(e,p)] M[(e,p)][(a,b)]
+// with W[m][(e,p)] = N^-1 at pixel p of the class member's tile I_e and
+// M[(e,p)][(a,b)] = B_IJ[p][a] B_IK[p][b].  A workgroup (4 waves, one per SIMD)
+// owns 128 members and sweeps the 32 column tiles of 128 output elements
+// (rows a0, a0+1 of the block) in one software pipeline whose steps are chunks
+// of 32 pixels of one term.  Each chunk of M is formed once in LDS (FP32
+// product, split into BF16 parts) and shared by all 128 members; W fragments
+// are read directly from the pre-split N^-1.  Each wave owns a 64 x 64
+// sub-tile (16 MFMA tiles), so every 16-byte operand fragment feeds four MFMA
+// tiles.  Loads for the next step (W) and the step after it (M inputs) and the
+// formation of the next M chunk are interleaved with the MFMAs (one MFMA, two
+// VALU); FP32 partials of each term are added to FP64 accumulators, which are
+// stored and cleared at the end of every column tile.
+template <int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict__ classes,
+                  const int32_t *__restrict__ cterms, const int32_t *__restrict__ cblk,
+                  const int32_t *__restrict__ citab, const float *__restrict__ ut32,
+                  const uint16_t *__restrict__ w0, const uint16_t *__restrict__ w1,
+                  const uint16_t *__restrict__ w2, double *__restrict__ out) {
+    constexpr int KP = 40;   // LDS pitch (BF16) of one output column's 32 chunk values
+    __shared__ __attribute__((aligned(16))) uint16_t sM[2][NP][128 * KP];
+    __shared__ int32_t sTile[128 * kMaxClassTerms];   // tile I of (member row, term)
+    __shared__ int32_t sBlk[128];                     // stored-block index of each member row
+    const int cls = mtiles[2 * blockIdx.x], m0 = mtiles[2 * blockIdx.x + 1];
+    const DevClass cl = classes[cls];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int nterms = cl.nterms;
+    const int nchunks = 2 * nterms;          // per column tile
+    const int nsteps = 32 * nchunks;         // whole sweep
+    const uint16_t *wq[3] = {w0, w1, w2};
+    const int32_t *terms = cterms + 2 * cl.term0;
+
+    for (int x = tid; x < 128 * nterms; x += 256) {
+        const int r = x / nterms, e = x - r * nterms;
+        const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
+        sTile[r * kMaxClassTerms + e] = citab[cl.itab0 + (int64_t)m * nterms + e];
+    }
+    if (tid < 128) sBlk[tid] = m0 + tid < cl.nblocks ? cblk[cl.blk0 + m0 + tid] : -1;
+
+    // generation map: thread owns output column gn of the tile and 16 pixels
+    const int gn = tid & 127, gk = tid >> 7;
+    struct GenRegs { floatx4 a[4], b[4]; };
+    auto gen_load = [&](int g, GenRegs &r) {
+        const int nt = g / nchunks, c = g - nt * nchunks;
+        const int e = c >> 1, p0 = 32 * (c & 1) + 16 * gk;
+        const float *s1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + (2 * nt + (gn >> 6)) * 64 + p0;
+        const float *s2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + (gn & 63) * 64 + p0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            r.a[x] = *(const floatx4 *)(s1 + 4 * x);
+            r.b[x] = *(const floatx4 *)(s2 + 4 * x);
+        }
+    };
+    auto gen_store = [&](int buf, const GenRegs &r) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            u32x4 words[NP];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = 2 * h + e / 2, y = 2 * (e % 2);
+                uint32_t parts[NP];
+                split_pair<NP>(r.a[x][y] * r.b[x][y], r.a[x][y + 1] * r.b[x][y + 1], parts);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) words[q][e] = parts[q];
+            }
+#pragma unroll
+            for (int q = 0; q < NP; ++q) *(u32x4 *)&sM[buf][q][gn * KP + 16 * gk + 8 * h] = words[q];
+        }
+    };
+    // W rows of this lane: tile rows 64 wm + 16 i + lr
+    auto a_load = [&](int g, bf16x8 (&af)[4][NP]) {
+        const int c = g % nchunks;
+        const int e = c >> 1, p0 = 32 * (c & 1) + 8 * lk;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int off = sTile[(64 * wm + 16 * i + lr) * kMaxClassTerms + e] * 64 + p0;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) af[i][q] = load_bf16x8(wq[q] + off);
+        }
+    };
+
+    doublex4 acc[4][4];
+    floatx4 part[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-    const int64_t t0 = term_ptr[blk], t1 = term_ptr[blk + 1];
-    for (int64_t t = t0; t < t1; ++t) {
-        const DevTerm tm = terms[t];
-        const int64_t abase = (int64_t)tm.uid_a * kBlockElems + lr * 64 + 8 * lk;
-        const int64_t bbase = (int64_t)tm.uid_b * kBlockElems + (32 * half + lr) * 64 + 8 * lk;
-        const double *w = ninv + (int64_t)tm.tile * 64 + 8 * lk;
-        floatx4 part[4][2];
+        for (int j = 0; j < 4; ++j) {
+            acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+            part[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+
+    auto step = [&](int g, bf16x8 (&ac)[4][NP], bf16x8 (&an)[4][NP], GenRegs &gl, const GenRegs &gs) {
+        const int buf = g & 1;
+        gen_load(min(g + 2, nsteps - 1), gl);
+        a_load(min(g + 1, nsteps - 1), an);
+        bf16x8 bfr[4][NP];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) part[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < NP; ++q)
+                bfr[j][q] = load_bf16x8(&sM[buf][q][(64 * wn + 16 * j + lr) * KP + 8 * lk]);
+        constexpr int NPROD = NP == 3 ? 6 : 3;
+        constexpr int pa3[6] = {1, 2, 0, 1, 0, 0}, pb3[6] = {1, 0, 2, 0, 1, 0};
+        constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const int p0 = 32 * ks;
-            float wf[8];
+        for (int pr = 0; pr < NPROD; ++pr) {
+            const int qa = NP == 3 ? pa3[pr] : pa2[pr];
+            const int qb = NP == 3 ? pb3[pr] : pb2[pr];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) wf[e] = (float)w[p0 + e];
-            bf16x8 bh[2], bm[2], bl[2];
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const floatx4 *src = (const floatx4 *)(ut32 + bbase + 16 * j * 64 + p0);
-                const floatx4 u0 = src[0], u1 = src[1];
-                u16x8 h, m, l;
+                for (int j = 0; j < 4; ++j)
+                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[i][qa], bfr[j][qb], part[i][j], 0, 0, 0);
+        }
+        gen_store(buf ^ 1, gs);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const float x = wf[e] * (e < 4 ? u0[e] : u1[e - 4]);
-                    const uint16_t hb = bf16_bits(x);
-                    const float r1 = x - bf16_value(hb);
-                    const uint16_t mb = bf16_bits(r1);
-                    h[e] = hb;
-                    m[e] = mb;
-                    if (NPARTS == 3) l[e] = bf16_bits(r1 - bf16_value(mb));
+        for (int x = 0; x < 16 * NPROD; ++x) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // two VALU
+        }
+        if (g & 1) {                         // end of a term
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
+                    part[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
-                bh[j] = __builtin_bit_cast(bf16x8, h);
-                bm[j] = __builtin_bit_cast(bf16x8, m);
-                if (NPARTS == 3) bl[j] = __builtin_bit_cast(bf16x8, l);
-            }
+            const int nt = g / nchunks;
+            if (g - nt * nchunks == nchunks - 1) {   // end of a column tile: store, clear
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t off = abase + 16 * i * 64 + p0;
-                const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(ubf_hi + off));
-                const bf16x8 am = __builtin_bit_cast(bf16x8, *(const u16x8 *)(ubf_mid + off));
-                bf16x8 al;
-                if (NPARTS == 3) al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(ubf_lo + off));
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    floatx4 c = part[i][j];
-                    if (NPARTS == 3) {
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[j], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], c, 0, 0, 0);
+                    for (int v = 0; v < 4; ++v) {
+                        const int blk = sBlk[64 * wm + 16 * i + 4 * lk + v];
+                        if (blk >= 0) {
+                            double *o = out + (int64_t)blk * kBlockElems + 128 * nt + 64 * wn + lr;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
+                        }
                     }
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[j], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[j], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], c, 0, 0, 0);
-                    part[i][j] = c;
-                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
             }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
+        __syncthreads();
+    };
+
+    GenRegs gin0, gin1;              // M inputs of even / odd steps
+    bf16x8 a0[4][NP], a1[4][NP];     // W fragments of even / odd steps
+    __syncthreads();                 // sTile, sBlk visible
+    gen_load(0, gin0);
+    gen_load(1, gin1);
+    a_load(0, a0);
+    gen_store(0, gin0);
+    __syncthreads();
+    for (int g = 0; g < nsteps; g += 2) {   // nsteps is even
+        step(g, a0, a1, gin0, gin1);
+        step(g + 1, a1, a0, gin1, gin0);
     }
-    double *o = out + blk * kBlockElems + 32 * half + lr;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                __builtin_nontemporal_store(acc[i][j][v], &o[(16 * i + 4 * lk + v) * 64 + 16 * j]);
 }
 
 }  // namespace
@@ -406,27 +541,27 @@ hipError_t launch_expand(const double *u64, const int32_t *blk_uid, int64_t nblo
     return hipGetLastError();
 }
 
-hipError_t launch_btnb(int prec, const double *u64, const float *ut32, const uint16_t *ubf_hi,
-                       const uint16_t *ubf_mid, const uint16_t *ubf_lo, const int64_t *term_ptr,
-                       const DevTerm *terms, const double *ninv, int64_t nblocks, double *out,
-                       hipStream_t st) {
-    if (nblocks == 0) return hipSuccess;
+hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
+    if (a.nblocks == 0) return hipSuccess;
     if (prec == 0) {
-        const int64_t grid = (nblocks + 3) / 4;
-        hipLaunchKernelGGL(k_btnb_f64, dim3((unsigned)grid), dim3(256), 0, st, u64, term_ptr,
-                           terms, ninv, nblocks, out);
-    } else {
-        const int64_t grid = (nblocks + 1) / 2;
-        if (prec == 1)
-            hipLaunchKernelGGL(k_btnb_f32, dim3((unsigned)grid), dim3(256), 0, st, u64, term_ptr,
-                               terms, ninv, nblocks, out);
-        else if (prec == 2)
-            hipLaunchKernelGGL(k_btnb_bf16<2>, dim3((unsigned)grid), dim3(256), 0, st, ubf_hi,
-                               ubf_mid, ubf_lo, ut32, term_ptr, terms, ninv, nblocks, out);
-        else
-            hipLaunchKernelGGL(k_btnb_bf16<3>, dim3((unsigned)grid), dim3(256), 0, st, ubf_hi,
-                               ubf_mid, ubf_lo, ut32, term_ptr, terms, ninv, nblocks, out);
+        hipLaunchKernelGGL(k_btnb_f64, dim3((unsigned)((a.nblocks + 3) / 4)), dim3(256), 0, st, a.u64,
+                           a.term_ptr, a.terms, a.ninv, a.nblocks, a.out);
+        return hipGetLastError();
     }
+    if (prec == 1) {
+        hipLaunchKernelGGL(k_btnb_f32, dim3((unsigned)((a.nblocks + 1) / 2)), dim3(256), 0, st, a.u64,
+                           a.term_ptr, a.terms, a.ninv, a.nblocks, a.out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_split_ninv, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,
+                       a.npix, a.wsplit[0], a.wsplit[1], a.wsplit[2]);
+    const dim3 grid((unsigned)a.nmtiles);
+    if (prec == 2)
+        hipLaunchKernelGGL(k_class_bf16<2>, grid, dim3(256), 0, st, a.mtiles, a.classes, a.class_terms,
+                           a.class_blk, a.class_itab, a.ut32, a.wsplit[0], a.wsplit[1], a.wsplit[2], a.out);
+    else
+        hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(256), 0, st, a.mtiles, a.classes, a.class_terms,
+                           a.class_blk, a.class_itab, a.ut32, a.wsplit[0], a.wsplit[1], a.wsplit[2], a.out);
     return hipGetLastError();
 }
 
