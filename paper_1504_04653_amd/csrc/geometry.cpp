@@ -370,7 +370,7 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
                 g.class_terms.insert(g.class_terms.end(), keys[c].begin(), keys[c].end());
                 g.class_blk.insert(g.class_blk.end(), members[c].begin(), members[c].end());
                 g.class_itab.insert(g.class_itab.end(), tiles_of[c].begin(), tiles_of[c].end());
-                for (int32_t m0 = 0; m0 < bc.nblocks; m0 += 128) {
+                for (int32_t m0 = 0; m0 < bc.nblocks; m0 += 64) {
                     g.mtiles.push_back((int32_t)c);
                     g.mtiles.push_back(m0);
                 }

@@ -27,6 +27,17 @@ typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr double kInv4Pi = 0.07957747154594767;   // 1 / (4 pi)
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Remap the workgroup index so that every XCD processes one contiguous range of
+// the work list: neighbouring items share operands, which then stay in that
+// XCD's L2.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int xcd_contiguous_index() {
+    const int n = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, i = b >> 3;
+    const int per = n >> 3, rem = n & 7;
+    return x * per + min(x, rem) + i;
+}
+
 // ---------------------------------------------------------------------------
 // a6: kernel table.  Node i holds b at s = |i - 1| h, y = s^2 (node 0 mirrors
 // node 2: the kernel is even in s).  Recurrence in y with D_l = P_l - P_{l-1}.
@@ -337,85 +348,62 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // Class GEMM, split BF16.  For a class of blocks sharing the multiset of
 // (B_IJ, B_IK) unique pairs, C[m][(a,b)] = sum_(e,p) W[m][(e,p)] M[(e,p)][(a,b)]
 // with W[m][(e,p)] = N^-1 at pixel p of the class member's tile I_e and
-// M[(e,p)][(a,b)] = B_IJ[p][a] B_IK[p][b].  A workgroup (4 waves, one per SIMD)
-// owns 128 members and sweeps the 32 column tiles of 128 output elements
-// (rows a0, a0+1 of the block) in one software pipeline whose steps are chunks
-// of 32 pixels of one term.  Each chunk of M is formed once in LDS (FP32
-// product, split into BF16 parts) and shared by all 128 members; W fragments
-// are read directly from the pre-split N^-1.  Each wave owns a 64 x 64
-// sub-tile (16 MFMA tiles), so every 16-byte operand fragment feeds four MFMA
-// tiles.  Loads for the next step (W) and the step after it (M inputs) and the
-// formation of the next M chunk are interleaved with the MFMAs (one MFMA, two
-// VALU); FP32 partials of each term are added to FP64 accumulators, which are
-// stored and cleared at the end of every column tile.
+// M[(e,p)][(a,b)] = B_IJ[p][a] B_IK[p][b].  One wave owns 64 members and sweeps
+// the 64 output rows a; each step is one chunk of 32 pixels of one term.  The
+// wave forms its own M fragments (FP32 product, split into BF16 parts) in
+// registers, so waves never wait on each other; W fragments are read directly
+// from the pre-split N^-1.  The 64 x 64 output tile (16 MFMA tiles) makes each
+// 16-byte operand fragment feed four MFMA tiles.  Loads for the next step (W)
+// and the step after it (B_IJ, B_IK values) and the formation of M are
+// interleaved with the MFMAs; FP32 partials of each term are added to FP64
+// accumulators, which are stored and cleared at the end of every row a.
 template <int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict__ classes,
                   const int32_t *__restrict__ cterms, const int32_t *__restrict__ cblk,
                   const int32_t *__restrict__ citab, const float *__restrict__ ut32,
                   const uint16_t *__restrict__ w0, const uint16_t *__restrict__ w1,
                   const uint16_t *__restrict__ w2, double *__restrict__ out) {
-    constexpr int KP = 40;   // LDS pitch (BF16) of one output column's 32 chunk values
-    __shared__ __attribute__((aligned(16))) uint16_t sM[2][NP][128 * KP];
-    __shared__ int32_t sTile[128 * kMaxClassTerms];   // tile I of (member row, term)
-    __shared__ int32_t sBlk[128];                     // stored-block index of each member row
-    const int cls = mtiles[2 * blockIdx.x], m0 = mtiles[2 * blockIdx.x + 1];
+    __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
+    __shared__ int32_t sBlk[64];                     // stored-block index of each member row
+    const int item = xcd_contiguous_index();
+    const int cls = mtiles[2 * item], m0 = mtiles[2 * item + 1];
     const DevClass cl = classes[cls];
-    const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
-    const int nchunks = 2 * nterms;          // per column tile
-    const int nsteps = 32 * nchunks;         // whole sweep
+    const int nchunks = 2 * nterms;          // per output row a
+    const int nsteps = 64 * nchunks;         // whole sweep
     const uint16_t *wq[3] = {w0, w1, w2};
     const int32_t *terms = cterms + 2 * cl.term0;
 
-    for (int x = tid; x < 128 * nterms; x += 256) {
+    for (int x = lane; x < 64 * nterms; x += 64) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    if (tid < 128) sBlk[tid] = m0 + tid < cl.nblocks ? cblk[cl.blk0 + m0 + tid] : -1;
+    sBlk[lane] = m0 + lane < cl.nblocks ? cblk[cl.blk0 + m0 + lane] : -1;
+    __syncthreads();
 
-    // generation map: thread owns output column gn of the tile and 16 pixels
-    const int gn = tid & 127, gk = tid >> 7;
-    struct GenRegs { floatx4 a[4], b[4]; };
-    auto gen_load = [&](int g, GenRegs &r) {
-        const int nt = g / nchunks, c = g - nt * nchunks;
-        const int e = c >> 1, p0 = 32 * (c & 1) + 16 * gk;
-        const float *s1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + (2 * nt + (gn >> 6)) * 64 + p0;
-        const float *s2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + (gn & 63) * 64 + p0;
+    struct GenRegs { floatx4 u1[2], u2[4][2]; };
+    auto gen_load = [&](int s, GenRegs &r) {
+        const int a = s / nchunks, c = s - a * nchunks;
+        const int e = c >> 1, p0 = 32 * (c & 1) + 8 * lk;
+        const float *s1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + p0;
+        const float *s2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + p0;
+        r.u1[0] = *(const floatx4 *)s1;
+        r.u1[1] = *(const floatx4 *)(s1 + 4);
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            r.a[x] = *(const floatx4 *)(s1 + 4 * x);
-            r.b[x] = *(const floatx4 *)(s2 + 4 * x);
+        for (int j = 0; j < 4; ++j) {
+            r.u2[j][0] = *(const floatx4 *)(s2 + 16 * j * 64);
+            r.u2[j][1] = *(const floatx4 *)(s2 + 16 * j * 64 + 4);
         }
     };
-    auto gen_store = [&](int buf, const GenRegs &r) {
-        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            u32x4 words[NP];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int x = 2 * h + e / 2, y = 2 * (e % 2);
-                uint32_t parts[NP];
-                split_pair<NP>(r.a[x][y] * r.b[x][y], r.a[x][y + 1] * r.b[x][y + 1], parts);
-#pragma unroll
-                for (int q = 0; q < NP; ++q) words[q][e] = parts[q];
-            }
-#pragma unroll
-            for (int q = 0; q < NP; ++q) *(u32x4 *)&sM[buf][q][gn * KP + 16 * gk + 8 * h] = words[q];
-        }
-    };
-    // W rows of this lane: tile rows 64 wm + 16 i + lr
-    auto a_load = [&](int g, bf16x8 (&af)[4][NP]) {
-        const int c = g % nchunks;
+    auto a_load = [&](int s, bf16x8 (&af)[4][NP]) {
+        const int c = s % nchunks;
         const int e = c >> 1, p0 = 32 * (c & 1) + 8 * lk;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int off = sTile[(64 * wm + 16 * i + lr) * kMaxClassTerms + e] * 64 + p0;
+            const int off = sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + p0;
 #pragma unroll
             for (int q = 0; q < NP; ++q) af[i][q] = load_bf16x8(wq[q] + off);
         }
@@ -431,16 +419,28 @@ void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict
             part[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
 
-    auto step = [&](int g, bf16x8 (&ac)[4][NP], bf16x8 (&an)[4][NP], GenRegs &gl, const GenRegs &gs) {
-        const int buf = g & 1;
-        gen_load(min(g + 2, nsteps - 1), gl);
-        a_load(min(g + 1, nsteps - 1), an);
+    // gu holds the B_IJ / B_IK values of step s; once M is formed it is reloaded
+    // with those of step s+2 (same parity).
+    auto step = [&](int s, bf16x8 (&ac)[4][NP], bf16x8 (&an)[4][NP], GenRegs &gu) {
+        a_load(min(s + 1, nsteps - 1), an);
+        // M fragments of this step: rows p (8 per lane), columns b = 16 j + lr
         bf16x8 bfr[4][NP];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            u32x4 words[NP];
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
-                bfr[j][q] = load_bf16x8(&sM[buf][q][(64 * wn + 16 * j + lr) * KP + 8 * lk]);
+            for (int e = 0; e < 4; ++e) {
+                const int h = e >> 1, y = 2 * (e & 1);
+                uint32_t parts[NP];
+                split_pair<NP>(gu.u1[h][y] * gu.u2[j][h][y], gu.u1[h][y + 1] * gu.u2[j][h][y + 1], parts);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) words[q][e] = parts[q];
+            }
+#pragma unroll
+            for (int q = 0; q < NP; ++q) bfr[j][q] = __builtin_bit_cast(bf16x8, words[q]);
+        }
+        gen_load(min(s + 2, nsteps - 1), gu);
         constexpr int NPROD = NP == 3 ? 6 : 3;
         constexpr int pa3[6] = {1, 2, 0, 1, 0, 0}, pb3[6] = {1, 0, 2, 0, 1, 0};
         constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
@@ -454,13 +454,13 @@ void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict
                 for (int j = 0; j < 4; ++j)
                     part[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[i][qa], bfr[j][qb], part[i][j], 0, 0, 0);
         }
-        gen_store(buf ^ 1, gs);
+        __builtin_amdgcn_sched_group_barrier(0x020, 4 * NP, 0);  // W loads of the next step first
 #pragma unroll
         for (int x = 0; x < 16 * NPROD; ++x) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // two VALU
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // three VALU
         }
-        if (g & 1) {                         // end of a term
+        if (s & 1) {                         // end of a term
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -469,15 +469,15 @@ void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict
                     for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
                     part[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
-            const int nt = g / nchunks;
-            if (g - nt * nchunks == nchunks - 1) {   // end of a column tile: store, clear
+            const int a = s / nchunks;
+            if (s - a * nchunks == nchunks - 1) {   // end of output row a: store, clear
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int blk = sBlk[64 * wm + 16 * i + 4 * lk + v];
+                        const int blk = sBlk[16 * i + 4 * lk + v];
                         if (blk >= 0) {
-                            double *o = out + (int64_t)blk * kBlockElems + 128 * nt + 64 * wn + lr;
+                            double *o = out + (int64_t)blk * kBlockElems + a * 64 + lr;
 #pragma unroll
                             for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
                         }
@@ -488,20 +488,16 @@ void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict
                     for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
             }
         }
-        __syncthreads();
     };
 
-    GenRegs gin0, gin1;              // M inputs of even / odd steps
+    GenRegs gin0, gin1;              // B_IJ / B_IK values of even / odd steps
     bf16x8 a0[4][NP], a1[4][NP];     // W fragments of even / odd steps
-    __syncthreads();                 // sTile, sBlk visible
     gen_load(0, gin0);
     gen_load(1, gin1);
     a_load(0, a0);
-    gen_store(0, gin0);
-    __syncthreads();
-    for (int g = 0; g < nsteps; g += 2) {   // nsteps is even
-        step(g, a0, a1, gin0, gin1);
-        step(g + 1, a1, a0, gin1, gin0);
+    for (int s = 0; s < nsteps; s += 2) {   // nsteps is even
+        step(s, a0, a1, gin0);
+        step(s + 1, a1, a0, gin1);
     }
 }
 
@@ -557,10 +553,10 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
                        a.npix, a.wsplit[0], a.wsplit[1], a.wsplit[2]);
     const dim3 grid((unsigned)a.nmtiles);
     if (prec == 2)
-        hipLaunchKernelGGL(k_class_bf16<2>, grid, dim3(256), 0, st, a.mtiles, a.classes, a.class_terms,
+        hipLaunchKernelGGL(k_class_bf16<2>, grid, dim3(64), 0, st, a.mtiles, a.classes, a.class_terms,
                            a.class_blk, a.class_itab, a.ut32, a.wsplit[0], a.wsplit[1], a.wsplit[2], a.out);
     else
-        hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(256), 0, st, a.mtiles, a.classes, a.class_terms,
+        hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(64), 0, st, a.mtiles, a.classes, a.class_terms,
                            a.class_blk, a.class_itab, a.ut32, a.wsplit[0], a.wsplit[1], a.wsplit[2], a.out);
     return hipGetLastError();
 }
