@@ -422,21 +422,30 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
     a.ninv = ninv_dev;
     a.out = out_dev;
     a.wsplit[0] = a.wsplit[1] = a.wsplit[2] = nullptr;
+    a.wf32 = nullptr;
     hipError_t e = hipSuccess;
-    if (prec >= SYMPIX_BF16X3 && geo.max_class_terms > sympix::kMaxClassTerms)
+    if (prec != SYMPIX_FP64 && geo.max_class_terms > sympix::kMaxClassTerms)
         return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
-    if (prec >= SYMPIX_BF16X3) {
-        // stream-ordered scratch for the split N^-1: concurrent calls stay independent
-        e = hipMallocAsync((void **)&a.wsplit[0], (size_t)geo.npix * 3 * sizeof(uint16_t), st);
+    void *scratch = nullptr;
+    if (prec != SYMPIX_FP64) {
+        // stream-ordered scratch for N^-1 in the MFMA operand format (FP32, or
+        // three BF16 parts): concurrent calls stay independent
+        const size_t bytes = (size_t)geo.npix * (prec == SYMPIX_FP32 ? sizeof(float) : 3 * sizeof(uint16_t));
+        e = hipMallocAsync(&scratch, bytes, st);
         if (e != hipSuccess)
-            return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 split")
+            return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 operands")
                                             : hip_fail(e, "hipMallocAsync");
-        a.wsplit[1] = a.wsplit[0] + geo.npix;
-        a.wsplit[2] = a.wsplit[1] + geo.npix;
+        if (prec == SYMPIX_FP32) {
+            a.wf32 = (float *)scratch;
+        } else {
+            a.wsplit[0] = (uint16_t *)scratch;
+            a.wsplit[1] = a.wsplit[0] + geo.npix;
+            a.wsplit[2] = a.wsplit[1] + geo.npix;
+        }
     }
     e = sympix::launch_btnb(prec, a, st);
-    if (a.wsplit[0]) {
-        hipError_t ef = hipFreeAsync(a.wsplit[0], st);
+    if (scratch) {
+        hipError_t ef = hipFreeAsync(scratch, st);
         if (e == hipSuccess) e = ef;
     }
     return after_launch(e, st, "sample_BtNB");

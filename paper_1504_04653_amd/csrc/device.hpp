@@ -63,6 +63,7 @@ struct BtnbArgs {
     const int32_t *class_terms, *class_blk, *class_itab, *mtiles;
     int64_t nmtiles;
     uint16_t *wsplit[3];      // scratch: N^-1 split into BF16 parts, npix each
+    float *wf32;              // scratch: N^-1 rounded to FP32, npix
     int64_t npix;
     int64_t nblocks;
     const double *ninv;

@@ -6,12 +6,13 @@
 //                  pair geometry, table lookup, radial cut; writes FP64
 //                  row-major and FP32 / BF16-split copies transposed via LDS
 //   k_expand       D-hat: streams each stored block from its unique block
-//   k_btnb_f64/f32 B-hat^T N^-1 B-hat (Eq. 15): one output block per wave (FP64)
-//                  or per wave pair (FP32), MFMA over the 64 pixels of each
-//                  contraction tile, FP64 accumulation across tiles
+//   k_btnb_f64     B-hat^T N^-1 B-hat (Eq. 15) in FP64: one output block per
+//                  wave, MFMA over the 64 pixels of each contraction tile
+//   k_ninv_f32     N^-1 rounded to FP32
+//   k_class_f32    FP32-MFMA contraction as one GEMM per class of blocks that
+//                  share their contraction pattern, FP64 accumulation across tiles
 //   k_split_ninv   N^-1 split into BF16 parts
-//   k_class_bf16   split-BF16 contraction as one GEMM per class of blocks that
-//                  share their contraction pattern
+//   k_class_bf16   the same GEMM in split BF16
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -217,67 +218,142 @@ __global__ __launch_bounds__(256) void k_btnb_f64(const double *__restrict__ u64
 }
 
 // ---------------------------------------------------------------------------
-// a9, FP32 MFMA: two waves per output block (columns 0-31 / 32-63).  Operands
-// are rounded to FP32 after folding w_p into B in FP64; each term's 64-pixel
-// sum runs in the FP32 MFMA accumulator and is added to FP64 accumulators.
+// a9, FP32 MFMA class GEMM.  Same decomposition as the split-BF16 form below:
+// C[m][(a,b)] = sum_(e,p) W[m][(e,p)] M[(e,p)][(a,b)], W = N^-1 rounded to FP32,
+// M = B_IJ[p][a] B_IK[p][b] formed as the FP32 product of the FP32 copies.
+// MFMA 16x16x4: lane (lr, lk) holds W[16 i + lr][p] and M[p][16 j + lr] for
+// p = 16 g + 4 lk + t, one MFMA per (i, j, t); the result lane holds members
+// 16 i + 4 lk + v of column b = 16 j + lr.  Four waves share one 64-member tile
+// and take every fourth output row a, so their W and B_IK reads coincide in L1.
+// Each step is 16 pixels of one term; its operands are loaded one step ahead.
+// A term's FP32 sum over its 64 pixels is added to FP64 accumulators, which are
+// stored and cleared at the end of every row a.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_btnb_f32(const double *__restrict__ u64,
-                                                  const int64_t *__restrict__ term_ptr,
-                                                  const DevTerm *__restrict__ terms,
-                                                  const double *__restrict__ ninv,
-                                                  int64_t nblocks, double *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_ninv_f32(const double *__restrict__ ninv, int64_t n,
+                                                  float *__restrict__ wf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wf[i] = (float)ninv[i];
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_class_f32(const int32_t *__restrict__ mtiles, const DevClass *__restrict__ classes,
+                 const int32_t *__restrict__ cterms, const int32_t *__restrict__ cblk,
+                 const int32_t *__restrict__ citab, const float *__restrict__ ut32,
+                 const float *__restrict__ wf, double *__restrict__ out) {
+    __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
+    __shared__ int32_t sBlk[64];                     // stored-block index of each member row
+    const int item = xcd_contiguous_index();
+    const int cls = mtiles[2 * item], m0 = mtiles[2 * item + 1];
+    const DevClass cl = classes[cls];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int64_t blk = (int64_t)blockIdx.x * 2 + (wave >> 1);
-    const int half = wave & 1;
-    if (blk >= nblocks) return;
-    const int lr = lane & 15, lk = lane >> 4;
-    doublex4 acc[4][2];
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int nterms = cl.nterms;
+    const int32_t *terms = cterms + 2 * cl.term0;
+
+    for (int x = threadIdx.x; x < 64 * nterms; x += 256) {
+        const int r = x / nterms, e = x - r * nterms;
+        const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
+        sTile[r * kMaxClassTerms + e] = citab[cl.itab0 + (int64_t)m * nterms + e];
+    }
+    if (threadIdx.x < 64) sBlk[lane] = m0 + lane < cl.nblocks ? cblk[cl.blk0 + m0 + lane] : -1;
+    __syncthreads();
+
+    // operand addresses of one term for output row a (lane part included)
+    struct Ptrs { const float *w[4], *u1, *u2; };
+    auto ptrs = [&](int a, int e, Ptrs &q) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            q.w[i] = wf + (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 4 * lk;
+        q.u1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 4 * lk;
+        q.u2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + 4 * lk;
+    };
+    struct Frag { floatx4 w[4], u1, u2[4]; };
+    auto load = [&](const Ptrs &q, int g, Frag &f) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f.w[i] = *(const floatx4 *)(q.w[i] + 16 * g);
+        f.u1 = *(const floatx4 *)(q.u1 + 16 * g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f.u2[j] = *(const floatx4 *)(q.u2 + 16 * j * 64 + 16 * g);
+    };
+
+    doublex4 acc[4][4];
+    floatx4 part[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-    const int64_t t0 = term_ptr[blk], t1 = term_ptr[blk + 1];
-    for (int64_t t = t0; t < t1; ++t) {
-        const DevTerm tm = terms[t];
-        const double *A = u64 + (int64_t)tm.uid_a * kBlockElems + lr;
-        const double *B = u64 + (int64_t)tm.uid_b * kBlockElems + 32 * half + lr;
-        const double *w = ninv + (int64_t)tm.tile * 64;
-        floatx4 part[4][2];
+        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    // One step: issue the next step's loads, then this step's products and
+    // MFMAs; the first step of a term starts its MFMA sums from zero.  The
+    // scheduling barrier keeps the next step's arithmetic (which waits on
+    // those loads) out of this step.
+    auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn, bool first) {
+        load(qn, gn, fn);
+        __builtin_amdgcn_sched_group_barrier(0x020, 9, 0);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int t = 0; t < 4; ++t) {
+            float bv[4];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) part[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-        for (int ks = 0; ks < 16; ++ks) {
-            const int p = ks * 4 + lk;
-            const double wp = w[p];
-            float a[4], b[2];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = (float)A[p * 64 + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = (float)(B[p * 64 + 16 * j] * wp);
+            for (int j = 0; j < 4; ++j) bv[j] = f.u1[t] * f.u2[j][t];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], part[i][j], 0, 0, 0);
+                for (int j = 0; j < 4; ++j)
+                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        f.w[i][t], bv[j], (first && t == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][j], 0, 0, 0);
         }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);   // products of pixel t
+            __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);  // their 16 MFMAs
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    Frag f0, f1;
+    Ptrs qc, qn;
+    int x = 0, e = 0;                    // row index (a = wave + 4 x) and term of this step
+    ptrs(wave, 0, qc);
+    load(qc, 0, f0);
+    for (int it = 0; it < 16 * nterms; ++it) {
+        int ne = e + 1, nx = x;
+        if (ne == nterms) {
+            ne = 0;
+            ++nx;
+        }
+        const int a = wave + 4 * x;
+        if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
+        else qn = qc;                    // past the last row: a harmless reload
+        step(f0, qc, 1, f1, true);
+        step(f1, qc, 2, f0, false);
+        step(f0, qc, 3, f1, false);
+        step(f1, qn, 0, f0, false);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
+        if (ne == 0) {                       // end of output row a: store, clear
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int blk = sBlk[16 * i + 4 * lk + v];
+                    if (blk >= 0) {
+                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + lr;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+        }
+        x = nx;
+        e = ne;
+        qc = qn;
     }
-    double *o = out + blk * kBlockElems + 32 * half + lr;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                __builtin_nontemporal_store(acc[i][j][v], &o[(16 * i + 4 * lk + v) * 64 + 16 * j]);
 }
 
 // ---------------------------------------------------------------------------
@@ -545,8 +621,10 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
         return hipGetLastError();
     }
     if (prec == 1) {
-        hipLaunchKernelGGL(k_btnb_f32, dim3((unsigned)((a.nblocks + 1) / 2)), dim3(256), 0, st, a.u64,
-                           a.term_ptr, a.terms, a.ninv, a.nblocks, a.out);
+        hipLaunchKernelGGL(k_ninv_f32, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,
+                           a.npix, a.wf32);
+        hipLaunchKernelGGL(k_class_f32, dim3((unsigned)a.nmtiles), dim3(256), 0, st, a.mtiles, a.classes,
+                           a.class_terms, a.class_blk, a.class_itab, a.ut32, a.wf32, a.out);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_split_ninv, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,

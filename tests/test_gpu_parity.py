@@ -194,7 +194,7 @@ def test_transition_grid_all_blocks():
     say(f"[t256] npix={g.npix} nblocks={g.nblocks} tiles={og.tiles_north[:8]}")
     kb = sp.Kernel(g, b_l, R)
     Cref = O.sample_BtNB(og, b_l, ninv, R, pairs)
-    for prec in ("fp64", "bf16x6"):
+    for prec in ("fp64", "fp32", "bf16x6"):
         C = run_BtNB(g, kb, dev(ninv), prec).cpu().numpy()
         rep = error_report(C, Cref, rows)
         say(f"[t256] BtNB {prec}: {rep}")
@@ -211,7 +211,7 @@ def test_transition_grid_all_blocks():
 
 @pytest.mark.parametrize("name,modes,n_random", [("c2", ("fp64", "bf16x6"), 24),
                                                  ("c3", ("fp64", "fp32", "bf16x6", "bf16x3"), 16),
-                                                 ("c4", ("fp64", "bf16x6", "bf16x3"), 12)])
+                                                 ("c4", ("fp64", "fp32", "bf16x6", "bf16x3"), 12)])
 def test_full_size_sampled(name, modes, n_random):
     cfg = S.CONFIGS[name]
     og = G.make_grid(cfg.lmax, cfg.k)
