@@ -14,7 +14,12 @@ value = stored B^T N^-1 B elements / step time in the headline precision mode
 (split BF16, 6 products); FP64 and the other modes are timed the same way and
 reported side by side under "modes".
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4]
+With --config c5 a step is one launch of the captured graph that contracts
+all 32 problems of the batched workload (lmax 256/512/1024/2048, FP32 MFMA with
+FP64 accumulation across contraction tiles; 172 GB of output); the beam kernels
+are tabulated before the timed region and the schedule is autotuned first.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c5]
                        [--modes bf16x6,fp64,bf16x3] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -106,12 +111,134 @@ def cpu_baseline(cfg, budget_s):
                       f"{dt:.1f} s wall"}
 
 
+def batch_inputs(sp, S):
+    """The 32 problems of the batched workload, with library grids shared per lmax."""
+    grids, probs = {}, []
+    for p in range(32):
+        prob = S.batch_problem(p)
+        lmax = prob["lmax"]
+        if lmax not in grids:
+            g = sp.Grid(lmax, 8)
+            grids[lmax] = (g, g.pixel_theta_phi())
+        g, (th, ph) = grids[lmax]
+        b_l, R = S.gaussian_beam(lmax, g.npix, prob["fwhm_pix"])
+        probs.append(dict(prob=prob, g=g, b_l=b_l, R=R, ninv=S.ninv_batch(th, ph, prob)))
+    return probs
+
+
+def cpu_baseline_batch(probs, budget_s):
+    """The oracle on random block-rows drawn across the batch's problems until
+    the time budget is spent."""
+    from oracle import grid as G
+    from oracle import operators as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    rng = np.random.default_rng(11)
+    grids, ops = {}, {}
+    t0 = time.perf_counter()
+    nblk = nrows = 0
+    while time.perf_counter() - t0 < budget_s:
+        i = int(rng.integers(len(probs)))
+        pr = probs[i]
+        lmax = pr["g"].lmax
+        if lmax not in grids:
+            grids[lmax] = G.make_grid(lmax, 8)
+        og = grids[lmax]
+        if i not in ops:
+            ops[i] = O.LocalOperator(og, pr["b_l"], pr["R"])
+        J = int(rng.integers(og.ntiles))
+        for K in og.tile_neighbours(J):
+            if K >= J:
+                O.btnb_block(ops[i], pr["ninv"], J, K)
+                nblk += 1
+        nrows += 1
+    dt = time.perf_counter() - t0
+    return {"value": nblk * 4096 / dt, "unit": "elements/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{nrows} random block-rows ({nblk} stored blocks) across the 32 problems, "
+                      f"grids and unique blocks built on first use inside the {dt:.1f} s wall"}
+
+
+def run_batch(args):
+    import torch
+
+    import paper_1504_04653_amd as sp
+    from workloads import synth as S
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    probs = batch_inputs(sp, S)
+    setup = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    for pr in probs:
+        pr["kb"] = sp.Kernel(pr["g"], pr["b_l"], pr["R"], stream=stream)
+        pr["ninv_dev"] = torch.as_tensor(pr["ninv"]).cuda()
+        pr["out"] = torch.empty(pr["g"].out_len, dtype=torch.float64, device="cuda")
+    nelem = sum(pr["g"].nblocks for pr in probs) * 4096
+    alg_flop = sum(2.0 * 64 ** 3 * pr["g"].nterms for pr in probs)
+    bt = sp.Batch([(pr["g"], pr["kb"], pr["ninv_dev"], pr["out"]) for pr in probs], stream=stream)
+    chosen, tune_ms = bt.tune(stream)
+    sched = {v: k for k, v in sp.SCHEDULES.items()}[chosen]
+    print(f"# workload c5: 32 problems, npix={sum(pr['g'].npix for pr in probs)} "
+          f"nblocks={nelem // 4096} output={nelem * 8 / 1e9:.1f} GB setup={setup:.1f}s; "
+          f"tune ms {[round(t, 2) for t in tune_ms]} -> {sched}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        bt.launch(stream)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t_start = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(args.steps):
+        bt.launch(stream)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    ms_step = wall * 1000.0 / args.steps
+    achieved = alg_flop / (ms.mean() * 1e-3) / 1e12
+    print(f"# c5 batch ({sched}): step {ms_step:.2f} ms wall, {ms.mean():.2f} ms per graph launch, "
+          f"{achieved:.1f} TFLOP/s ({achieved / PEAK['fp32'] * 100:.1f}% of FP32 MFMA peak)",
+          file=sys.stderr, flush=True)
+    line = {
+        "metric": "B^T N^-1 B elements/s, 32-problem batch in one graph launch (FP32 MFMA)",
+        "value": nelem / (ms_step * 1e-3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sympix batch: 32 problems, lmax 256/512/1024/2048 (8 each), "
+                               "beam FWHM U[2,5] px cut 3 FWHM, N^-1 U[0.5,2] x cap mask U[0,0.3], "
+                               "seeds 5000+p",
+                   "problems": 32, "npix": int(sum(pr["g"].npix for pr in probs)),
+                   "nblocks": int(nelem // 4096), "schedule": sched,
+                   "tune_ms": [round(t, 3) for t in tune_ms], "setup_s": round(setup, 2)},
+        "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK["fp32"], "achieved": achieved,
+                     "frac": achieved / PEAK["fp32"], "kernel": "k_batch_f32" if chosen != 2 else "k_class_f32",
+                     "traffic": recorded_traffic("fp32", "c5")},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(probs, args.cpu_seconds)
+    bt.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.config == "c5":
+        run_batch(args)
+        return
     import torch
 
     import paper_1504_04653_amd as sp

@@ -171,6 +171,60 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
                                  int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
                                  void *stream);
 
+/* ---- Batches: many B-hat^T N^-1 B-hat problems in one graph launch ----------
+ * Eq. 15 evaluated for n independent problems (own grid, beam kernel, N^-1 and
+ * output each) by one captured HIP graph: a persistent FP32-MFMA contraction
+ * (FP64 accumulation across contraction tiles, as SYMPIX_FP32) pulls
+ * (problem, 64-block tile) work items from per-XCD queues.  Results are
+ * bitwise identical to sympix_sample_BtNB(..., SYMPIX_FP32, ...) per problem,
+ * under every schedule. */
+typedef struct sympix_batch sympix_batch;
+
+typedef struct {
+    const sympix_grid *g;
+    const sympix_kernel *b;   /* beam kernel tabulated for g */
+    const double *ninv_dev;   /* device, float64, npix values, 8-byte aligned */
+    int64_t ninv_len;         /* must be npix */
+    double *out_dev;          /* device, float64, nblocks k^4 values, 16-byte aligned */
+    int64_t out_len;          /* must be nblocks k^4 */
+} sympix_problem;
+
+typedef enum {
+    SYMPIX_SCHED_XCD_QUEUES = 0,  /* persistent; one queue per XCD, items in grid order (default) */
+    SYMPIX_SCHED_GLOBAL_LPT = 1,  /* persistent; one queue, largest items first */
+    SYMPIX_SCHED_PER_PROBLEM = 2, /* one class-GEMM launch per problem, in sequence */
+    SYMPIX_NSCHED = 3
+} sympix_schedule;
+
+/* Build a batch over problems p[0..n) (copied; the buffers they point to must
+ * stay allocated, and the grids and kernels alive, until the batch is
+ * destroyed) and capture its graph with the default schedule.  prec must be
+ * SYMPIX_FP32.  The batch owns its device tables and FP32 N^-1 scratch
+ * (4 npix bytes per problem).  stream: the call synchronises it once while
+ * uploading tables.
+ * Errors: EINVAL (NULL, n < 1, misaligned or overlapping outputs, problems on
+ * another device), ESIZE (a length mismatch), EUNSUPPORTED (prec other than
+ * FP32, k != 8), ENOMEM, EHIP. */
+sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t prec, void *stream,
+                                  sympix_batch **out);
+
+/* Re-capture the batch's graph with schedule s (a sympix_schedule). */
+sympix_status sympix_batch_set_schedule(sympix_batch *bt, int32_t s);
+
+/* Autotune: time one launch of every schedule on stream (after one warm-up
+ * launch each; the outputs are overwritten), keep the fastest and report it in
+ * *chosen and the times in ms_out[SYMPIX_NSCHED] (either may be NULL).  The
+ * choice is remembered for batches of the same shape in this process. */
+sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen, double *ms_out);
+
+/* Enqueue the batch's graph on stream: converts every N^-1 to FP32 and writes
+ * every output.  Launches on one device must not overlap in time (they share
+ * the batch's queue counters and scratch). */
+sympix_status sympix_batch_launch(sympix_batch *bt, void *stream);
+
+/* Free a batch. NULL is ignored.  No launch of it may be in flight. */
+void sympix_batch_destroy(sympix_batch *bt);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *sympix_last_error(void);
 

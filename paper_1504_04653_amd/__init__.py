@@ -72,10 +72,26 @@ _sample_D = _sig("sympix_sample_D", [_vp, _vp, _vp, _i64, _vp])
 _sample_BtNB = _sig("sympix_sample_BtNB", [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp])
 _last_error = _sig("sympix_last_error", [], ctypes.c_char_p)
 
+
+class Problem(ctypes.Structure):
+    _fields_ = [("g", _vp), ("b", _vp), ("ninv_dev", _vp), ("ninv_len", _i64), ("out_dev", _vp),
+                ("out_len", _i64)]
+
+
+_batch_create = _sig("sympix_batch_create", [ctypes.POINTER(Problem), _i32, _i32, _vp, ctypes.POINTER(_vp)])
+_batch_set_schedule = _sig("sympix_batch_set_schedule", [_vp, _i32])
+_batch_tune = _sig("sympix_batch_tune", [_vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64)])
+_batch_launch = _sig("sympix_batch_launch", [_vp, _vp])
+_batch_destroy = _sig("sympix_batch_destroy", [_vp], None)
+
+SCHED_XCD_QUEUES, SCHED_GLOBAL_LPT, SCHED_PER_PROBLEM = 0, 1, 2
+SCHEDULES = {"xcd_queues": SCHED_XCD_QUEUES, "global_lpt": SCHED_GLOBAL_LPT, "per_problem": SCHED_PER_PROBLEM}
+
 EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sympix_grid_rings",
             "sympix_grid_bands", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_unique",
             "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
-            "sympix_sample_BtNB", "sympix_last_error")
+            "sympix_sample_BtNB", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_tune",
+            "sympix_batch_launch", "sympix_batch_destroy", "sympix_last_error")
 
 
 def _check(status):
@@ -247,3 +263,48 @@ def sample_BtNB(grid: Grid, kernel: Kernel, ninv, out, prec=FP64, stream=None):
 def raw_call(name):
     """The ctypes function of an exported symbol (for ABI-level tests)."""
     return getattr(_lib, name)
+
+
+class Batch:
+    """Many B-hat^T N^-1 B-hat problems (FP32 mode) in one captured graph.
+
+    problems: sequence of (grid, kernel, ninv, out) with ninv / out contiguous
+    float64 CUDA tensors.  The batch keeps references to all of them."""
+
+    def __init__(self, problems, prec=FP32, stream=None):
+        if isinstance(prec, str):
+            prec = PRECISIONS[prec]
+        self._keep = list(problems)
+        arr = (Problem * len(self._keep))()
+        for i, (grid, kernel, ninv, out) in enumerate(self._keep):
+            _require_f64_device(ninv, "ninv")
+            _require_f64_device(out, "out")
+            arr[i] = Problem(grid.handle, kernel.handle, _ptr(ninv), _numel(ninv), _ptr(out), _numel(out))
+        h = _vp()
+        _check(_batch_create(arr, len(self._keep), int(prec), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _batch_destroy(h)
+            self._h = None
+
+    def set_schedule(self, schedule):
+        if isinstance(schedule, str):
+            schedule = SCHEDULES[schedule]
+        _check(_batch_set_schedule(self._h, int(schedule)))
+
+    def tune(self, stream=None):
+        """Time every schedule once, keep the fastest; returns (chosen, ms per schedule)."""
+        chosen = _i32(-1)
+        ms = (_f64 * len(SCHEDULES))()
+        _check(_batch_tune(self._h, _stream(stream), ctypes.byref(chosen), ms))
+        return chosen.value, list(ms)
+
+    def launch(self, stream=None):
+        _check(_batch_launch(self._h, _stream(stream)))
+

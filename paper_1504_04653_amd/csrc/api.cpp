@@ -2,12 +2,14 @@
 // tables and launches.  Declarations and contracts are in include/sympix.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -416,7 +418,7 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
     a.class_blk = dg->class_blk;
     a.class_itab = dg->class_itab;
     a.mtiles = dg->mtiles;
-    a.nmtiles = (int64_t)geo.mtiles.size() / 2;
+    a.nmtiles = (int64_t)geo.mtiles.size() / 4;
     a.nblocks = geo.nblocks();
     a.npix = geo.npix;
     a.ninv = ninv_dev;
@@ -449,6 +451,314 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
         if (e == hipSuccess) e = ef;
     }
     return after_launch(e, st, "sample_BtNB");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches (a10): many problems, one captured graph.
+// ---------------------------------------------------------------------------
+struct sympix_batch {
+    int device = 0;
+    int32_t nprob = 0;
+    int32_t schedule = SYMPIX_SCHED_XCD_QUEUES;
+    int32_t nworkgroups = 0;
+    std::vector<sympix::ProblemDesc> hdesc;
+    std::vector<const double *> ninv;
+    std::vector<int64_t> npix, nmtiles;
+    std::vector<int32_t> item_prob, item_tile, item_cost;   // natural order
+    sympix::ProblemDesc *d_desc = nullptr;
+    int32_t *d_items = nullptr;
+    int32_t *d_qb = nullptr;
+    int32_t *d_counters = nullptr;
+    float *d_wf = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string shape;
+};
+
+namespace {
+
+constexpr int kBatchQueues = 8;   // one per XCD
+
+std::mutex g_tune_mu;
+std::map<std::string, int32_t> g_tune_cache;   // batch shape -> schedule
+
+void free_batch(sympix_batch *bt) {
+    if (bt->exec) hipGraphExecDestroy(bt->exec);
+    if (bt->graph) hipGraphDestroy(bt->graph);
+    if (bt->cap) hipStreamDestroy(bt->cap);
+    hipFree(bt->d_desc);
+    hipFree(bt->d_items);
+    hipFree(bt->d_qb);
+    hipFree(bt->d_counters);
+    hipFree(bt->d_wf);
+    delete bt;
+}
+
+// Order the work items and bound the queues for schedule s, then capture the
+// batch's launches into a fresh graph.
+sympix_status capture_batch(sympix_batch *bt, int32_t s) {
+    const int64_t nitems = (int64_t)bt->item_prob.size();
+    std::vector<int64_t> order(nitems);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<int32_t> qb;
+    if (s == SYMPIX_SCHED_XCD_QUEUES) {
+        // contiguous ranges of equal work (sum of contraction tiles per item)
+        const double total = std::accumulate(bt->item_cost.begin(), bt->item_cost.end(), 0.0);
+        qb.push_back(0);
+        double run = 0.0;
+        int64_t i = 0;
+        for (int q = 1; q < kBatchQueues; ++q) {
+            while (i < nitems && run + 0.5 * bt->item_cost[i] < total * q / kBatchQueues) run += bt->item_cost[i++];
+            qb.push_back((int32_t)i);
+        }
+        qb.push_back((int32_t)nitems);
+    } else if (s == SYMPIX_SCHED_GLOBAL_LPT) {
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t a, int64_t b) { return bt->item_cost[a] > bt->item_cost[b]; });
+        qb = {0, (int32_t)nitems};
+    } else {
+        qb = {0, 0};
+    }
+    std::vector<int32_t> items(2 * nitems);
+    for (int64_t i = 0; i < nitems; ++i) {
+        items[2 * i] = bt->item_prob[order[i]];
+        items[2 * i + 1] = bt->item_tile[order[i]];
+    }
+    hipError_t e = hipSuccess;
+    if (nitems > 0) e = hipMemcpy(bt->d_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bt->d_qb, qb.data(), qb.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "uploading batch work items");
+
+    if (bt->exec) hipGraphExecDestroy(bt->exec);
+    if (bt->graph) hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+
+    sympix::BatchLaunch bl;
+    bl.nprob = bt->nprob;
+    bl.host_desc = bt->hdesc.data();
+    bl.ninv = bt->ninv.data();
+    bl.npix = bt->npix.data();
+    bl.nmtiles = bt->nmtiles.data();
+    bl.desc = bt->d_desc;
+    bl.items = bt->d_items;
+    bl.nitems = nitems;
+    bl.qb = bt->d_qb;
+    bl.nq = (int32_t)qb.size() - 1;
+    bl.counters = bt->d_counters;
+    bl.persistent = s != SYMPIX_SCHED_PER_PROBLEM;
+    bl.nworkgroups = bt->nworkgroups;
+
+    e = hipStreamBeginCapture(bt->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t el = sympix::launch_batch(bl, bt->cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(bt->cap, &graph);
+    if (el != hipSuccess || e != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return hip_fail(el != hipSuccess ? el : e, "capturing the batch graph");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    bt->graph = graph;
+    bt->exec = exec;
+    bt->schedule = s;
+    return SYMPIX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t prec, void *stream,
+                                  sympix_batch **out) {
+    if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p || n < 1) return fail(SYMPIX_EINVAL, "need at least one problem");
+    if (prec != SYMPIX_FP32) return fail(SYMPIX_EUNSUPPORTED, "batches run in SYMPIX_FP32 only");
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    for (int32_t i = 0; i < n; ++i) {
+        sympix_status s = check_kernel_use(p[i].g, p[i].b);
+        if (s != SYMPIX_OK) return fail(s, "problem " + std::to_string(i) + ": " + g_last_error);
+        const Geometry &geo = p[i].g->geo;
+        if (p[i].ninv_len != geo.npix)
+            return fail(SYMPIX_ESIZE, "problem " + std::to_string(i) + ": ninv_len must be npix");
+        if (p[i].out_len != geo.nblocks() * sympix::kBlockElems)
+            return fail(SYMPIX_ESIZE, "problem " + std::to_string(i) + ": out_len must be nblocks * k^4");
+        if ((geo.npix > 0 && !p[i].ninv_dev) || (p[i].out_len > 0 && !p[i].out_dev))
+            return fail(SYMPIX_EINVAL, "problem " + std::to_string(i) + ": NULL device buffer");
+        if (((uintptr_t)p[i].out_dev) % 16 || ((uintptr_t)p[i].ninv_dev) % 8)
+            return fail(SYMPIX_EINVAL, "problem " + std::to_string(i) +
+                                           ": out_dev must be 16-byte and ninv_dev 8-byte aligned");
+        if (geo.max_class_terms > sympix::kMaxClassTerms)
+            return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
+        if (p[i].out_len > 0)
+            spans.emplace_back((uintptr_t)p[i].out_dev, (uintptr_t)(p[i].out_dev + p[i].out_len));
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return fail(SYMPIX_EINVAL, "problem outputs overlap");
+
+    sympix_batch *bt = new (std::nothrow) sympix_batch();
+    if (!bt) return fail(SYMPIX_ENOMEM, "host allocation");
+    bt->device = p[0].b->device;
+    bt->nprob = n;
+    hipError_t e = hipSuccess;
+    int64_t wf_total = 0;
+    std::string shape;
+    {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, bt->device);
+        if (e != hipSuccess) {
+            free_batch(bt);
+            return hip_fail(e, "hipGetDeviceProperties");
+        }
+        shape = std::string(prop.gcnArchName) + "|fp32";
+        int occ = 0;
+        e = sympix::batch_occupancy(&occ);
+        if (e != hipSuccess) {
+            free_batch(bt);
+            return hip_fail(e, "occupancy query");
+        }
+        bt->nworkgroups = std::max(1, occ) * prop.multiProcessorCount;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const Geometry &geo = p[i].g->geo;
+        const DevGrid *dg = nullptr;
+        sympix_status s = device_tables(p[i].g, bt->device, &dg);
+        if (s != SYMPIX_OK) {
+            free_batch(bt);
+            return s;
+        }
+        sympix::ProblemDesc d{dg->mtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
+                              p[i].b->ut32, nullptr, p[i].out_dev};
+        bt->hdesc.push_back(d);
+        bt->ninv.push_back(p[i].ninv_dev);
+        bt->npix.push_back(geo.npix);
+        const int64_t nmt = (int64_t)geo.mtiles.size() / 4;
+        bt->nmtiles.push_back(nmt);
+        for (int64_t t = 0; t < nmt; ++t) {
+            bt->item_prob.push_back(i);
+            bt->item_tile.push_back((int32_t)t);
+            bt->item_cost.push_back(geo.classes[geo.mtiles[4 * t]].nterms * geo.mtiles[4 * t + 2]);
+        }
+        wf_total += geo.npix;
+        shape += "|" + std::to_string(geo.lmax) + ":" + std::to_string(geo.nblocks());
+    }
+    bt->shape = shape;
+    const int64_t nitems = (int64_t)bt->item_prob.size();
+    if (nitems >= (int64_t)INT32_MAX / 2) {
+        free_batch(bt);
+        return fail(SYMPIX_ESIZE, "too many work items for one batch");
+    }
+    e = hipMalloc((void **)&bt->d_desc, n * sizeof(sympix::ProblemDesc));
+    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_items, std::max<int64_t>(1, 2 * nitems) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_qb, (kBatchQueues + 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_counters, kBatchQueues * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_wf, std::max<int64_t>(1, wf_total) * sizeof(float));
+    if (e != hipSuccess) {
+        free_batch(bt);
+        return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the batch")
+                                        : hip_fail(e, "hipMalloc");
+    }
+    int64_t off = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        bt->hdesc[i].wf = bt->d_wf + off;
+        off += bt->npix[i];
+    }
+    e = hipMemcpy(bt->d_desc, bt->hdesc.data(), n * sizeof(sympix::ProblemDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_batch(bt);
+        return hip_fail(e, "batch set-up");
+    }
+    int32_t sched = SYMPIX_SCHED_XCD_QUEUES;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(bt->shape);
+        if (it != g_tune_cache.end()) sched = it->second;
+    }
+    sympix_status s = capture_batch(bt, sched);
+    if (s != SYMPIX_OK) {
+        free_batch(bt);
+        return s;
+    }
+    *out = bt;
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_batch_set_schedule(sympix_batch *bt, int32_t s) {
+    if (!bt) return fail(SYMPIX_EINVAL, "NULL batch");
+    if (s < 0 || s >= SYMPIX_NSCHED) return fail(SYMPIX_EINVAL, "unknown schedule");
+    return capture_batch(bt, s);
+}
+
+sympix_status sympix_batch_launch(sympix_batch *bt, void *stream) {
+    if (!bt || !bt->exec) return fail(SYMPIX_EINVAL, "NULL batch");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != bt->device) return fail(SYMPIX_EINVAL, "batch lives on another device than the current one");
+    hipStream_t st = (hipStream_t)stream;
+    return after_launch(hipGraphLaunch(bt->exec, st), st, "batch launch");
+}
+
+sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen, double *ms_out) {
+    if (!bt) return fail(SYMPIX_EINVAL, "NULL batch");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    double best_ms = 0.0;
+    int32_t best = -1;
+    sympix_status s = SYMPIX_OK;
+    for (int32_t c = 0; c < SYMPIX_NSCHED && s == SYMPIX_OK; ++c) {
+        s = capture_batch(bt, c);
+        if (s != SYMPIX_OK) break;
+        e = hipGraphLaunch(bt->exec, st);                       // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = hipGraphLaunch(bt->exec, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            s = hip_fail(e, "timing a batch schedule");
+            break;
+        }
+        if (ms_out) ms_out[c] = ms;
+        if (best < 0 || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s != SYMPIX_OK) return s;
+    s = capture_batch(bt, best);
+    if (s != SYMPIX_OK) return s;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[bt->shape] = best;
+    }
+    if (chosen) *chosen = best;
+    return SYMPIX_OK;
+}
+
+void sympix_batch_destroy(sympix_batch *bt) {
+    if (bt) free_batch(bt);
 }
 
 }  // extern "C"

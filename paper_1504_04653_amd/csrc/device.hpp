@@ -71,4 +71,34 @@ struct BtnbArgs {
 };
 hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st);
 
+// Operands of the FP32 class GEMM for one problem (device pointers).
+struct ProblemDesc {
+    const int32_t *mtiles;
+    const DevClass *classes;
+    const int32_t *cterms, *cblk, *citab;
+    const float *ut32;
+    float *wf;                // N^-1 rounded to FP32 (written by the launch)
+    double *out;
+};
+
+// a10: one batched launch.  host_desc / ninv / npix / nmtiles are host arrays
+// of nprob entries; desc, items, qb and counters live on the device.
+struct BatchLaunch {
+    int32_t nprob;
+    const ProblemDesc *host_desc;
+    const double *const *ninv;
+    const int64_t *npix;
+    const int64_t *nmtiles;
+    const ProblemDesc *desc;
+    const int32_t *items;     // 2 per item: problem, member tile
+    int64_t nitems;
+    const int32_t *qb;        // nq + 1 queue bounds
+    int32_t nq;
+    int32_t *counters;        // nq
+    bool persistent;          // false: one class-GEMM launch per problem
+    int32_t nworkgroups;
+};
+hipError_t launch_batch(const BatchLaunch &b, hipStream_t st);
+hipError_t batch_occupancy(int *workgroups_per_cu);
+
 }  // namespace sympix

@@ -370,9 +370,21 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
                 g.class_terms.insert(g.class_terms.end(), keys[c].begin(), keys[c].end());
                 g.class_blk.insert(g.class_blk.end(), members[c].begin(), members[c].end());
                 g.class_itab.insert(g.class_itab.end(), tiles_of[c].begin(), tiles_of[c].end());
-                for (int32_t m0 = 0; m0 < bc.nblocks; m0 += 64) {
-                    g.mtiles.push_back((int32_t)c);
-                    g.mtiles.push_back(m0);
+                // member tiles of 64 rows; a tail of at most 48 members goes
+                // into tiles of 32 and / or 16 rows
+                auto tile = [&](int32_t m0, int32_t groups) {
+                    g.mtiles.insert(g.mtiles.end(), {(int32_t)c, m0, groups, 0});
+                };
+                int32_t m0 = 0;
+                for (; bc.nblocks - m0 > 48; m0 += 64) tile(m0, 4);
+                const int32_t r = bc.nblocks - m0;
+                if (r > 32) {
+                    tile(m0, 2);
+                    tile(m0 + 32, 1);
+                } else if (r > 16) {
+                    tile(m0, 2);
+                } else if (r > 0) {
+                    tile(m0, 1);
                 }
                 g.classes.push_back(bc);
             }

@@ -69,7 +69,8 @@ struct Geometry {
     std::vector<int32_t> class_terms;   // 2 per term: uid_a, uid_b
     std::vector<int32_t> class_blk;     // stored-block index of each class member
     std::vector<int32_t> class_itab;    // tile I of each (member, term)
-    std::vector<int32_t> mtiles;        // 2 per m-tile: class, first member
+    std::vector<int32_t> mtiles;        // 4 per member tile: class, first member,
+                                        // 16-row groups (1, 2 or 4), 0
     int32_t max_class_terms = 0;
 
     double y_pattern_max = 0.0;   // max 1 - cos(gamma) over all pattern pairs

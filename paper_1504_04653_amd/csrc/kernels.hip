@@ -11,6 +11,8 @@
 //   k_ninv_f32     N^-1 rounded to FP32
 //   k_class_f32    FP32-MFMA contraction as one GEMM per class of blocks that
 //                  share their contraction pattern, FP64 accumulation across tiles
+//   k_batch_f32    the FP32 class GEMM of many problems in one persistent
+//                  launch fed by per-XCD work queues
 //   k_split_ninv   N^-1 split into BF16 parts
 //   k_class_bf16   the same GEMM in split BF16
 #include <hip/hip_runtime.h>
@@ -235,51 +237,52 @@ __global__ __launch_bounds__(256) void k_ninv_f32(const double *__restrict__ nin
     if (i < n) wf[i] = (float)ninv[i];
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_class_f32(const int32_t *__restrict__ mtiles, const DevClass *__restrict__ classes,
-                 const int32_t *__restrict__ cterms, const int32_t *__restrict__ cblk,
-                 const int32_t *__restrict__ citab, const float *__restrict__ ut32,
-                 const float *__restrict__ wf, double *__restrict__ out) {
-    __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
-    __shared__ int32_t sBlk[64];                     // stored-block index of each member row
-    const int item = xcd_contiguous_index();
-    const int cls = mtiles[2 * item], m0 = mtiles[2 * item + 1];
-    const DevClass cl = classes[cls];
+// One member tile (item) of one problem with NI groups of 16 member rows; all
+// 256 threads of the workgroup take part.  sTile / sBlk are the workgroup's
+// LDS tables.
+template <int NI>
+__device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, int32_t *sTile,
+                                               int32_t *sBlk) {
+    const float *__restrict__ ut32 = pd.ut32;
+    const float *__restrict__ wf = pd.wf;
+    double *__restrict__ out = pd.out;
+    const int cls = pd.mtiles[4 * item], m0 = pd.mtiles[4 * item + 1];
+    const DevClass cl = pd.classes[cls];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
-    const int32_t *terms = cterms + 2 * cl.term0;
+    const int32_t *terms = pd.cterms + 2 * cl.term0;
 
-    for (int x = threadIdx.x; x < 64 * nterms; x += 256) {
+    for (int x = threadIdx.x; x < 16 * NI * nterms; x += 256) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
-        sTile[r * kMaxClassTerms + e] = citab[cl.itab0 + (int64_t)m * nterms + e];
+        sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    if (threadIdx.x < 64) sBlk[lane] = m0 + lane < cl.nblocks ? cblk[cl.blk0 + m0 + lane] : -1;
+    if (threadIdx.x < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
     __syncthreads();
 
     // operand addresses of one term for output row a (lane part included)
-    struct Ptrs { const float *w[4], *u1, *u2; };
+    struct Ptrs { const float *w[NI], *u1, *u2; };
     auto ptrs = [&](int a, int e, Ptrs &q) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NI; ++i)
             q.w[i] = wf + (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 4 * lk;
         q.u1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 4 * lk;
         q.u2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + 4 * lk;
     };
-    struct Frag { floatx4 w[4], u1, u2[4]; };
+    struct Frag { floatx4 w[NI], u1, u2[4]; };
     auto load = [&](const Ptrs &q, int g, Frag &f) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) f.w[i] = *(const floatx4 *)(q.w[i] + 16 * g);
+        for (int i = 0; i < NI; ++i) f.w[i] = *(const floatx4 *)(q.w[i] + 16 * g);
         f.u1 = *(const floatx4 *)(q.u1 + 16 * g);
 #pragma unroll
         for (int j = 0; j < 4; ++j) f.u2[j] = *(const floatx4 *)(q.u2 + 16 * j * 64 + 16 * g);
     };
 
-    doublex4 acc[4][4];
-    floatx4 part[4][4];
+    doublex4 acc[NI][4];
+    floatx4 part[NI][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
     // One step: issue the next step's loads, then this step's products and
@@ -288,14 +291,14 @@ void k_class_f32(const int32_t *__restrict__ mtiles, const DevClass *__restrict_
     // those loads) out of this step.
     auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn, bool first) {
         load(qn, gn, fn);
-        __builtin_amdgcn_sched_group_barrier(0x020, 9, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, NI + 5, 0);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             float bv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) bv[j] = f.u1[t] * f.u2[j][t];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
@@ -304,7 +307,7 @@ void k_class_f32(const int32_t *__restrict__ mtiles, const DevClass *__restrict_
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);   // products of pixel t
-            __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);  // their 16 MFMAs
+            __builtin_amdgcn_sched_group_barrier(0x008, 4 * NI, 0);  // their MFMAs
         }
         __builtin_amdgcn_sched_barrier(0);
     };
@@ -328,14 +331,14 @@ void k_class_f32(const int32_t *__restrict__ mtiles, const DevClass *__restrict_
         step(f0, qc, 3, f1, false);
         step(f1, qn, 0, f0, false);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
         if (ne == 0) {                       // end of output row a: store, clear
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int blk = sBlk[16 * i + 4 * lk + v];
@@ -346,13 +349,70 @@ void k_class_f32(const int32_t *__restrict__ mtiles, const DevClass *__restrict_
                     }
                 }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
         }
         x = nx;
         e = ne;
         qc = qn;
+    }
+}
+
+__device__ __forceinline__ void class_f32_item(const ProblemDesc &pd, int item, int32_t *sTile, int32_t *sBlk) {
+    const int groups = pd.mtiles[4 * item + 2];
+    if (groups == 4) class_f32_tile<4>(pd, item, sTile, sBlk);
+    else if (groups == 2) class_f32_tile<2>(pd, item, sTile, sBlk);
+    else class_f32_tile<1>(pd, item, sTile, sBlk);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_class_f32(ProblemDesc pd) {
+    __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
+    __shared__ int32_t sBlk[64];                     // stored-block index of each member row
+    class_f32_item(pd, xcd_contiguous_index(), sTile, sBlk);
+}
+
+// ---------------------------------------------------------------------------
+// a10: many problems in one persistent launch.  Work items (problem, member
+// tile) sit in nq queues, queue q holding items [qb[q], qb[q+1]).  Workgroup b
+// drains queue b mod nq first (with one queue per XCD and items in natural
+// order, the tiles an XCD runs together share operands in its L2), then steals
+// from the others.  Counters only grow, so every workgroup leaves once all
+// queues are empty.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_fill_i32(int32_t *p, int32_t n, int32_t v) {
+    for (int i = threadIdx.x; i < n; i += 64) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restrict__ items,
+                 const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
+    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sBlk[64];
+    __shared__ int32_t sItem;
+    const int home = blockIdx.x % nq;
+    int tried = 0;                       // queues found empty (thread 0)
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tried < nq) {
+                const int q = (home + tried) % nq;
+                const int c = atomicAdd(&counters[q], 1);
+                if (c < qb[q + 1] - qb[q]) {
+                    it = qb[q] + c;
+                    break;
+                }
+                ++tried;
+            }
+            sItem = it;
+        }
+        __syncthreads();
+        const int it = sItem;
+        __syncthreads();                 // every thread has read sItem before it changes
+        if (it < 0) break;
+        const ProblemDesc pd = probs[items[2 * it]];
+        class_f32_item(pd, items[2 * it + 1], sTile, sBlk);
     }
 }
 
@@ -443,7 +503,7 @@ void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict
     __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
     __shared__ int32_t sBlk[64];                     // stored-block index of each member row
     const int item = xcd_contiguous_index();
-    const int cls = mtiles[2 * item], m0 = mtiles[2 * item + 1];
+    const int cls = mtiles[4 * item], m0 = mtiles[4 * item + 1], rows = 16 * mtiles[4 * item + 2];
     const DevClass cl = classes[cls];
     const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
@@ -457,7 +517,7 @@ void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    sBlk[lane] = m0 + lane < cl.nblocks ? cblk[cl.blk0 + m0 + lane] : -1;
+    sBlk[lane] = lane < rows && m0 + lane < cl.nblocks ? cblk[cl.blk0 + m0 + lane] : -1;
     __syncthreads();
 
     struct GenRegs { floatx4 u1[2], u2[4][2]; };
@@ -623,8 +683,8 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
     if (prec == 1) {
         hipLaunchKernelGGL(k_ninv_f32, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,
                            a.npix, a.wf32);
-        hipLaunchKernelGGL(k_class_f32, dim3((unsigned)a.nmtiles), dim3(256), 0, st, a.mtiles, a.classes,
-                           a.class_terms, a.class_blk, a.class_itab, a.ut32, a.wf32, a.out);
+        ProblemDesc pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.ut32, a.wf32, a.out};
+        hipLaunchKernelGGL(k_class_f32, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_split_ninv, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,
@@ -637,6 +697,29 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
         hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(64), 0, st, a.mtiles, a.classes, a.class_terms,
                            a.class_blk, a.class_itab, a.ut32, a.wsplit[0], a.wsplit[1], a.wsplit[2], a.out);
     return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.counters, b.nq, 0);
+    for (int p = 0; p < b.nprob; ++p)
+        if (b.npix[p] > 0)
+            hipLaunchKernelGGL(k_ninv_f32, dim3((unsigned)((b.npix[p] + 255) / 256)), dim3(256), 0, st,
+                               b.ninv[p], b.npix[p], b.host_desc[p].wf);
+    if (b.persistent) {
+        if (b.nitems > 0)
+            hipLaunchKernelGGL(k_batch_f32, dim3((unsigned)b.nworkgroups), dim3(256), 0, st, b.desc,
+                               b.items, b.qb, b.nq, b.counters);
+    } else {
+        for (int p = 0; p < b.nprob; ++p)
+            if (b.nmtiles[p] > 0)
+                hipLaunchKernelGGL(k_class_f32, dim3((unsigned)b.nmtiles[p]), dim3(256), 0, st,
+                                   b.host_desc[p]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t batch_occupancy(int *workgroups_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f32, 256, 0);
 }
 
 }  // namespace sympix

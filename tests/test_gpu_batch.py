@@ -1,0 +1,192 @@
+"""GPU parity of batched launches: many B-hat^T N^-1 B-hat problems (FP32 MFMA,
+FP64 accumulation across contraction tiles) in one captured graph.
+
+Every schedule must give results bitwise identical to the single-problem FP32
+path (each work item is computed by the same arithmetic whichever workgroup
+takes it), and those results must meet the FP32 gate against the oracle.
+Graph replays are checked with eager work and synchronisations in between.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1504_04653_amd as sp
+from oracle import grid as G
+from oracle import operators as O
+from workloads import synth as S
+
+from _parity import block_index, error_report, stored_pairs
+
+pytestmark = pytest.mark.gpu
+
+GATE_FP32 = 1e-6
+
+# (lmax, problem index whose beam / mask draws are used): mixed sizes, with
+# two problems on one grid
+SMALL = [(64, 0), (128, 1), (64, 2), (256, 3), (96, 4), (160, 5)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def make_problems(spec):
+    grids, probs = {}, []
+    for lmax, p in spec:
+        if lmax not in grids:
+            grids[lmax] = (G.make_grid(lmax, 8), sp.Grid(lmax, 8))
+        og, g = grids[lmax]
+        prob = dict(S.batch_problem(p))
+        prob["lmax"] = lmax
+        ring, _, _, phi = og.pixel_coords()
+        ninv = S.ninv_batch(og.theta[ring], phi, prob)
+        b_l, R = S.gaussian_beam(lmax, g.npix, prob["fwhm_pix"])
+        probs.append(dict(og=og, g=g, ninv=ninv, b_l=b_l, R=R, kb=sp.Kernel(g, b_l, R),
+                          ninv_dev=dev(ninv),
+                          out=torch.empty(g.out_len, dtype=torch.float64, device="cuda")))
+    return probs
+
+
+def single_fp32(p):
+    out = torch.empty(p["g"].out_len, dtype=torch.float64, device="cuda")
+    sp.sample_BtNB(p["g"], p["kb"], p["ninv_dev"], out, "fp32")
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.fixture(scope="module")
+def small():
+    probs = make_problems(SMALL)
+    bt = sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]) for p in probs])
+    ref = [single_fp32(p) for p in probs]
+    say("[batch] problems " + ", ".join(f"lmax {p['g'].lmax}: {p['g'].nblocks} blocks" for p in probs))
+    yield dict(probs=probs, bt=bt, ref=ref)
+    bt.close()
+
+
+def launch_and_check(small, tag):
+    for p in small["probs"]:
+        p["out"].fill_(float("nan"))
+    torch.cuda.synchronize()
+    small["bt"].launch()
+    torch.cuda.synchronize()
+    for i, (p, r) in enumerate(zip(small["probs"], small["ref"])):
+        assert torch.equal(p["out"], r), f"{tag}: problem {i} differs from the single-problem FP32 path"
+
+
+@pytest.mark.parametrize("schedule", ["xcd_queues", "global_lpt", "per_problem"])
+def test_every_schedule_matches_single_problem_path(small, schedule):
+    small["bt"].set_schedule(schedule)
+    launch_and_check(small, schedule)
+    say(f"[batch] schedule {schedule}: bitwise equal to sample_BtNB fp32 for {len(small['probs'])} problems")
+
+
+def test_single_problem_path_against_oracle(small):
+    for i, (p, r) in enumerate(zip(small["probs"], small["ref"])):
+        pairs = stored_pairs(p["og"])
+        rows = [J for J, _ in pairs]
+        Cref = O.sample_BtNB(p["og"], p["b_l"], p["ninv"], p["R"], pairs)
+        rep = error_report(r.view(-1, 64, 64).cpu().numpy(), Cref, rows)
+        say(f"[batch] problem {i} lmax {p['g'].lmax}: {rep}")
+        assert rep["gate"] <= GATE_FP32
+
+
+def test_graph_replays_with_eager_work_between(small):
+    small["bt"].set_schedule("xcd_queues")
+    for r in range(3):
+        x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        s = float((x * x).sum())           # eager kernels and a host sync between replays
+        assert s > 0
+        launch_and_check(small, f"replay {r}")
+
+
+def test_tune_picks_a_schedule_and_keeps_results(small):
+    chosen, ms = small["bt"].tune()
+    say(f"[batch] tune: chosen {chosen}, ms per schedule {ms}")
+    assert chosen in (0, 1, 2)
+    assert all(t > 0 for t in ms)
+    assert ms[chosen] == min(ms)
+    launch_and_check(small, "after tune")
+
+
+def test_batch_argument_errors(small):
+    p = small["probs"][0]
+    q = small["probs"][2]                   # same grid as p
+    with pytest.raises(sp.SympixError) as ei:
+        sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"])], prec="fp64")
+    assert ei.value.code == "EUNSUPPORTED"
+    short = torch.empty(p["g"].out_len - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(sp.SympixError) as ei:
+        sp.Batch([(p["g"], p["kb"], p["ninv_dev"], short)])
+    assert ei.value.code == "ESIZE"
+    with pytest.raises(sp.SympixError) as ei:
+        sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]), (q["g"], q["kb"], q["ninv_dev"], p["out"])])
+    assert ei.value.code == "EINVAL"
+    other = small["probs"][1]               # kernel of another grid
+    with pytest.raises(sp.SympixError) as ei:
+        sp.Batch([(p["g"], other["kb"], p["ninv_dev"], p["out"])])
+    assert ei.value.code == "EINVAL"
+
+
+# --- the 32-problem batch at full size, sampled block-rows --------------------
+
+def c5_rows(og, seed):
+    """Block-rows compared per problem: the first tile of the polar band, of
+    the first band whose tile count differs from a neighbour's and of an
+    equatorial band, and one random tile."""
+    rng = np.random.default_rng(seed)
+    nb = len(og.band_tiles)
+    trans = [b for b in range(nb) if any(og.band_tiles[x] != og.band_tiles[b] for x in og.band_neighbours(b))]
+    rows = {0, int(og.band_tile0[trans[0]]) if trans else 0, int(og.band_tile0[nb - 1]),
+            int(rng.integers(og.ntiles))}
+    return sorted(rows)
+
+
+def test_c5_full_batch_sampled():
+    spec = [(S.BATCH_LMAX[p % 4], p) for p in range(32)]
+    probs = make_problems(spec)
+    total = sum(p["g"].nblocks for p in probs) * 4096 * 8
+    say(f"[c5] 32 problems, {sum(p['g'].npix for p in probs)} pixels, output {total / 1e9:.1f} GB")
+    bt = sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]) for p in probs])
+    chosen, ms = bt.tune()
+    say(f"[c5] tune: chosen {chosen}, ms per schedule {[round(t, 2) for t in ms]}")
+    for p in probs:
+        p["out"].fill_(float("nan"))
+    bt.launch()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, p in enumerate(probs):
+        og, g = p["og"], p["g"]
+        rows = c5_rows(og, seed=7000 + i)
+        brp, bcol = g.blocks()
+        idx, pairs = block_index(og, brp, bcol, rows)
+        op = O.LocalOperator(og, p["b_l"], p["R"])
+        Cref = np.stack([O.btnb_block(op, p["ninv"], J, K) for J, K in pairs])
+        C = p["out"].view(-1, 64, 64)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+        rep = error_report(C, Cref, [J for J, _ in pairs])
+        worst = max(worst, rep["gate"])
+        say(f"[c5] problem {i} lmax {g.lmax}: {len(idx)} blocks, {rep}")
+        assert rep["gate"] <= GATE_FP32
+        assert not bool(torch.isnan(p["out"]).any()), f"problem {i}: a block was not written"
+    say(f"[c5] worst gate {worst:.3e}")
+    bt.close()
+    for p in probs:
+        del p["out"]
+    torch.cuda.empty_cache()
