@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--modes", default="bf16x6,fp64,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device-to-device copy of BYTES bytes (a reference "
+                         "kernel of known traffic for HBM counter runs)")
     return ap.parse_args()
 
 
@@ -263,6 +266,16 @@ def main():
     alg_flop = 2.0 * 64 ** 3 * g.nterms
     print(f"# workload {args.config}: lmax={cfg.lmax} npix={g.npix} nblocks={g.nblocks} "
           f"nterms={g.nterms} nunique={g.nunique} grid_setup={setup_grid:.2f}s", file=sys.stderr, flush=True)
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {4 * n} bytes read and written", file=sys.stderr, flush=True)
+        del src, dst
 
     def step(prec, ev):
         ev[0].record(stream)

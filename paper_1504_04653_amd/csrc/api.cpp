@@ -45,6 +45,8 @@ struct DevGrid {
     double *ring_sin = nullptr;
     UInfo *uinfo = nullptr;
     int32_t *blk_uid = nullptr;
+    int32_t *exp_blk = nullptr;
+    int32_t *exp_items = nullptr;
     int64_t *term_ptr = nullptr;
     DevTerm *terms = nullptr;
     sympix::DevClass *classes = nullptr;
@@ -68,6 +70,8 @@ void free_dev(DevGrid &d) {
     hipFree(d.ring_sin);
     hipFree(d.uinfo);
     hipFree(d.blk_uid);
+    hipFree(d.exp_blk);
+    hipFree(d.exp_items);
     hipFree(d.term_ptr);
     hipFree(d.terms);
     hipFree(d.classes);
@@ -134,6 +138,8 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.ring_sin, geo.sin_theta.data(), geo.sin_theta.size());
     if (e == hipSuccess) e = upload(&d.uinfo, uinfo.data(), uinfo.size());
     if (e == hipSuccess) e = upload(&d.blk_uid, geo.blk_uid.data(), geo.blk_uid.size());
+    if (e == hipSuccess) e = upload(&d.exp_blk, geo.exp_blk.data(), geo.exp_blk.size());
+    if (e == hipSuccess) e = upload(&d.exp_items, geo.exp_items.data(), geo.exp_items.size());
     if (e == hipSuccess) e = upload(&d.term_ptr, geo.term_ptr.data(), geo.term_ptr.size());
     if (e == hipSuccess) e = upload(&d.terms, terms.data(), terms.size());
     if (e == hipSuccess)
@@ -385,7 +391,7 @@ sympix_status sympix_sample_D(const sympix_grid *g, const sympix_kernel *d, doub
     s = device_tables(g, d->device, &dg);
     if (s != SYMPIX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    return after_launch(sympix::launch_expand(d->u64, dg->blk_uid, geo.nblocks(), out_dev, st), st,
+    return after_launch(sympix::launch_expand(d->u64, dg->exp_items, (int64_t)geo.exp_items.size() / 4, dg->exp_blk, out_dev, st), st,
                         "sample_D");
 }
 

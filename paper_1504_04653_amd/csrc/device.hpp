@@ -49,9 +49,10 @@ hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, in
                               const double *ring_theta, const double *ring_sin,
                               double *u64, float *ut32, uint16_t *ubf_hi, uint16_t *ubf_mid,
                               uint16_t *ubf_lo, hipStream_t st);
-// a8: D-hat expansion, out[blk] = u64[blk_uid[blk]]
-hipError_t launch_expand(const double *u64, const int32_t *blk_uid, int64_t nblocks, double *out,
-                         hipStream_t st);
+// a8: D-hat expansion: each work item {uid, first, count, 0} copies unique
+// block uid into the stored blocks exp_blk[first .. first + count)
+hipError_t launch_expand(const double *u64, const int32_t *items, int64_t nitems, const int32_t *exp_blk,
+                         double *out, hipStream_t st);
 // a9: B-hat^T N^-1 B-hat contraction
 struct BtnbArgs {
     const double *u64;

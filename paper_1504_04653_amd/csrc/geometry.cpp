@@ -320,6 +320,20 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
             g.blk_ptr[J + 1] = (int64_t)g.blk_col.size();
         }
 
+        // D-hat expansion list: stored blocks grouped by unique block, in work
+        // items of at most 64 blocks {uid, first, count, 0}
+        {
+            std::vector<int32_t> cnt(g.nunique() + 1, 0);
+            for (int32_t u : g.blk_uid) ++cnt[u + 1];
+            for (int64_t u = 0; u < g.nunique(); ++u) cnt[u + 1] += cnt[u];
+            g.exp_blk.assign(g.nblocks(), 0);
+            std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+            for (int64_t n = 0; n < g.nblocks(); ++n) g.exp_blk[pos[g.blk_uid[n]]++] = (int32_t)n;
+            for (int64_t u = 0; u < g.nunique(); ++u)
+                for (int32_t f = cnt[u]; f < cnt[u + 1]; f += 64)
+                    g.exp_items.insert(g.exp_items.end(), {(int32_t)u, f, std::min(64, cnt[u + 1] - f), 0});
+        }
+
         // block classes: key = sorted (uid_a, uid_b) pairs of the block's terms
         {
             struct VecHash {

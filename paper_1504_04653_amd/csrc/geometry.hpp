@@ -60,6 +60,11 @@ struct Geometry {
     std::vector<int32_t> blk_col;
     std::vector<int32_t> blk_uid;
 
+    // D-hat expansion: stored blocks ordered by unique block, and work items
+    // of at most 64 of them, 4 ints each {uid, first in exp_blk, count, 0}
+    std::vector<int32_t> exp_blk;
+    std::vector<int32_t> exp_items;
+
     // contraction terms per stored block (CSR, I ascending)
     std::vector<int64_t> term_ptr;
     std::vector<Term> terms;

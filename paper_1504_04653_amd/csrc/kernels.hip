@@ -147,18 +147,23 @@ __global__ __launch_bounds__(256) void k_unique_eval(KTable kt, const UInfo *__r
 }
 
 // ---------------------------------------------------------------------------
-// a8: D-hat expansion.  Each stored block is a 32 KiB copy of its unique block,
-// streamed with 16-byte non-temporal stores.
+// a8: D-hat expansion.  Each stored block is a 32 KiB copy of its unique block.
+// A workgroup holds one unique block in registers (8 x 16 bytes per thread)
+// and writes it to up to 64 stored blocks with 16-byte non-temporal stores,
+// so the unique blocks are read once and the kernel only streams writes.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_expand(const double *__restrict__ u64,
-                                                const int32_t *__restrict__ blk_uid,
-                                                int64_t nblocks, double *__restrict__ out) {
-    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
-        const doublex2 *src = (const doublex2 *)(u64 + (int64_t)blk_uid[b] * kBlockElems);
-        doublex2 *dst = (doublex2 *)(out + b * kBlockElems);
-        doublex2 v[8];
+                                                const int32_t *__restrict__ items,
+                                                const int32_t *__restrict__ exp_blk,
+                                                double *__restrict__ out) {
+    const int32_t uid = items[4 * blockIdx.x], first = items[4 * blockIdx.x + 1];
+    const int32_t count = items[4 * blockIdx.x + 2];
+    const doublex2 *src = (const doublex2 *)(u64 + (int64_t)uid * kBlockElems);
+    doublex2 v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = src[threadIdx.x + 256 * j];
+    for (int j = 0; j < 8; ++j) v[j] = src[threadIdx.x + 256 * j];
+    for (int n = 0; n < count; ++n) {
+        doublex2 *dst = (doublex2 *)(out + (int64_t)exp_blk[first + n] * kBlockElems);
 #pragma unroll
         for (int j = 0; j < 8; ++j) __builtin_nontemporal_store(v[j], &dst[threadIdx.x + 256 * j]);
     }
@@ -665,11 +670,10 @@ hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, in
     return hipGetLastError();
 }
 
-hipError_t launch_expand(const double *u64, const int32_t *blk_uid, int64_t nblocks, double *out,
-                         hipStream_t st) {
-    if (nblocks == 0) return hipSuccess;
-    const int64_t grid = nblocks < 4096 ? nblocks : 4096;
-    hipLaunchKernelGGL(k_expand, dim3((unsigned)grid), dim3(256), 0, st, u64, blk_uid, nblocks, out);
+hipError_t launch_expand(const double *u64, const int32_t *items, int64_t nitems, const int32_t *exp_blk,
+                         double *out, hipStream_t st) {
+    if (nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)nitems), dim3(256), 0, st, u64, items, exp_blk, out);
     return hipGetLastError();
 }
 
