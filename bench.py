@@ -42,7 +42,7 @@ HEADLINE = "bf16x6"
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}     # TFLOP/s, dense
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}                   # MFMA products per term
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAME = {"fp64": "k_btnb_f64", "fp32": "k_class_f32", "bf16x3": "k_class_bf16<2>",
+KERNEL_NAME = {"fp64": "k_class_f64", "fp32": "k_class_f32", "bf16x3": "k_class_bf16<2>",
                "bf16x6": "k_class_bf16<3>"}
 
 

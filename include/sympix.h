@@ -161,9 +161,10 @@ sympix_status sympix_sample_D(const sympix_grid *g, const sympix_kernel *d, doub
 
 /* Stored blocks of B-hat^T N^-1 B-hat (Eq. 15):
  *   C_JK = sum_{I in nbr(J) & nbr(K)} B_IJ^T diag(ninv_I) B_IK,
- * with ninv_dev (device, float64, npix values in pixel order, >= 0; negative or
- * NaN values are not checked and give undefined results) and out_dev (device,
- * float64, nblocks k^4 values, stored-block order).
+ * with ninv_dev (device, float64, npix values in pixel order, 32-byte aligned,
+ * >= 0; negative or NaN values are not checked and give undefined results) and
+ * out_dev (device, float64, nblocks k^4 values, stored-block order, 16-byte
+ * aligned).
  *   prec: a sympix_precision.  FP64 is bitwise reproducible run to run.
  * Errors: EINVAL, ESIZE (ninv_len != npix or out_len != nblocks k^4),
  *         EUNSUPPORTED (k != 8), EHIP. */

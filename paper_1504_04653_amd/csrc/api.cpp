@@ -17,7 +17,6 @@
 #include "device.hpp"
 #include "geometry.hpp"
 
-using sympix::DevTerm;
 using sympix::Geometry;
 using sympix::UInfo;
 
@@ -47,8 +46,6 @@ struct DevGrid {
     int32_t *blk_uid = nullptr;
     int32_t *exp_blk = nullptr;
     int32_t *exp_items = nullptr;
-    int64_t *term_ptr = nullptr;
-    DevTerm *terms = nullptr;
     sympix::DevClass *classes = nullptr;
     int32_t *class_terms = nullptr;
     int32_t *class_blk = nullptr;
@@ -72,8 +69,6 @@ void free_dev(DevGrid &d) {
     hipFree(d.blk_uid);
     hipFree(d.exp_blk);
     hipFree(d.exp_items);
-    hipFree(d.term_ptr);
-    hipFree(d.terms);
     hipFree(d.classes);
     hipFree(d.class_terms);
     hipFree(d.class_blk);
@@ -99,7 +94,7 @@ struct sympix_kernel {
     double *table = nullptr;
     double *u64 = nullptr;
     float *ut32 = nullptr;
-    uint16_t *bf[3] = {nullptr, nullptr, nullptr};
+    double *u64t = nullptr;
 };
 
 namespace {
@@ -128,9 +123,6 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
         x.pad0 = x.pad1 = 0;
         uinfo[u] = x;
     }
-    std::vector<DevTerm> terms(geo.terms.size());
-    for (size_t t = 0; t < geo.terms.size(); ++t)
-        terms[t] = DevTerm{geo.terms[t].uid_a, geo.terms[t].uid_b, geo.terms[t].tile, 0};
     static_assert(sizeof(sympix::DevClass) == sizeof(sympix::BlockClass), "class layout");
     DevGrid d;
     hipError_t e = hipSuccess;
@@ -140,8 +132,6 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.blk_uid, geo.blk_uid.data(), geo.blk_uid.size());
     if (e == hipSuccess) e = upload(&d.exp_blk, geo.exp_blk.data(), geo.exp_blk.size());
     if (e == hipSuccess) e = upload(&d.exp_items, geo.exp_items.data(), geo.exp_items.size());
-    if (e == hipSuccess) e = upload(&d.term_ptr, geo.term_ptr.data(), geo.term_ptr.size());
-    if (e == hipSuccess) e = upload(&d.terms, terms.data(), terms.size());
     if (e == hipSuccess)
         e = upload(&d.classes, reinterpret_cast<const sympix::DevClass *>(geo.classes.data()),
                    geo.classes.size());
@@ -182,7 +172,7 @@ void free_kernel(sympix_kernel *kr) {
     hipFree(kr->table);
     hipFree(kr->u64);
     hipFree(kr->ut32);
-    for (auto &p : kr->bf) hipFree(p);
+    hipFree(kr->u64t);
     delete kr;
 }
 
@@ -340,7 +330,7 @@ sympix_status sympix_kernel_tabulate(const sympix_grid *g, const double *coef_l,
     if (e == hipSuccess) e = hipMalloc((void **)&kr->table, (size_t)n_nodes * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&kr->u64, nu * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&kr->ut32, nu * sizeof(float));
-    for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipMalloc((void **)&kr->bf[q], nu * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&kr->u64t, nu * sizeof(double));
     if (e != hipSuccess) {
         free_kernel(kr);
         return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the kernel failed")
@@ -353,9 +343,8 @@ sympix_status sympix_kernel_tabulate(const sympix_grid *g, const double *coef_l,
     }
     e = sympix::launch_tabulate(kr->coef, lmax, kr->h, kr->table, n_nodes, st);
     if (e == hipSuccess)
-        e = sympix::launch_unique_eval(ktable(kr), dg->uinfo, geo.nunique(), geo.k, dg->ring_theta,
-                                       dg->ring_sin, kr->u64, kr->ut32, kr->bf[0], kr->bf[1],
-                                       kr->bf[2], st);
+        e = sympix::launch_unique_eval(ktable(kr), dg->uinfo, geo.nunique(), dg->ring_theta, dg->ring_sin,
+                                       kr->u64, kr->u64t, kr->ut32, st);
     s = after_launch(e, st, "tabulate / unique-block evaluation");
     if (s != SYMPIX_OK) {
         hipStreamSynchronize(st);
@@ -407,18 +396,15 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
         return fail(SYMPIX_ESIZE, "out_len must be nblocks * k^4");
     if ((geo.npix > 0 && !ninv_dev) || (out_len > 0 && !out_dev))
         return fail(SYMPIX_EINVAL, "NULL device buffer");
-    if (((uintptr_t)out_dev) % 16 || ((uintptr_t)ninv_dev) % 8)
-        return fail(SYMPIX_EINVAL, "out_dev must be 16-byte and ninv_dev 8-byte aligned");
+    if (((uintptr_t)out_dev) % 16 || ((uintptr_t)ninv_dev) % 32)
+        return fail(SYMPIX_EINVAL, "out_dev must be 16-byte and ninv_dev 32-byte aligned");
     const DevGrid *dg = nullptr;
     s = device_tables(g, b->device, &dg);
     if (s != SYMPIX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     sympix::BtnbArgs a;
-    a.u64 = b->u64;
+    a.u64t = b->u64t;
     a.ut32 = b->ut32;
-    for (int q = 0; q < 3; ++q) a.ubf[q] = b->bf[q];
-    a.term_ptr = dg->term_ptr;
-    a.terms = dg->terms;
     a.classes = dg->classes;
     a.class_terms = dg->class_terms;
     a.class_blk = dg->class_blk;
@@ -432,7 +418,7 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
     a.wsplit[0] = a.wsplit[1] = a.wsplit[2] = nullptr;
     a.wf32 = nullptr;
     hipError_t e = hipSuccess;
-    if (prec != SYMPIX_FP64 && geo.max_class_terms > sympix::kMaxClassTerms)
+    if (geo.max_class_terms > sympix::kMaxClassTerms)
         return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
     void *scratch = nullptr;
     if (prec != SYMPIX_FP64) {

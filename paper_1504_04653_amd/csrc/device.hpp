@@ -17,10 +17,6 @@ struct UInfo {
     int32_t pad0, pad1;
 };
 
-struct DevTerm {
-    int32_t uid_a, uid_b, tile, pad;
-};
-
 // A class of stored blocks sharing their contraction pattern (see geometry.hpp).
 struct DevClass {
     int32_t nterms, nblocks, term0, blk0;
@@ -44,22 +40,18 @@ hipError_t launch_tabulate(const double *coef, int32_t lmax, double h, double *t
                            int32_t n_nodes, hipStream_t st);
 // evaluation of the table at arbitrary y (tests of the interpolation)
 hipError_t launch_eval(KTable kt, const double *y, double *out, int64_t n, hipStream_t st);
-// a7: every unique block, FP64 row-major + FP32 and BF16 (3 parts) transposed
-hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, int32_t k,
-                              const double *ring_theta, const double *ring_sin,
-                              double *u64, float *ut32, uint16_t *ubf_hi, uint16_t *ubf_mid,
-                              uint16_t *ubf_lo, hipStream_t st);
+// a7: every unique block, FP64 row-major [uid][p][q] plus FP64 and FP32
+// copies transposed [uid][q][p]
+hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, const double *ring_theta,
+                              const double *ring_sin, double *u64, double *u64t, float *ut32, hipStream_t st);
 // a8: D-hat expansion: each work item {uid, first, count, 0} copies unique
 // block uid into the stored blocks exp_blk[first .. first + count)
 hipError_t launch_expand(const double *u64, const int32_t *items, int64_t nitems, const int32_t *exp_blk,
                          double *out, hipStream_t st);
 // a9: B-hat^T N^-1 B-hat contraction
 struct BtnbArgs {
-    const double *u64;
+    const double *u64t;
     const float *ut32;
-    const uint16_t *ubf[3];
-    const int64_t *term_ptr;
-    const DevTerm *terms;
     const DevClass *classes;
     const int32_t *class_terms, *class_blk, *class_itab, *mtiles;
     int64_t nmtiles;
@@ -71,6 +63,16 @@ struct BtnbArgs {
     double *out;
 };
 hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st);
+
+// Operands of the FP64 class GEMM (device pointers).
+struct ProblemDesc64 {
+    const int32_t *mtiles;
+    const DevClass *classes;
+    const int32_t *cterms, *cblk, *citab;
+    const double *u64t;
+    const double *w;          // N^-1
+    double *out;
+};
 
 // Operands of the FP32 class GEMM for one problem (device pointers).
 struct ProblemDesc {

@@ -4,10 +4,10 @@
 //   k_eval         table lookups at arbitrary y (interpolation tests)
 //   k_unique_eval  one workgroup per unique block (Section 2.3 symmetry keys):
 //                  pair geometry, table lookup, radial cut; writes FP64
-//                  row-major and FP32 / BF16-split copies transposed via LDS
+//                  row-major and FP64 / FP32 copies transposed via LDS
 //   k_expand       D-hat: streams each stored block from its unique block
-//   k_btnb_f64     B-hat^T N^-1 B-hat (Eq. 15) in FP64: one output block per
-//                  wave, MFMA over the 64 pixels of each contraction tile
+//   k_class_f64    B-hat^T N^-1 B-hat (Eq. 15) in FP64 as one GEMM per class of
+//                  blocks that share their contraction pattern
 //   k_ninv_f32     N^-1 rounded to FP32
 //   k_class_f32    FP32-MFMA contraction as one GEMM per class of blocks that
 //                  share their contraction pattern, FP64 accumulation across tiles
@@ -105,10 +105,8 @@ __global__ __launch_bounds__(256) void k_unique_eval(KTable kt, const UInfo *__r
                                                      const double *__restrict__ ring_theta,
                                                      const double *__restrict__ ring_sin,
                                                      double *__restrict__ u64,
-                                                     float *__restrict__ ut32,
-                                                     uint16_t *__restrict__ ubf_hi,
-                                                     uint16_t *__restrict__ ubf_mid,
-                                                     uint16_t *__restrict__ ubf_lo) {
+                                                     double *__restrict__ u64t,
+                                                     float *__restrict__ ut32) {
     __shared__ double tile[64][65];
     const int64_t uid = blockIdx.x;
     const UInfo inf = uinfo[uid];
@@ -135,14 +133,8 @@ __global__ __launch_bounds__(256) void k_unique_eval(KTable kt, const UInfo *__r
     for (int e = threadIdx.x; e < kBlockElems; e += 256) {
         const int q = e >> 6, p = e & 63;   // transposed layout [q][p]
         const double v = tile[p][q];
+        u64t[base + e] = v;
         ut32[base + e] = (float)v;
-        const uint16_t h = bf16_bits((float)v);
-        const double r1 = v - (double)bf16_value(h);
-        const uint16_t m = bf16_bits((float)r1);
-        const double r2 = r1 - (double)bf16_value(m);
-        ubf_hi[base + e] = h;
-        ubf_mid[base + e] = m;
-        ubf_lo[base + e] = bf16_bits((float)r2);
     }
 }
 
@@ -170,58 +162,131 @@ __global__ __launch_bounds__(256) void k_expand(const double *__restrict__ u64,
 }
 
 // ---------------------------------------------------------------------------
-// a9, FP64: one wave per output block C_JK (64 x 64), 16 MFMA 16x16x4 tiles
-// per wave.  For a term I: A = B_IJ (rows p in I, cols a in J), B = B_IK, and
-// C[a][b] += sum_p A[p][a] w_p B[p][b].  MFMA operand lanes: A fragment holds
-// (row a = 16 i + lane%16, k = p), B fragment (k = p, col b = 16 j + lane%16),
-// with p = 4 ks + lane/16.  The FP64 result interleaves rows: lane holds rows
-// lane/16 + 4 v of column lane%16 (the FP32/BF16 16x16 forms hold 4 (lane/16) + v).
+// a9, FP64 MFMA class GEMM (the class decomposition is described with the
+// FP32 form below).  W = N^-1 as given, M = B_IJ[p][a] B_IK[p][b] formed in
+// FP64 from the transposed FP64 unique blocks.  MFMA 16x16x4 FP64: lane
+// (lr, lk) holds W[16 i + lr][p] and M[p][16 j + lr] for p = 16 g + 4 lk + t;
+// its result holds members 16 i + lk + 4 v of column b = 16 j + lr.  The MFMA
+// accumulates in FP64 across all terms of an output row, so there is no
+// separate accumulation step; four waves share a member tile and take every
+// fourth row a; each step (16 pixels of one term) loads the next step's
+// operands before its own MFMAs.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_btnb_f64(const double *__restrict__ u64,
-                                                  const int64_t *__restrict__ term_ptr,
-                                                  const DevTerm *__restrict__ terms,
-                                                  const double *__restrict__ ninv,
-                                                  int64_t nblocks, double *__restrict__ out) {
+template <int NI>
+__device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item, int32_t *sTile,
+                                               int32_t *sBlk) {
+    const double *__restrict__ ut = pd.u64t;
+    const double *__restrict__ wv = pd.w;
+    double *__restrict__ out = pd.out;
+    const int cls = pd.mtiles[4 * item], m0 = pd.mtiles[4 * item + 1];
+    const DevClass cl = pd.classes[cls];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int64_t blk = (int64_t)blockIdx.x * 4 + wave;
-    if (blk >= nblocks) return;
-    const int lr = lane & 15, lk = lane >> 4;
-    doublex4 acc[4][4];
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int nterms = cl.nterms;
+    const int32_t *terms = pd.cterms + 2 * cl.term0;
+
+    for (int x = threadIdx.x; x < 16 * NI * nterms; x += 256) {
+        const int r = x / nterms, e = x - r * nterms;
+        const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
+        sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
+    }
+    if (threadIdx.x < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+    __syncthreads();
+
+    struct Ptrs { const double *w[NI], *u1, *u2; };
+    auto ptrs = [&](int a, int e, Ptrs &q) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NI; ++i)
+            q.w[i] = wv + (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 4 * lk;
+        q.u1 = ut + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 4 * lk;
+        q.u2 = ut + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + 4 * lk;
+    };
+    struct Frag { doublex4 w[NI], u1, u2[4]; };
+    auto load = [&](const Ptrs &q, int g, Frag &f) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) f.w[i] = *(const doublex4 *)(q.w[i] + 16 * g);
+        f.u1 = *(const doublex4 *)(q.u1 + 16 * g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f.u2[j] = *(const doublex4 *)(q.u2 + 16 * j * 64 + 16 * g);
+    };
+
+    doublex4 acc[NI][4];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-    const int64_t t0 = term_ptr[blk], t1 = term_ptr[blk + 1];
-    for (int64_t t = t0; t < t1; ++t) {
-        const DevTerm tm = terms[t];
-        const double *A = u64 + (int64_t)tm.uid_a * kBlockElems + lr;
-        const double *B = u64 + (int64_t)tm.uid_b * kBlockElems + lr;
-        const double *w = ninv + (int64_t)tm.tile * 64;
-#pragma unroll 2
-        for (int ks = 0; ks < 16; ++ks) {
-            const int p = ks * 4 + lk;
-            const double wp = w[p];
-            double a[4], b[4];
+    auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn) {
+        load(qn, gn, fn);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = A[p * 64 + 16 * i];
+        for (int t = 0; t < 4; ++t) {
+            double bv[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = B[p * 64 + 16 * j] * wp;
+            for (int j = 0; j < 4; ++j) bv[j] = f.u1[t] * f.u2[j][t];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.w[i][t], bv[j], acc[i][j], 0, 0, 0);
         }
+        __builtin_amdgcn_sched_group_barrier(0x020, 2 * (NI + 5), 0);   // loads first
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);          // products of pixel t
+            __builtin_amdgcn_sched_group_barrier(0x008, 4 * NI, 0);     // their MFMAs
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    Frag f0, f1;
+    Ptrs qc, qn;
+    int x = 0, e = 0;                    // row index (a = wave + 4 x) and term of this step
+    ptrs(wave, 0, qc);
+    load(qc, 0, f0);
+    for (int it = 0; it < 16 * nterms; ++it) {
+        int ne = e + 1, nx = x;
+        if (ne == nterms) {
+            ne = 0;
+            ++nx;
+        }
+        const int a = wave + 4 * x;
+        if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
+        else qn = qc;                    // past the last row: a harmless reload
+        step(f0, qc, 1, f1);
+        step(f1, qc, 2, f0);
+        step(f0, qc, 3, f1);
+        step(f1, qn, 0, f0);
+        if (ne == 0) {                   // end of output row a: store, clear
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int blk = sBlk[16 * i + lk + 4 * v];
+                    if (blk >= 0) {
+                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + lr;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+        }
+        x = nx;
+        e = ne;
+        qc = qn;
     }
-    double *o = out + blk * kBlockElems + lr;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                __builtin_nontemporal_store(acc[i][j][v], &o[(16 * i + lk + 4 * v) * 64 + 16 * j]);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_class_f64(ProblemDesc64 pd) {
+    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sBlk[64];
+    const int item = xcd_contiguous_index();
+    const int groups = pd.mtiles[4 * item + 2];
+    if (groups == 4) class_f64_tile<4>(pd, item, sTile, sBlk);
+    else if (groups == 2) class_f64_tile<2>(pd, item, sTile, sBlk);
+    else class_f64_tile<1>(pd, item, sTile, sBlk);
 }
 
 // ---------------------------------------------------------------------------
@@ -659,14 +724,11 @@ hipError_t launch_eval(KTable kt, const double *y, double *out, int64_t n, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, int32_t k,
-                              const double *ring_theta, const double *ring_sin, double *u64,
-                              float *ut32, uint16_t *ubf_hi, uint16_t *ubf_mid, uint16_t *ubf_lo,
-                              hipStream_t st) {
-    (void)k;
+hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, const double *ring_theta,
+                              const double *ring_sin, double *u64, double *u64t, float *ut32, hipStream_t st) {
     if (nunique == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_unique_eval, dim3((unsigned)nunique), dim3(256), 0, st, kt, uinfo,
-                       ring_theta, ring_sin, u64, ut32, ubf_hi, ubf_mid, ubf_lo);
+    hipLaunchKernelGGL(k_unique_eval, dim3((unsigned)nunique), dim3(256), 0, st, kt, uinfo, ring_theta,
+                       ring_sin, u64, u64t, ut32);
     return hipGetLastError();
 }
 
@@ -680,8 +742,8 @@ hipError_t launch_expand(const double *u64, const int32_t *items, int64_t nitems
 hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
     if (a.nblocks == 0) return hipSuccess;
     if (prec == 0) {
-        hipLaunchKernelGGL(k_btnb_f64, dim3((unsigned)((a.nblocks + 3) / 4)), dim3(256), 0, st, a.u64,
-                           a.term_ptr, a.terms, a.ninv, a.nblocks, a.out);
+        ProblemDesc64 pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.u64t, a.ninv, a.out};
+        hipLaunchKernelGGL(k_class_f64, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
         return hipGetLastError();
     }
     if (prec == 1) {
