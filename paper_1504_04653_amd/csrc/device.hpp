@@ -74,6 +74,16 @@ struct ProblemDesc64 {
     double *out;
 };
 
+// Operands of the split-BF16 class GEMM (device pointers).
+struct ProblemDescB {
+    const int32_t *mtiles;
+    const DevClass *classes;
+    const int32_t *cterms, *cblk, *citab;
+    const float *ut32;
+    const uint16_t *w[3];     // N^-1 split into BF16 parts
+    double *out;
+};
+
 // Operands of the FP32 class GEMM for one problem (device pointers).
 struct ProblemDesc {
     const int32_t *mtiles;

@@ -517,20 +517,6 @@ __device__ __forceinline__ void split_pair(float y0, float y1, uint32_t *out) {
     }
 }
 
-// part += a * b over the kept products (smallest first).
-template <int NP>
-__device__ __forceinline__ floatx4 split_mfma(const bf16x8 *a, const bf16x8 *b, floatx4 c) {
-    if constexpr (NP == 3) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], c, 0, 0, 0);
-    }
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], c, 0, 0, 0);
-    return c;
-}
-
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p) {
     return __builtin_bit_cast(bf16x8, *(const u16x8 *)p);
 }
@@ -551,160 +537,162 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
     w2[i] = bf16_bits((float)(r1 - (double)bf16_value(m)));
 }
 
-// Class GEMM, split BF16.  For a class of blocks sharing the multiset of
-// (B_IJ, B_IK) unique pairs, C[m][(a,b)] = sum_(e,p) W[m][(e,p)] M[(e,p)][(a,b)]
-// with W[m][(e,p)] = N^-1 at pixel p of the class member's tile I_e and
-// M[(e,p)][(a,b)] = B_IJ[p][a] B_IK[p][b].  One wave owns 64 members and sweeps
-// the 64 output rows a; each step is one chunk of 32 pixels of one term.  The
-// wave forms its own M fragments (FP32 product, split into BF16 parts) in
-// registers, so waves never wait on each other; W fragments are read directly
-// from the pre-split N^-1.  The 64 x 64 output tile (16 MFMA tiles) makes each
-// 16-byte operand fragment feed four MFMA tiles.  Loads for the next step (W)
-// and the step after it (B_IJ, B_IK values) and the formation of M are
-// interleaved with the MFMAs; FP32 partials of each term are added to FP64
-// accumulators, which are stored and cleared at the end of every row a.
-template <int NP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_class_bf16(const int32_t *__restrict__ mtiles, const DevClass *__restrict__ classes,
-                  const int32_t *__restrict__ cterms, const int32_t *__restrict__ cblk,
-                  const int32_t *__restrict__ citab, const float *__restrict__ ut32,
-                  const uint16_t *__restrict__ w0, const uint16_t *__restrict__ w1,
-                  const uint16_t *__restrict__ w2, double *__restrict__ out) {
-    __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
-    __shared__ int32_t sBlk[64];                     // stored-block index of each member row
-    const int item = xcd_contiguous_index();
-    const int cls = mtiles[4 * item], m0 = mtiles[4 * item + 1], rows = 16 * mtiles[4 * item + 2];
-    const DevClass cl = classes[cls];
-    const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
+// Split-BF16 class GEMM (the decomposition of the FP32 form above): W = N^-1
+// split into NP BF16 parts, M = B_IJ[p][a] B_IK[p][b] formed as an FP32
+// product and split into NP parts in registers; NP = 3 keeps the products hh,
+// hm, mh, hl, lh, mm (smallest first), NP = 2 keeps hh, hm, mh.  MFMA
+// 16x16x32 BF16: lane (lr, lk) holds W[16 i + lr][p0 + 8 lk + 0..7] and
+// M[p0 + 8 lk + 0..7][16 j + lr]; the result holds members 16 i + 4 lk + v.
+// Four waves per member tile, wave w taking output rows a = w mod 4, so the W
+// fragments and the B_IK values of a step are shared through L1.  A step is 32 pixels (half a
+// term): the next step's loads go out first, then the M fragments of the four
+// 16-column groups are formed and split (FP32 product, NP BF16 parts) while
+// the MFMAs of the groups already formed run; a term's FP32 sums are added to
+// the FP64 accumulators after its second step.
+template <int NP, int NI>
+__device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item, int32_t *sTile,
+                                                int32_t *sBlk) {
+    const float *__restrict__ ut32 = pd.ut32;
+    double *__restrict__ out = pd.out;
+    const int cls = pd.mtiles[4 * item], m0 = pd.mtiles[4 * item + 1];
+    const DevClass cl = pd.classes[cls];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
-    const int nchunks = 2 * nterms;          // per output row a
-    const int nsteps = 64 * nchunks;         // whole sweep
-    const uint16_t *wq[3] = {w0, w1, w2};
-    const int32_t *terms = cterms + 2 * cl.term0;
+    const int32_t *terms = pd.cterms + 2 * cl.term0;
 
-    for (int x = lane; x < 64 * nterms; x += 64) {
+    for (int x = threadIdx.x; x < 16 * NI * nterms; x += 256) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
-        sTile[r * kMaxClassTerms + e] = citab[cl.itab0 + (int64_t)m * nterms + e];
+        sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    sBlk[lane] = lane < rows && m0 + lane < cl.nblocks ? cblk[cl.blk0 + m0 + lane] : -1;
+    if (threadIdx.x < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
     __syncthreads();
 
-    struct GenRegs { floatx4 u1[2], u2[4][2]; };
-    auto gen_load = [&](int s, GenRegs &r) {
-        const int a = s / nchunks, c = s - a * nchunks;
-        const int e = c >> 1, p0 = 32 * (c & 1) + 8 * lk;
-        const float *s1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + p0;
-        const float *s2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + p0;
-        r.u1[0] = *(const floatx4 *)s1;
-        r.u1[1] = *(const floatx4 *)(s1 + 4);
+    // operand offsets of one term for output row a (lane part included)
+    struct Ptrs { int64_t w[NI]; const float *u1, *u2; };
+    auto ptrs = [&](int a, int e, Ptrs &q) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) q.w[i] = (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 8 * lk;
+        q.u1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 8 * lk;
+        q.u2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + 8 * lk;
+    };
+    struct Frag { bf16x8 w[NI][NP]; floatx4 u1[2], u2[4][2]; };
+    auto load = [&](const Ptrs &q, int h, Frag &f) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int k = 0; k < NP; ++k) f.w[i][k] = load_bf16x8(pd.w[k] + q.w[i] + 32 * h);
+        f.u1[0] = *(const floatx4 *)(q.u1 + 32 * h);
+        f.u1[1] = *(const floatx4 *)(q.u1 + 32 * h + 4);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            r.u2[j][0] = *(const floatx4 *)(s2 + 16 * j * 64);
-            r.u2[j][1] = *(const floatx4 *)(s2 + 16 * j * 64 + 4);
-        }
-    };
-    auto a_load = [&](int s, bf16x8 (&af)[4][NP]) {
-        const int c = s % nchunks;
-        const int e = c >> 1, p0 = 32 * (c & 1) + 8 * lk;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int off = sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + p0;
-#pragma unroll
-            for (int q = 0; q < NP; ++q) af[i][q] = load_bf16x8(wq[q] + off);
+            f.u2[j][0] = *(const floatx4 *)(q.u2 + 16 * j * 64 + 32 * h);
+            f.u2[j][1] = *(const floatx4 *)(q.u2 + 16 * j * 64 + 32 * h + 4);
         }
     };
 
-    doublex4 acc[4][4];
-    floatx4 part[4][4];
+    doublex4 acc[NI][4];
+    floatx4 part[NI][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-            part[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
-
-    // gu holds the B_IJ / B_IK values of step s; once M is formed it is reloaded
-    // with those of step s+2 (same parity).
-    auto step = [&](int s, bf16x8 (&ac)[4][NP], bf16x8 (&an)[4][NP], GenRegs &gu) {
-        a_load(min(s + 1, nsteps - 1), an);
-        // M fragments of this step: rows p (8 per lane), columns b = 16 j + lr
-        bf16x8 bfr[4][NP];
+        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    constexpr int NPROD = NP == 3 ? 6 : 3;
+    auto step = [&](const Frag &f, const Ptrs &qn, int hn, Frag &fn, bool first) {
+        load(qn, hn, fn);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
             u32x4 words[NP];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int h = e >> 1, y = 2 * (e & 1);
+                const int hh = e >> 1, y = 2 * (e & 1);
                 uint32_t parts[NP];
-                split_pair<NP>(gu.u1[h][y] * gu.u2[j][h][y], gu.u1[h][y + 1] * gu.u2[j][h][y + 1], parts);
+                split_pair<NP>(f.u1[hh][y] * f.u2[j][hh][y], f.u1[hh][y + 1] * f.u2[j][hh][y + 1], parts);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) words[q][e] = parts[q];
+                for (int k = 0; k < NP; ++k) words[k][e] = parts[k];
             }
+            bf16x8 bfr[NP];
 #pragma unroll
-            for (int q = 0; q < NP; ++q) bfr[j][q] = __builtin_bit_cast(bf16x8, words[q]);
-        }
-        gen_load(min(s + 2, nsteps - 1), gu);
-        constexpr int NPROD = NP == 3 ? 6 : 3;
-        constexpr int pa3[6] = {1, 2, 0, 1, 0, 0}, pb3[6] = {1, 0, 2, 0, 1, 0};
-        constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
+            for (int k = 0; k < NP; ++k) bfr[k] = __builtin_bit_cast(bf16x8, words[k]);
+            constexpr int pa3[6] = {1, 2, 0, 1, 0, 0}, pb3[6] = {1, 0, 2, 0, 1, 0};
+            constexpr int pa2[3] = {1, 0, 0}, pb2[3] = {0, 1, 0};
 #pragma unroll
-        for (int pr = 0; pr < NPROD; ++pr) {
-            const int qa = NP == 3 ? pa3[pr] : pa2[pr];
-            const int qb = NP == 3 ? pb3[pr] : pb2[pr];
+            for (int pr = 0; pr < NPROD; ++pr) {
+                const int qa = NP == 3 ? pa3[pr] : pa2[pr];
+                const int qb = NP == 3 ? pb3[pr] : pb2[pr];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[i][qa], bfr[j][qb], part[i][j], 0, 0, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x020, 4 * NP, 0);  // W loads of the next step first
-#pragma unroll
-        for (int x = 0; x < 16 * NPROD; ++x) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // three VALU
-        }
-        if (s & 1) {                         // end of a term
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
-                    part[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-                }
-            const int a = s / nchunks;
-            if (s - a * nchunks == nchunks - 1) {   // end of output row a: store, clear
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int blk = sBlk[16 * i + 4 * lk + v];
-                        if (blk >= 0) {
-                            double *o = out + (int64_t)blk * kBlockElems + a * 64 + lr;
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
-                        }
-                    }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+                for (int i = 0; i < NI; ++i)
+                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        f.w[i][qa], bfr[qb], (first && pr == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][j], 0, 0, 0);
             }
         }
+        __builtin_amdgcn_sched_group_barrier(0x020, NI * NP + 10, 0);     // loads first
+        __builtin_amdgcn_sched_group_barrier(0x002, 13 * NP + 2, 0);       // M of columns 0-15
+#pragma unroll
+        for (int x = 0; x < 4 * NPROD * NI; ++x) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);            // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);            // two VALU
+        }
+        __builtin_amdgcn_sched_barrier(0);
     };
 
-    GenRegs gin0, gin1;              // B_IJ / B_IK values of even / odd steps
-    bf16x8 a0[4][NP], a1[4][NP];     // W fragments of even / odd steps
-    gen_load(0, gin0);
-    gen_load(1, gin1);
-    a_load(0, a0);
-    for (int s = 0; s < nsteps; s += 2) {   // nsteps is even
-        step(s, a0, a1, gin0);
-        step(s + 1, a1, a0, gin1);
+    Frag f0, f1;
+    Ptrs qc, qn;
+    int x = 0, e = 0;                    // row index (a = wave + 4 x) and term of this step
+    ptrs(wave, 0, qc);
+    load(qc, 0, f0);
+    for (int it = 0; it < 16 * nterms; ++it) {
+        int ne = e + 1, nx = x;
+        if (ne == nterms) {
+            ne = 0;
+            ++nx;
+        }
+        const int a = wave + 4 * x;
+        if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
+        else qn = qc;                    // past the last row: a harmless reload
+        step(f0, qc, 1, f1, true);
+        step(f1, qn, 0, f0, false);
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
+        if (ne == 0) {                   // end of output row a: store, clear
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int blk = sBlk[16 * i + 4 * lk + v];
+                    if (blk >= 0) {
+                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + lr;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+        }
+        x = nx;
+        e = ne;
+        qc = qn;
     }
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_class_bf16(ProblemDescB pd) {
+    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sBlk[64];
+    const int item = xcd_contiguous_index();
+    const int groups = pd.mtiles[4 * item + 2];
+    if (groups == 4) class_bf16_tile<NP, 4>(pd, item, sTile, sBlk);
+    else if (groups == 2) class_bf16_tile<NP, 2>(pd, item, sTile, sBlk);
+    else class_bf16_tile<NP, 1>(pd, item, sTile, sBlk);
 }
 
 }  // namespace
@@ -756,12 +744,10 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_split_ninv, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,
                        a.npix, a.wsplit[0], a.wsplit[1], a.wsplit[2]);
     const dim3 grid((unsigned)a.nmtiles);
-    if (prec == 2)
-        hipLaunchKernelGGL(k_class_bf16<2>, grid, dim3(64), 0, st, a.mtiles, a.classes, a.class_terms,
-                           a.class_blk, a.class_itab, a.ut32, a.wsplit[0], a.wsplit[1], a.wsplit[2], a.out);
-    else
-        hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(64), 0, st, a.mtiles, a.classes, a.class_terms,
-                           a.class_blk, a.class_itab, a.ut32, a.wsplit[0], a.wsplit[1], a.wsplit[2], a.out);
+    ProblemDescB pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.ut32,
+                    {a.wsplit[0], a.wsplit[1], a.wsplit[2]}, a.out};
+    if (prec == 2) hipLaunchKernelGGL(k_class_bf16<2>, grid, dim3(256), 0, st, pd);
+    else hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(256), 0, st, pd);
     return hipGetLastError();
 }
 
