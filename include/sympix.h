@@ -134,15 +134,21 @@ sympix_status sympix_grid_unique(const sympix_grid *g, int32_t *uid, int32_t *ke
  *            are uniform in s = sqrt(1 - cos gamma) over the pattern's range
  *            (or the radius, if smaller); lookups use 4-point Lagrange
  *            interpolation in s, mirrored at s = 0 where the kernel is even.
- *   stream:  hipStream_t for the device work.
+ *   stream:  hipStream_t for the device work.  The kernel's device tables are
+ *            allocated in stream order on it and the coefficients are copied
+ *            asynchronously, so the call does not wait for the device; work
+ *            on other streams that uses the kernel must be ordered after it.
  * The FP64 recurrence in y = 1 - cos gamma runs on the device; the unique
- * blocks are stored in FP64 and in the split forms the precision modes read.
+ * blocks are stored in FP64 (row-major and transposed) and in FP32.
  * Errors: EINVAL, ESIZE (ncoef < 1), ENOMEM, EHIP. */
 sympix_status sympix_kernel_tabulate(const sympix_grid *g, const double *coef_l, int32_t ncoef,
                                      double radius, int32_t n_nodes, void *stream,
                                      sympix_kernel **out);
 
-/* Free a kernel. NULL is ignored.  No call using it may be in flight. */
+/* Free a kernel. NULL is ignored.  The device memory is released in stream
+ * order on the null stream (after the work already queued on blocking
+ * streams); work on non-blocking streams that uses the kernel must have
+ * completed. */
 void sympix_kernel_destroy(sympix_kernel *kr);
 
 /* Evaluate the tabulated kernel (with its radial cut) at n arguments

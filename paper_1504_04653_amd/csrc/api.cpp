@@ -95,6 +95,7 @@ struct sympix_kernel {
     double *u64 = nullptr;
     float *ut32 = nullptr;
     double *u64t = nullptr;
+    void *block = nullptr;    // one stream-ordered allocation holding all of the above
 };
 
 namespace {
@@ -167,13 +168,60 @@ sympix::KTable ktable(const sympix_kernel *kr) {
     return kt;
 }
 
+// Stream-ordered release on the null stream: it follows all work already
+// queued on blocking streams and does not stall the host.
 void free_kernel(sympix_kernel *kr) {
-    hipFree(kr->coef);
-    hipFree(kr->table);
-    hipFree(kr->u64);
-    hipFree(kr->ut32);
-    hipFree(kr->u64t);
+    if (kr->block) {
+        int cur = 0;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        if (have && cur != kr->device) hipSetDevice(kr->device);
+        hipFreeAsync(kr->block, nullptr);
+        if (have && cur != kr->device) hipSetDevice(cur);
+    }
     delete kr;
+}
+
+// Pinned staging slots for the coefficient upload, so that it is an
+// asynchronous copy in stream order (a pageable copy would wait for the
+// device).  A slot is reused only after its previous copy has completed.
+struct CoefSlot {
+    double *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+std::mutex g_coef_mu;
+std::map<int, std::vector<CoefSlot>> g_coef_slots;   // per device
+std::map<int, size_t> g_coef_next;
+
+hipError_t upload_coefficients(int device, const std::vector<double> &coef, double *dst, hipStream_t st) {
+    std::lock_guard<std::mutex> lock(g_coef_mu);
+    auto &ring = g_coef_slots[device];
+    if (ring.empty()) ring.resize(8);
+    CoefSlot &slot = ring[g_coef_next[device]++ % ring.size()];
+    hipError_t e = hipSuccess;
+    if (slot.pending) {
+        e = hipEventSynchronize(slot.done);
+        if (e != hipSuccess) return e;
+        slot.pending = false;
+    }
+    if (!slot.done) {
+        e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    if (slot.cap < coef.size()) {
+        if (slot.host) hipHostFree(slot.host);
+        slot.host = nullptr;
+        slot.cap = 0;
+        e = hipHostMalloc((void **)&slot.host, coef.size() * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        slot.cap = coef.size();
+    }
+    std::memcpy(slot.host, coef.data(), coef.size() * sizeof(double));
+    e = hipMemcpyAsync(dst, slot.host, coef.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(slot.done, st);
+    if (e == hipSuccess) slot.pending = true;
+    return e;
 }
 
 sympix_status check_kernel_use(const sympix_grid *g, const sympix_kernel *kr) {
@@ -326,18 +374,28 @@ sympix_status sympix_kernel_tabulate(const sympix_grid *g, const double *coef_l,
     std::vector<double> coef(lmax + 1, 0.0);
     for (int32_t l = 0; l <= lmax && l < ncoef; ++l) coef[l] = coef_l[l];
     const size_t nu = (size_t)geo.nunique() * sympix::kBlockElems;
-    e = hipMalloc((void **)&kr->coef, coef.size() * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&kr->table, (size_t)n_nodes * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&kr->u64, nu * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&kr->ut32, nu * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc((void **)&kr->u64t, nu * sizeof(double));
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_table = up(coef.size() * sizeof(double));
+    const size_t o_u64 = o_table + up((size_t)n_nodes * sizeof(double));
+    const size_t o_u64t = o_u64 + up(nu * sizeof(double));
+    const size_t o_ut32 = o_u64t + up(nu * sizeof(double));
+    const size_t total = o_ut32 + up(nu * sizeof(float));
+    e = hipMallocAsync(&kr->block, total, st);
     if (e != hipSuccess) {
+        kr->block = nullptr;
         free_kernel(kr);
         return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the kernel failed")
-                                        : hip_fail(e, "hipMalloc");
+                                        : hip_fail(e, "hipMallocAsync");
     }
-    e = hipMemcpy(kr->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice);
+    char *base = (char *)kr->block;
+    kr->coef = (double *)base;
+    kr->table = (double *)(base + o_table);
+    kr->u64 = (double *)(base + o_u64);
+    kr->u64t = (double *)(base + o_u64t);
+    kr->ut32 = (float *)(base + o_ut32);
+    e = upload_coefficients(device, coef, kr->coef, st);
     if (e != hipSuccess) {
+        hipStreamSynchronize(st);
         free_kernel(kr);
         return hip_fail(e, "copying coefficients");
     }
