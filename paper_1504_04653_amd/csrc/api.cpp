@@ -51,6 +51,7 @@ struct DevGrid {
     int32_t *class_blk = nullptr;
     int32_t *class_itab = nullptr;
     int32_t *mtiles = nullptr;
+    int32_t *wtiles = nullptr;
 };
 
 template <class T>
@@ -74,6 +75,7 @@ void free_dev(DevGrid &d) {
     hipFree(d.class_blk);
     hipFree(d.class_itab);
     hipFree(d.mtiles);
+    hipFree(d.wtiles);
     d = DevGrid();
 }
 
@@ -140,6 +142,7 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.class_blk, geo.class_blk.data(), geo.class_blk.size());
     if (e == hipSuccess) e = upload(&d.class_itab, geo.class_itab.data(), geo.class_itab.size());
     if (e == hipSuccess) e = upload(&d.mtiles, geo.mtiles.data(), geo.mtiles.size());
+    if (e == hipSuccess) e = upload(&d.wtiles, geo.wtiles.data(), geo.wtiles.size());
     if (e != hipSuccess) {
         free_dev(d);
         return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for grid tables failed")
@@ -469,6 +472,8 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
     a.class_itab = dg->class_itab;
     a.mtiles = dg->mtiles;
     a.nmtiles = (int64_t)geo.mtiles.size() / 4;
+    a.wtiles = dg->wtiles;
+    a.nwtiles = (int64_t)geo.wtiles.size() / 4;
     a.nblocks = geo.nblocks();
     a.npix = geo.npix;
     a.ninv = ninv_dev;

@@ -551,45 +551,58 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // the FP64 accumulators after its second step.
 template <int NP, int NI>
 __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item, int32_t *sTile,
-                                                int32_t *sBlk) {
+                                                int32_t *sBlk, u16x8 *sW, floatx4 *sU) {
     const float *__restrict__ ut32 = pd.ut32;
     double *__restrict__ out = pd.out;
     const int cls = pd.mtiles[4 * item], m0 = pd.mtiles[4 * item + 1];
     const DevClass cl = pd.classes[cls];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
     const int32_t *terms = pd.cterms + 2 * cl.term0;
 
-    for (int x = threadIdx.x; x < 16 * NI * nterms; x += 256) {
+    for (int x = tid; x < 16 * NI * nterms; x += 256) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    if (threadIdx.x < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+    if (tid < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
     __syncthreads();
 
-    // operand offsets of one term for output row a (lane part included)
-    struct Ptrs { int64_t w[NI]; const float *u1, *u2; };
-    auto ptrs = [&](int a, int e, Ptrs &q) {
+    // Staging of the operands every wave shares (they do not depend on the
+    // output row): W of the tile's rows and the B_IK values of 32 pixels of one
+    // term, loaded by the whole workgroup with 16-byte loads (4 threads per row
+    // and part for W, 8 per row for B_IK) and written to an LDS buffer.
+    const int srow = tid >> 2, ssub = tid & 3;                  // W: row, 16-byte chunk
+    struct Stage { u16x8 w[NP]; floatx4 u[2]; };
+    auto stage_load = [&](int e, int h, Stage &st) {
+        if (srow < 16 * NI) {
+            const int64_t o = (int64_t)sTile[srow * kMaxClassTerms + e] * 64 + 32 * h + 8 * ssub;
 #pragma unroll
-        for (int i = 0; i < NI; ++i) q.w[i] = (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 8 * lk;
-        q.u1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 8 * lk;
-        q.u2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + 8 * lk;
-    };
-    struct Frag { bf16x8 w[NI][NP]; floatx4 u1[2], u2[4][2]; };
-    auto load = [&](const Ptrs &q, int h, Frag &f) {
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int k = 0; k < NP; ++k) f.w[i][k] = load_bf16x8(pd.w[k] + q.w[i] + 32 * h);
-        f.u1[0] = *(const floatx4 *)(q.u1 + 32 * h);
-        f.u1[1] = *(const floatx4 *)(q.u1 + 32 * h + 4);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            f.u2[j][0] = *(const floatx4 *)(q.u2 + 16 * j * 64 + 32 * h);
-            f.u2[j][1] = *(const floatx4 *)(q.u2 + 16 * j * 64 + 32 * h + 4);
+            for (int k = 0; k < NP; ++k) st.w[k] = *(const u16x8 *)(pd.w[k] + o);
         }
+        const float *u2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + 32 * h;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q;
+            st.u[q] = *(const floatx4 *)(u2 + (c >> 3) * 64 + 4 * (c & 7));
+        }
+    };
+    auto stage_store = [&](const Stage &st, int buf) {
+        if (srow < 16 * NI) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) sW[((buf * NP + k) * 64 + srow) * 4 + ssub] = st.w[k];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) sU[buf * 512 + tid + 256 * q] = st.u[q];
+    };
+    // B_IJ values of this wave's output row (not shared)
+    struct Own { floatx4 u1[2]; };
+    auto own_load = [&](int a, int e, int h, Own &o) {
+        const float *p1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 32 * h + 8 * lk;
+        o.u1[0] = *(const floatx4 *)p1;
+        o.u1[1] = *(const floatx4 *)(p1 + 4);
     };
 
     doublex4 acc[NI][4];
@@ -599,19 +612,32 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
     constexpr int NPROD = NP == 3 ? 6 : 3;
-    auto step = [&](const Frag &f, const Ptrs &qn, int hn, Frag &fn, bool first) {
-        load(qn, hn, fn);
+    // One step: the workgroup's loads for the next step go out first; then the
+    // MFMAs of this step from LDS buffer buf (W fragments, and M formed from the
+    // staged B_IK values and this wave's B_IJ values); the next step's staged
+    // operands are written to the other buffer; one barrier.
+    auto step = [&](const Own &oc, int buf, int en, int hn, Stage &stn, bool first) {
+        stage_load(en, hn, stn);
+        bf16x8 wf[NI][NP];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                wf[i][k] = __builtin_bit_cast(bf16x8, sW[((buf * NP + k) * 64 + 16 * i + lr) * 4 + lk]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+            const floatx4 u2a = sU[buf * 512 + (16 * j + lr) * 8 + 2 * lk];
+            const floatx4 u2b = sU[buf * 512 + (16 * j + lr) * 8 + 2 * lk + 1];
             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
             u32x4 words[NP];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int hh = e >> 1, y = 2 * (e & 1);
+            for (int q = 0; q < 4; ++q) {
+                const int hh = q >> 1, y = 2 * (q & 1);
+                const floatx4 &u2 = hh ? u2b : u2a;
                 uint32_t parts[NP];
-                split_pair<NP>(f.u1[hh][y] * f.u2[j][hh][y], f.u1[hh][y + 1] * f.u2[j][hh][y + 1], parts);
+                split_pair<NP>(oc.u1[hh][y] * u2[y], oc.u1[hh][y + 1] * u2[y + 1], parts);
 #pragma unroll
-                for (int k = 0; k < NP; ++k) words[k][e] = parts[k];
+                for (int k = 0; k < NP; ++k) words[k][q] = parts[k];
             }
             bf16x8 bfr[NP];
 #pragma unroll
@@ -625,24 +651,27 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 #pragma unroll
                 for (int i = 0; i < NI; ++i)
                     part[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        f.w[i][qa], bfr[qb], (first && pr == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][j], 0, 0, 0);
+                        wf[i][qa], bfr[qb], (first && pr == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][j], 0, 0, 0);
             }
         }
-        __builtin_amdgcn_sched_group_barrier(0x020, NI * NP + 10, 0);     // loads first
-        __builtin_amdgcn_sched_group_barrier(0x002, 13 * NP + 2, 0);       // M of columns 0-15
+        stage_store(stn, buf ^ 1);
+        __builtin_amdgcn_sched_group_barrier(0x020, NP + 4, 0);             // global loads first
+        __builtin_amdgcn_sched_group_barrier(0x100, NI * NP + 8, 0);        // LDS operand reads
 #pragma unroll
         for (int x = 0; x < 4 * NPROD * NI; ++x) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);            // one MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);            // two VALU
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);             // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);             // two VALU
         }
-        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
     };
 
-    Frag f0, f1;
-    Ptrs qc, qn;
-    int x = 0, e = 0;                    // row index (a = wave + 4 x) and term of this step
-    ptrs(wave, 0, qc);
-    load(qc, 0, f0);
+    Stage sa, sb;
+    Own o0, o1;
+    int x = 0, e = 0;                    // row index (a = wave + 4 x) and term
+    stage_load(0, 0, sa);
+    stage_store(sa, 0);
+    own_load(wave, 0, 0, o0);
+    __syncthreads();
     for (int it = 0; it < 16 * nterms; ++it) {
         int ne = e + 1, nx = x;
         if (ne == nterms) {
@@ -650,10 +679,12 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
             ++nx;
         }
         const int a = wave + 4 * x;
-        if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
-        else qn = qc;                    // past the last row: a harmless reload
-        step(f0, qc, 1, f1, true);
-        step(f1, qn, 0, f0, false);
+        const bool last = nx >= 16;      // past the last row: harmless reloads of this term
+        const int la = last ? a : wave + 4 * nx, le = last ? e : ne;
+        own_load(a, e, 1, o1);
+        step(o0, 0, e, 1, sb, true);
+        own_load(la, le, 0, o0);
+        step(o1, 1, le, 0, sa, false);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -679,7 +710,6 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         }
         x = nx;
         e = ne;
-        qc = qn;
     }
 }
 
@@ -688,11 +718,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[64];
+    __shared__ u16x8 sW[2 * NP * 64 * 4];            // staged W, two buffers
+    __shared__ floatx4 sU[2 * 512];                  // staged B_IK values, two buffers
     const int item = xcd_contiguous_index();
     const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_bf16_tile<NP, 4>(pd, item, sTile, sBlk);
-    else if (groups == 2) class_bf16_tile<NP, 2>(pd, item, sTile, sBlk);
-    else class_bf16_tile<NP, 1>(pd, item, sTile, sBlk);
+    if (groups == 4) class_bf16_tile<NP, 4>(pd, item, sTile, sBlk, sW, sU);
+    else if (groups == 2) class_bf16_tile<NP, 2>(pd, item, sTile, sBlk, sW, sU);
+    else class_bf16_tile<NP, 1>(pd, item, sTile, sBlk, sW, sU);
 }
 
 }  // namespace
