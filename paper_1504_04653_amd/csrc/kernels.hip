@@ -589,13 +589,21 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
             st.u[q] = *(const floatx4 *)(u2 + (c >> 3) * 64 + 4 * (c & 7));
         }
     };
+    // LDS layouts, in 16-byte chunks: W row r (64 bytes) keeps its chunk c at
+    // 4 r + (c ^ ((r >> 1) & 3)), a B_IK row b (128 bytes) its chunk c at
+    // 8 b + (c ^ (b & 7)), so the 8 lanes of every LDS access phase, reading
+    // or writing, touch 8 different bank groups
     auto stage_store = [&](const Stage &st, int buf) {
         if (srow < 16 * NI) {
 #pragma unroll
-            for (int k = 0; k < NP; ++k) sW[((buf * NP + k) * 64 + srow) * 4 + ssub] = st.w[k];
+            for (int k = 0; k < NP; ++k)
+                sW[((buf * NP + k) * 64 + srow) * 4 + (ssub ^ ((srow >> 1) & 3))] = st.w[k];
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) sU[buf * 512 + tid + 256 * q] = st.u[q];
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q, b = c >> 3;
+            sU[buf * 512 + b * 8 + ((c & 7) ^ (b & 7))] = st.u[q];
+        }
     };
     // B_IJ values of this wave's output row (not shared)
     struct Own { floatx4 u1[2]; };
@@ -623,11 +631,12 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         for (int i = 0; i < NI; ++i)
 #pragma unroll
             for (int k = 0; k < NP; ++k)
-                wf[i][k] = __builtin_bit_cast(bf16x8, sW[((buf * NP + k) * 64 + 16 * i + lr) * 4 + lk]);
+                wf[i][k] = __builtin_bit_cast(bf16x8, sW[((buf * NP + k) * 64 + 16 * i + lr) * 4 + (lk ^ ((lr >> 1) & 3))]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const floatx4 u2a = sU[buf * 512 + (16 * j + lr) * 8 + 2 * lk];
-            const floatx4 u2b = sU[buf * 512 + (16 * j + lr) * 8 + 2 * lk + 1];
+            const int b = 16 * j + lr;
+            const floatx4 u2a = sU[buf * 512 + b * 8 + ((2 * lk) ^ (b & 7))];
+            const floatx4 u2b = sU[buf * 512 + b * 8 + ((2 * lk + 1) ^ (b & 7))];
             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
             u32x4 words[NP];
 #pragma unroll
