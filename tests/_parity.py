@@ -11,7 +11,10 @@ from workloads import synth as S
 
 def gate(C, ref, rows):
     """max |C - ref| / M_J with M_J the largest |ref| over the compared blocks of
-    block-row J (rows[n] is the J of block n)."""
+    block-row J (rows[n] is the J of block n); infinite if any value is not
+    finite (a NaN would otherwise drop out of the maximum)."""
+    if not (np.isfinite(C).all() and np.isfinite(ref).all()):
+        return float("inf")
     rows = np.asarray(rows)
     mj = {}
     for n, J in enumerate(rows):
@@ -35,7 +38,8 @@ def error_report(C, ref, rows):
     # rows whose blocks are all zero (fully masked N^-1) compare absolutely
     rel = np.abs(C - ref) / np.maximum(np.maximum(np.abs(ref), 1e-8 * scale), 1e-300)
     return {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
-            "max": float(rel.max()), "gate": gate(C, ref, rows)}
+            "max": float(rel.max()), "gate": gate(C, ref, rows),
+            "nonfinite": int(np.size(C) - np.count_nonzero(np.isfinite(C)))}
 
 
 def stored_pairs(g: G.Grid):
