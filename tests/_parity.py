@@ -36,7 +36,8 @@ def error_report(C, ref, rows):
         mj[J] = max(mj.get(J, 0.0), float(np.abs(ref[n]).max()))
     scale = np.array([mj[J] for J in rows])[:, None, None]
     # rows whose blocks are all zero (fully masked N^-1) compare absolutely
-    rel = np.abs(C - ref) / np.maximum(np.maximum(np.abs(ref), 1e-8 * scale), 1e-300)
+    with np.errstate(invalid="ignore"):
+        rel = np.abs(C - ref) / np.maximum(np.maximum(np.abs(ref), 1e-8 * scale), 1e-300)
     return {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
             "max": float(rel.max()), "gate": gate(C, ref, rows),
             "nonfinite": int(np.size(C) - np.count_nonzero(np.isfinite(C)))}
