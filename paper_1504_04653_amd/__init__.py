@@ -20,6 +20,11 @@ if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is missing: build it with paper_1504_04653_amd.build.build() "
                       "(or __graft_entry__.build()); there is no fallback path")
 
+# torch is imported before the library is loaded so that the library binds to
+# the HIP runtime torch already carries: two HIP / HSA runtimes in one process
+# do not share the device (the second one finds none).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(_LIB_PATH)
 
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3

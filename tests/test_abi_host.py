@@ -130,3 +130,19 @@ def test_grid_handles_are_independent():
     b = sp.Grid(100, 8)
     del a
     assert b.rings()[0].shape == (112,)
+
+
+def test_one_hip_runtime_in_the_process():
+    """Importing the binding must leave exactly one HIP runtime mapped (the
+    one torch carries); a second copy would not see the device."""
+    import subprocess
+    import sys
+    code = ("import paper_1504_04653_amd, torch\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
+
