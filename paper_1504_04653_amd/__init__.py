@@ -154,7 +154,7 @@ class Grid:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _grid_destroy is not None:   # None at interpreter exit
             _grid_destroy(h)
             self._h = None
 
@@ -232,7 +232,7 @@ class Kernel:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _kernel_destroy is not None:
             _kernel_destroy(h)
             self._h = None
 
@@ -294,7 +294,7 @@ class Batch:
 
     def close(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _batch_destroy is not None:
             _batch_destroy(h)
             self._h = None
 

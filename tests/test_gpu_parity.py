@@ -207,6 +207,38 @@ def test_transition_grid_all_blocks():
     assert rep["gate"] <= GATE["fp64"]
 
 
+# --- degenerate grids: one or two bands per hemisphere, bands of 1-3 tiles ------
+
+@pytest.mark.parametrize("lmax", [1, 7, 8, 15, 16, 40])
+def test_tiny_grids_all_blocks(lmax):
+    og = G.make_grid(lmax, 8)
+    g = sp.Grid(lmax, 8)
+    rng = np.random.default_rng(1000 + lmax)
+    ninv = rng.uniform(0.5, 2.0, g.npix)
+    b_l, R = S.gaussian_beam(lmax, g.npix, 3.0)
+    pairs = stored_pairs(og)
+    rows = [J for J, _ in pairs]
+    say(f"[tiny {lmax}] npix={g.npix} nblocks={g.nblocks} tiles={list(og.tiles_north)}")
+    kb = sp.Kernel(g, b_l, R)
+    Cref = O.sample_BtNB(og, b_l, ninv, R, pairs)
+    n_dev = dev(ninv)
+    zero = torch.zeros(g.npix, dtype=torch.float64, device="cuda")
+    for prec in ("fp64", "fp32", "bf16x6", "bf16x3"):
+        C = run_BtNB(g, kb, n_dev, prec).cpu().numpy()
+        rep = error_report(C, Cref, rows)
+        say(f"[tiny {lmax}] BtNB {prec}: {rep}")
+        assert rep["gate"] <= GATE[prec]
+        # N^-1 = 0 everywhere: every mode returns exact zeros
+        Z = run_BtNB(g, kb, zero, prec)
+        assert int(torch.count_nonzero(Z)) == 0
+    kd = sp.Kernel(g, S.prior(lmax), 0.0)
+    D = run_D(g, kd).cpu().numpy()
+    Dref = O.sample_D(og, S.prior(lmax), None, pairs)
+    rep = error_report(D, Dref, rows)
+    say(f"[tiny {lmax}] D fp64: {rep}")
+    assert rep["gate"] <= GATE["fp64"]
+
+
 # --- full-size configurations, sampled block-rows ------------------------------
 
 @pytest.mark.parametrize("name,modes,n_random", [("c2", ("fp64", "bf16x6"), 24),
