@@ -14,6 +14,9 @@ Definitions followed
   because B-hat(p, q) vanishes unless tile(p) neighbours tile(q).  The stored
   blocks are the pairs (J, K) with K a neighbour of J and K >= J (the pattern
   of D-hat), each k^2 x k^2, rows and columns in tile-local order c*k + r.
+* Section 4.1 (pixel-domain convolution): g_i = sum_j b(n_i . n_j) f_j, a plain
+  sum over the samples j whose tile neighbours the tile of i (no quadrature
+  weights), i.e. g = B-hat f; blockwise g_J = sum_{K in nbr(J)} B_JK f_K.
 * Section 2.3 / 4.1: a block depends on the two tiles only through their
   bands and the exact rational phi offset between them, so blocks are cached
   on the key (band_I, band_J, (t_J T_I - t_I T_J) mod T_I T_J).  The brute
@@ -162,3 +165,23 @@ def sample_BtNB(g: Grid, b_l, ninv, radius=None, pairs=None):
     if not pairs:
         return np.zeros((0, g.k ** 2, g.k ** 2))
     return np.stack([btnb_block(op, ninv, J, K) for J, K in pairs])
+
+
+def convolve(g: Grid, b_l, f, radius=None, tiles=None):
+    """Pixel-domain convolution of Section 4.1, g = B-hat f: for every output
+    tile J, g_J = sum_{K in nbr(J)} B_JK f_K with the local blocks above (f and
+    g in pixel order).  tiles: the output tiles to compute (all by default);
+    returns an array (len(tiles), k^2)."""
+    f = np.asarray(f, dtype=np.float64)
+    op = LocalOperator(g, b_l, radius)
+    k2 = g.k ** 2
+    if tiles is None:
+        tiles = range(g.ntiles)
+    out = []
+    for J in tiles:
+        acc = np.zeros(k2)
+        for K in op.neighbours(J):
+            acc += op.block(J, K) @ f[K * k2:(K + 1) * k2]
+        out.append(acc)
+    return np.stack(out) if out else np.zeros((0, k2))
+
