@@ -19,8 +19,11 @@ all 32 problems of the batched workload (lmax 256/512/1024/2048, FP32 MFMA with
 FP64 accumulation across contraction tiles; 172 GB of output); the beam kernels
 are tabulated before the timed region and the schedule is autotuned first.
 
+With --op conv a step is one pixel-domain convolution g = B-hat f (FP64) of
+the configuration's grid and beam.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c5]
-                       [--modes bf16x6,fp64,bf16x3] [--no-cpu-baseline]
+                       [--op btnb|conv] [--modes bf16x6,fp64,bf16x3] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -52,6 +55,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c4")
+    ap.add_argument("--op", default="btnb", choices=["btnb", "conv"],
+                    help="btnb: the D-hat / B-hat^T N^-1 B-hat step (default); conv: the pixel-domain "
+                         "convolution g = B-hat f")
     ap.add_argument("--modes", default="bf16x6,fp64,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -233,6 +239,95 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_baseline_conv(cfg, budget_s):
+    """The oracle's convolution on random output tiles until the budget is spent."""
+    from oracle import grid as G
+    from oracle import operators as O
+    from workloads import synth as S
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    og = G.make_grid(cfg.lmax, cfg.k)
+    f = np.random.default_rng(1).standard_normal(og.npix)
+    b_l, R = S.gaussian_beam(cfg.lmax, og.npix, cfg.fwhm_pix)
+    op = O.LocalOperator(og, b_l, R)
+    rng = np.random.default_rng(3)
+    t0 = time.perf_counter()
+    ntiles = 0
+    k2 = og.k ** 2
+    while time.perf_counter() - t0 < budget_s:
+        J = int(rng.integers(og.ntiles))
+        acc = np.zeros(k2)
+        for K in op.neighbours(J):
+            acc += op.block(J, K) @ f[K * k2:(K + 1) * k2]
+        ntiles += 1
+    dt = time.perf_counter() - t0
+    return {"value": ntiles * k2 / dt, "unit": "pixels/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{ntiles} random output tiles of the lmax={cfg.lmax} convolution, "
+                      f"unique blocks evaluated on first use, {dt:.1f} s wall"}
+
+
+def run_conv(args):
+    import torch
+
+    import paper_1504_04653_amd as sp
+    from workloads import synth as S
+
+    cfg = S.CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    g = sp.Grid(cfg.lmax, cfg.k)
+    b_l, R = S.gaussian_beam(cfg.lmax, g.npix, cfg.fwhm_pix)
+    stream = torch.cuda.current_stream()
+    kb = sp.Kernel(g, b_l, R, stream=stream)
+    f = torch.as_tensor(np.random.default_rng(1).standard_normal(g.npix)).cuda()
+    out = torch.empty(g.npix, dtype=torch.float64, device="cuda")
+    pairs = g.nadjacency
+    alg_flop = 2.0 * 64 * 64 * pairs
+    for _ in range(args.warmup):
+        sp.convolve(g, kb, f, out, stream=stream)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t_start = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(args.steps):
+        sp.convolve(g, kb, f, out, stream=stream)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    ms_step = wall * 1000.0 / args.steps
+    achieved = alg_flop / (ms.mean() * 1e-3) / 1e12
+    hbm = 16.0 * g.npix / (ms.mean() * 1e-3) / 1e9
+    print(f"# conv {args.config}: lmax={cfg.lmax} npix={g.npix} neighbour pairs={pairs}; "
+          f"{ms.mean():.3f} ms per call, {achieved:.1f} TFLOP/s ({achieved / PEAK['fp64'] * 100:.1f}% of FP64 "
+          f"MFMA peak), f+g {hbm:.0f} GB/s", file=sys.stderr, flush=True)
+    line = {
+        "metric": "pixel-domain convolution g = B-hat f, output pixels/s",
+        "value": g.npix / (ms_step * 1e-3),
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"sympix lmax={cfg.lmax} k={cfg.k} beam FWHM {cfg.fwhm_pix:g} px cut 3 FWHM, "
+                               f"f ~ N(0,1) seed 1",
+                   "lmax": cfg.lmax, "npix": g.npix, "neighbour_pairs": int(pairs)},
+        "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK["fp64"], "achieved": achieved,
+                     "frac": achieved / PEAK["fp64"], "kernel": "k_convolve",
+                     "traffic": recorded_traffic("conv", args.config)},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_conv(cfg, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -241,6 +336,9 @@ def main():
         sys.exit(2)
     if args.config == "c5":
         run_batch(args)
+        return
+    if args.op == "conv":
+        run_conv(args)
         return
     import torch
 

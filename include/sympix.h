@@ -165,6 +165,17 @@ sympix_status sympix_kernel_eval(const sympix_kernel *kr, const double *y_dev, d
 sympix_status sympix_sample_D(const sympix_grid *g, const sympix_kernel *d, double *out_dev,
                               int64_t out_len, void *stream);
 
+/* Pixel-domain convolution (Section 4.1): out_i = sum_j b(n_i . n_j) f_j over
+ * the pairs whose tiles are the same or neighbouring (and within the kernel's
+ * radius), i.e. out = B-hat f with the local blocks of kernel b; a plain sum
+ * over samples, no quadrature weights.  f_dev and out_dev: device, float64,
+ * npix values in pixel order, 16-byte aligned, not overlapping.  FP64
+ * throughout, bitwise reproducible run to run.
+ * Errors: EINVAL (NULL, overlap, misalignment, kernel of another grid), ESIZE
+ * (f_len or out_len != npix), EUNSUPPORTED (k != 8), EHIP. */
+sympix_status sympix_convolve(const sympix_grid *g, const sympix_kernel *b, const double *f_dev,
+                              int64_t f_len, double *out_dev, int64_t out_len, void *stream);
+
 /* Stored blocks of B-hat^T N^-1 B-hat (Eq. 15):
  *   C_JK = sum_{I in nbr(J) & nbr(K)} B_IJ^T diag(ninv_I) B_IK,
  * with ninv_dev (device, float64, npix values in pixel order, 32-byte aligned,

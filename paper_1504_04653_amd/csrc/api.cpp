@@ -52,6 +52,8 @@ struct DevGrid {
     int32_t *class_itab = nullptr;
     int32_t *mtiles = nullptr;
     int32_t *wtiles = nullptr;
+    int32_t *conv_chunks = nullptr;
+    int32_t *conv_slots = nullptr;
 };
 
 template <class T>
@@ -76,6 +78,8 @@ void free_dev(DevGrid &d) {
     hipFree(d.class_itab);
     hipFree(d.mtiles);
     hipFree(d.wtiles);
+    hipFree(d.conv_chunks);
+    hipFree(d.conv_slots);
     d = DevGrid();
 }
 
@@ -143,6 +147,8 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.class_itab, geo.class_itab.data(), geo.class_itab.size());
     if (e == hipSuccess) e = upload(&d.mtiles, geo.mtiles.data(), geo.mtiles.size());
     if (e == hipSuccess) e = upload(&d.wtiles, geo.wtiles.data(), geo.wtiles.size());
+    if (e == hipSuccess) e = upload(&d.conv_chunks, geo.conv_chunks.data(), geo.conv_chunks.size());
+    if (e == hipSuccess) e = upload(&d.conv_slots, geo.conv_slots.data(), geo.conv_slots.size());
     if (e != hipSuccess) {
         free_dev(d);
         return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for grid tables failed")
@@ -443,6 +449,26 @@ sympix_status sympix_sample_D(const sympix_grid *g, const sympix_kernel *d, doub
     hipStream_t st = (hipStream_t)stream;
     return after_launch(sympix::launch_expand(d->u64, dg->exp_items, (int64_t)geo.exp_items.size() / 4, dg->exp_blk, out_dev, st), st,
                         "sample_D");
+}
+
+sympix_status sympix_convolve(const sympix_grid *g, const sympix_kernel *b, const double *f_dev,
+                              int64_t f_len, double *out_dev, int64_t out_len, void *stream) {
+    sympix_status s = check_kernel_use(g, b);
+    if (s != SYMPIX_OK) return s;
+    const Geometry &geo = g->geo;
+    if (f_len != geo.npix || out_len != geo.npix) return fail(SYMPIX_ESIZE, "f_len and out_len must be npix");
+    if (geo.npix > 0 && (!f_dev || !out_dev)) return fail(SYMPIX_EINVAL, "NULL device buffer");
+    if (((uintptr_t)f_dev) % 16 || ((uintptr_t)out_dev) % 16)
+        return fail(SYMPIX_EINVAL, "f_dev and out_dev must be 16-byte aligned");
+    if (f_dev && out_dev && f_dev < out_dev + out_len && out_dev < f_dev + f_len)
+        return fail(SYMPIX_EINVAL, "f_dev and out_dev overlap");
+    const DevGrid *dg = nullptr;
+    s = device_tables(g, b->device, &dg);
+    if (s != SYMPIX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    return after_launch(sympix::launch_convolve(b->u64, dg->conv_chunks, (int64_t)geo.conv_chunks.size() / 4,
+                                                dg->conv_slots, f_dev, out_dev, st),
+                        st, "convolve");
 }
 
 sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,

@@ -48,6 +48,9 @@ hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, co
 // block uid into the stored blocks exp_blk[first .. first + count)
 hipError_t launch_expand(const double *u64, const int32_t *items, int64_t nitems, const int32_t *exp_blk,
                          double *out, hipStream_t st);
+// pixel-domain convolution g = B-hat f over chunks of 16 output tiles
+hipError_t launch_convolve(const double *u64, const int32_t *chunks, int64_t nchunks, const int32_t *slots,
+                           const double *f, double *g, hipStream_t st);
 // a9: B-hat^T N^-1 B-hat contraction
 struct BtnbArgs {
     const double *u64t;

@@ -80,6 +80,12 @@ struct Geometry {
                                         // 1, 2, 4, 8 or 16), for the split-BF16 GEMM
     int32_t max_class_terms = 0;
 
+    // convolution g = B-hat f: chunks of up to 16 consecutive output tiles of
+    // one band {first tile, tiles, first slot, slots}; per slot a unique block
+    // and, for each of the 16 tiles, the input tile K it multiplies (-1: none)
+    std::vector<int32_t> conv_chunks;   // 4 per chunk
+    std::vector<int32_t> conv_slots;    // 17 per slot: uid, K[16]
+
     double y_pattern_max = 0.0;   // max 1 - cos(gamma) over all pattern pairs
 
     int64_t nblocks() const { return (int64_t)blk_col.size(); }

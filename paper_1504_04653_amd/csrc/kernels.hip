@@ -6,6 +6,8 @@
 //                  pair geometry, table lookup, radial cut; writes FP64
 //                  row-major and FP64 / FP32 copies transposed via LDS
 //   k_expand       D-hat: streams each stored block from its unique block
+//   k_convolve     pixel-domain convolution g = B-hat f, one FP64 GEMM per
+//                  unique block over 16 output tiles
 //   k_class_f64    B-hat^T N^-1 B-hat (Eq. 15) in FP64 as one GEMM per class of
 //                  blocks that share their contraction pattern
 //   k_ninv_f32     N^-1 rounded to FP32
@@ -158,6 +160,67 @@ __global__ __launch_bounds__(256) void k_expand(const double *__restrict__ u64,
         doublex2 *dst = (doublex2 *)(out + (int64_t)exp_blk[first + n] * kBlockElems);
 #pragma unroll
         for (int j = 0; j < 8; ++j) __builtin_nontemporal_store(v[j], &dst[threadIdx.x + 256 * j]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pixel-domain convolution g = B-hat f (Section 4.1): g_J = sum_{K in nbr(J)}
+// B_JK f_K.  One wave per chunk of 16 consecutive output tiles of a band.  For
+// every unique block u the chunk uses, one FP64 GEMM C += U_u F_u with
+// C[p][j] the outputs of tile J0 + j and F_u[q][j] = f of the input tile that
+// tile J0 + j multiplies with u (zero when it does not), so each unique block
+// is read once per 16 tiles.  MFMA 16x16x4 FP64 with contraction index
+// q = 16 lk + ks: lane (lr, lk) holds U[16 i + lr][16 lk + ks] and
+// F[16 lk + ks][lr]; its result holds rows 16 i + lk + 4 v of column lr.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_convolve(const double *__restrict__ u64, const int32_t *__restrict__ chunks,
+                const int32_t *__restrict__ slots, const double *__restrict__ f, double *__restrict__ g) {
+    const int ch = xcd_contiguous_index();
+    const int J0 = chunks[4 * ch], n = chunks[4 * ch + 1];
+    const int s0 = chunks[4 * ch + 2], ns = chunks[4 * ch + 3];
+    const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
+    doublex4 c[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int sl = 0; sl < ns; ++sl) {
+        const int32_t *slot = slots + 17 * (int64_t)(s0 + sl);
+        const int uid = slot[0];
+        const int K = slot[1 + lr];
+        double bv[16];
+        if (K >= 0) {
+            const doublex2 *fp = (const doublex2 *)(f + (int64_t)K * 64 + 16 * lk);
+#pragma unroll
+            for (int x = 0; x < 8; ++x) {
+                const doublex2 v = fp[x];
+                bv[2 * x] = v[0];
+                bv[2 * x + 1] = v[1];
+            }
+        } else {
+#pragma unroll
+            for (int x = 0; x < 16; ++x) bv[x] = 0.0;
+        }
+        const double *ub = u64 + (int64_t)uid * kBlockElems + 16 * lk;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const doublex2 *up = (const doublex2 *)(ub + (16 * i + lr) * 64);
+            double av[16];
+#pragma unroll
+            for (int x = 0; x < 8; ++x) {
+                const doublex2 v = up[x];
+                av[2 * x] = v[0];
+                av[2 * x + 1] = v[1];
+            }
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) c[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], c[i], 0, 0, 0);
+        }
+    }
+    if (lr < n) {
+        double *o = g + (int64_t)(J0 + lr) * 64;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[16 * i + lk + 4 * v] = c[i][v];
     }
 }
 
@@ -813,6 +876,13 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
 
 hipError_t batch_occupancy(int *workgroups_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f32, 256, 0);
+}
+
+hipError_t launch_convolve(const double *u64, const int32_t *chunks, int64_t nchunks, const int32_t *slots,
+                           const double *f, double *g, hipStream_t st) {
+    if (nchunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_convolve, dim3((unsigned)nchunks), dim3(64), 0, st, u64, chunks, slots, f, g);
+    return hipGetLastError();
 }
 
 }  // namespace sympix
