@@ -165,62 +165,53 @@ __global__ __launch_bounds__(256) void k_expand(const double *__restrict__ u64,
 
 // ---------------------------------------------------------------------------
 // Pixel-domain convolution g = B-hat f (Section 4.1): g_J = sum_{K in nbr(J)}
-// B_JK f_K.  One wave per chunk of 16 consecutive output tiles of a band.  For
+// B_JK f_K.  One workgroup per chunk of 16 consecutive output tiles of a band,
+// wave i computing output rows 16 i .. 16 i + 15 of all 16 tiles.  For
 // every unique block u the chunk uses, one FP64 GEMM C += U_u F_u with
 // C[p][j] the outputs of tile J0 + j and F_u[q][j] = f of the input tile that
 // tile J0 + j multiplies with u (zero when it does not), so each unique block
-// is read once per 16 tiles.  MFMA 16x16x4 FP64 with contraction index
-// q = 16 lk + ks: lane (lr, lk) holds U[16 i + lr][16 lk + ks] and
-// F[16 lk + ks][lr]; its result holds rows 16 i + lk + 4 v of column lr.
+// is read once per 16 tiles.  MFMA 16x16x4 FP64, MFMA m = 2 x + t with
+// contraction index q = 8 x + 2 lk + t: lane (lr, lk) holds U[16 i + lr][q] and
+// F[q][lr]; its result holds rows 16 i + lk + 4 v of column lr.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_convolve(const double *__restrict__ u64, const int32_t *__restrict__ chunks,
-                const int32_t *__restrict__ slots, const double *__restrict__ f, double *__restrict__ g) {
+__global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64, const int32_t *__restrict__ chunks,
+                                                  const int32_t *__restrict__ slots, const double *__restrict__ f,
+                                                  double *__restrict__ g) {
     const int ch = xcd_contiguous_index();
     const int J0 = chunks[4 * ch], n = chunks[4 * ch + 1];
     const int s0 = chunks[4 * ch + 2], ns = chunks[4 * ch + 3];
-    const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
-    doublex4 c[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) c[i] = doublex4{0.0, 0.0, 0.0, 0.0};
-    for (int sl = 0; sl < ns; ++sl) {
-        const int32_t *slot = slots + 17 * (int64_t)(s0 + sl);
-        const int uid = slot[0];
+    const int i = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's rows 16 i .. 16 i + 15
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    struct Ops { doublex2 a[8], b[8]; };
+    auto load = [&](int sl, Ops &o) {
+        const int32_t *slot = slots + 17 * (int64_t)(s0 + min(sl, ns - 1));
         const int K = slot[1 + lr];
-        double bv[16];
-        if (K >= 0) {
-            const doublex2 *fp = (const doublex2 *)(f + (int64_t)K * 64 + 16 * lk);
+        // chunk x of a row holds q = 8 x + 2 lk, 8 x + 2 lk + 1: the four lanes of a
+        // row read 64 contiguous bytes per load
+        const doublex2 *up = (const doublex2 *)(u64 + (int64_t)slot[0] * kBlockElems + (16 * i + lr) * 64 + 2 * lk);
+        const doublex2 *fp = (const doublex2 *)(f + (int64_t)max(K, 0) * 64 + 2 * lk);
 #pragma unroll
-            for (int x = 0; x < 8; ++x) {
-                const doublex2 v = fp[x];
-                bv[2 * x] = v[0];
-                bv[2 * x + 1] = v[1];
-            }
-        } else {
-#pragma unroll
-            for (int x = 0; x < 16; ++x) bv[x] = 0.0;
+        for (int x = 0; x < 8; ++x) {
+            o.a[x] = up[4 * x];
+            o.b[x] = K >= 0 ? fp[4 * x] : doublex2{0.0, 0.0};
         }
-        const double *ub = u64 + (int64_t)uid * kBlockElems + 16 * lk;
+    };
+    doublex4 c = doublex4{0.0, 0.0, 0.0, 0.0};
+    Ops o0, o1;
+    load(0, o0);
+    for (int sl = 0; sl < ns; sl += 2) {      // the operands of the next slot load during the MFMAs
+        load(sl + 1, o1);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const doublex2 *up = (const doublex2 *)(ub + (16 * i + lr) * 64);
-            double av[16];
+        for (int ks = 0; ks < 16; ++ks) c = __builtin_amdgcn_mfma_f64_16x16x4f64(o0.a[ks >> 1][ks & 1], o0.b[ks >> 1][ks & 1], c, 0, 0, 0);
+        if (sl + 1 >= ns) break;
+        load(sl + 2, o0);
 #pragma unroll
-            for (int x = 0; x < 8; ++x) {
-                const doublex2 v = up[x];
-                av[2 * x] = v[0];
-                av[2 * x + 1] = v[1];
-            }
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks) c[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], c[i], 0, 0, 0);
-        }
+        for (int ks = 0; ks < 16; ++ks) c = __builtin_amdgcn_mfma_f64_16x16x4f64(o1.a[ks >> 1][ks & 1], o1.b[ks >> 1][ks & 1], c, 0, 0, 0);
     }
     if (lr < n) {
-        double *o = g + (int64_t)(J0 + lr) * 64;
+        double *o = g + (int64_t)(J0 + lr) * 64 + 16 * i + lk;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) o[16 * i + lk + 4 * v] = c[i][v];
+        for (int v = 0; v < 4; ++v) o[4 * v] = c[v];
     }
 }
 
@@ -881,7 +872,7 @@ hipError_t batch_occupancy(int *workgroups_per_cu) {
 hipError_t launch_convolve(const double *u64, const int32_t *chunks, int64_t nchunks, const int32_t *slots,
                            const double *f, double *g, hipStream_t st) {
     if (nchunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_convolve, dim3((unsigned)nchunks), dim3(64), 0, st, u64, chunks, slots, f, g);
+    hipLaunchKernelGGL(k_convolve, dim3((unsigned)nchunks), dim3(256), 0, st, u64, chunks, slots, f, g);
     return hipGetLastError();
 }
 
