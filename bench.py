@@ -170,6 +170,20 @@ def cpu_baseline_batch(probs, budget_s):
                       f"grids and unique blocks built on first use inside the {dt:.1f} s wall"}
 
 
+def copy_calibration(torch, nbytes):
+    """One plain device copy of nbytes (read and written), launched first so
+    that counter runs can scale FETCH_SIZE / WRITE_SIZE by a known size."""
+    if nbytes <= 0:
+        return
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"# copy calibration: {4 * (nbytes // 4)} bytes read and written", file=sys.stderr, flush=True)
+    del src, dst
+
+
 def run_batch(args):
     import torch
 
@@ -177,6 +191,7 @@ def run_batch(args):
     from workloads import synth as S
 
     torch.cuda.set_device(0)
+    copy_calibration(torch, args.copy_calibration)
     t0 = time.perf_counter()
     probs = batch_inputs(sp, S)
     setup = time.perf_counter() - t0
@@ -277,6 +292,7 @@ def run_conv(args):
 
     cfg = S.CONFIGS[args.config]
     torch.cuda.set_device(0)
+    copy_calibration(torch, args.copy_calibration)
     g = sp.Grid(cfg.lmax, cfg.k)
     b_l, R = S.gaussian_beam(cfg.lmax, g.npix, cfg.fwhm_pix)
     stream = torch.cuda.current_stream()
@@ -365,15 +381,7 @@ def main():
     print(f"# workload {args.config}: lmax={cfg.lmax} npix={g.npix} nblocks={g.nblocks} "
           f"nterms={g.nterms} nunique={g.nunique} grid_setup={setup_grid:.2f}s", file=sys.stderr, flush=True)
 
-    if args.copy_calibration > 0:
-        n = args.copy_calibration // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"# copy calibration: {4 * n} bytes read and written", file=sys.stderr, flush=True)
-        del src, dst
+    copy_calibration(torch, args.copy_calibration)
 
     def step(prec, ev):
         ev[0].record(stream)
