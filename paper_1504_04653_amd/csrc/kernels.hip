@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64
 // ---------------------------------------------------------------------------
 template <int NI>
 __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item, int32_t *sTile,
-                                               int32_t *sBlk) {
+                                               int32_t *sBlk, int32_t *sTerm) {
     const double *__restrict__ ut = pd.u64t;
     const double *__restrict__ wv = pd.w;
     double *__restrict__ out = pd.out;
@@ -245,6 +245,7 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
     if (threadIdx.x < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+    if (threadIdx.x < 2 * nterms) sTerm[threadIdx.x] = terms[threadIdx.x];   // unique-block pairs of the class
     __syncthreads();
 
     struct Ptrs { const double *w[NI], *u1, *u2; };
@@ -252,8 +253,8 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
 #pragma unroll
         for (int i = 0; i < NI; ++i)
             q.w[i] = wv + (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 4 * lk;
-        q.u1 = ut + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 4 * lk;
-        q.u2 = ut + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + 4 * lk;
+        q.u1 = ut + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 4 * lk;
+        q.u2 = ut + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + lr * 64 + 4 * lk;
     };
     struct Frag { doublex4 w[NI], u1, u2[4]; };
     auto load = [&](const Ptrs &q, int g, Frag &f) {
@@ -336,11 +337,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_class_f64(ProblemDesc64 pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[64];
+    __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     const int item = xcd_contiguous_index();
     const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_f64_tile<4>(pd, item, sTile, sBlk);
-    else if (groups == 2) class_f64_tile<2>(pd, item, sTile, sBlk);
-    else class_f64_tile<1>(pd, item, sTile, sBlk);
+    if (groups == 4) class_f64_tile<4>(pd, item, sTile, sBlk, sTerm);
+    else if (groups == 2) class_f64_tile<2>(pd, item, sTile, sBlk, sTerm);
+    else class_f64_tile<1>(pd, item, sTile, sBlk, sTerm);
 }
 
 // ---------------------------------------------------------------------------
@@ -366,7 +368,7 @@ __global__ __launch_bounds__(256) void k_ninv_f32(const double *__restrict__ nin
 // LDS tables.
 template <int NI>
 __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, int32_t *sTile,
-                                               int32_t *sBlk) {
+                                               int32_t *sBlk, int32_t *sTerm) {
     const float *__restrict__ ut32 = pd.ut32;
     const float *__restrict__ wf = pd.wf;
     double *__restrict__ out = pd.out;
@@ -383,6 +385,7 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
     if (threadIdx.x < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+    if (threadIdx.x < 2 * nterms) sTerm[threadIdx.x] = terms[threadIdx.x];   // unique-block pairs of the class
     __syncthreads();
 
     // operand addresses of one term for output row a (lane part included)
@@ -391,8 +394,8 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
 #pragma unroll
         for (int i = 0; i < NI; ++i)
             q.w[i] = wf + (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 4 * lk;
-        q.u1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 4 * lk;
-        q.u2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + lr * 64 + 4 * lk;
+        q.u1 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 4 * lk;
+        q.u2 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + lr * 64 + 4 * lk;
     };
     struct Frag { floatx4 w[NI], u1, u2[4]; };
     auto load = [&](const Ptrs &q, int g, Frag &f) {
@@ -483,18 +486,20 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     }
 }
 
-__device__ __forceinline__ void class_f32_item(const ProblemDesc &pd, int item, int32_t *sTile, int32_t *sBlk) {
+__device__ __forceinline__ void class_f32_item(const ProblemDesc &pd, int item, int32_t *sTile, int32_t *sBlk,
+                                               int32_t *sTerm) {
     const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_f32_tile<4>(pd, item, sTile, sBlk);
-    else if (groups == 2) class_f32_tile<2>(pd, item, sTile, sBlk);
-    else class_f32_tile<1>(pd, item, sTile, sBlk);
+    if (groups == 4) class_f32_tile<4>(pd, item, sTile, sBlk, sTerm);
+    else if (groups == 2) class_f32_tile<2>(pd, item, sTile, sBlk, sTerm);
+    else class_f32_tile<1>(pd, item, sTile, sBlk, sTerm);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_class_f32(ProblemDesc pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
     __shared__ int32_t sBlk[64];                     // stored-block index of each member row
-    class_f32_item(pd, xcd_contiguous_index(), sTile, sBlk);
+    __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
+    class_f32_item(pd, xcd_contiguous_index(), sTile, sBlk, sTerm);
 }
 
 // ---------------------------------------------------------------------------
@@ -514,6 +519,7 @@ void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restric
                  const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[64];
+    __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ int32_t sItem;
     const int home = blockIdx.x % nq;
     int tried = 0;                       // queues found empty (thread 0)
@@ -536,7 +542,7 @@ void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restric
         __syncthreads();                 // every thread has read sItem before it changes
         if (it < 0) break;
         const ProblemDesc pd = probs[items[2 * it]];
-        class_f32_item(pd, items[2 * it + 1], sTile, sBlk);
+        class_f32_item(pd, items[2 * it + 1], sTile, sBlk, sTerm);
     }
 }
 
@@ -605,7 +611,7 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // the FP64 accumulators after its second step.
 template <int NP, int NI>
 __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item, int32_t *sTile,
-                                                int32_t *sBlk, u16x8 *sW, floatx4 *sU) {
+                                                int32_t *sBlk, int32_t *sTerm, u16x8 *sW, floatx4 *sU) {
     const float *__restrict__ ut32 = pd.ut32;
     double *__restrict__ out = pd.out;
     const int cls = pd.mtiles[4 * item], m0 = pd.mtiles[4 * item + 1];
@@ -622,6 +628,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
     if (tid < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+    if (tid < 2 * nterms) sTerm[tid] = terms[tid];   // unique-block pairs of the class
     __syncthreads();
 
     // Staging of the operands every wave shares (they do not depend on the
@@ -629,42 +636,48 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     // term, loaded by the whole workgroup with 16-byte loads (4 threads per row
     // and part for W, 8 per row for B_IK) and written to an LDS buffer.
     const int srow = tid >> 2, ssub = tid & 3;                  // W: row, 16-byte chunk
+    // Rows past the tile's 16 NI members load the last member's values into
+    // LDS rows no wave reads, so every thread issues the same loads.
+    const int wrow = min(srow, 16 * NI - 1);
+    // Addresses of one step (row a, term e, half h): W offset of this thread's
+    // staged row, B_IK rows of the term, and this lane's B_IJ values of row a.
+    struct Addr { int64_t wo; const float *u2, *p1; };
+    auto addr = [&](int a, int e, int h) {
+        Addr r;
+        r.wo = (int64_t)sTile[wrow * kMaxClassTerms + e] * 64 + 32 * h + 8 * ssub;
+        r.u2 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + 32 * h;
+        r.p1 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 32 * h + 8 * lk;
+        return r;
+    };
     struct Stage { u16x8 w[NP]; floatx4 u[2]; };
-    auto stage_load = [&](int e, int h, Stage &st) {
-        if (srow < 16 * NI) {
-            const int64_t o = (int64_t)sTile[srow * kMaxClassTerms + e] * 64 + 32 * h + 8 * ssub;
+    struct Own { floatx4 u1[2]; };        // B_IJ values of this wave's output row (not shared)
+    auto loads = [&](const Addr &ad, Stage &st, Own &o) {
 #pragma unroll
-            for (int k = 0; k < NP; ++k) st.w[k] = *(const u16x8 *)(pd.w[k] + o);
-        }
-        const float *u2 = ut32 + (int64_t)terms[2 * e + 1] * kBlockElems + 32 * h;
+        for (int k = 0; k < NP; ++k) st.w[k] = *(const u16x8 *)(pd.w[k] + ad.wo);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int c = tid + 256 * q;
-            st.u[q] = *(const floatx4 *)(u2 + (c >> 3) * 64 + 4 * (c & 7));
+            st.u[q] = *(const floatx4 *)(ad.u2 + (c >> 3) * 64 + 4 * (c & 7));
         }
+        o.u1[0] = *(const floatx4 *)ad.p1;
+        o.u1[1] = *(const floatx4 *)(ad.p1 + 4);
     };
     // LDS layouts, in 16-byte chunks: W row r (64 bytes) keeps its chunk c at
-    // 4 r + (c ^ ((r >> 1) & 3)), a B_IK row b (128 bytes) its chunk c at
-    // 8 b + (c ^ (b & 7)), so the 8 lanes of every LDS access phase, reading
-    // or writing, touch 8 different bank groups
+    // 4 r + (c ^ wsw(r)), a B_IK row b (128 bytes) its chunk c at 8 b + (c ^
+    // usw(b)).  Every read and write phase then touches distinct banks, whether
+    // a 16-byte access is served 8 lanes at a time over 32 banks or 16 lanes
+    // at a time over 64 banks.
+    auto wsw = [](int r) { return ((r >> 1) ^ (r >> 3)) & 3; };
+    auto usw = [](int b) { return ((b >> 1) ^ (b << 2)) & 7; };
     auto stage_store = [&](const Stage &st, int buf) {
-        if (srow < 16 * NI) {
 #pragma unroll
-            for (int k = 0; k < NP; ++k)
-                sW[((buf * NP + k) * 64 + srow) * 4 + (ssub ^ ((srow >> 1) & 3))] = st.w[k];
-        }
+        for (int k = 0; k < NP; ++k)
+            sW[((buf * NP + k) * 64 + srow) * 4 + (ssub ^ wsw(srow))] = st.w[k];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int c = tid + 256 * q, b = c >> 3;
-            sU[buf * 512 + b * 8 + ((c & 7) ^ (b & 7))] = st.u[q];
+            sU[buf * 512 + b * 8 + ((c & 7) ^ usw(b))] = st.u[q];
         }
-    };
-    // B_IJ values of this wave's output row (not shared)
-    struct Own { floatx4 u1[2]; };
-    auto own_load = [&](int a, int e, int h, Own &o) {
-        const float *p1 = ut32 + (int64_t)terms[2 * e] * kBlockElems + a * 64 + 32 * h + 8 * lk;
-        o.u1[0] = *(const floatx4 *)p1;
-        o.u1[1] = *(const floatx4 *)(p1 + 4);
     };
 
     doublex4 acc[NI][4];
@@ -674,23 +687,27 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
     constexpr int NPROD = NP == 3 ? 6 : 3;
-    // One step: the workgroup's loads for the next step go out first; then the
-    // MFMAs of this step from LDS buffer buf (W fragments, and M formed from the
-    // staged B_IK values and this wave's B_IJ values); the next step's staged
-    // operands are written to the other buffer; one barrier.
-    auto step = [&](const Own &oc, int buf, int en, int hn, Stage &stn, bool first) {
-        stage_load(en, hn, stn);
+    // One step, in three scheduling regions: (1) the loads of the next step
+    // (addresses read from LDS one step earlier); (2) the MFMAs of this step
+    // from LDS buffer buf (W fragments, and M formed from the staged B_IK
+    // values and this wave's B_IJ values), with the addresses of the step after
+    // next read meanwhile; (3) the next step's staged operands written to the
+    // other buffer, and one barrier.
+    auto step = [&](const Own &oc, int buf, const Addr &an, Stage &stn, Own &on, bool first, int ca, int ce,
+                    int ch) {
+        loads(an, stn, on);
+        __builtin_amdgcn_sched_barrier(0);
         bf16x8 wf[NI][NP];
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
             for (int k = 0; k < NP; ++k)
-                wf[i][k] = __builtin_bit_cast(bf16x8, sW[((buf * NP + k) * 64 + 16 * i + lr) * 4 + (lk ^ ((lr >> 1) & 3))]);
+                wf[i][k] = __builtin_bit_cast(bf16x8, sW[((buf * NP + k) * 64 + 16 * i + lr) * 4 + (lk ^ wsw(16 * i + lr))]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int b = 16 * j + lr;
-            const floatx4 u2a = sU[buf * 512 + b * 8 + ((2 * lk) ^ (b & 7))];
-            const floatx4 u2b = sU[buf * 512 + b * 8 + ((2 * lk + 1) ^ (b & 7))];
+            const floatx4 u2a = sU[buf * 512 + b * 8 + ((2 * lk) ^ usw(b))];
+            const floatx4 u2b = sU[buf * 512 + b * 8 + ((2 * lk + 1) ^ usw(b))];
             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
             u32x4 words[NP];
 #pragma unroll
@@ -717,23 +734,32 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
                         wf[i][qa], bfr[qb], (first && pr == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][j], 0, 0, 0);
             }
         }
-        stage_store(stn, buf ^ 1);
-        __builtin_amdgcn_sched_group_barrier(0x020, NP + 4, 0);             // global loads first
-        __builtin_amdgcn_sched_group_barrier(0x100, NI * NP + 8, 0);        // LDS operand reads
+        const Addr after = addr(ca, ce, ch);
+        __builtin_amdgcn_sched_group_barrier(0x100, NI * NP + 11, 0);       // LDS reads
 #pragma unroll
         for (int x = 0; x < 4 * NPROD * NI; ++x) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);             // one MFMA
             __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);             // two VALU
         }
+        __builtin_amdgcn_sched_barrier(0);
+        stage_store(stn, buf ^ 1);
         __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+        return after;
     };
 
-    Stage sa, sb;
+    // Step h of a term computes from LDS buffer h.  Cursor: row index x
+    // (a = wave + 4 x) and term e; past the last row the loads repeat the
+    // last term's addresses.
+    Stage s0, s1;
     Own o0, o1;
-    int x = 0, e = 0;                    // row index (a = wave + 4 x) and term
-    stage_load(0, 0, sa);
-    stage_store(sa, 0);
-    own_load(wave, 0, 0, o0);
+    int x = 0, e = 0;
+    {
+        const Addr a0 = addr(wave, 0, 0);
+        loads(a0, s0, o0);
+        stage_store(s0, 0);
+    }
+    Addr an = addr(wave, 0, 1);            // the next step's addresses
     __syncthreads();
     for (int it = 0; it < 16 * nterms; ++it) {
         int ne = e + 1, nx = x;
@@ -742,12 +768,10 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
             ++nx;
         }
         const int a = wave + 4 * x;
-        const bool last = nx >= 16;      // past the last row: harmless reloads of this term
+        const bool last = nx >= 16;
         const int la = last ? a : wave + 4 * nx, le = last ? e : ne;
-        own_load(a, e, 1, o1);
-        step(o0, 0, e, 1, sb, true);
-        own_load(la, le, 0, o0);
-        step(o1, 1, le, 0, sa, false);
+        const Addr a2 = step(o0, 0, an, s1, o1, true, la, le, 0);
+        an = step(o1, 1, a2, s0, o0, false, la, le, 1);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -781,13 +805,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[64];
+    __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ u16x8 sW[2 * NP * 64 * 4];            // staged W, two buffers
     __shared__ floatx4 sU[2 * 512];                  // staged B_IK values, two buffers
     const int item = xcd_contiguous_index();
     const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_bf16_tile<NP, 4>(pd, item, sTile, sBlk, sW, sU);
-    else if (groups == 2) class_bf16_tile<NP, 2>(pd, item, sTile, sBlk, sW, sU);
-    else class_bf16_tile<NP, 1>(pd, item, sTile, sBlk, sW, sU);
+    if (groups == 4) class_bf16_tile<NP, 4>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    else if (groups == 2) class_bf16_tile<NP, 2>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    else class_bf16_tile<NP, 1>(pd, item, sTile, sBlk, sTerm, sW, sU);
 }
 
 }  // namespace
