@@ -603,12 +603,14 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // hm, mh, hl, lh, mm (smallest first), NP = 2 keeps hh, hm, mh.  MFMA
 // 16x16x32 BF16: lane (lr, lk) holds W[16 i + lr][p0 + 8 lk + 0..7] and
 // M[p0 + 8 lk + 0..7][16 j + lr]; the result holds members 16 i + 4 lk + v.
-// Four waves per member tile, wave w taking output rows a = w mod 4, so the W
-// fragments and the B_IK values of a step are shared through L1.  A step is 32 pixels (half a
-// term): the next step's loads go out first, then the M fragments of the four
-// 16-column groups are formed and split (FP32 product, NP BF16 parts) while
-// the MFMAs of the groups already formed run; a term's FP32 sums are added to
-// the FP64 accumulators after its second step.
+// Eight waves per member tile.  Waves w and w + 4 share a SIMD and take the
+// output rows a = w mod 4, wave w < 4 the columns b < 32 and wave w + 4 the
+// columns b >= 32: a wave's own VALU work (forming and splitting M, the FP64
+// accumulation) does not overlap its MFMAs, but it does overlap those of the
+// other wave on its SIMD.  The operands all waves share (W of the tile's
+// rows, the B_IK values of a step) are staged through LDS.  A step is 32
+// pixels (half a term); a term's FP32 sums are added to the FP64 accumulators
+// after its second step.
 template <int NP, int NI>
 __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item, int32_t *sTile,
                                                 int32_t *sBlk, int32_t *sTerm, u16x8 *sW, floatx4 *sU) {
@@ -618,11 +620,12 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     const DevClass cl = pd.classes[cls];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rw = wave & 3, ch = wave >> 2;          // row phase, column half
     const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
     const int32_t *terms = pd.cterms + 2 * cl.term0;
 
-    for (int x = tid; x < 16 * NI * nterms; x += 256) {
+    for (int x = tid; x < 16 * NI * nterms; x += 512) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
@@ -631,61 +634,67 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     if (tid < 2 * nterms) sTerm[tid] = terms[tid];   // unique-block pairs of the class
     __syncthreads();
 
-    // Staging of the operands every wave shares (they do not depend on the
-    // output row): W of the tile's rows and the B_IK values of 32 pixels of one
-    // term, loaded by the whole workgroup with 16-byte loads (4 threads per row
-    // and part for W, 8 per row for B_IK) and written to an LDS buffer.
-    const int srow = tid >> 2, ssub = tid & 3;                  // W: row, 16-byte chunk
-    // Rows past the tile's 16 NI members load the last member's values into
-    // LDS rows no wave reads, so every thread issues the same loads.
-    const int wrow = min(srow, 16 * NI - 1);
-    // Addresses of one step (row a, term e, half h): W offset of this thread's
-    // staged row, B_IK rows of the term, and this lane's B_IJ values of row a.
-    struct Addr { int64_t wo; const float *u2, *p1; };
+    // Staging: W is 256 NP chunks of 16 bytes (part c >> 8, row (c & 255) >> 2,
+    // chunk c & 3), B_IK of one step 512 chunks (row c >> 3, chunk c & 7).
+    // Thread t takes W chunks t + 512 r and B_IK chunk t; for NP = 3 the
+    // threads past the last W chunk repeat one (same value to the same LDS
+    // place), so every thread issues the same loads.  Rows past the tile's
+    // 16 NI members load the last member's values into LDS rows no wave reads.
+    constexpr int NWC = (256 * NP + 511) / 512;
+    const uint16_t *wsrc[NWC];
+    int wrow[NWC], wdst[NWC];
+    auto wsw = [](int r) { return ((r >> 1) ^ (r >> 3)) & 3; };
+    auto usw = [](int b) { return ((b >> 1) ^ (b << 2)) & 7; };
+#pragma unroll
+    for (int r = 0; r < NWC; ++r) {
+        int c = tid + 512 * r;
+        if (c >= 256 * NP) c -= 256;
+        const int k = __builtin_amdgcn_readfirstlane(c >> 8), q = c & 255, row = q >> 2, sub = q & 3;
+        wsrc[r] = pd.w[k] + 8 * sub;
+        wrow[r] = min(row, 16 * NI - 1) * kMaxClassTerms;
+        // LDS layouts, in 16-byte chunks: W row r (64 bytes) keeps its chunk c at
+        // 4 r + (c ^ wsw(r)), a B_IK row b (128 bytes) its chunk c at 8 b + (c ^
+        // usw(b)); every read and write phase then touches distinct banks,
+        // whether a 16-byte access is served 8 lanes at a time over 32 banks or
+        // 16 lanes at a time over 64 banks.
+        wdst[r] = (k * 64 + row) * 4 + (sub ^ wsw(row));
+    }
+    const int ub = tid >> 3, uc = tid & 7;
+    const int usrc = ub * 64 + 4 * uc, udst = ub * 8 + (uc ^ usw(ub));
+
+    // Addresses of one step (row a, term e, half h): W offsets of this
+    // thread's staged chunks, B_IK rows of the term, and this lane's B_IJ
+    // values of row a.
+    struct Addr { int64_t wo[NWC]; const float *u2, *p1; };
     auto addr = [&](int a, int e, int h) {
         Addr r;
-        r.wo = (int64_t)sTile[wrow * kMaxClassTerms + e] * 64 + 32 * h + 8 * ssub;
+#pragma unroll
+        for (int q = 0; q < NWC; ++q) r.wo[q] = (int64_t)sTile[wrow[q] + e] * 64 + 32 * h;
         r.u2 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + 32 * h;
         r.p1 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 32 * h + 8 * lk;
         return r;
     };
-    struct Stage { u16x8 w[NP]; floatx4 u[2]; };
+    struct Stage { u16x8 w[NWC]; floatx4 u; };
     struct Own { floatx4 u1[2]; };        // B_IJ values of this wave's output row (not shared)
     auto loads = [&](const Addr &ad, Stage &st, Own &o) {
 #pragma unroll
-        for (int k = 0; k < NP; ++k) st.w[k] = *(const u16x8 *)(pd.w[k] + ad.wo);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + 256 * q;
-            st.u[q] = *(const floatx4 *)(ad.u2 + (c >> 3) * 64 + 4 * (c & 7));
-        }
+        for (int q = 0; q < NWC; ++q) st.w[q] = *(const u16x8 *)(wsrc[q] + ad.wo[q]);
+        st.u = *(const floatx4 *)(ad.u2 + usrc);
         o.u1[0] = *(const floatx4 *)ad.p1;
         o.u1[1] = *(const floatx4 *)(ad.p1 + 4);
     };
-    // LDS layouts, in 16-byte chunks: W row r (64 bytes) keeps its chunk c at
-    // 4 r + (c ^ wsw(r)), a B_IK row b (128 bytes) its chunk c at 8 b + (c ^
-    // usw(b)).  Every read and write phase then touches distinct banks, whether
-    // a 16-byte access is served 8 lanes at a time over 32 banks or 16 lanes
-    // at a time over 64 banks.
-    auto wsw = [](int r) { return ((r >> 1) ^ (r >> 3)) & 3; };
-    auto usw = [](int b) { return ((b >> 1) ^ (b << 2)) & 7; };
     auto stage_store = [&](const Stage &st, int buf) {
 #pragma unroll
-        for (int k = 0; k < NP; ++k)
-            sW[((buf * NP + k) * 64 + srow) * 4 + (ssub ^ wsw(srow))] = st.w[k];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + 256 * q, b = c >> 3;
-            sU[buf * 512 + b * 8 + ((c & 7) ^ usw(b))] = st.u[q];
-        }
+        for (int q = 0; q < NWC; ++q) sW[buf * NP * 256 + wdst[q]] = st.w[q];
+        sU[buf * 512 + udst] = st.u;
     };
 
-    doublex4 acc[NI][4];
-    floatx4 part[NI][4];
+    doublex4 acc[NI][2];
+    floatx4 part[NI][2];
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
     constexpr int NPROD = NP == 3 ? 6 : 3;
     // One step, in three scheduling regions: (1) the loads of the next step
     // (addresses read from LDS one step earlier); (2) the MFMAs of this step
@@ -694,7 +703,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     // next read meanwhile; (3) the next step's staged operands written to the
     // other buffer, and one barrier.
     auto step = [&](const Own &oc, int buf, const Addr &an, Stage &stn, Own &on, bool first, int ca, int ce,
-                    int ch) {
+                    int ch_) {
         loads(an, stn, on);
         __builtin_amdgcn_sched_barrier(0);
         bf16x8 wf[NI][NP];
@@ -704,8 +713,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
             for (int k = 0; k < NP; ++k)
                 wf[i][k] = __builtin_bit_cast(bf16x8, sW[((buf * NP + k) * 64 + 16 * i + lr) * 4 + (lk ^ wsw(16 * i + lr))]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int b = 16 * j + lr;
+        for (int jj = 0; jj < 2; ++jj) {
+            const int b = 32 * ch + 16 * jj + lr;
             const floatx4 u2a = sU[buf * 512 + b * 8 + ((2 * lk) ^ usw(b))];
             const floatx4 u2b = sU[buf * 512 + b * 8 + ((2 * lk + 1) ^ usw(b))];
             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -730,14 +739,14 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
                 const int qb = NP == 3 ? pb3[pr] : pb2[pr];
 #pragma unroll
                 for (int i = 0; i < NI; ++i)
-                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        wf[i][qa], bfr[qb], (first && pr == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][j], 0, 0, 0);
+                    part[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        wf[i][qa], bfr[qb], (first && pr == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][jj], 0, 0, 0);
             }
         }
-        const Addr after = addr(ca, ce, ch);
-        __builtin_amdgcn_sched_group_barrier(0x100, NI * NP + 11, 0);       // LDS reads
+        const Addr after = addr(ca, ce, ch_);
+        __builtin_amdgcn_sched_group_barrier(0x100, NI * NP + 6 + NWC, 0);   // LDS reads
 #pragma unroll
-        for (int x = 0; x < 4 * NPROD * NI; ++x) {
+        for (int x = 0; x < 2 * NPROD * NI; ++x) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);             // one MFMA
             __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);             // two VALU
         }
@@ -749,17 +758,17 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     };
 
     // Step h of a term computes from LDS buffer h.  Cursor: row index x
-    // (a = wave + 4 x) and term e; past the last row the loads repeat the
-    // last term's addresses.
+    // (a = rw + 4 x) and term e; past the last row the loads repeat the last
+    // term's addresses.
     Stage s0, s1;
     Own o0, o1;
     int x = 0, e = 0;
     {
-        const Addr a0 = addr(wave, 0, 0);
+        const Addr a0 = addr(rw, 0, 0);
         loads(a0, s0, o0);
         stage_store(s0, 0);
     }
-    Addr an = addr(wave, 0, 1);            // the next step's addresses
+    Addr an = addr(rw, 0, 1);              // the next step's addresses
     __syncthreads();
     for (int it = 0; it < 16 * nterms; ++it) {
         int ne = e + 1, nx = x;
@@ -767,15 +776,15 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
             ne = 0;
             ++nx;
         }
-        const int a = wave + 4 * x;
+        const int a = rw + 4 * x;
         const bool last = nx >= 16;
-        const int la = last ? a : wave + 4 * nx, le = last ? e : ne;
+        const int la = last ? a : rw + 4 * nx, le = last ? e : ne;
         const Addr a2 = step(o0, 0, an, s1, o1, true, la, le, 0);
         an = step(o1, 1, a2, s0, o0, false, la, le, 1);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
         if (ne == 0) {                   // end of output row a: store, clear
@@ -785,15 +794,15 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
                 for (int v = 0; v < 4; ++v) {
                     const int blk = sBlk[16 * i + 4 * lk + v];
                     if (blk >= 0) {
-                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + lr;
+                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + 32 * ch + lr;
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
+                        for (int j = 0; j < 2; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
                     }
                 }
 #pragma unroll
             for (int i = 0; i < NI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+                for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
         }
         x = nx;
         e = ne;
@@ -801,7 +810,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 }
 
 template <int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[64];
@@ -866,8 +875,8 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)a.nmtiles);
     ProblemDescB pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.ut32,
                     {a.wsplit[0], a.wsplit[1], a.wsplit[2]}, a.out};
-    if (prec == 2) hipLaunchKernelGGL(k_class_bf16<2>, grid, dim3(256), 0, st, pd);
-    else hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(256), 0, st, pd);
+    if (prec == 2) hipLaunchKernelGGL(k_class_bf16<2>, grid, dim3(512), 0, st, pd);
+    else hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(512), 0, st, pd);
     return hipGetLastError();
 }
 
