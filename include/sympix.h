@@ -189,6 +189,22 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
                                  int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
                                  void *stream);
 
+/* Both local operators of Eq. 16 in one call: outD_dev receives the D-hat
+ * blocks of kernel d (as sympix_sample_D) and outC_dev the B-hat^T N^-1 B-hat
+ * blocks of kernel b (as sympix_sample_BtNB with the same prec), bitwise equal
+ * to the two separate calls.  In the split-BF16 modes one launch writes both:
+ * the D-hat copies, bound by HBM writes, proceed under the contraction's
+ * arithmetic.  In the FP32 and FP64 modes the D-hat expansion runs first, on
+ * the same stream.  outD_dev and outC_dev: device, float64, nblocks k^4 values
+ * each, stored-block order, 16-byte aligned, not overlapping each other or
+ * ninv_dev.  Both kernels must belong to g and live on the current device.
+ * Errors: EINVAL (NULL, overlap, misalignment, kernel of another grid or
+ * device), ESIZE (ninv_len != npix or an output length != nblocks k^4),
+ * EUNSUPPORTED (k != 8), EHIP. */
+sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d, const sympix_kernel *b,
+                                   const double *ninv_dev, int64_t ninv_len, int32_t prec, double *outD_dev,
+                                   int64_t outD_len, double *outC_dev, int64_t outC_len, void *stream);
+
 /* ---- Batches: many B-hat^T N^-1 B-hat problems in one graph launch ----------
  * Eq. 15 evaluated for n independent problems (own grid, beam kernel, N^-1 and
  * output each) by one captured HIP graph: a persistent FP32-MFMA contraction

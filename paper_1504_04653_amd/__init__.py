@@ -75,6 +75,7 @@ _kernel_destroy = _sig("sympix_kernel_destroy", [_vp], None)
 _kernel_eval = _sig("sympix_kernel_eval", [_vp, _vp, _vp, _i64, _vp])
 _sample_D = _sig("sympix_sample_D", [_vp, _vp, _vp, _i64, _vp])
 _sample_BtNB = _sig("sympix_sample_BtNB", [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp])
+_sample_D_BtNB = _sig("sympix_sample_D_BtNB", [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp, _i64, _vp])
 _convolve = _sig("sympix_convolve", [_vp, _vp, _vp, _i64, _vp, _i64, _vp])
 _last_error = _sig("sympix_last_error", [], ctypes.c_char_p)
 
@@ -96,7 +97,7 @@ SCHEDULES = {"xcd_queues": SCHED_XCD_QUEUES, "global_lpt": SCHED_GLOBAL_LPT, "pe
 EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sympix_grid_rings",
             "sympix_grid_bands", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_unique",
             "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
-            "sympix_sample_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_tune",
+            "sympix_sample_BtNB", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_tune",
             "sympix_batch_launch", "sympix_batch_destroy", "sympix_last_error")
 
 
@@ -264,6 +265,19 @@ def sample_BtNB(grid: Grid, kernel: Kernel, ninv, out, prec=FP64, stream=None):
     _check(_sample_BtNB(grid.handle, kernel.handle, _ptr(ninv), _numel(ninv), int(prec), _ptr(out),
                         _numel(out), _stream(stream)))
     return out
+
+
+def sample_D_BtNB(grid: Grid, kd: Kernel, kb: Kernel, ninv, out_D, out_C, prec=FP64, stream=None):
+    """D-hat blocks of kd into out_D and B-hat^T N^-1 B-hat blocks of kb into
+    out_C in one call (one launch in the split-BF16 modes)."""
+    if isinstance(prec, str):
+        prec = PRECISIONS[prec]
+    _require_f64_device(ninv, "ninv")
+    _require_f64_device(out_D, "out_D")
+    _require_f64_device(out_C, "out_C")
+    _check(_sample_D_BtNB(grid.handle, kd.handle, kb.handle, _ptr(ninv), _numel(ninv), int(prec), _ptr(out_D),
+                          _numel(out_D), _ptr(out_C), _numel(out_C), _stream(stream)))
+    return out_D, out_C
 
 
 def convolve(grid: Grid, kernel: Kernel, f, out, stream=None):

@@ -244,6 +244,91 @@ sympix_status check_kernel_use(const sympix_grid *g, const sympix_kernel *kr) {
     return SYMPIX_OK;
 }
 
+// B-hat^T N^-1 B-hat into out_dev and, with a D-hat kernel d, the D-hat
+// blocks into outD_dev: in the split-BF16 modes one launch writes both, in
+// the FP32 / FP64 modes the D-hat expansion runs first on the same stream.
+sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sympix_kernel *b,
+                          const double *ninv_dev, int64_t ninv_len, int32_t prec, double *outD_dev,
+                          int64_t outD_len, double *out_dev, int64_t out_len, void *stream, const char *what) {
+    sympix_status s = check_kernel_use(g, b);
+    if (s != SYMPIX_OK) return s;
+    const Geometry &geo = g->geo;
+    if (prec < SYMPIX_FP64 || prec > SYMPIX_BF16X6) return fail(SYMPIX_EINVAL, "unknown precision mode");
+    if (ninv_len != geo.npix) return fail(SYMPIX_ESIZE, "ninv_len must be npix");
+    const int64_t want = geo.nblocks() * sympix::kBlockElems;
+    if (out_len != want || (d && outD_len != want)) return fail(SYMPIX_ESIZE, "output lengths must be nblocks * k^4");
+    if ((geo.npix > 0 && !ninv_dev) || (out_len > 0 && !out_dev) || (d && out_len > 0 && !outD_dev))
+        return fail(SYMPIX_EINVAL, "NULL device buffer");
+    if (((uintptr_t)out_dev) % 16 || ((uintptr_t)ninv_dev) % 32 || ((uintptr_t)outD_dev) % 16)
+        return fail(SYMPIX_EINVAL, "outputs must be 16-byte and ninv_dev 32-byte aligned");
+    if (d && out_len > 0) {
+        auto overlap = [](const void *p, size_t np, const void *q, size_t nq) {
+            return (const char *)p < (const char *)q + nq && (const char *)q < (const char *)p + np;
+        };
+        const size_t ob = (size_t)out_len * sizeof(double), nb = (size_t)ninv_len * sizeof(double);
+        if (overlap(outD_dev, ob, out_dev, ob) || overlap(outD_dev, ob, ninv_dev, nb))
+            return fail(SYMPIX_EINVAL, "the D-hat output overlaps another buffer");
+    }
+    if (d && d->device != b->device) return fail(SYMPIX_EINVAL, "the two kernels live on different devices");
+    const DevGrid *dg = nullptr;
+    s = device_tables(g, b->device, &dg);
+    if (s != SYMPIX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (geo.max_class_terms > sympix::kMaxClassTerms)
+        return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
+    const bool fused = d && (prec == SYMPIX_BF16X3 || prec == SYMPIX_BF16X6);
+    if (d && !fused) {
+        s = after_launch(sympix::launch_expand(d->u64, dg->exp_items, (int64_t)geo.exp_items.size() / 4,
+                                               dg->exp_blk, outD_dev, st),
+                         st, what);
+        if (s != SYMPIX_OK) return s;
+    }
+    sympix::BtnbArgs a;
+    a.u64t = b->u64t;
+    a.ut32 = b->ut32;
+    a.classes = dg->classes;
+    a.class_terms = dg->class_terms;
+    a.class_blk = dg->class_blk;
+    a.class_itab = dg->class_itab;
+    a.mtiles = dg->mtiles;
+    a.nmtiles = (int64_t)geo.mtiles.size() / 4;
+    a.wtiles = dg->wtiles;
+    a.nwtiles = (int64_t)geo.wtiles.size() / 4;
+    a.nblocks = geo.nblocks();
+    a.npix = geo.npix;
+    a.ninv = ninv_dev;
+    a.out = out_dev;
+    a.wsplit[0] = a.wsplit[1] = a.wsplit[2] = nullptr;
+    a.wf32 = nullptr;
+    a.du64 = fused ? d->u64 : nullptr;
+    a.blk_uid = fused ? dg->blk_uid : nullptr;
+    a.outD = fused ? outD_dev : nullptr;
+    hipError_t e = hipSuccess;
+    void *scratch = nullptr;
+    if (prec != SYMPIX_FP64) {
+        // stream-ordered scratch for N^-1 in the MFMA operand format (FP32, or
+        // three BF16 parts): concurrent calls stay independent
+        const size_t bytes = (size_t)geo.npix * (prec == SYMPIX_FP32 ? sizeof(float) : 3 * sizeof(uint16_t));
+        e = hipMallocAsync(&scratch, bytes, st);
+        if (e != hipSuccess)
+            return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 operands")
+                                            : hip_fail(e, "hipMallocAsync");
+        if (prec == SYMPIX_FP32) {
+            a.wf32 = (float *)scratch;
+        } else {
+            a.wsplit[0] = (uint16_t *)scratch;
+            a.wsplit[1] = a.wsplit[0] + geo.npix;
+            a.wsplit[2] = a.wsplit[1] + geo.npix;
+        }
+    }
+    e = sympix::launch_btnb(prec, a, st);
+    if (scratch) {
+        hipError_t ef = hipFreeAsync(scratch, st);
+        if (e == hipSuccess) e = ef;
+    }
+    return after_launch(e, st, what);
+}
+
 }  // namespace
 
 extern "C" {
@@ -474,64 +559,16 @@ sympix_status sympix_convolve(const sympix_grid *g, const sympix_kernel *b, cons
 sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
                                  int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
                                  void *stream) {
-    sympix_status s = check_kernel_use(g, b);
+    return sample_btnb(g, nullptr, b, ninv_dev, ninv_len, prec, nullptr, 0, out_dev, out_len, stream, "sample_BtNB");
+}
+
+sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d, const sympix_kernel *b,
+                                   const double *ninv_dev, int64_t ninv_len, int32_t prec, double *outD_dev,
+                                   int64_t outD_len, double *outC_dev, int64_t outC_len, void *stream) {
+    sympix_status s = check_kernel_use(g, d);
     if (s != SYMPIX_OK) return s;
-    const Geometry &geo = g->geo;
-    if (prec < SYMPIX_FP64 || prec > SYMPIX_BF16X6) return fail(SYMPIX_EINVAL, "unknown precision mode");
-    if (ninv_len != geo.npix) return fail(SYMPIX_ESIZE, "ninv_len must be npix");
-    if (out_len != geo.nblocks() * sympix::kBlockElems)
-        return fail(SYMPIX_ESIZE, "out_len must be nblocks * k^4");
-    if ((geo.npix > 0 && !ninv_dev) || (out_len > 0 && !out_dev))
-        return fail(SYMPIX_EINVAL, "NULL device buffer");
-    if (((uintptr_t)out_dev) % 16 || ((uintptr_t)ninv_dev) % 32)
-        return fail(SYMPIX_EINVAL, "out_dev must be 16-byte and ninv_dev 32-byte aligned");
-    const DevGrid *dg = nullptr;
-    s = device_tables(g, b->device, &dg);
-    if (s != SYMPIX_OK) return s;
-    hipStream_t st = (hipStream_t)stream;
-    sympix::BtnbArgs a;
-    a.u64t = b->u64t;
-    a.ut32 = b->ut32;
-    a.classes = dg->classes;
-    a.class_terms = dg->class_terms;
-    a.class_blk = dg->class_blk;
-    a.class_itab = dg->class_itab;
-    a.mtiles = dg->mtiles;
-    a.nmtiles = (int64_t)geo.mtiles.size() / 4;
-    a.wtiles = dg->wtiles;
-    a.nwtiles = (int64_t)geo.wtiles.size() / 4;
-    a.nblocks = geo.nblocks();
-    a.npix = geo.npix;
-    a.ninv = ninv_dev;
-    a.out = out_dev;
-    a.wsplit[0] = a.wsplit[1] = a.wsplit[2] = nullptr;
-    a.wf32 = nullptr;
-    hipError_t e = hipSuccess;
-    if (geo.max_class_terms > sympix::kMaxClassTerms)
-        return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
-    void *scratch = nullptr;
-    if (prec != SYMPIX_FP64) {
-        // stream-ordered scratch for N^-1 in the MFMA operand format (FP32, or
-        // three BF16 parts): concurrent calls stay independent
-        const size_t bytes = (size_t)geo.npix * (prec == SYMPIX_FP32 ? sizeof(float) : 3 * sizeof(uint16_t));
-        e = hipMallocAsync(&scratch, bytes, st);
-        if (e != hipSuccess)
-            return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 operands")
-                                            : hip_fail(e, "hipMallocAsync");
-        if (prec == SYMPIX_FP32) {
-            a.wf32 = (float *)scratch;
-        } else {
-            a.wsplit[0] = (uint16_t *)scratch;
-            a.wsplit[1] = a.wsplit[0] + geo.npix;
-            a.wsplit[2] = a.wsplit[1] + geo.npix;
-        }
-    }
-    e = sympix::launch_btnb(prec, a, st);
-    if (scratch) {
-        hipError_t ef = hipFreeAsync(scratch, st);
-        if (e == hipSuccess) e = ef;
-    }
-    return after_launch(e, st, "sample_BtNB");
+    return sample_btnb(g, d, b, ninv_dev, ninv_len, prec, outD_dev, outD_len, outC_dev, outC_len, stream,
+                       "sample_D_BtNB");
 }
 
 }  // extern "C"

@@ -64,6 +64,11 @@ struct BtnbArgs {
     int64_t nblocks;
     const double *ninv;
     double *out;
+    // optional D-hat blocks written by the same launch (split-BF16 modes):
+    // stored block n gets unique block blk_uid[n] of du64 (row-major FP64)
+    const double *du64;
+    const int32_t *blk_uid;
+    double *outD;             // nullptr: B-hat^T N^-1 B-hat only
 };
 hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st);
 
@@ -85,6 +90,9 @@ struct ProblemDescB {
     const float *ut32;
     const uint16_t *w[3];     // N^-1 split into BF16 parts
     double *out;
+    const double *du64;       // D-hat: unique blocks, row-major FP64 (with outD)
+    const int32_t *blk_uid;   // unique block of each stored block
+    double *outD;             // D-hat output, or nullptr
 };
 
 // Operands of the FP32 class GEMM for one problem (device pointers).

@@ -611,7 +611,12 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // rows, the B_IK values of a step) are staged through LDS.  A step is 32
 // pixels (half a term); a term's FP32 sums are added to the FP64 accumulators
 // after its second step.
-template <int NP, int NI>
+// With WD the launch also writes D-hat: the D-hat block of every stored block
+// of the tile is its unique block, copied in 16-byte chunks, two per thread
+// and step (loads with the step's loads, stores after its MFMAs), so that
+// these writes proceed under the contraction's arithmetic; chunks left after
+// the last step are copied at the end of the tile.
+template <int NP, int NI, bool WD>
 __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item, int32_t *sTile,
                                                 int32_t *sBlk, int32_t *sTerm, u16x8 *sW, floatx4 *sU) {
     const float *__restrict__ ut32 = pd.ut32;
@@ -630,7 +635,11 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    if (tid < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+    if (tid < 64) {
+        const int blk = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+        sBlk[lane] = blk;
+        if constexpr (WD) sBlk[64 + lane] = blk >= 0 ? pd.blk_uid[blk] : 0;   // D-hat source block
+    }
     if (tid < 2 * nterms) sTerm[tid] = terms[tid];   // unique-block pairs of the class
     __syncthreads();
 
@@ -688,6 +697,28 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         for (int q = 0; q < NWC; ++q) sW[buf * NP * 256 + wdst[q]] = st.w[q];
         sU[buf * 512 + udst] = st.u;
     };
+    // D-hat copy: chunk c is 16 bytes (c & 2047) of member row c >> 11; a
+    // wave's 64 chunks lie in one row, so the row index is uniform.
+    constexpr int kDChunks = 16 * NI * 2048;
+    struct DCopy { doublex2 v[2]; int blk[2]; int off[2]; };
+    auto dload = [&](int stp, DCopy &dc) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int c0 = __builtin_amdgcn_readfirstlane((2 * stp + r) * 512 + 64 * wave);
+            const bool ok = c0 < kDChunks;
+            const int m = ok ? c0 >> 11 : 0;
+            const int off = 2 * ((c0 & 2047) + lane);
+            dc.blk[r] = ok ? sBlk[m] : -1;
+            dc.off[r] = off;
+            dc.v[r] = *(const doublex2 *)(pd.du64 + (int64_t)sBlk[64 + m] * kBlockElems + off);
+        }
+    };
+    auto dstore = [&](const DCopy &dc) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+            if (dc.blk[r] >= 0)
+                __builtin_nontemporal_store(dc.v[r], (doublex2 *)(pd.outD + (int64_t)dc.blk[r] * kBlockElems + dc.off[r]));
+    };
 
     doublex4 acc[NI][2];
     floatx4 part[NI][2];
@@ -703,8 +734,10 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     // next read meanwhile; (3) the next step's staged operands written to the
     // other buffer, and one barrier.
     auto step = [&](const Own &oc, int buf, const Addr &an, Stage &stn, Own &on, bool first, int ca, int ce,
-                    int ch_) {
+                    int ch_, int stp) {
         loads(an, stn, on);
+        DCopy dc;
+        if constexpr (WD) dload(stp, dc);
         __builtin_amdgcn_sched_barrier(0);
         bf16x8 wf[NI][NP];
 #pragma unroll
@@ -752,6 +785,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         }
         __builtin_amdgcn_sched_barrier(0);
         stage_store(stn, buf ^ 1);
+        if constexpr (WD) dstore(dc);
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
         return after;
@@ -779,8 +813,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         const int a = rw + 4 * x;
         const bool last = nx >= 16;
         const int la = last ? a : rw + 4 * nx, le = last ? e : ne;
-        const Addr a2 = step(o0, 0, an, s1, o1, true, la, le, 0);
-        an = step(o1, 1, a2, s0, o0, false, la, le, 1);
+        const Addr a2 = step(o0, 0, an, s1, o1, true, la, le, 0, 2 * it);
+        an = step(o1, 1, a2, s0, o0, false, la, le, 1, 2 * it + 1);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -807,21 +841,28 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         x = nx;
         e = ne;
     }
+    if constexpr (WD) {                  // D-hat chunks past the last step
+        for (int stp = 32 * nterms; 1024 * stp < kDChunks; ++stp) {
+            DCopy dc;
+            dload(stp, dc);
+            dstore(dc);
+        }
+    }
 }
 
-template <int NP>
+template <int NP, bool WD>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
-    __shared__ int32_t sBlk[64];
+    __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ u16x8 sW[2 * NP * 64 * 4];            // staged W, two buffers
     __shared__ floatx4 sU[2 * 512];                  // staged B_IK values, two buffers
     const int item = xcd_contiguous_index();
     const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_bf16_tile<NP, 4>(pd, item, sTile, sBlk, sTerm, sW, sU);
-    else if (groups == 2) class_bf16_tile<NP, 2>(pd, item, sTile, sBlk, sTerm, sW, sU);
-    else class_bf16_tile<NP, 1>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    if (groups == 4) class_bf16_tile<NP, 4, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    else if (groups == 2) class_bf16_tile<NP, 2, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    else class_bf16_tile<NP, 1, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
 }
 
 }  // namespace
@@ -874,9 +915,14 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
                        a.npix, a.wsplit[0], a.wsplit[1], a.wsplit[2]);
     const dim3 grid((unsigned)a.nmtiles);
     ProblemDescB pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.ut32,
-                    {a.wsplit[0], a.wsplit[1], a.wsplit[2]}, a.out};
-    if (prec == 2) hipLaunchKernelGGL(k_class_bf16<2>, grid, dim3(512), 0, st, pd);
-    else hipLaunchKernelGGL(k_class_bf16<3>, grid, dim3(512), 0, st, pd);
+                    {a.wsplit[0], a.wsplit[1], a.wsplit[2]}, a.out, a.du64, a.blk_uid, a.outD};
+    if (a.outD) {
+        if (prec == 2) hipLaunchKernelGGL((k_class_bf16<2, true>), grid, dim3(512), 0, st, pd);
+        else hipLaunchKernelGGL((k_class_bf16<3, true>), grid, dim3(512), 0, st, pd);
+    } else {
+        if (prec == 2) hipLaunchKernelGGL((k_class_bf16<2, false>), grid, dim3(512), 0, st, pd);
+        else hipLaunchKernelGGL((k_class_bf16<3, false>), grid, dim3(512), 0, st, pd);
+    }
     return hipGetLastError();
 }
 
