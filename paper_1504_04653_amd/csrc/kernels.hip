@@ -613,9 +613,9 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // after its second step.
 // With WD the launch also writes D-hat: the D-hat block of every stored block
 // of the tile is its unique block, copied in 16-byte chunks, two per thread
-// and step (loads with the step's loads, stores after its MFMAs), so that
-// these writes proceed under the contraction's arithmetic; chunks left after
-// the last step are copied at the end of the tile.
+// and step (loaded with one step's loads, stored after the next step's), so
+// that these writes proceed under the contraction's arithmetic; chunks left
+// after the last step are copied at the end of the tile.
 template <int NP, int NI, bool WD>
 __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item, int32_t *sTile,
                                                 int32_t *sBlk, int32_t *sTerm, u16x8 *sW, floatx4 *sU) {
@@ -733,11 +733,18 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     // values and this wave's B_IJ values), with the addresses of the step after
     // next read meanwhile; (3) the next step's staged operands written to the
     // other buffer, and one barrier.
+    // D-hat chunks are stored one step after they are loaded, right after the
+    // step's own loads: stores and loads share one wait counter, and a store
+    // placed there is only waited for by the staging wait of the next step.
     auto step = [&](const Own &oc, int buf, const Addr &an, Stage &stn, Own &on, bool first, int ca, int ce,
-                    int ch_, int stp) {
+                    int ch_, int stp, DCopy &dprev) {
         loads(an, stn, on);
-        DCopy dc;
-        if constexpr (WD) dload(stp, dc);
+        if constexpr (WD) {
+            DCopy dc;
+            dload(stp, dc);
+            dstore(dprev);
+            dprev = dc;
+        }
         __builtin_amdgcn_sched_barrier(0);
         bf16x8 wf[NI][NP];
 #pragma unroll
@@ -785,7 +792,6 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         }
         __builtin_amdgcn_sched_barrier(0);
         stage_store(stn, buf ^ 1);
-        if constexpr (WD) dstore(dc);
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
         return after;
@@ -803,6 +809,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         stage_store(s0, 0);
     }
     Addr an = addr(rw, 0, 1);              // the next step's addresses
+    DCopy dpend;                           // D-hat chunks loaded, not yet stored
+    dpend.blk[0] = dpend.blk[1] = -1;
     __syncthreads();
     for (int it = 0; it < 16 * nterms; ++it) {
         int ne = e + 1, nx = x;
@@ -813,8 +821,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         const int a = rw + 4 * x;
         const bool last = nx >= 16;
         const int la = last ? a : rw + 4 * nx, le = last ? e : ne;
-        const Addr a2 = step(o0, 0, an, s1, o1, true, la, le, 0, 2 * it);
-        an = step(o1, 1, a2, s0, o0, false, la, le, 1, 2 * it + 1);
+        const Addr a2 = step(o0, 0, an, s1, o1, true, la, le, 0, 2 * it, dpend);
+        an = step(o1, 1, a2, s0, o0, false, la, le, 1, 2 * it + 1, dpend);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -841,7 +849,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         x = nx;
         e = ne;
     }
-    if constexpr (WD) {                  // D-hat chunks past the last step
+    if constexpr (WD) {                  // the last step's chunks, then those past the last step
+        dstore(dpend);
         for (int stp = 32 * nterms; 1024 * stp < kDChunks; ++stp) {
             DCopy dc;
             dload(stp, dc);
