@@ -50,19 +50,35 @@ __device__ __forceinline__ int xcd_contiguous_index() {
 __global__ __launch_bounds__(256) void k_tabulate(const double *__restrict__ coef, int lmax,
                                                   double h, double *__restrict__ table,
                                                   int n_nodes) {
+    // Per-degree factors of the recurrence, staged in LDS a chunk of degrees
+    // at a time by the whole workgroup: step l takes d <- A_l d - B_l y p with
+    // A_l = l / (l + 1), B_l = (2l + 1) / (l + 1), then p <- p + d (now
+    // P_{l+1}(1 - y)), and adds C_l p, C_l = (2l + 3) coef_{l+1} / 4 pi.
+    constexpr int kChunk = 1024;
+    __shared__ double sA[kChunk], sB[kChunk], sC[kChunk];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_nodes) return;
     const double s = (double)(i > 0 ? i - 1 : 1) * h;
     const double y = s * s;
     double p = 1.0;
     double acc = coef[0] * kInv4Pi;
-    double d = -y;
-    for (int l = 0; l < lmax; ++l) {
-        if (l > 0) d = ((double)l * d - (double)(2 * l + 1) * y * p) / (double)(l + 1);
-        p = p + d;
-        acc += (double)(2 * l + 3) * coef[l + 1] * kInv4Pi * p;
+    double d = 0.0;                      // step 0 gives d = -y (A_0 = 0, B_0 = 1)
+    for (int l0 = 0; l0 < lmax; l0 += kChunk) {
+        const int n = min(kChunk, lmax - l0);
+        __syncthreads();                 // the previous chunk is used up
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            const int l = l0 + t;
+            sA[t] = (double)l / (double)(l + 1);
+            sB[t] = (double)(2 * l + 1) / (double)(l + 1);
+            sC[t] = (double)(2 * l + 3) * coef[l + 1] * kInv4Pi;
+        }
+        __syncthreads();
+        for (int t = 0; t < n; ++t) {
+            d = sA[t] * d - sB[t] * y * p;
+            p = p + d;
+            acc += sC[t] * p;
+        }
     }
-    table[i] = acc;
+    if (i < n_nodes) table[i] = acc;
 }
 
 // 4-point Lagrange interpolation in s = sqrt(y) on nodes -1, 0, 1, 2 around
