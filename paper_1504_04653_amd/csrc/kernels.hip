@@ -619,11 +619,15 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // hm, mh, hl, lh, mm (smallest first), NP = 2 keeps hh, hm, mh.  MFMA
 // 16x16x32 BF16: lane (lr, lk) holds W[16 i + lr][p0 + 8 lk + 0..7] and
 // M[p0 + 8 lk + 0..7][16 j + lr]; the result holds members 16 i + 4 lk + v.
-// Eight waves per member tile.  Waves w and w + 4 share a SIMD and take the
-// output rows a = w mod 4, wave w < 4 the columns b < 32 and wave w + 4 the
-// columns b >= 32: a wave's own VALU work (forming and splitting M, the FP64
-// accumulation) does not overlap its MFMAs, but it does overlap those of the
-// other wave on its SIMD.  The operands all waves share (W of the tile's
+// Two waves run on each SIMD: a wave's own VALU work (forming and splitting M,
+// the FP64 accumulation) does not overlap its MFMAs, but it does overlap those
+// of the other wave on its SIMD.  Each wave holds half the columns of its
+// output rows.  Without D-hat (NW = 4) a workgroup of 4 waves takes a member
+// tile, wave w the rows a = w mod 2 and the column half w / 2, and two such
+// workgroups share a CU, so the two waves of a SIMD belong to different
+// workgroups and their steps drift apart.  With D-hat (NW = 8) one workgroup
+// of 8 waves takes the tile, wave w the rows a = w mod 4 and the column half
+// w / 4; there the copies run better with the larger workgroup.  The operands all waves share (W of the tile's
 // rows, the B_IK values of a step) are staged through LDS.  A step is 32
 // pixels (half a term); a term's FP32 sums are added to the FP64 accumulators
 // after its second step.
@@ -641,12 +645,14 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     const DevClass cl = pd.classes[cls];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int rw = wave & 3, ch = wave >> 2;          // row phase, column half
+    constexpr int NW = WD ? 8 : 4, NT = 64 * NW;     // waves, threads
+    constexpr int RP = NW / 2, RPW = 64 / RP;          // row phases, rows per wave
+    const int rw = wave % RP, ch = wave / RP;          // row phase, column half
     const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
     const int32_t *terms = pd.cterms + 2 * cl.term0;
 
-    for (int x = tid; x < 16 * NI * nterms; x += 512) {
+    for (int x = tid; x < 16 * NI * nterms; x += NT) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
@@ -661,18 +667,19 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 
     // Staging: W is 256 NP chunks of 16 bytes (part c >> 8, row (c & 255) >> 2,
     // chunk c & 3), B_IK of one step 512 chunks (row c >> 3, chunk c & 7).
-    // Thread t takes W chunks t + 512 r and B_IK chunk t; for NP = 3 the
-    // threads past the last W chunk repeat one (same value to the same LDS
-    // place), so every thread issues the same loads.  Rows past the tile's
-    // 16 NI members load the last member's values into LDS rows no wave reads.
-    constexpr int NWC = (256 * NP + 511) / 512;
+    // Thread t takes W chunks t + NT r and B_IK chunks t + NT q; with 512
+    // threads and NP = 3 the threads past the last W chunk repeat one (same
+    // value to the same LDS place), so every thread issues the same loads.
+    // Rows past the tile's 16 NI members load the last member's values into
+    // LDS rows no wave reads.
+    constexpr int NWC = (256 * NP + NT - 1) / NT, NUC = 512 / NT;
     const uint16_t *wsrc[NWC];
     int wrow[NWC], wdst[NWC];
     auto wsw = [](int r) { return ((r >> 1) ^ (r >> 3)) & 3; };
     auto usw = [](int b) { return ((b >> 1) ^ (b << 2)) & 7; };
 #pragma unroll
     for (int r = 0; r < NWC; ++r) {
-        int c = tid + 512 * r;
+        int c = tid + NT * r;
         if (c >= 256 * NP) c -= 256;
         const int k = __builtin_amdgcn_readfirstlane(c >> 8), q = c & 255, row = q >> 2, sub = q & 3;
         wsrc[r] = pd.w[k] + 8 * sub;
@@ -684,8 +691,13 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         // 16 lanes at a time over 64 banks.
         wdst[r] = (k * 64 + row) * 4 + (sub ^ wsw(row));
     }
-    const int ub = tid >> 3, uc = tid & 7;
-    const int usrc = ub * 64 + 4 * uc, udst = ub * 8 + (uc ^ usw(ub));
+    int usrc[NUC], udst[NUC];
+#pragma unroll
+    for (int q = 0; q < NUC; ++q) {
+        const int c = tid + NT * q, ub = c >> 3, uc = c & 7;
+        usrc[q] = ub * 64 + 4 * uc;
+        udst[q] = ub * 8 + (uc ^ usw(ub));
+    }
 
     // Addresses of one step (row a, term e, half h): W offsets of this
     // thread's staged chunks, B_IK rows of the term, and this lane's B_IJ
@@ -699,19 +711,21 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         r.p1 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 32 * h + 8 * lk;
         return r;
     };
-    struct Stage { u16x8 w[NWC]; floatx4 u; };
+    struct Stage { u16x8 w[NWC]; floatx4 u[NUC]; };
     struct Own { floatx4 u1[2]; };        // B_IJ values of this wave's output row (not shared)
     auto loads = [&](const Addr &ad, Stage &st, Own &o) {
 #pragma unroll
         for (int q = 0; q < NWC; ++q) st.w[q] = *(const u16x8 *)(wsrc[q] + ad.wo[q]);
-        st.u = *(const floatx4 *)(ad.u2 + usrc);
+#pragma unroll
+        for (int q = 0; q < NUC; ++q) st.u[q] = *(const floatx4 *)(ad.u2 + usrc[q]);
         o.u1[0] = *(const floatx4 *)ad.p1;
         o.u1[1] = *(const floatx4 *)(ad.p1 + 4);
     };
     auto stage_store = [&](const Stage &st, int buf) {
 #pragma unroll
         for (int q = 0; q < NWC; ++q) sW[buf * NP * 256 + wdst[q]] = st.w[q];
-        sU[buf * 512 + udst] = st.u;
+#pragma unroll
+        for (int q = 0; q < NUC; ++q) sU[buf * 512 + udst[q]] = st.u[q];
     };
     // D-hat copy: chunk c is 16 bytes (c & 2047) of member row c >> 11; a
     // wave's 64 chunks lie in one row, so the row index is uniform.
@@ -720,7 +734,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     auto dload = [&](int stp, DCopy &dc) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            const int c0 = __builtin_amdgcn_readfirstlane((2 * stp + r) * 512 + 64 * wave);
+            const int c0 = __builtin_amdgcn_readfirstlane((2 * stp + r) * NT + 64 * wave);
             const bool ok = c0 < kDChunks;
             const int m = ok ? c0 >> 11 : 0;
             const int off = 2 * ((c0 & 2047) + lane);
@@ -814,7 +828,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     };
 
     // Step h of a term computes from LDS buffer h.  Cursor: row index x
-    // (a = rw + 4 x) and term e; past the last row the loads repeat the last
+    // (a = rw + RP x) and term e; past the last row the loads repeat the last
     // term's addresses.
     Stage s0, s1;
     Own o0, o1;
@@ -828,15 +842,15 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     DCopy dpend;                           // D-hat chunks loaded, not yet stored
     dpend.blk[0] = dpend.blk[1] = -1;
     __syncthreads();
-    for (int it = 0; it < 16 * nterms; ++it) {
+    for (int it = 0; it < RPW * nterms; ++it) {
         int ne = e + 1, nx = x;
         if (ne == nterms) {
             ne = 0;
             ++nx;
         }
-        const int a = rw + 4 * x;
-        const bool last = nx >= 16;
-        const int la = last ? a : rw + 4 * nx, le = last ? e : ne;
+        const int a = rw + RP * x;
+        const bool last = nx >= RPW;
+        const int la = last ? a : rw + RP * nx, le = last ? e : ne;
         const Addr a2 = step(o0, 0, an, s1, o1, true, la, le, 0, 2 * it, dpend);
         an = step(o1, 1, a2, s0, o0, false, la, le, 1, 2 * it + 1, dpend);
 #pragma unroll
@@ -867,7 +881,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
         dstore(dpend);
-        for (int stp = 32 * nterms; 1024 * stp < kDChunks; ++stp) {
+        for (int stp = 2 * RPW * nterms; 2 * NT * stp < kDChunks; ++stp) {
             DCopy dc;
             dload(stp, dc);
             dstore(dc);
@@ -876,7 +890,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 }
 
 template <int NP, bool WD>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(WD ? 512 : 256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
@@ -945,8 +959,8 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
         if (prec == 2) hipLaunchKernelGGL((k_class_bf16<2, true>), grid, dim3(512), 0, st, pd);
         else hipLaunchKernelGGL((k_class_bf16<3, true>), grid, dim3(512), 0, st, pd);
     } else {
-        if (prec == 2) hipLaunchKernelGGL((k_class_bf16<2, false>), grid, dim3(512), 0, st, pd);
-        else hipLaunchKernelGGL((k_class_bf16<3, false>), grid, dim3(512), 0, st, pd);
+        if (prec == 2) hipLaunchKernelGGL((k_class_bf16<2, false>), grid, dim3(256), 0, st, pd);
+        else hipLaunchKernelGGL((k_class_bf16<3, false>), grid, dim3(256), 0, st, pd);
     }
     return hipGetLastError();
 }
