@@ -59,7 +59,9 @@ def parse():
     ap.add_argument("--op", default="btnb", choices=["btnb", "conv"],
                     help="btnb: the D-hat / B-hat^T N^-1 B-hat step (default); conv: the pixel-domain "
                          "convolution g = B-hat f")
-    ap.add_argument("--modes", default="bf16x6,fp64,bf16x3")
+    ap.add_argument("--modes", default=None,
+                    help="precision modes, the first is the headline (default bf16x6,fp64,bf16x3; "
+                         "for --config c5 bf16x6,fp32)")
     ap.add_argument("--separate", action="store_true",
                     help="sample D-hat and B^T N^-1 B with the two separate calls (default: the combined "
                          "call, one launch in the split-BF16 modes)")
@@ -68,7 +70,10 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES bytes (a reference "
                          "kernel of known traffic for HBM counter runs)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.modes is None:
+        args.modes = "bf16x6,fp32" if args.config == "c5" else "bf16x6,fp64,bf16x3"
+    return args
 
 
 def kernels_hash():
@@ -206,55 +211,66 @@ def run_batch(args):
         pr["out"] = torch.empty(pr["g"].out_len, dtype=torch.float64, device="cuda")
     nelem = sum(pr["g"].nblocks for pr in probs) * 4096
     alg_flop = sum(2.0 * 64 ** 3 * pr["g"].nterms for pr in probs)
-    bt = sp.Batch([(pr["g"], pr["kb"], pr["ninv_dev"], pr["out"]) for pr in probs], stream=stream)
-    chosen, tune_ms = bt.tune(stream)
-    sched = {v: k for k, v in sp.SCHEDULES.items()}[chosen]
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     print(f"# workload c5: 32 problems, npix={sum(pr['g'].npix for pr in probs)} "
-          f"nblocks={nelem // 4096} output={nelem * 8 / 1e9:.1f} GB setup={setup:.1f}s; "
-          f"tune ms {[round(t, 2) for t in tune_ms]} -> {sched}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        bt.launch(stream)
-    torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    t_start = time.perf_counter()
-    evs[0].record(stream)
-    for i in range(args.steps):
-        bt.launch(stream)
-        evs[i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
-    ms_step = wall * 1000.0 / args.steps
-    achieved = alg_flop / (ms.mean() * 1e-3) / 1e12
-    print(f"# c5 batch ({sched}): step {ms_step:.2f} ms wall, {ms.mean():.2f} ms per graph launch, "
-          f"{achieved:.1f} TFLOP/s ({achieved / PEAK['fp32'] * 100:.1f}% of FP32 MFMA peak)",
-          file=sys.stderr, flush=True)
+          f"nblocks={nelem // 4096} output={nelem * 8 / 1e9:.1f} GB setup={setup:.1f}s", file=sys.stderr, flush=True)
+    results = {}
+    for prec in modes:
+        bt = sp.Batch([(pr["g"], pr["kb"], pr["ninv_dev"], pr["out"]) for pr in probs], prec=prec, stream=stream)
+        chosen, tune_ms = bt.tune(stream)
+        sched = {v: k for k, v in sp.SCHEDULES.items()}[chosen]
+        for _ in range(args.warmup):
+            bt.launch(stream)
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        t_start = time.perf_counter()
+        evs[0].record(stream)
+        for i in range(args.steps):
+            bt.launch(stream)
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        bt.close()
+        ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+        ms_step = wall * 1000.0 / args.steps
+        achieved = PRODUCTS[prec] * alg_flop / (ms.mean() * 1e-3) / 1e12
+        kern = {"fp32": ("k_batch_f32", "k_class_f32"), "bf16x6": ("k_batch_bf16<3>", "k_class_bf16<3, false>"),
+                "bf16x3": ("k_batch_bf16<2>", "k_class_bf16<2, false>")}[prec][1 if chosen == 2 else 0]
+        results[prec] = {
+            "elements_per_s": nelem / (ms_step * 1e-3), "ms_per_step": ms_step, "graph_launch_ms": ms.mean(),
+            "schedule": sched, "tune_ms": [round(t, 3) for t in tune_ms],
+            "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec], "achieved": achieved,
+                         "frac": achieved / PEAK[prec], "kernel": kern,
+                         "traffic": recorded_traffic(prec, "c5")},
+        }
+        print(f"# c5 batch {prec} ({sched}; tune ms {[round(t, 2) for t in tune_ms]}): step {ms_step:.2f} ms wall, "
+              f"{ms.mean():.2f} ms per graph launch, {achieved:.1f} TFLOP/s "
+              f"({achieved / PEAK[prec] * 100:.1f}% of {PEAK[prec]} TFLOP/s)", file=sys.stderr, flush=True)
+    head = results[modes[0]]
     line = {
-        "metric": "B^T N^-1 B elements/s, 32-problem batch in one graph launch (FP32 MFMA)",
-        "value": nelem / (ms_step * 1e-3),
+        "metric": "B^T N^-1 B elements/s, 32-problem batch in one graph launch",
+        "value": head["elements_per_s"],
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if modes[0].startswith("bf16") else "f32",
         "data": "synthetic",
         "config": {"workload": "sympix batch: 32 problems, lmax 256/512/1024/2048 (8 each), "
                                "beam FWHM U[2,5] px cut 3 FWHM, N^-1 U[0.5,2] x cap mask U[0,0.3], "
                                "seeds 5000+p",
                    "problems": 32, "npix": int(sum(pr["g"].npix for pr in probs)),
-                   "nblocks": int(nelem // 4096), "schedule": sched,
-                   "tune_ms": [round(t, 3) for t in tune_ms], "setup_s": round(setup, 2)},
-        "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK["fp32"], "achieved": achieved,
-                     "frac": achieved / PEAK["fp32"], "kernel": "k_batch_f32" if chosen != 2 else "k_class_f32",
-                     "traffic": recorded_traffic("fp32", "c5")},
+                   "nblocks": int(nelem // 4096), "precision": modes[0], "schedule": head["schedule"],
+                   "tune_ms": head["tune_ms"], "setup_s": round(setup, 2)},
+        "roofline": head["roofline"],
+        "modes": results,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_batch(probs, args.cpu_seconds)
-    bt.close()
     print(json.dumps(line), flush=True)
 
 

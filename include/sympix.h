@@ -207,11 +207,11 @@ sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d,
 
 /* ---- Batches: many B-hat^T N^-1 B-hat problems in one graph launch ----------
  * Eq. 15 evaluated for n independent problems (own grid, beam kernel, N^-1 and
- * output each) by one captured HIP graph: a persistent FP32-MFMA contraction
- * (FP64 accumulation across contraction tiles, as SYMPIX_FP32) pulls
- * (problem, 64-block tile) work items from per-XCD queues.  Results are
- * bitwise identical to sympix_sample_BtNB(..., SYMPIX_FP32, ...) per problem,
- * under every schedule. */
+ * output each) by one captured HIP graph: a persistent contraction in FP32
+ * MFMA or split-BF16 MFMA (FP64 accumulation across contraction tiles, as the
+ * single-problem modes) pulls (problem, 64-block tile) work items from
+ * per-XCD queues.  Results are bitwise identical to sympix_sample_BtNB(...,
+ * prec, ...) per problem, under every schedule. */
 typedef struct sympix_batch sympix_batch;
 
 typedef struct {
@@ -232,13 +232,14 @@ typedef enum {
 
 /* Build a batch over problems p[0..n) (copied; the buffers they point to must
  * stay allocated, and the grids and kernels alive, until the batch is
- * destroyed) and capture its graph with the default schedule.  prec must be
- * SYMPIX_FP32.  The batch owns its device tables and FP32 N^-1 scratch
- * (4 npix bytes per problem).  stream: the call synchronises it once while
+ * destroyed) and capture its graph with the default schedule.  prec:
+ * SYMPIX_FP32, SYMPIX_BF16X3 or SYMPIX_BF16X6.  The batch owns its device
+ * tables and its N^-1 operand scratch (4 npix bytes per problem in FP32, 6 in
+ * the split-BF16 modes).  stream: the call synchronises it once while
  * uploading tables.
  * Errors: EINVAL (NULL, n < 1, misaligned or overlapping outputs, problems on
- * another device), ESIZE (a length mismatch), EUNSUPPORTED (prec other than
- * FP32, k != 8), ENOMEM, EHIP. */
+ * another device), ESIZE (a length mismatch), EUNSUPPORTED (prec SYMPIX_FP64,
+ * k != 8), ENOMEM, EHIP. */
 sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t prec, void *stream,
                                   sympix_batch **out);
 
@@ -251,8 +252,8 @@ sympix_status sympix_batch_set_schedule(sympix_batch *bt, int32_t s);
  * choice is remembered for batches of the same shape in this process. */
 sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen, double *ms_out);
 
-/* Enqueue the batch's graph on stream: converts every N^-1 to FP32 and writes
- * every output.  Launches on one device must not overlap in time (they share
+/* Enqueue the batch's graph on stream: converts every N^-1 to the operand
+ * format (FP32, or BF16 parts) and writes every output.  Launches on one device must not overlap in time (they share
  * the batch's queue counters and scratch). */
 sympix_status sympix_batch_launch(sympix_batch *bt, void *stream);
 

@@ -294,7 +294,7 @@ def raw_call(name):
 
 
 class Batch:
-    """Many B-hat^T N^-1 B-hat problems (FP32 mode) in one captured graph.
+    """Many B-hat^T N^-1 B-hat problems (FP32 or split-BF16 mode) in one captured graph.
 
     problems: sequence of (grid, kernel, ninv, out) with ninv / out contiguous
     float64 CUDA tensors.  The batch keeps references to all of them."""

@@ -579,9 +579,12 @@ sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d,
 struct sympix_batch {
     int device = 0;
     int32_t nprob = 0;
+    int32_t prec = SYMPIX_FP32;
     int32_t schedule = SYMPIX_SCHED_XCD_QUEUES;
     int32_t nworkgroups = 0;
-    std::vector<sympix::ProblemDesc> hdesc;
+    std::vector<sympix::ProblemDesc> hdesc;        // FP32
+    std::vector<sympix::ProblemDescB> hdescb;      // split BF16
+    std::vector<uint16_t *> wsplit;                // split BF16: 3 N^-1 parts per problem
     std::vector<const double *> ninv;
     std::vector<int64_t> npix, nmtiles;
     std::vector<int32_t> item_prob, item_tile, item_cost;   // natural order
@@ -590,6 +593,8 @@ struct sympix_batch {
     int32_t *d_qb = nullptr;
     int32_t *d_counters = nullptr;
     float *d_wf = nullptr;
+    sympix::ProblemDescB *d_descb = nullptr;
+    uint16_t *d_wsplit = nullptr;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -612,6 +617,8 @@ void free_batch(sympix_batch *bt) {
     hipFree(bt->d_qb);
     hipFree(bt->d_counters);
     hipFree(bt->d_wf);
+    hipFree(bt->d_descb);
+    hipFree(bt->d_wsplit);
     delete bt;
 }
 
@@ -657,7 +664,11 @@ sympix_status capture_batch(sympix_batch *bt, int32_t s) {
 
     sympix::BatchLaunch bl;
     bl.nprob = bt->nprob;
+    bl.prec = bt->prec;
     bl.host_desc = bt->hdesc.data();
+    bl.host_descb = bt->hdescb.data();
+    bl.wsplit = bt->wsplit.data();
+    bl.descb = bt->d_descb;
     bl.ninv = bt->ninv.data();
     bl.npix = bt->npix.data();
     bl.nmtiles = bt->nmtiles.data();
@@ -700,7 +711,8 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!p || n < 1) return fail(SYMPIX_EINVAL, "need at least one problem");
-    if (prec != SYMPIX_FP32) return fail(SYMPIX_EUNSUPPORTED, "batches run in SYMPIX_FP32 only");
+    if (prec != SYMPIX_FP32 && prec != SYMPIX_BF16X3 && prec != SYMPIX_BF16X6)
+        return fail(SYMPIX_EUNSUPPORTED, "batches run in SYMPIX_FP32, SYMPIX_BF16X3 or SYMPIX_BF16X6");
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int32_t i = 0; i < n; ++i) {
         sympix_status s = check_kernel_use(p[i].g, p[i].b);
@@ -728,6 +740,8 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     if (!bt) return fail(SYMPIX_ENOMEM, "host allocation");
     bt->device = p[0].b->device;
     bt->nprob = n;
+    bt->prec = prec;
+    const bool bf16 = prec != SYMPIX_FP32;
     hipError_t e = hipSuccess;
     int64_t wf_total = 0;
     std::string shape;
@@ -738,9 +752,9 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
             free_batch(bt);
             return hip_fail(e, "hipGetDeviceProperties");
         }
-        shape = std::string(prop.gcnArchName) + "|fp32";
+        shape = std::string(prop.gcnArchName) + (bf16 ? (prec == SYMPIX_BF16X3 ? "|bf16x3" : "|bf16x6") : "|fp32");
         int occ = 0;
-        e = sympix::batch_occupancy(&occ);
+        e = sympix::batch_occupancy(prec, &occ);
         if (e != hipSuccess) {
             free_batch(bt);
             return hip_fail(e, "occupancy query");
@@ -758,6 +772,9 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
         sympix::ProblemDesc d{dg->mtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
                               p[i].b->ut32, nullptr, p[i].out_dev};
         bt->hdesc.push_back(d);
+        sympix::ProblemDescB db{dg->mtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
+                                p[i].b->ut32, {nullptr, nullptr, nullptr}, p[i].out_dev, nullptr, nullptr, nullptr};
+        bt->hdescb.push_back(db);
         bt->ninv.push_back(p[i].ninv_dev);
         bt->npix.push_back(geo.npix);
         const int64_t nmt = (int64_t)geo.mtiles.size() / 4;
@@ -780,7 +797,13 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_items, std::max<int64_t>(1, 2 * nitems) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_qb, (kBatchQueues + 1) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_counters, kBatchQueues * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_wf, std::max<int64_t>(1, wf_total) * sizeof(float));
+    if (bf16) {
+        if (e == hipSuccess) e = hipMalloc((void **)&bt->d_descb, n * sizeof(sympix::ProblemDescB));
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&bt->d_wsplit, std::max<int64_t>(1, 3 * wf_total) * sizeof(uint16_t));
+    } else if (e == hipSuccess) {
+        e = hipMalloc((void **)&bt->d_wf, std::max<int64_t>(1, wf_total) * sizeof(float));
+    }
     if (e != hipSuccess) {
         free_batch(bt);
         return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the batch")
@@ -788,10 +811,20 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     }
     int64_t off = 0;
     for (int32_t i = 0; i < n; ++i) {
-        bt->hdesc[i].wf = bt->d_wf + off;
+        if (bf16) {
+            for (int k = 0; k < 3; ++k) {
+                uint16_t *w = bt->d_wsplit + k * wf_total + off;
+                bt->hdescb[i].w[k] = w;
+                bt->wsplit.push_back(w);
+            }
+        } else {
+            bt->hdesc[i].wf = bt->d_wf + off;
+        }
         off += bt->npix[i];
     }
     e = hipMemcpy(bt->d_desc, bt->hdesc.data(), n * sizeof(sympix::ProblemDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess && bf16)
+        e = hipMemcpy(bt->d_descb, bt->hdescb.data(), n * sizeof(sympix::ProblemDescB), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {

@@ -105,11 +105,18 @@ struct ProblemDesc {
     double *out;
 };
 
-// a10: one batched launch.  host_desc / ninv / npix / nmtiles are host arrays
-// of nprob entries; desc, items, qb and counters live on the device.
+// a10: one batched launch.  host_desc / host_descb / ninv / npix / nmtiles /
+// wsplit are host arrays of nprob entries (wsplit: 3 per problem); desc,
+// descb, items, qb and counters live on the device.  prec: 1 FP32 (desc,
+// host_desc), 2 or 3 split BF16 with that many parts (descb, host_descb, and
+// the N^-1 parts in wsplit).
 struct BatchLaunch {
     int32_t nprob;
+    int32_t prec;
     const ProblemDesc *host_desc;
+    const ProblemDescB *host_descb;
+    uint16_t *const *wsplit;
+    const ProblemDescB *descb;
     const double *const *ninv;
     const int64_t *npix;
     const int64_t *nmtiles;
@@ -123,6 +130,6 @@ struct BatchLaunch {
     int32_t nworkgroups;
 };
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t st);
-hipError_t batch_occupancy(int *workgroups_per_cu);
+hipError_t batch_occupancy(int prec, int *workgroups_per_cu);
 
 }  // namespace sympix

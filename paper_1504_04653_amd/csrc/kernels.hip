@@ -17,6 +17,7 @@
 //                  launch fed by per-XCD work queues
 //   k_split_ninv   N^-1 split into BF16 parts
 //   k_class_bf16   the same GEMM in split BF16
+//   k_batch_bf16   many problems in one persistent launch, split BF16
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -554,7 +555,7 @@ void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restric
             sItem = it;
         }
         __syncthreads();
-        const int it = sItem;
+        const int it = __builtin_amdgcn_readfirstlane(sItem);   // uniform: descriptors in scalar registers
         __syncthreads();                 // every thread has read sItem before it changes
         if (it < 0) break;
         const ProblemDesc pd = probs[items[2 * it]];
@@ -889,6 +890,17 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     }
 }
 
+// One member tile (item) of one problem; sTile, sBlk, sTerm, sW and sU are the
+// workgroup's LDS tables and staging buffers.
+template <int NP, bool WD>
+__device__ __forceinline__ void class_bf16_item(const ProblemDescB &pd, int item, int32_t *sTile, int32_t *sBlk,
+                                                int32_t *sTerm, u16x8 *sW, floatx4 *sU) {
+    const int groups = pd.mtiles[4 * item + 2];
+    if (groups == 4) class_bf16_tile<NP, 4, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    else if (groups == 2) class_bf16_tile<NP, 2, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    else class_bf16_tile<NP, 1, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
+}
+
 template <int NP, bool WD>
 __global__ __launch_bounds__(WD ? 512 : 256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_class_bf16(ProblemDescB pd) {
@@ -897,11 +909,44 @@ void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ u16x8 sW[2 * NP * 64 * 4];            // staged W, two buffers
     __shared__ floatx4 sU[2 * 512];                  // staged B_IK values, two buffers
-    const int item = xcd_contiguous_index();
-    const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_bf16_tile<NP, 4, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
-    else if (groups == 2) class_bf16_tile<NP, 2, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
-    else class_bf16_tile<NP, 1, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    class_bf16_item<NP, WD>(pd, xcd_contiguous_index(), sTile, sBlk, sTerm, sW, sU);
+}
+
+// Many problems in one persistent launch, split BF16 (the queues and their
+// draining as in k_batch_f32; two workgroups of 4 waves per CU).
+template <int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_batch_bf16(const ProblemDescB *__restrict__ probs, const int32_t *__restrict__ items,
+                  const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
+    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sBlk[128];
+    __shared__ int32_t sTerm[2 * kMaxClassTerms];
+    __shared__ u16x8 sW[2 * NP * 64 * 4];
+    __shared__ floatx4 sU[2 * 512];
+    __shared__ int32_t sItem;
+    const int home = blockIdx.x % nq;
+    int tried = 0;                       // queues found empty (thread 0)
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tried < nq) {
+                const int q = (home + tried) % nq;
+                const int c = atomicAdd(&counters[q], 1);
+                if (c < qb[q + 1] - qb[q]) {
+                    it = qb[q] + c;
+                    break;
+                }
+                ++tried;
+            }
+            sItem = it;
+        }
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(sItem);   // uniform: descriptors in scalar registers
+        __syncthreads();                 // every thread has read sItem before it changes
+        if (it < 0) break;
+        const ProblemDescB pd = probs[items[2 * it]];
+        class_bf16_item<NP, false>(pd, items[2 * it + 1], sTile, sBlk, sTerm, sW, sU);
+    }
 }
 
 }  // namespace
@@ -967,25 +1012,46 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
 
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.counters, b.nq, 0);
-    for (int p = 0; p < b.nprob; ++p)
-        if (b.npix[p] > 0)
-            hipLaunchKernelGGL(k_ninv_f32, dim3((unsigned)((b.npix[p] + 255) / 256)), dim3(256), 0, st,
-                               b.ninv[p], b.npix[p], b.host_desc[p].wf);
+    const bool bf16 = b.prec != 1;
+    for (int p = 0; p < b.nprob; ++p) {
+        if (b.npix[p] == 0) continue;
+        const dim3 g((unsigned)((b.npix[p] + 255) / 256));
+        if (!bf16) {
+            hipLaunchKernelGGL(k_ninv_f32, g, dim3(256), 0, st, b.ninv[p], b.npix[p], b.host_desc[p].wf);
+        } else {
+            uint16_t *const *w = b.wsplit + 3 * p;
+            hipLaunchKernelGGL(k_split_ninv, g, dim3(256), 0, st, b.ninv[p], b.npix[p], w[0], w[1], w[2]);
+        }
+    }
     if (b.persistent) {
-        if (b.nitems > 0)
-            hipLaunchKernelGGL(k_batch_f32, dim3((unsigned)b.nworkgroups), dim3(256), 0, st, b.desc,
-                               b.items, b.qb, b.nq, b.counters);
+        if (b.nitems > 0) {
+            const dim3 g((unsigned)b.nworkgroups);
+            if (!bf16)
+                hipLaunchKernelGGL(k_batch_f32, g, dim3(256), 0, st, b.desc, b.items, b.qb, b.nq, b.counters);
+            else if (b.prec == 2)
+                hipLaunchKernelGGL(k_batch_bf16<2>, g, dim3(256), 0, st, b.descb, b.items, b.qb, b.nq, b.counters);
+            else
+                hipLaunchKernelGGL(k_batch_bf16<3>, g, dim3(256), 0, st, b.descb, b.items, b.qb, b.nq, b.counters);
+        }
     } else {
-        for (int p = 0; p < b.nprob; ++p)
-            if (b.nmtiles[p] > 0)
-                hipLaunchKernelGGL(k_class_f32, dim3((unsigned)b.nmtiles[p]), dim3(256), 0, st,
-                                   b.host_desc[p]);
+        for (int p = 0; p < b.nprob; ++p) {
+            if (b.nmtiles[p] == 0) continue;
+            const dim3 g((unsigned)b.nmtiles[p]);
+            if (!bf16)
+                hipLaunchKernelGGL(k_class_f32, g, dim3(256), 0, st, b.host_desc[p]);
+            else if (b.prec == 2)
+                hipLaunchKernelGGL((k_class_bf16<2, false>), g, dim3(256), 0, st, b.host_descb[p]);
+            else
+                hipLaunchKernelGGL((k_class_bf16<3, false>), g, dim3(256), 0, st, b.host_descb[p]);
+        }
     }
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int *workgroups_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f32, 256, 0);
+hipError_t batch_occupancy(int prec, int *workgroups_per_cu) {
+    if (prec == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f32, 256, 0);
+    if (prec == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<2>, 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<3>, 256, 0);
 }
 
 hipError_t launch_convolve(const double *u64, const int32_t *chunks, int64_t nchunks, const int32_t *slots,

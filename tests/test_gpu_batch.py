@@ -1,10 +1,12 @@
-"""GPU parity of batched launches: many B-hat^T N^-1 B-hat problems (FP32 MFMA,
-FP64 accumulation across contraction tiles) in one captured graph.
+"""GPU parity of batched launches: many B-hat^T N^-1 B-hat problems (FP32 or
+split-BF16 MFMA, FP64 accumulation across contraction tiles) in one captured
+graph.
 
-Every schedule must give results bitwise identical to the single-problem FP32
-path (each work item is computed by the same arithmetic whichever workgroup
-takes it), and those results must meet the FP32 gate against the oracle.
-Graph replays are checked with eager work and synchronisations in between.
+Every schedule must give results bitwise identical to the single-problem path
+of the same mode (each work item is computed by the same arithmetic whichever
+workgroup takes it), and those results must meet the mode's gate against the
+oracle.  Graph replays are checked with eager work and synchronisations in
+between.
 """
 import sys
 
@@ -22,7 +24,8 @@ from _parity import block_index, error_report, stored_pairs
 
 pytestmark = pytest.mark.gpu
 
-GATE_FP32 = 1e-6
+GATE = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 2.0 ** -15}
+BATCH_MODES = ["fp32", "bf16x6", "bf16x3"]
 
 # (lmax, problem index whose beam / mask draws are used): mixed sizes, with
 # two problems on one grid
@@ -64,20 +67,27 @@ def make_problems(spec):
     return probs
 
 
-def single_fp32(p):
+def single(p, prec):
     out = torch.empty(p["g"].out_len, dtype=torch.float64, device="cuda")
-    sp.sample_BtNB(p["g"], p["kb"], p["ninv_dev"], out, "fp32")
+    sp.sample_BtNB(p["g"], p["kb"], p["ninv_dev"], out, prec)
     torch.cuda.synchronize()
     return out
 
 
 @pytest.fixture(scope="module")
-def small():
+def problems():
     probs = make_problems(SMALL)
-    bt = sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]) for p in probs])
-    ref = [single_fp32(p) for p in probs]
     say("[batch] problems " + ", ".join(f"lmax {p['g'].lmax}: {p['g'].nblocks} blocks" for p in probs))
-    yield dict(probs=probs, bt=bt, ref=ref)
+    return probs
+
+
+@pytest.fixture(scope="module", params=BATCH_MODES)
+def small(request, problems):
+    prec = request.param
+    probs = problems
+    bt = sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]) for p in probs], prec=prec)
+    ref = [single(p, prec) for p in probs]
+    yield dict(probs=probs, bt=bt, ref=ref, prec=prec)
     bt.close()
 
 
@@ -88,14 +98,14 @@ def launch_and_check(small, tag):
     small["bt"].launch()
     torch.cuda.synchronize()
     for i, (p, r) in enumerate(zip(small["probs"], small["ref"])):
-        assert torch.equal(p["out"], r), f"{tag}: problem {i} differs from the single-problem FP32 path"
+        assert torch.equal(p["out"], r), f"{tag}: problem {i} differs from the single-problem {small['prec']} path"
 
 
 @pytest.mark.parametrize("schedule", ["xcd_queues", "global_lpt", "per_problem"])
 def test_every_schedule_matches_single_problem_path(small, schedule):
     small["bt"].set_schedule(schedule)
     launch_and_check(small, schedule)
-    say(f"[batch] schedule {schedule}: bitwise equal to sample_BtNB fp32 for {len(small['probs'])} problems")
+    say(f"[batch {small['prec']}] schedule {schedule}: bitwise equal to sample_BtNB for {len(small['probs'])} problems")
 
 
 def test_single_problem_path_against_oracle(small):
@@ -104,8 +114,8 @@ def test_single_problem_path_against_oracle(small):
         rows = [J for J, _ in pairs]
         Cref = O.sample_BtNB(p["og"], p["b_l"], p["ninv"], p["R"], pairs)
         rep = error_report(r.view(-1, 64, 64).cpu().numpy(), Cref, rows)
-        say(f"[batch] problem {i} lmax {p['g'].lmax}: {rep}")
-        assert rep["gate"] <= GATE_FP32
+        say(f"[batch {small['prec']}] problem {i} lmax {p['g'].lmax}: {rep}")
+        assert rep["gate"] <= GATE[small["prec"]]
 
 
 def test_graph_replays_with_eager_work_between(small):
@@ -119,7 +129,7 @@ def test_graph_replays_with_eager_work_between(small):
 
 def test_tune_picks_a_schedule_and_keeps_results(small):
     chosen, ms = small["bt"].tune()
-    say(f"[batch] tune: chosen {chosen}, ms per schedule {ms}")
+    say(f"[batch {small['prec']}] tune: chosen {chosen}, ms per schedule {ms}")
     assert chosen in (0, 1, 2)
     assert all(t > 0 for t in ms)
     assert ms[chosen] == min(ms)
@@ -159,14 +169,15 @@ def c5_rows(og, seed):
     return sorted(rows)
 
 
-def test_c5_full_batch_sampled():
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_c5_full_batch_sampled(prec):
     spec = [(S.BATCH_LMAX[p % 4], p) for p in range(32)]
     probs = make_problems(spec)
     total = sum(p["g"].nblocks for p in probs) * 4096 * 8
-    say(f"[c5] 32 problems, {sum(p['g'].npix for p in probs)} pixels, output {total / 1e9:.1f} GB")
-    bt = sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]) for p in probs])
+    say(f"[c5 {prec}] 32 problems, {sum(p['g'].npix for p in probs)} pixels, output {total / 1e9:.1f} GB")
+    bt = sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]) for p in probs], prec=prec)
     chosen, ms = bt.tune()
-    say(f"[c5] tune: chosen {chosen}, ms per schedule {[round(t, 2) for t in ms]}")
+    say(f"[c5 {prec}] tune: chosen {chosen}, ms per schedule {[round(t, 2) for t in ms]}")
     for p in probs:
         p["out"].fill_(float("nan"))
     bt.launch()
@@ -182,10 +193,10 @@ def test_c5_full_batch_sampled():
         C = p["out"].view(-1, 64, 64)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
         rep = error_report(C, Cref, [J for J, _ in pairs])
         worst = max(worst, rep["gate"])
-        say(f"[c5] problem {i} lmax {g.lmax}: {len(idx)} blocks, {rep}")
-        assert rep["gate"] <= GATE_FP32
+        say(f"[c5 {prec}] problem {i} lmax {g.lmax}: {len(idx)} blocks, {rep}")
+        assert rep["gate"] <= GATE[prec]
         assert not bool(torch.isnan(p["out"]).any()), f"problem {i}: a block was not written"
-    say(f"[c5] worst gate {worst:.3e}")
+    say(f"[c5 {prec}] worst gate {worst:.3e}")
     bt.close()
     for p in probs:
         del p["out"]

@@ -25,7 +25,7 @@ from _parity import block_index, config_inputs, error_report, sample_rows
 
 pytestmark = pytest.mark.gpu
 
-GATE = {"fp64": 1e-10, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1e-5}
+GATE = {"fp64": 1e-10, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 2.0 ** -15}
 MODES = ("fp64", "fp32", "bf16x6", "bf16x3")
 
 

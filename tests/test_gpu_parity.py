@@ -2,7 +2,9 @@
 
 Gates (max |GPU - oracle| / M_J, M_J the largest oracle value of block-row J):
 FP64 1e-10; FP32 and BF16X6 1e-6.  BF16X3 (two-part split) is reported and
-held to 1e-5.  Every test prints the per-element error distribution.
+held to 2^-15: its products err by up to about 2^-16, and a sum may be half the
+sum of its absolute products.  Every test prints the per-element error
+distribution.
 """
 import math
 import sys
@@ -22,7 +24,7 @@ from _parity import block_index, config_inputs, error_report, gate, sample_rows,
 
 pytestmark = pytest.mark.gpu
 
-GATE = {"fp64": 1e-10, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1e-5}
+GATE = {"fp64": 1e-10, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 2.0 ** -15}
 
 
 def say(*a):
