@@ -46,7 +46,7 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}     # T
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}                   # MFMA products per term
 HBM_PEAK = 8000.0                                                              # GB/s
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAME = {"fp64": "k_class_f64", "fp32": "k_class_f32", "bf16x3": "k_class_bf16<2, false>",
+KERNEL_NAME = {"fp64": "k_class_f64<false>", "fp32": "k_class_f32<false>", "bf16x3": "k_class_bf16<2, false>",
                "bf16x6": "k_class_bf16<3, false>"}
 
 
@@ -64,7 +64,7 @@ def parse():
                          "for --config c5 bf16x6,fp32)")
     ap.add_argument("--separate", action="store_true",
                     help="sample D-hat and B^T N^-1 B with the two separate calls (default: the combined "
-                         "call, one launch in the split-BF16 modes)")
+                         "call, one launch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -427,10 +427,7 @@ def main():
         return r_mfma
 
     def fused_mode(prec):
-        # the combined call is one launch in the split-BF16 modes; in FP32 /
-        # FP64 it runs the two kernels in turn, so the separate calls (timed
-        # apart) are used there
-        return not args.separate and prec in ("bf16x3", "bf16x6")
+        return not args.separate
 
     def step(prec, ev):
         ev[0].record(stream)
@@ -469,7 +466,7 @@ def main():
                          e[0].elapsed_time(e[3])] for e in evs])   # ms
         t_tab, t_a, t_b, t_step = seg.mean(axis=0)
         # separate calls: t_a = D-hat, t_b = contraction; combined call: t_a =
-        # both outputs (one launch in the split-BF16 modes)
+        # both outputs (one launch)
         fused = fused_mode(prec)
         t_D, t_C = (None, t_a) if fused else (t_a, t_b)
         ms_step = wall * 1000.0 / args.steps
@@ -501,9 +498,8 @@ def main():
 
     head = HEADLINE if HEADLINE in results else modes[0]
     hr = results[head]
-    # the committed counter rows are taken on the default step (combined call
-    # in the split-BF16 modes)
-    traffic = recorded_traffic(head, args.config) if not (args.separate and head.startswith("bf16")) else None
+    # the committed counter rows are taken on the default step (combined call)
+    traffic = recorded_traffic(head, args.config) if not args.separate else None
     roof = dict(hr["btnb_roofline"])
     roof["kernel"] = KERNEL_NAME[head]
     if hr["D_and_btnb_one_launch"]:

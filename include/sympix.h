@@ -192,10 +192,9 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
 /* Both local operators of Eq. 16 in one call: outD_dev receives the D-hat
  * blocks of kernel d (as sympix_sample_D) and outC_dev the B-hat^T N^-1 B-hat
  * blocks of kernel b (as sympix_sample_BtNB with the same prec), bitwise equal
- * to the two separate calls.  In the split-BF16 modes one launch writes both:
- * the D-hat copies, bound by HBM writes, proceed under the contraction's
- * arithmetic.  In the FP32 and FP64 modes the D-hat expansion runs first, on
- * the same stream.  outD_dev and outC_dev: device, float64, nblocks k^4 values
+ * to the two separate calls.  One launch writes both: the D-hat copies, bound
+ * by HBM writes, proceed under the contraction's arithmetic.  outD_dev and
+ * outC_dev: device, float64, nblocks k^4 values
  * each, stored-block order, 16-byte aligned, not overlapping each other or
  * ninv_dev.  Both kernels must belong to g and live on the current device.
  * Errors: EINVAL (NULL, overlap, misalignment, kernel of another grid or

@@ -245,8 +245,7 @@ sympix_status check_kernel_use(const sympix_grid *g, const sympix_kernel *kr) {
 }
 
 // B-hat^T N^-1 B-hat into out_dev and, with a D-hat kernel d, the D-hat
-// blocks into outD_dev: in the split-BF16 modes one launch writes both, in
-// the FP32 / FP64 modes the D-hat expansion runs first on the same stream.
+// blocks into outD_dev, both written by one class-GEMM launch.
 sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sympix_kernel *b,
                           const double *ninv_dev, int64_t ninv_len, int32_t prec, double *outD_dev,
                           int64_t outD_len, double *out_dev, int64_t out_len, void *stream, const char *what) {
@@ -276,13 +275,7 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
     hipStream_t st = (hipStream_t)stream;
     if (geo.max_class_terms > sympix::kMaxClassTerms)
         return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
-    const bool fused = d && (prec == SYMPIX_BF16X3 || prec == SYMPIX_BF16X6);
-    if (d && !fused) {
-        s = after_launch(sympix::launch_expand(d->u64, dg->exp_items, (int64_t)geo.exp_items.size() / 4,
-                                               dg->exp_blk, outD_dev, st),
-                         st, what);
-        if (s != SYMPIX_OK) return s;
-    }
+    const bool fused = d != nullptr;
     sympix::BtnbArgs a;
     a.u64t = b->u64t;
     a.ut32 = b->ut32;

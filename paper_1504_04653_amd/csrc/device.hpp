@@ -64,7 +64,7 @@ struct BtnbArgs {
     int64_t nblocks;
     const double *ninv;
     double *out;
-    // optional D-hat blocks written by the same launch (split-BF16 modes):
+    // optional D-hat blocks written by the same launch:
     // stored block n gets unique block blk_uid[n] of du64 (row-major FP64)
     const double *du64;
     const int32_t *blk_uid;
@@ -80,6 +80,9 @@ struct ProblemDesc64 {
     const double *u64t;
     const double *w;          // N^-1
     double *out;
+    const double *du64;       // D-hat: unique blocks, row-major FP64 (with outD)
+    const int32_t *blk_uid;   // unique block of each stored block
+    double *outD;             // D-hat output, or nullptr
 };
 
 // Operands of the split-BF16 class GEMM (device pointers).
@@ -103,6 +106,9 @@ struct ProblemDesc {
     const float *ut32;
     float *wf;                // N^-1 rounded to FP32 (written by the launch)
     double *out;
+    const double *du64;       // D-hat: unique blocks, row-major FP64 (with outD)
+    const int32_t *blk_uid;   // unique block of each stored block
+    double *outD;             // D-hat output, or nullptr
 };
 
 // a10: one batched launch.  host_desc / host_descb / ninv / npix / nmtiles /

@@ -233,6 +233,44 @@ __global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64
 }
 
 // ---------------------------------------------------------------------------
+// D-hat copies made by a class-GEMM launch for the stored blocks of its tile
+// (the combined call): each stored block gets its unique D-hat block
+// (row-major FP64).  Chunk c of a tile is 16 bytes (c & 2047) of member row
+// c >> 11; a wave's 64 chunks lie in one row, so the row is uniform.  Step stp
+// of a workgroup of NT threads loads chunks [2 NT stp, 2 NT (stp + 1)), two per
+// thread; they are stored one step later, right after that step's loads:
+// stores and loads share one wait counter, and a store placed there is waited
+// for only by the next step's operand wait.  sBlk[m] is the stored block of
+// member row m (-1: none), sBlk[64 + m] its unique D-hat block.
+// ---------------------------------------------------------------------------
+struct DCopy {
+    doublex2 v[2];
+    int blk[2], off[2];
+};
+
+template <int NT>
+__device__ __forceinline__ void dcopy_load(const double *__restrict__ du64, const int32_t *sBlk, int nchunks,
+                                           int stp, int wave, int lane, DCopy &dc) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int c0 = __builtin_amdgcn_readfirstlane((2 * stp + r) * NT + 64 * wave);
+        const bool ok = c0 < nchunks;
+        const int m = ok ? c0 >> 11 : 0;
+        const int off = 2 * ((c0 & 2047) + lane);
+        dc.blk[r] = ok ? sBlk[m] : -1;
+        dc.off[r] = off;
+        dc.v[r] = *(const doublex2 *)(du64 + (int64_t)sBlk[64 + m] * kBlockElems + off);
+    }
+}
+
+__device__ __forceinline__ void dcopy_store(double *__restrict__ outD, const DCopy &dc) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        if (dc.blk[r] >= 0)
+            __builtin_nontemporal_store(dc.v[r], (doublex2 *)(outD + (int64_t)dc.blk[r] * kBlockElems + dc.off[r]));
+}
+
+// ---------------------------------------------------------------------------
 // a9, FP64 MFMA class GEMM (the class decomposition is described with the
 // FP32 form below).  W = N^-1 as given, M = B_IJ[p][a] B_IK[p][b] formed in
 // FP64 from the transposed FP64 unique blocks.  MFMA 16x16x4 FP64: lane
@@ -243,7 +281,7 @@ __global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64
 // fourth row a; each step (16 pixels of one term) loads the next step's
 // operands before its own MFMAs.
 // ---------------------------------------------------------------------------
-template <int NI>
+template <int NI, bool WD>
 __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item, int32_t *sTile,
                                                int32_t *sBlk, int32_t *sTerm) {
     const double *__restrict__ ut = pd.u64t;
@@ -261,7 +299,11 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    if (threadIdx.x < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+    if (threadIdx.x < 64) {
+        const int blk = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+        sBlk[lane] = blk;
+        if constexpr (WD) sBlk[64 + lane] = blk >= 0 ? pd.blk_uid[blk] : 0;   // D-hat source block
+    }
     if (threadIdx.x < 2 * nterms) sTerm[threadIdx.x] = terms[threadIdx.x];   // unique-block pairs of the class
     __syncthreads();
 
@@ -287,8 +329,15 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
     for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-    auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn) {
+    constexpr int kDChunks = 16 * NI * 2048;   // D-hat chunks of the tile
+    auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn, int stp, DCopy &dprev) {
         load(qn, gn, fn);
+        if constexpr (WD) {
+            DCopy dc;
+            dcopy_load<256>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(pd.outD, dprev);
+            dprev = dc;
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             double bv[4];
@@ -314,6 +363,8 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
     int x = 0, e = 0;                    // row index (a = wave + 4 x) and term of this step
     ptrs(wave, 0, qc);
     load(qc, 0, f0);
+    DCopy dpend;                         // D-hat chunks loaded, not yet stored
+    dpend.blk[0] = dpend.blk[1] = -1;
     for (int it = 0; it < 16 * nterms; ++it) {
         int ne = e + 1, nx = x;
         if (ne == nterms) {
@@ -323,10 +374,10 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         const int a = wave + 4 * x;
         if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
         else qn = qc;                    // past the last row: a harmless reload
-        step(f0, qc, 1, f1);
-        step(f1, qc, 2, f0);
-        step(f0, qc, 3, f1);
-        step(f1, qn, 0, f0);
+        step(f0, qc, 1, f1, 4 * it, dpend);
+        step(f1, qc, 2, f0, 4 * it + 1, dpend);
+        step(f0, qc, 3, f1, 4 * it + 2, dpend);
+        step(f1, qn, 0, f0, 4 * it + 3, dpend);
         if (ne == 0) {                   // end of output row a: store, clear
 #pragma unroll
             for (int i = 0; i < NI; ++i)
@@ -348,18 +399,27 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         e = ne;
         qc = qn;
     }
+    if constexpr (WD) {                  // the last step's chunks, then those past the last step
+        dcopy_store(pd.outD, dpend);
+        for (int stp = 64 * nterms; 512 * stp < kDChunks; ++stp) {
+            DCopy dc;
+            dcopy_load<256>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(pd.outD, dc);
+        }
+    }
 }
 
+template <bool WD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_class_f64(ProblemDesc64 pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
-    __shared__ int32_t sBlk[64];
+    __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     const int item = xcd_contiguous_index();
     const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_f64_tile<4>(pd, item, sTile, sBlk, sTerm);
-    else if (groups == 2) class_f64_tile<2>(pd, item, sTile, sBlk, sTerm);
-    else class_f64_tile<1>(pd, item, sTile, sBlk, sTerm);
+    if (groups == 4) class_f64_tile<4, WD>(pd, item, sTile, sBlk, sTerm);
+    else if (groups == 2) class_f64_tile<2, WD>(pd, item, sTile, sBlk, sTerm);
+    else class_f64_tile<1, WD>(pd, item, sTile, sBlk, sTerm);
 }
 
 // ---------------------------------------------------------------------------
@@ -383,7 +443,7 @@ __global__ __launch_bounds__(256) void k_ninv_f32(const double *__restrict__ nin
 // One member tile (item) of one problem with NI groups of 16 member rows; all
 // 256 threads of the workgroup take part.  sTile / sBlk are the workgroup's
 // LDS tables.
-template <int NI>
+template <int NI, bool WD>
 __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, int32_t *sTile,
                                                int32_t *sBlk, int32_t *sTerm) {
     const float *__restrict__ ut32 = pd.ut32;
@@ -401,7 +461,11 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    if (threadIdx.x < 64) sBlk[lane] = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+    if (threadIdx.x < 64) {
+        const int blk = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
+        sBlk[lane] = blk;
+        if constexpr (WD) sBlk[64 + lane] = blk >= 0 ? pd.blk_uid[blk] : 0;   // D-hat source block
+    }
     if (threadIdx.x < 2 * nterms) sTerm[threadIdx.x] = terms[threadIdx.x];   // unique-block pairs of the class
     __syncthreads();
 
@@ -433,8 +497,15 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     // MFMAs; the first step of a term starts its MFMA sums from zero.  The
     // scheduling barrier keeps the next step's arithmetic (which waits on
     // those loads) out of this step.
-    auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn, bool first) {
+    constexpr int kDChunks = 16 * NI * 2048;   // D-hat chunks of the tile
+    auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn, bool first, int stp, DCopy &dprev) {
         load(qn, gn, fn);
+        if constexpr (WD) {
+            DCopy dc;
+            dcopy_load<256>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(pd.outD, dprev);
+            dprev = dc;
+        }
         __builtin_amdgcn_sched_group_barrier(0x020, NI + 5, 0);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -461,6 +532,8 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     int x = 0, e = 0;                    // row index (a = wave + 4 x) and term of this step
     ptrs(wave, 0, qc);
     load(qc, 0, f0);
+    DCopy dpend;                         // D-hat chunks loaded, not yet stored
+    dpend.blk[0] = dpend.blk[1] = -1;
     for (int it = 0; it < 16 * nterms; ++it) {
         int ne = e + 1, nx = x;
         if (ne == nterms) {
@@ -470,10 +543,10 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
         const int a = wave + 4 * x;
         if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
         else qn = qc;                    // past the last row: a harmless reload
-        step(f0, qc, 1, f1, true);
-        step(f1, qc, 2, f0, false);
-        step(f0, qc, 3, f1, false);
-        step(f1, qn, 0, f0, false);
+        step(f0, qc, 1, f1, true, 4 * it, dpend);
+        step(f1, qc, 2, f0, false, 4 * it + 1, dpend);
+        step(f0, qc, 3, f1, false, 4 * it + 2, dpend);
+        step(f1, qn, 0, f0, false, 4 * it + 3, dpend);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -501,22 +574,32 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
         e = ne;
         qc = qn;
     }
+    if constexpr (WD) {                  // the last step's chunks, then those past the last step
+        dcopy_store(pd.outD, dpend);
+        for (int stp = 64 * nterms; 512 * stp < kDChunks; ++stp) {
+            DCopy dc;
+            dcopy_load<256>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(pd.outD, dc);
+        }
+    }
 }
 
+template <bool WD>
 __device__ __forceinline__ void class_f32_item(const ProblemDesc &pd, int item, int32_t *sTile, int32_t *sBlk,
                                                int32_t *sTerm) {
     const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_f32_tile<4>(pd, item, sTile, sBlk, sTerm);
-    else if (groups == 2) class_f32_tile<2>(pd, item, sTile, sBlk, sTerm);
-    else class_f32_tile<1>(pd, item, sTile, sBlk, sTerm);
+    if (groups == 4) class_f32_tile<4, WD>(pd, item, sTile, sBlk, sTerm);
+    else if (groups == 2) class_f32_tile<2, WD>(pd, item, sTile, sBlk, sTerm);
+    else class_f32_tile<1, WD>(pd, item, sTile, sBlk, sTerm);
 }
 
+template <bool WD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_class_f32(ProblemDesc pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
-    __shared__ int32_t sBlk[64];                     // stored-block index of each member row
+    __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
-    class_f32_item(pd, xcd_contiguous_index(), sTile, sBlk, sTerm);
+    class_f32_item<WD>(pd, xcd_contiguous_index(), sTile, sBlk, sTerm);
 }
 
 // ---------------------------------------------------------------------------
@@ -559,7 +642,7 @@ void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restric
         __syncthreads();                 // every thread has read sItem before it changes
         if (it < 0) break;
         const ProblemDesc pd = probs[items[2 * it]];
-        class_f32_item(pd, items[2 * it + 1], sTile, sBlk, sTerm);
+        class_f32_item<false>(pd, items[2 * it + 1], sTile, sBlk, sTerm);
     }
 }
 
@@ -728,28 +811,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 #pragma unroll
         for (int q = 0; q < NUC; ++q) sU[buf * 512 + udst[q]] = st.u[q];
     };
-    // D-hat copy: chunk c is 16 bytes (c & 2047) of member row c >> 11; a
-    // wave's 64 chunks lie in one row, so the row index is uniform.
-    constexpr int kDChunks = 16 * NI * 2048;
-    struct DCopy { doublex2 v[2]; int blk[2]; int off[2]; };
-    auto dload = [&](int stp, DCopy &dc) {
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int c0 = __builtin_amdgcn_readfirstlane((2 * stp + r) * NT + 64 * wave);
-            const bool ok = c0 < kDChunks;
-            const int m = ok ? c0 >> 11 : 0;
-            const int off = 2 * ((c0 & 2047) + lane);
-            dc.blk[r] = ok ? sBlk[m] : -1;
-            dc.off[r] = off;
-            dc.v[r] = *(const doublex2 *)(pd.du64 + (int64_t)sBlk[64 + m] * kBlockElems + off);
-        }
-    };
-    auto dstore = [&](const DCopy &dc) {
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-            if (dc.blk[r] >= 0)
-                __builtin_nontemporal_store(dc.v[r], (doublex2 *)(pd.outD + (int64_t)dc.blk[r] * kBlockElems + dc.off[r]));
-    };
+    constexpr int kDChunks = 16 * NI * 2048;   // D-hat chunks of the tile
 
     doublex4 acc[NI][2];
     floatx4 part[NI][2];
@@ -764,16 +826,13 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     // values and this wave's B_IJ values), with the addresses of the step after
     // next read meanwhile; (3) the next step's staged operands written to the
     // other buffer, and one barrier.
-    // D-hat chunks are stored one step after they are loaded, right after the
-    // step's own loads: stores and loads share one wait counter, and a store
-    // placed there is only waited for by the staging wait of the next step.
     auto step = [&](const Own &oc, int buf, const Addr &an, Stage &stn, Own &on, bool first, int ca, int ce,
                     int ch_, int stp, DCopy &dprev) {
         loads(an, stn, on);
         if constexpr (WD) {
             DCopy dc;
-            dload(stp, dc);
-            dstore(dprev);
+            dcopy_load<NT>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(pd.outD, dprev);
             dprev = dc;
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -881,11 +940,11 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         e = ne;
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
-        dstore(dpend);
+        dcopy_store(pd.outD, dpend);
         for (int stp = 2 * RPW * nterms; 2 * NT * stp < kDChunks; ++stp) {
             DCopy dc;
-            dload(stp, dc);
-            dstore(dc);
+            dcopy_load<NT>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(pd.outD, dc);
         }
     }
 }
@@ -984,15 +1043,19 @@ hipError_t launch_expand(const double *u64, const int32_t *items, int64_t nitems
 hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
     if (a.nblocks == 0) return hipSuccess;
     if (prec == 0) {
-        ProblemDesc64 pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.u64t, a.ninv, a.out};
-        hipLaunchKernelGGL(k_class_f64, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
+        ProblemDesc64 pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.u64t, a.ninv, a.out,
+                         a.du64, a.blk_uid, a.outD};
+        if (a.outD) hipLaunchKernelGGL(k_class_f64<true>, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
+        else hipLaunchKernelGGL(k_class_f64<false>, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
         return hipGetLastError();
     }
     if (prec == 1) {
         hipLaunchKernelGGL(k_ninv_f32, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,
                            a.npix, a.wf32);
-        ProblemDesc pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.ut32, a.wf32, a.out};
-        hipLaunchKernelGGL(k_class_f32, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
+        ProblemDesc pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.ut32, a.wf32, a.out,
+                       a.du64, a.blk_uid, a.outD};
+        if (a.outD) hipLaunchKernelGGL(k_class_f32<true>, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
+        else hipLaunchKernelGGL(k_class_f32<false>, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_split_ninv, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,
@@ -1038,7 +1101,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
             if (b.nmtiles[p] == 0) continue;
             const dim3 g((unsigned)b.nmtiles[p]);
             if (!bf16)
-                hipLaunchKernelGGL(k_class_f32, g, dim3(256), 0, st, b.host_desc[p]);
+                hipLaunchKernelGGL(k_class_f32<false>, g, dim3(256), 0, st, b.host_desc[p]);
             else if (b.prec == 2)
                 hipLaunchKernelGGL((k_class_bf16<2, false>), g, dim3(256), 0, st, b.host_descb[p]);
             else
