@@ -15,9 +15,11 @@ value = stored B^T N^-1 B elements / step time in the headline precision mode
 reported side by side under "modes".
 
 With --config c5 a step is one launch of the captured graph that contracts
-all 32 problems of the batched workload (lmax 256/512/1024/2048, FP32 MFMA with
-FP64 accumulation across contraction tiles; 172 GB of output); the beam kernels
-are tabulated before the timed region and the schedule is autotuned first.
+all 32 problems of the batched workload (lmax 256/512/1024/2048; split BF16x6
+and FP32 MFMA, FP64 accumulation across contraction tiles; 172 GB of output),
+one batch per mode, the first reported as the headline; the beam kernels
+are tabulated before the timed region and the schedule and tile shape are
+autotuned first.
 
 With --op conv a step is one pixel-domain convolution g = B-hat f (FP64) of
 the configuration's grid and beam.
@@ -218,7 +220,7 @@ def run_batch(args):
     for prec in modes:
         bt = sp.Batch([(pr["g"], pr["kb"], pr["ninv_dev"], pr["out"]) for pr in probs], prec=prec, stream=stream)
         chosen, tune_ms = bt.tune(stream)
-        sched = {v: k for k, v in sp.SCHEDULES.items()}[chosen]
+        sched = sp.plan_name(chosen)        # "schedule/tiling"
         for _ in range(args.warmup):
             bt.launch(stream)
         torch.cuda.synchronize()
@@ -235,7 +237,8 @@ def run_batch(args):
         ms_step = wall * 1000.0 / args.steps
         achieved = PRODUCTS[prec] * alg_flop / (ms.mean() * 1e-3) / 1e12
         kern = {"fp32": ("k_batch_f32", "k_class_f32"), "bf16x6": ("k_batch_bf16<3>", "k_class_bf16<3, false>"),
-                "bf16x3": ("k_batch_bf16<2>", "k_class_bf16<2, false>")}[prec][1 if chosen == 2 else 0]
+                "bf16x3": ("k_batch_bf16<2>", "k_class_bf16<2, false>")}[prec][
+            1 if chosen % len(sp.SCHEDULES) == sp.SCHED_PER_PROBLEM else 0]
         results[prec] = {
             "elements_per_s": nelem / (ms_step * 1e-3), "ms_per_step": ms_step, "graph_launch_ms": ms.mean(),
             "schedule": sched, "tune_ms": [round(t, 3) for t in tune_ms],

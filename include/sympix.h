@@ -229,6 +229,16 @@ typedef enum {
     SYMPIX_NSCHED = 3
 } sympix_schedule;
 
+/* Tile shape of the work items: member tiles of 64 stored blocks (tails of
+ * 32 / 16, the default), or of 32 (tails of 16), which wastes less work on
+ * the small classes of low-lmax grids.  A plan is schedule + SYMPIX_NSCHED *
+ * tiling. */
+typedef enum {
+    SYMPIX_TILES_64 = 0,
+    SYMPIX_TILES_32 = 1,
+    SYMPIX_NTILINGS = 2
+} sympix_tiling;
+
 /* Build a batch over problems p[0..n) (copied; the buffers they point to must
  * stay allocated, and the grids and kernels alive, until the batch is
  * destroyed) and capture its graph with the default schedule.  prec:
@@ -242,13 +252,20 @@ typedef enum {
 sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t prec, void *stream,
                                   sympix_batch **out);
 
-/* Re-capture the batch's graph with schedule s (a sympix_schedule). */
+/* Re-capture the batch's graph with schedule s (a sympix_schedule), keeping
+ * its tile shape. */
 sympix_status sympix_batch_set_schedule(sympix_batch *bt, int32_t s);
 
-/* Autotune: time one launch of every schedule on stream (after one warm-up
- * launch each; the outputs are overwritten), keep the fastest and report it in
- * *chosen and the times in ms_out[SYMPIX_NSCHED] (either may be NULL).  The
- * choice is remembered for batches of the same shape in this process. */
+/* Re-capture the batch's graph with tile shape t (a sympix_tiling), keeping
+ * its schedule. */
+sympix_status sympix_batch_set_tiling(sympix_batch *bt, int32_t t);
+
+/* Autotune: time one launch of every plan (schedule and tile shape) on stream
+ * (after one warm-up launch each; the outputs are overwritten), keep the
+ * fastest and report its plan in *chosen and the times in
+ * ms_out[SYMPIX_NSCHED * SYMPIX_NTILINGS], indexed by plan (either may be
+ * NULL).  The choice is remembered for batches of the same problems and mode
+ * in this process. */
 sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen, double *ms_out);
 
 /* Enqueue the batch's graph on stream: converts every N^-1 to the operand

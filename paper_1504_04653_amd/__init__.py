@@ -87,17 +87,27 @@ class Problem(ctypes.Structure):
 
 _batch_create = _sig("sympix_batch_create", [ctypes.POINTER(Problem), _i32, _i32, _vp, ctypes.POINTER(_vp)])
 _batch_set_schedule = _sig("sympix_batch_set_schedule", [_vp, _i32])
+_batch_set_tiling = _sig("sympix_batch_set_tiling", [_vp, _i32])
 _batch_tune = _sig("sympix_batch_tune", [_vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64)])
 _batch_launch = _sig("sympix_batch_launch", [_vp, _vp])
 _batch_destroy = _sig("sympix_batch_destroy", [_vp], None)
 
 SCHED_XCD_QUEUES, SCHED_GLOBAL_LPT, SCHED_PER_PROBLEM = 0, 1, 2
 SCHEDULES = {"xcd_queues": SCHED_XCD_QUEUES, "global_lpt": SCHED_GLOBAL_LPT, "per_problem": SCHED_PER_PROBLEM}
+TILES_64, TILES_32 = 0, 1
+TILINGS = {"tiles64": TILES_64, "tiles32": TILES_32}
+
+
+def plan_name(plan):
+    """'schedule/tiling' of a tuner plan (schedule + len(SCHEDULES) * tiling)."""
+    sched = {v: k for k, v in SCHEDULES.items()}[plan % len(SCHEDULES)]
+    tiling = {v: k for k, v in TILINGS.items()}[plan // len(SCHEDULES)]
+    return f"{sched}/{tiling}"
 
 EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sympix_grid_rings",
             "sympix_grid_bands", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_unique",
             "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
-            "sympix_sample_BtNB", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_tune",
+            "sympix_sample_BtNB", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
             "sympix_batch_launch", "sympix_batch_destroy", "sympix_last_error")
 
 
@@ -326,10 +336,16 @@ class Batch:
             schedule = SCHEDULES[schedule]
         _check(_batch_set_schedule(self._h, int(schedule)))
 
+    def set_tiling(self, tiling):
+        if isinstance(tiling, str):
+            tiling = TILINGS[tiling]
+        _check(_batch_set_tiling(self._h, int(tiling)))
+
     def tune(self, stream=None):
-        """Time every schedule once, keep the fastest; returns (chosen, ms per schedule)."""
+        """Time every plan (schedule, tile shape) once, keep the fastest; returns
+        (chosen plan, ms per plan), plan = schedule + len(SCHEDULES) * tiling."""
         chosen = _i32(-1)
-        ms = (_f64 * len(SCHEDULES))()
+        ms = (_f64 * (len(SCHEDULES) * len(TILINGS)))()
         _check(_batch_tune(self._h, _stream(stream), ctypes.byref(chosen), ms))
         return chosen.value, list(ms)
 

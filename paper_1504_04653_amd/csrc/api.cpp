@@ -51,7 +51,7 @@ struct DevGrid {
     int32_t *class_blk = nullptr;
     int32_t *class_itab = nullptr;
     int32_t *mtiles = nullptr;
-    int32_t *wtiles = nullptr;
+    int32_t *mtiles32 = nullptr;
     int32_t *conv_chunks = nullptr;
     int32_t *conv_slots = nullptr;
 };
@@ -77,7 +77,7 @@ void free_dev(DevGrid &d) {
     hipFree(d.class_blk);
     hipFree(d.class_itab);
     hipFree(d.mtiles);
-    hipFree(d.wtiles);
+    hipFree(d.mtiles32);
     hipFree(d.conv_chunks);
     hipFree(d.conv_slots);
     d = DevGrid();
@@ -146,7 +146,7 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.class_blk, geo.class_blk.data(), geo.class_blk.size());
     if (e == hipSuccess) e = upload(&d.class_itab, geo.class_itab.data(), geo.class_itab.size());
     if (e == hipSuccess) e = upload(&d.mtiles, geo.mtiles.data(), geo.mtiles.size());
-    if (e == hipSuccess) e = upload(&d.wtiles, geo.wtiles.data(), geo.wtiles.size());
+    if (e == hipSuccess) e = upload(&d.mtiles32, geo.mtiles32.data(), geo.mtiles32.size());
     if (e == hipSuccess) e = upload(&d.conv_chunks, geo.conv_chunks.data(), geo.conv_chunks.size());
     if (e == hipSuccess) e = upload(&d.conv_slots, geo.conv_slots.data(), geo.conv_slots.size());
     if (e != hipSuccess) {
@@ -285,8 +285,6 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
     a.class_itab = dg->class_itab;
     a.mtiles = dg->mtiles;
     a.nmtiles = (int64_t)geo.mtiles.size() / 4;
-    a.wtiles = dg->wtiles;
-    a.nwtiles = (int64_t)geo.wtiles.size() / 4;
     a.nblocks = geo.nblocks();
     a.npix = geo.npix;
     a.ninv = ninv_dev;
@@ -574,19 +572,23 @@ struct sympix_batch {
     int32_t nprob = 0;
     int32_t prec = SYMPIX_FP32;
     int32_t schedule = SYMPIX_SCHED_XCD_QUEUES;
+    int32_t tiling = SYMPIX_TILES_64;
     int32_t nworkgroups = 0;
-    std::vector<sympix::ProblemDesc> hdesc;        // FP32
-    std::vector<sympix::ProblemDescB> hdescb;      // split BF16
+    // per tile shape (sympix_tiling): problem descriptors, tile counts, work
+    // items in natural order
+    std::vector<sympix::ProblemDesc> hdesc[SYMPIX_NTILINGS];     // FP32
+    std::vector<sympix::ProblemDescB> hdescb[SYMPIX_NTILINGS];   // split BF16
+    std::vector<int64_t> nmtiles[SYMPIX_NTILINGS];
+    std::vector<int32_t> item_prob[SYMPIX_NTILINGS], item_tile[SYMPIX_NTILINGS], item_cost[SYMPIX_NTILINGS];
     std::vector<uint16_t *> wsplit;                // split BF16: 3 N^-1 parts per problem
     std::vector<const double *> ninv;
-    std::vector<int64_t> npix, nmtiles;
-    std::vector<int32_t> item_prob, item_tile, item_cost;   // natural order
-    sympix::ProblemDesc *d_desc = nullptr;
+    std::vector<int64_t> npix;
+    sympix::ProblemDesc *d_desc[SYMPIX_NTILINGS] = {};
     int32_t *d_items = nullptr;
     int32_t *d_qb = nullptr;
     int32_t *d_counters = nullptr;
     float *d_wf = nullptr;
-    sympix::ProblemDescB *d_descb = nullptr;
+    sympix::ProblemDescB *d_descb[SYMPIX_NTILINGS] = {};
     uint16_t *d_wsplit = nullptr;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -599,51 +601,55 @@ namespace {
 constexpr int kBatchQueues = 8;   // one per XCD
 
 std::mutex g_tune_mu;
-std::map<std::string, int32_t> g_tune_cache;   // batch shape -> schedule
+std::map<std::string, int32_t> g_tune_cache;   // batch shape -> plan (schedule + NSCHED tiling)
 
 void free_batch(sympix_batch *bt) {
     if (bt->exec) hipGraphExecDestroy(bt->exec);
     if (bt->graph) hipGraphDestroy(bt->graph);
     if (bt->cap) hipStreamDestroy(bt->cap);
-    hipFree(bt->d_desc);
+    for (int t = 0; t < SYMPIX_NTILINGS; ++t) {
+        hipFree(bt->d_desc[t]);
+        hipFree(bt->d_descb[t]);
+    }
     hipFree(bt->d_items);
     hipFree(bt->d_qb);
     hipFree(bt->d_counters);
     hipFree(bt->d_wf);
-    hipFree(bt->d_descb);
     hipFree(bt->d_wsplit);
     delete bt;
 }
 
-// Order the work items and bound the queues for schedule s, then capture the
-// batch's launches into a fresh graph.
-sympix_status capture_batch(sympix_batch *bt, int32_t s) {
-    const int64_t nitems = (int64_t)bt->item_prob.size();
+// Order the work items of tile shape t and bound the queues for schedule s,
+// then capture the batch's launches into a fresh graph.
+sympix_status capture_batch(sympix_batch *bt, int32_t s, int32_t t) {
+    const std::vector<int32_t> &item_prob = bt->item_prob[t], &item_tile = bt->item_tile[t],
+                               &item_cost = bt->item_cost[t];
+    const int64_t nitems = (int64_t)item_prob.size();
     std::vector<int64_t> order(nitems);
     std::iota(order.begin(), order.end(), 0);
     std::vector<int32_t> qb;
     if (s == SYMPIX_SCHED_XCD_QUEUES) {
         // contiguous ranges of equal work (sum of contraction tiles per item)
-        const double total = std::accumulate(bt->item_cost.begin(), bt->item_cost.end(), 0.0);
+        const double total = std::accumulate(item_cost.begin(), item_cost.end(), 0.0);
         qb.push_back(0);
         double run = 0.0;
         int64_t i = 0;
         for (int q = 1; q < kBatchQueues; ++q) {
-            while (i < nitems && run + 0.5 * bt->item_cost[i] < total * q / kBatchQueues) run += bt->item_cost[i++];
+            while (i < nitems && run + 0.5 * item_cost[i] < total * q / kBatchQueues) run += item_cost[i++];
             qb.push_back((int32_t)i);
         }
         qb.push_back((int32_t)nitems);
     } else if (s == SYMPIX_SCHED_GLOBAL_LPT) {
         std::stable_sort(order.begin(), order.end(),
-                         [&](int64_t a, int64_t b) { return bt->item_cost[a] > bt->item_cost[b]; });
+                         [&](int64_t a, int64_t b) { return item_cost[a] > item_cost[b]; });
         qb = {0, (int32_t)nitems};
     } else {
         qb = {0, 0};
     }
     std::vector<int32_t> items(2 * nitems);
     for (int64_t i = 0; i < nitems; ++i) {
-        items[2 * i] = bt->item_prob[order[i]];
-        items[2 * i + 1] = bt->item_tile[order[i]];
+        items[2 * i] = item_prob[order[i]];
+        items[2 * i + 1] = item_tile[order[i]];
     }
     hipError_t e = hipSuccess;
     if (nitems > 0) e = hipMemcpy(bt->d_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice);
@@ -658,14 +664,14 @@ sympix_status capture_batch(sympix_batch *bt, int32_t s) {
     sympix::BatchLaunch bl;
     bl.nprob = bt->nprob;
     bl.prec = bt->prec;
-    bl.host_desc = bt->hdesc.data();
-    bl.host_descb = bt->hdescb.data();
+    bl.host_desc = bt->hdesc[t].data();
+    bl.host_descb = bt->hdescb[t].data();
     bl.wsplit = bt->wsplit.data();
-    bl.descb = bt->d_descb;
+    bl.descb = bt->d_descb[t];
     bl.ninv = bt->ninv.data();
     bl.npix = bt->npix.data();
-    bl.nmtiles = bt->nmtiles.data();
-    bl.desc = bt->d_desc;
+    bl.nmtiles = bt->nmtiles[t].data();
+    bl.desc = bt->d_desc[t];
     bl.items = bt->d_items;
     bl.nitems = nitems;
     bl.qb = bt->d_qb;
@@ -692,6 +698,7 @@ sympix_status capture_batch(sympix_batch *bt, int32_t s) {
     bt->graph = graph;
     bt->exec = exec;
     bt->schedule = s;
+    bt->tiling = t;
     return SYMPIX_OK;
 }
 
@@ -762,36 +769,42 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
             free_batch(bt);
             return s;
         }
-        sympix::ProblemDesc d{dg->mtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
-                              p[i].b->ut32, nullptr, p[i].out_dev};
-        bt->hdesc.push_back(d);
-        sympix::ProblemDescB db{dg->mtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
-                                p[i].b->ut32, {nullptr, nullptr, nullptr}, p[i].out_dev, nullptr, nullptr, nullptr};
-        bt->hdescb.push_back(db);
+        for (int t = 0; t < SYMPIX_NTILINGS; ++t) {
+            const int32_t *dtiles = t == SYMPIX_TILES_64 ? dg->mtiles : dg->mtiles32;
+            const std::vector<int32_t> &tiles = t == SYMPIX_TILES_64 ? geo.mtiles : geo.mtiles32;
+            sympix::ProblemDesc d{dtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
+                                  p[i].b->ut32, nullptr, p[i].out_dev, nullptr, nullptr, nullptr};
+            bt->hdesc[t].push_back(d);
+            sympix::ProblemDescB db{dtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
+                                    p[i].b->ut32, {nullptr, nullptr, nullptr}, p[i].out_dev, nullptr, nullptr, nullptr};
+            bt->hdescb[t].push_back(db);
+            const int64_t nmt = (int64_t)tiles.size() / 4;
+            bt->nmtiles[t].push_back(nmt);
+            for (int64_t k = 0; k < nmt; ++k) {
+                bt->item_prob[t].push_back(i);
+                bt->item_tile[t].push_back((int32_t)k);
+                bt->item_cost[t].push_back(geo.classes[tiles[4 * k]].nterms * tiles[4 * k + 2]);
+            }
+        }
         bt->ninv.push_back(p[i].ninv_dev);
         bt->npix.push_back(geo.npix);
-        const int64_t nmt = (int64_t)geo.mtiles.size() / 4;
-        bt->nmtiles.push_back(nmt);
-        for (int64_t t = 0; t < nmt; ++t) {
-            bt->item_prob.push_back(i);
-            bt->item_tile.push_back((int32_t)t);
-            bt->item_cost.push_back(geo.classes[geo.mtiles[4 * t]].nterms * geo.mtiles[4 * t + 2]);
-        }
         wf_total += geo.npix;
         shape += "|" + std::to_string(geo.lmax) + ":" + std::to_string(geo.nblocks());
     }
     bt->shape = shape;
-    const int64_t nitems = (int64_t)bt->item_prob.size();
+    const int64_t nitems = (int64_t)std::max(bt->item_prob[0].size(), bt->item_prob[1].size());
     if (nitems >= (int64_t)INT32_MAX / 2) {
         free_batch(bt);
         return fail(SYMPIX_ESIZE, "too many work items for one batch");
     }
-    e = hipMalloc((void **)&bt->d_desc, n * sizeof(sympix::ProblemDesc));
+    for (int t = 0; t < SYMPIX_NTILINGS && e == hipSuccess; ++t) {
+        e = hipMalloc((void **)&bt->d_desc[t], n * sizeof(sympix::ProblemDesc));
+        if (e == hipSuccess && bf16) e = hipMalloc((void **)&bt->d_descb[t], n * sizeof(sympix::ProblemDescB));
+    }
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_items, std::max<int64_t>(1, 2 * nitems) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_qb, (kBatchQueues + 1) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_counters, kBatchQueues * sizeof(int32_t));
     if (bf16) {
-        if (e == hipSuccess) e = hipMalloc((void **)&bt->d_descb, n * sizeof(sympix::ProblemDescB));
         if (e == hipSuccess)
             e = hipMalloc((void **)&bt->d_wsplit, std::max<int64_t>(1, 3 * wf_total) * sizeof(uint16_t));
     } else if (e == hipSuccess) {
@@ -804,33 +817,34 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     }
     int64_t off = 0;
     for (int32_t i = 0; i < n; ++i) {
-        if (bf16) {
-            for (int k = 0; k < 3; ++k) {
-                uint16_t *w = bt->d_wsplit + k * wf_total + off;
-                bt->hdescb[i].w[k] = w;
-                bt->wsplit.push_back(w);
-            }
-        } else {
-            bt->hdesc[i].wf = bt->d_wf + off;
+        for (int k = 0; k < 3 && bf16; ++k) bt->wsplit.push_back(bt->d_wsplit + k * wf_total + off);
+        for (int t = 0; t < SYMPIX_NTILINGS; ++t) {
+            if (bf16)
+                for (int k = 0; k < 3; ++k) bt->hdescb[t][i].w[k] = bt->wsplit[3 * i + k];
+            else
+                bt->hdesc[t][i].wf = bt->d_wf + off;
         }
         off += bt->npix[i];
     }
-    e = hipMemcpy(bt->d_desc, bt->hdesc.data(), n * sizeof(sympix::ProblemDesc), hipMemcpyHostToDevice);
-    if (e == hipSuccess && bf16)
-        e = hipMemcpy(bt->d_descb, bt->hdescb.data(), n * sizeof(sympix::ProblemDescB), hipMemcpyHostToDevice);
+    for (int t = 0; t < SYMPIX_NTILINGS && e == hipSuccess; ++t) {
+        e = hipMemcpy(bt->d_desc[t], bt->hdesc[t].data(), n * sizeof(sympix::ProblemDesc), hipMemcpyHostToDevice);
+        if (e == hipSuccess && bf16)
+            e = hipMemcpy(bt->d_descb[t], bt->hdescb[t].data(), n * sizeof(sympix::ProblemDescB),
+                          hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         free_batch(bt);
         return hip_fail(e, "batch set-up");
     }
-    int32_t sched = SYMPIX_SCHED_XCD_QUEUES;
+    int32_t plan = SYMPIX_SCHED_XCD_QUEUES + SYMPIX_NSCHED * SYMPIX_TILES_64;
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tune_cache.find(bt->shape);
-        if (it != g_tune_cache.end()) sched = it->second;
+        if (it != g_tune_cache.end()) plan = it->second;
     }
-    sympix_status s = capture_batch(bt, sched);
+    sympix_status s = capture_batch(bt, plan % SYMPIX_NSCHED, plan / SYMPIX_NSCHED);
     if (s != SYMPIX_OK) {
         free_batch(bt);
         return s;
@@ -842,7 +856,13 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
 sympix_status sympix_batch_set_schedule(sympix_batch *bt, int32_t s) {
     if (!bt) return fail(SYMPIX_EINVAL, "NULL batch");
     if (s < 0 || s >= SYMPIX_NSCHED) return fail(SYMPIX_EINVAL, "unknown schedule");
-    return capture_batch(bt, s);
+    return capture_batch(bt, s, bt->tiling);
+}
+
+sympix_status sympix_batch_set_tiling(sympix_batch *bt, int32_t t) {
+    if (!bt) return fail(SYMPIX_EINVAL, "NULL batch");
+    if (t < 0 || t >= SYMPIX_NTILINGS) return fail(SYMPIX_EINVAL, "unknown tiling");
+    return capture_batch(bt, bt->schedule, t);
 }
 
 sympix_status sympix_batch_launch(sympix_batch *bt, void *stream) {
@@ -868,8 +888,8 @@ sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen,
     double best_ms = 0.0;
     int32_t best = -1;
     sympix_status s = SYMPIX_OK;
-    for (int32_t c = 0; c < SYMPIX_NSCHED && s == SYMPIX_OK; ++c) {
-        s = capture_batch(bt, c);
+    for (int32_t c = 0; c < SYMPIX_NSCHED * SYMPIX_NTILINGS && s == SYMPIX_OK; ++c) {
+        s = capture_batch(bt, c % SYMPIX_NSCHED, c / SYMPIX_NSCHED);
         if (s != SYMPIX_OK) break;
         e = hipGraphLaunch(bt->exec, st);                       // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -891,7 +911,7 @@ sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen,
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (s != SYMPIX_OK) return s;
-    s = capture_batch(bt, best);
+    s = capture_batch(bt, best % SYMPIX_NSCHED, best / SYMPIX_NSCHED);
     if (s != SYMPIX_OK) return s;
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);

@@ -56,8 +56,8 @@ struct BtnbArgs {
     const double *u64t;
     const float *ut32;
     const DevClass *classes;
-    const int32_t *class_terms, *class_blk, *class_itab, *mtiles, *wtiles;
-    int64_t nmtiles, nwtiles;
+    const int32_t *class_terms, *class_blk, *class_itab, *mtiles;
+    int64_t nmtiles;
     uint16_t *wsplit[3];      // scratch: N^-1 split into BF16 parts, npix each
     float *wf32;              // scratch: N^-1 rounded to FP32, npix
     int64_t npix;

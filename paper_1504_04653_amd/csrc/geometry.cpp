@@ -431,17 +431,11 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
                 } else if (r > 0) {
                     tile(m0, 1);
                 }
-                // wide tiles of 256 rows (16 groups of 16); the tail goes into
-                // tiles of 128, 64, 32 and 16 rows
+                // the second tile shape a batch may use: tiles of 32 rows, a
+                // tail of at most 16 members in a tile of 16
                 int32_t mb = 0;
-                for (; bc.nblocks - mb > 192; mb += 256)
-                    g.wtiles.insert(g.wtiles.end(), {(int32_t)c, mb, 16, 0});
-                for (int32_t rb = bc.nblocks - mb; rb > 0;) {
-                    const int32_t gs = rb > 64 ? 8 : rb > 32 ? 4 : rb > 16 ? 2 : 1;
-                    g.wtiles.insert(g.wtiles.end(), {(int32_t)c, mb, gs, 0});
-                    mb += 16 * gs;
-                    rb -= 16 * gs;
-                }
+                for (; bc.nblocks - mb > 16; mb += 32) g.mtiles32.insert(g.mtiles32.end(), {(int32_t)c, mb, 2, 0});
+                if (bc.nblocks - mb > 0) g.mtiles32.insert(g.mtiles32.end(), {(int32_t)c, mb, 1, 0});
                 g.classes.push_back(bc);
             }
         }

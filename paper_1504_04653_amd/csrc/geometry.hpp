@@ -76,8 +76,8 @@ struct Geometry {
     std::vector<int32_t> class_itab;    // tile I of each (member, term)
     std::vector<int32_t> mtiles;        // 4 per member tile: class, first member,
                                         // 16-row groups (1, 2 or 4), 0
-    std::vector<int32_t> wtiles;        // the same with up to 256 rows (groups
-                                        // 1, 2, 4, 8 or 16), for the split-BF16 GEMM
+    std::vector<int32_t> mtiles32;      // the same with tiles of at most 32 rows
+                                        // (groups 1 or 2): a tile shape for batches
     int32_t max_class_terms = 0;
 
     // convolution g = B-hat f: chunks of up to 16 consecutive output tiles of

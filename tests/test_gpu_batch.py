@@ -101,11 +101,13 @@ def launch_and_check(small, tag):
         assert torch.equal(p["out"], r), f"{tag}: problem {i} differs from the single-problem {small['prec']} path"
 
 
+@pytest.mark.parametrize("tiling", ["tiles64", "tiles32"])
 @pytest.mark.parametrize("schedule", ["xcd_queues", "global_lpt", "per_problem"])
-def test_every_schedule_matches_single_problem_path(small, schedule):
+def test_every_schedule_matches_single_problem_path(small, schedule, tiling):
+    small["bt"].set_tiling(tiling)
     small["bt"].set_schedule(schedule)
-    launch_and_check(small, schedule)
-    say(f"[batch {small['prec']}] schedule {schedule}: bitwise equal to sample_BtNB for {len(small['probs'])} problems")
+    launch_and_check(small, f"{schedule}/{tiling}")
+    say(f"[batch {small['prec']}] {schedule}/{tiling}: bitwise equal to sample_BtNB for {len(small['probs'])} problems")
 
 
 def test_single_problem_path_against_oracle(small):
@@ -119,6 +121,7 @@ def test_single_problem_path_against_oracle(small):
 
 
 def test_graph_replays_with_eager_work_between(small):
+    small["bt"].set_tiling("tiles64")
     small["bt"].set_schedule("xcd_queues")
     for r in range(3):
         x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
@@ -127,10 +130,11 @@ def test_graph_replays_with_eager_work_between(small):
         launch_and_check(small, f"replay {r}")
 
 
-def test_tune_picks_a_schedule_and_keeps_results(small):
+def test_tune_picks_a_plan_and_keeps_results(small):
     chosen, ms = small["bt"].tune()
-    say(f"[batch {small['prec']}] tune: chosen {chosen}, ms per schedule {ms}")
-    assert chosen in (0, 1, 2)
+    say(f"[batch {small['prec']}] tune: chosen {sp.plan_name(chosen)}, ms per plan {ms}")
+    assert len(ms) == len(sp.SCHEDULES) * len(sp.TILINGS)
+    assert chosen in range(len(ms))
     assert all(t > 0 for t in ms)
     assert ms[chosen] == min(ms)
     launch_and_check(small, "after tune")
@@ -153,6 +157,10 @@ def test_batch_argument_errors(small):
     with pytest.raises(sp.SympixError) as ei:
         sp.Batch([(p["g"], other["kb"], p["ninv_dev"], p["out"])])
     assert ei.value.code == "EINVAL"
+    for bad in (lambda: small["bt"].set_schedule(3), lambda: small["bt"].set_tiling(2)):
+        with pytest.raises(sp.SympixError) as ei:
+            bad()
+        assert ei.value.code == "EINVAL"
 
 
 # --- the 32-problem batch at full size, sampled block-rows --------------------
@@ -177,7 +185,7 @@ def test_c5_full_batch_sampled(prec):
     say(f"[c5 {prec}] 32 problems, {sum(p['g'].npix for p in probs)} pixels, output {total / 1e9:.1f} GB")
     bt = sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]) for p in probs], prec=prec)
     chosen, ms = bt.tune()
-    say(f"[c5 {prec}] tune: chosen {chosen}, ms per schedule {[round(t, 2) for t in ms]}")
+    say(f"[c5 {prec}] tune: chosen {sp.plan_name(chosen)}, ms per plan {[round(t, 2) for t in ms]}")
     for p in probs:
         p["out"].fill_(float("nan"))
     bt.launch()
