@@ -279,7 +279,7 @@ def sample_BtNB(grid: Grid, kernel: Kernel, ninv, out, prec=FP64, stream=None):
 
 def sample_D_BtNB(grid: Grid, kd: Kernel, kb: Kernel, ninv, out_D, out_C, prec=FP64, stream=None):
     """D-hat blocks of kd into out_D and B-hat^T N^-1 B-hat blocks of kb into
-    out_C in one call (one launch in the split-BF16 modes)."""
+    out_C in one call and one launch."""
     if isinstance(prec, str):
         prec = PRECISIONS[prec]
     _require_f64_device(ninv, "ninv")

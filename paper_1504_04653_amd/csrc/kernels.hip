@@ -9,7 +9,8 @@
 //   k_convolve     pixel-domain convolution g = B-hat f, one FP64 GEMM per
 //                  unique block over 16 output tiles
 //   k_class_f64    B-hat^T N^-1 B-hat (Eq. 15) in FP64 as one GEMM per class of
-//                  blocks that share their contraction pattern
+//                  blocks that share their contraction pattern; the class
+//                  kernels' <true> instantiations also copy D-hat (combined call)
 //   k_ninv_f32     N^-1 rounded to FP32
 //   k_class_f32    FP32-MFMA contraction as one GEMM per class of blocks that
 //                  share their contraction pattern, FP64 accumulation across tiles
@@ -245,29 +246,31 @@ __global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64
 // ---------------------------------------------------------------------------
 struct DCopy {
     doublex2 v[2];
-    int blk[2], off[2];
+    double *dst[2];            // uniform: where the chunk row goes (nullptr: nowhere)
 };
 
 template <int NT>
-__device__ __forceinline__ void dcopy_load(const double *__restrict__ du64, const int32_t *sBlk, int nchunks,
-                                           int stp, int wave, int lane, DCopy &dc) {
+__device__ __forceinline__ void dcopy_load(const double *__restrict__ du64, double *__restrict__ outD,
+                                           const int32_t *sBlk, int nchunks, int stp, int wave, int lane,
+                                           DCopy &dc) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int c0 = __builtin_amdgcn_readfirstlane((2 * stp + r) * NT + 64 * wave);
         const bool ok = c0 < nchunks;
         const int m = ok ? c0 >> 11 : 0;
-        const int off = 2 * ((c0 & 2047) + lane);
-        dc.blk[r] = ok ? sBlk[m] : -1;
-        dc.off[r] = off;
-        dc.v[r] = *(const doublex2 *)(du64 + (int64_t)sBlk[64 + m] * kBlockElems + off);
+        const int blk = __builtin_amdgcn_readfirstlane(sBlk[m]);
+        const int uid = __builtin_amdgcn_readfirstlane(sBlk[64 + m]);
+        const int base = 2 * (c0 & 2047);
+        const double *src = du64 + (int64_t)uid * kBlockElems + base;
+        dc.v[r] = *(const doublex2 *)(src + 2 * lane);
+        dc.dst[r] = ok && blk >= 0 ? outD + (int64_t)blk * kBlockElems + base : nullptr;
     }
 }
 
-__device__ __forceinline__ void dcopy_store(double *__restrict__ outD, const DCopy &dc) {
+__device__ __forceinline__ void dcopy_store(const DCopy &dc, int lane) {
 #pragma unroll
     for (int r = 0; r < 2; ++r)
-        if (dc.blk[r] >= 0)
-            __builtin_nontemporal_store(dc.v[r], (doublex2 *)(outD + (int64_t)dc.blk[r] * kBlockElems + dc.off[r]));
+        if (dc.dst[r]) __builtin_nontemporal_store(dc.v[r], (doublex2 *)(dc.dst[r] + 2 * lane));
 }
 
 // ---------------------------------------------------------------------------
@@ -334,8 +337,8 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         load(qn, gn, fn);
         if constexpr (WD) {
             DCopy dc;
-            dcopy_load<256>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
-            dcopy_store(pd.outD, dprev);
+            dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(dprev, lane);
             dprev = dc;
         }
 #pragma unroll
@@ -364,7 +367,7 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
     ptrs(wave, 0, qc);
     load(qc, 0, f0);
     DCopy dpend;                         // D-hat chunks loaded, not yet stored
-    dpend.blk[0] = dpend.blk[1] = -1;
+    dpend.dst[0] = dpend.dst[1] = nullptr;
     for (int it = 0; it < 16 * nterms; ++it) {
         int ne = e + 1, nx = x;
         if (ne == nterms) {
@@ -400,11 +403,11 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         qc = qn;
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
-        dcopy_store(pd.outD, dpend);
+        dcopy_store(dpend, lane);
         for (int stp = 64 * nterms; 512 * stp < kDChunks; ++stp) {
             DCopy dc;
-            dcopy_load<256>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
-            dcopy_store(pd.outD, dc);
+            dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(dc, lane);
         }
     }
 }
@@ -502,8 +505,8 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
         load(qn, gn, fn);
         if constexpr (WD) {
             DCopy dc;
-            dcopy_load<256>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
-            dcopy_store(pd.outD, dprev);
+            dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(dprev, lane);
             dprev = dc;
         }
         __builtin_amdgcn_sched_group_barrier(0x020, NI + 5, 0);
@@ -533,7 +536,7 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     ptrs(wave, 0, qc);
     load(qc, 0, f0);
     DCopy dpend;                         // D-hat chunks loaded, not yet stored
-    dpend.blk[0] = dpend.blk[1] = -1;
+    dpend.dst[0] = dpend.dst[1] = nullptr;
     for (int it = 0; it < 16 * nterms; ++it) {
         int ne = e + 1, nx = x;
         if (ne == nterms) {
@@ -575,11 +578,11 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
         qc = qn;
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
-        dcopy_store(pd.outD, dpend);
+        dcopy_store(dpend, lane);
         for (int stp = 64 * nterms; 512 * stp < kDChunks; ++stp) {
             DCopy dc;
-            dcopy_load<256>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
-            dcopy_store(pd.outD, dc);
+            dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(dc, lane);
         }
     }
 }
@@ -831,8 +834,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         loads(an, stn, on);
         if constexpr (WD) {
             DCopy dc;
-            dcopy_load<NT>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
-            dcopy_store(pd.outD, dprev);
+            dcopy_load<NT>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(dprev, lane);
             dprev = dc;
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -900,7 +903,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     }
     Addr an = addr(rw, 0, 1);              // the next step's addresses
     DCopy dpend;                           // D-hat chunks loaded, not yet stored
-    dpend.blk[0] = dpend.blk[1] = -1;
+    dpend.dst[0] = dpend.dst[1] = nullptr;
     __syncthreads();
     for (int it = 0; it < RPW * nterms; ++it) {
         int ne = e + 1, nx = x;
@@ -940,11 +943,11 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         e = ne;
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
-        dcopy_store(pd.outD, dpend);
+        dcopy_store(dpend, lane);
         for (int stp = 2 * RPW * nterms; 2 * NT * stp < kDChunks; ++stp) {
             DCopy dc;
-            dcopy_load<NT>(pd.du64, sBlk, kDChunks, stp, wave, lane, dc);
-            dcopy_store(pd.outD, dc);
+            dcopy_load<NT>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_store(dc, lane);
         }
     }
 }
