@@ -406,9 +406,6 @@ def main():
 
     copy_calibration(torch, args.copy_calibration)
 
-    # One step: tabulate the beam and prior kernels (with their unique
-    # blocks), then sample D-hat and B^T N^-1 B.  Events: 0 start, 1 kernels
-    # tabulated, 2 D-hat done (separate calls only), 3 step done.
     def roofline(prec, t_ms, fused):
         """The binding roof of the contraction launch: MFMA work at the dense
         peak of its operand type, or (when the launch also writes D-hat) HBM
@@ -432,6 +429,10 @@ def main():
     def fused_mode(prec):
         return not args.separate
 
+    # One step: tabulate the beam and prior kernels (with their unique
+    # blocks), then sample D-hat and B^T N^-1 B.  Events: 0 start, 1 kernels
+    # tabulated, 2 D-hat done (separate calls) or both done (combined call),
+    # 3 step done.
     def step(prec, ev):
         ev[0].record(stream)
         kb = sp.Kernel(g, b_l, R, stream=stream)

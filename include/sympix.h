@@ -181,10 +181,11 @@ sympix_status sympix_convolve(const sympix_grid *g, const sympix_kernel *b, cons
  * with ninv_dev (device, float64, npix values in pixel order, 32-byte aligned,
  * >= 0; negative or NaN values are not checked and give undefined results) and
  * out_dev (device, float64, nblocks k^4 values, stored-block order, 16-byte
- * aligned).
+ * aligned, not overlapping ninv_dev).
  *   prec: a sympix_precision.  FP64 is bitwise reproducible run to run.
- * Errors: EINVAL, ESIZE (ninv_len != npix or out_len != nblocks k^4),
- *         EUNSUPPORTED (k != 8), EHIP. */
+ * Errors: EINVAL (NULL, misalignment, out_dev overlapping ninv_dev, kernel of
+ *         another grid or device), ESIZE (ninv_len != npix or out_len !=
+ *         nblocks k^4), EUNSUPPORTED (k != 8), EHIP. */
 sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
                                  int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
                                  void *stream);

@@ -260,12 +260,13 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
         return fail(SYMPIX_EINVAL, "NULL device buffer");
     if (((uintptr_t)out_dev) % 16 || ((uintptr_t)ninv_dev) % 32 || ((uintptr_t)outD_dev) % 16)
         return fail(SYMPIX_EINVAL, "outputs must be 16-byte and ninv_dev 32-byte aligned");
-    if (d && out_len > 0) {
+    if (out_len > 0) {
         auto overlap = [](const void *p, size_t np, const void *q, size_t nq) {
             return (const char *)p < (const char *)q + nq && (const char *)q < (const char *)p + np;
         };
         const size_t ob = (size_t)out_len * sizeof(double), nb = (size_t)ninv_len * sizeof(double);
-        if (overlap(outD_dev, ob, out_dev, ob) || overlap(outD_dev, ob, ninv_dev, nb))
+        if (overlap(out_dev, ob, ninv_dev, nb)) return fail(SYMPIX_EINVAL, "the output overlaps ninv_dev");
+        if (d && (overlap(outD_dev, ob, out_dev, ob) || overlap(outD_dev, ob, ninv_dev, nb)))
             return fail(SYMPIX_EINVAL, "the D-hat output overlaps another buffer");
     }
     if (d && d->device != b->device) return fail(SYMPIX_EINVAL, "the two kernels live on different devices");

@@ -174,6 +174,14 @@ def test_c1_errors_through_the_abi(c1):
     with pytest.raises(sp.SympixError) as e:
         sp.sample_BtNB(g, kb, n, out, 7)
     assert e.value.code == "EINVAL"
+    # output overlapping N^-1: one buffer holding both, 32-byte aligned
+    shared = torch.zeros(g.out_len + g.npix + 4, dtype=torch.float64, device="cuda")
+    off = (-(shared.data_ptr() // 8)) % 4
+    n_in = shared[off:off + g.npix]
+    n_in.copy_(n)
+    with pytest.raises(sp.SympixError) as e:
+        sp.sample_BtNB(g, kb, n_in, shared[off + g.npix - 2:off + g.npix - 2 + g.out_len], "fp64")
+    assert e.value.code == "EINVAL"
     k4 = sp.Grid(40, 4)
     kk = sp.Kernel(k4, np.ones(41), 0.0)
     with pytest.raises(sp.SympixError) as e:
