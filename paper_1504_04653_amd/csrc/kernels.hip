@@ -723,6 +723,12 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // and step (loaded with one step's loads, stored after the next step's), so
 // that these writes proceed under the contraction's arithmetic; chunks left
 // after the last step are copied at the end of the tile.
+// LDS staging buffers of the split-BF16 kernels: four (operands staged two
+// steps ahead, one barrier per term) where they fit, else two (one step
+// ahead, one barrier per step).  Two 4-wave BF16x6 workgroups per CU would
+// need 2 x 85 KB with four.
+__host__ __device__ constexpr int bf16_buffers(int np, bool wd) { return wd || np == 2 ? 4 : 2; }
+
 template <int NP, int NI, bool WD>
 __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item, int32_t *sTile,
                                                 int32_t *sBlk, int32_t *sTerm, u16x8 *sW, floatx4 *sU) {
@@ -786,25 +792,32 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         udst[q] = ub * 8 + (uc ^ usw(ub));
     }
 
-    // Addresses of one step (row a, term e, half h): W offsets of this
-    // thread's staged chunks, B_IK rows of the term, and this lane's B_IJ
+    // Addresses of one step (term e, half h) for the staged operands (W
+    // offsets of this thread's chunks, B_IK rows), and of this lane's B_IJ
     // values of row a.
-    struct Addr { int64_t wo[NWC]; const float *u2, *p1; };
-    auto addr = [&](int a, int e, int h) {
-        Addr r;
+    struct SAddr { int64_t wo[NWC]; const float *u2; };
+    struct OAddr { const float *p1; };
+    auto saddr = [&](int e, int h) {
+        SAddr r;
 #pragma unroll
         for (int q = 0; q < NWC; ++q) r.wo[q] = (int64_t)sTile[wrow[q] + e] * 64 + 32 * h;
         r.u2 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + 32 * h;
+        return r;
+    };
+    auto oaddr = [&](int a, int e, int h) {
+        OAddr r;
         r.p1 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 32 * h + 8 * lk;
         return r;
     };
     struct Stage { u16x8 w[NWC]; floatx4 u[NUC]; };
     struct Own { floatx4 u1[2]; };        // B_IJ values of this wave's output row (not shared)
-    auto loads = [&](const Addr &ad, Stage &st, Own &o) {
+    auto stage_load = [&](const SAddr &ad, Stage &st) {
 #pragma unroll
         for (int q = 0; q < NWC; ++q) st.w[q] = *(const u16x8 *)(wsrc[q] + ad.wo[q]);
 #pragma unroll
         for (int q = 0; q < NUC; ++q) st.u[q] = *(const floatx4 *)(ad.u2 + usrc[q]);
+    };
+    auto own_load = [&](const OAddr &ad, Own &o) {
         o.u1[0] = *(const floatx4 *)ad.p1;
         o.u1[1] = *(const floatx4 *)(ad.p1 + 4);
     };
@@ -829,9 +842,18 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     // values and this wave's B_IJ values), with the addresses of the step after
     // next read meanwhile; (3) the next step's staged operands written to the
     // other buffer, and one barrier.
-    auto step = [&](const Own &oc, int buf, const Addr &an, Stage &stn, Own &on, bool first, int ca, int ce,
-                    int ch_, int stp, DCopy &dprev) {
-        loads(an, stn, on);
+    // One step, in three scheduling regions: (1) the loads of the staged
+    // operands of a later step (two ahead with four buffers, else the next)
+    // and of this wave's B_IJ values of the next step; (2) the MFMAs of this
+    // step from LDS buffer buf (W fragments, and M formed from the staged B_IK
+    // values and this wave's B_IJ values), with the addresses the next step
+    // needs read meanwhile; (3) the staged operands written to buffer sbuf,
+    // and a barrier where the schedule needs one.
+    auto step = [&](const Own &oc, int buf, const SAddr &sa, const OAddr &oa, int sbuf, Stage &stn, Own &on,
+                    bool first, bool bar, int nse, int nsh, int noa, int noe, int noh, SAddr &sa_n, OAddr &oa_n,
+                    int stp, DCopy &dprev) {
+        stage_load(sa, stn);
+        own_load(oa, on);
         if constexpr (WD) {
             DCopy dc;
             dcopy_load<NT>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
@@ -876,7 +898,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
                         wf[i][qa], bfr[qb], (first && pr == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][jj], 0, 0, 0);
             }
         }
-        const Addr after = addr(ca, ce, ch_);
+        sa_n = saddr(nse, nsh);
+        oa_n = oaddr(noa, noe, noh);
         __builtin_amdgcn_sched_group_barrier(0x100, NI * NP + 6 + NWC, 0);   // LDS reads
 #pragma unroll
         for (int x = 0; x < 2 * NPROD * NI; ++x) {
@@ -884,45 +907,74 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
             __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);             // two VALU
         }
         __builtin_amdgcn_sched_barrier(0);
-        stage_store(stn, buf ^ 1);
-        __syncthreads();
+        stage_store(stn, sbuf);
+        if (bar) __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
-        return after;
     };
 
-    // Step h of a term computes from LDS buffer h.  Cursor: row index x
-    // (a = rw + RP x) and term e; past the last row the loads repeat the last
-    // term's addresses.
-    Stage s0, s1;
-    Own o0, o1;
-    int x = 0, e = 0;
-    {
-        const Addr a0 = addr(rw, 0, 0);
-        loads(a0, s0, o0);
-        stage_store(s0, 0);
-    }
-    Addr an = addr(rw, 0, 1);              // the next step's addresses
-    DCopy dpend;                           // D-hat chunks loaded, not yet stored
-    dpend.dst[0] = dpend.dst[1] = nullptr;
-    __syncthreads();
-    for (int it = 0; it < RPW * nterms; ++it) {
-        int ne = e + 1, nx = x;
+    // With four buffers, iteration it (one term of one row) computes from
+    // buffers 2 (it & 1) + h, fills the other pair for iteration it + 1, and
+    // ends with the only barrier of the term.  With two, step h computes from
+    // buffer h and fills the other one for the next step, and every step ends
+    // with a barrier.  Cursors: row index x (a = rw + RP x) and term e; past
+    // the last row they repeat (harmless reloads into buffers no step reads).
+    constexpr bool AHEAD2 = bf16_buffers(NP, WD) == 4;
+    auto next = [&](int cx, int ce, int &nx, int &ne) {
+        ne = ce + 1;
+        nx = cx;
         if (ne == nterms) {
             ne = 0;
             ++nx;
         }
-        const int a = rw + RP * x;
-        const bool last = nx >= RPW;
-        const int la = last ? a : rw + RP * nx, le = last ? e : ne;
-        const Addr a2 = step(o0, 0, an, s1, o1, true, la, le, 0, 2 * it, dpend);
-        an = step(o1, 1, a2, s0, o0, false, la, le, 1, 2 * it + 1, dpend);
+        if (nx >= RPW) {
+            nx = cx;
+            ne = ce;
+        }
+    };
+    Stage s0, s1;
+    Own o0, o1;
+    int x = 0, e = 0;
+    int x1, e1;
+    next(0, 0, x1, e1);
+    SAddr sa;
+    {
+        Stage t0;
+        stage_load(saddr(0, 0), t0);
+        own_load(oaddr(rw, 0, 0), o0);
+        if constexpr (AHEAD2) {
+            Stage t1;
+            stage_load(saddr(0, 1), t1);
+            stage_store(t1, 1);
+            sa = saddr(e1, 0);
+        } else {
+            sa = saddr(0, 1);
+        }
+        stage_store(t0, 0);
+    }
+    OAddr oa = oaddr(rw, 0, 1);
+    DCopy dpend;                           // D-hat chunks loaded, not yet stored
+    dpend.dst[0] = dpend.dst[1] = nullptr;
+    __syncthreads();
+    for (int it = 0; it < RPW * nterms; ++it) {
+        next(x, e, x1, e1);
+        const int a = rw + RP * x, a1 = rw + RP * x1;
+        if constexpr (AHEAD2) {
+            int x2, e2;
+            next(x1, e1, x2, e2);
+            const int ib = 2 * (it & 1), nb = 2 - ib;
+            step(o0, ib, sa, oa, nb, s1, o1, true, false, e1, 1, a1, e1, 0, sa, oa, 2 * it, dpend);
+            step(o1, ib + 1, sa, oa, nb + 1, s0, o0, false, true, e2, 0, a1, e1, 1, sa, oa, 2 * it + 1, dpend);
+        } else {
+            step(o0, 0, sa, oa, 1, s1, o1, true, true, e1, 0, a1, e1, 0, sa, oa, 2 * it, dpend);
+            step(o1, 1, sa, oa, 0, s0, o0, false, true, e1, 1, a1, e1, 1, sa, oa, 2 * it + 1, dpend);
+        }
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
-        if (ne == 0) {                   // end of output row a: store, clear
+        if (e == nterms - 1) {           // end of output row a: store, clear
 #pragma unroll
             for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -939,8 +991,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
         }
-        x = nx;
-        e = ne;
+        x = x1;
+        e = e1;
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
         dcopy_store(dpend, lane);
@@ -969,8 +1021,8 @@ void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
-    __shared__ u16x8 sW[2 * NP * 64 * 4];            // staged W, two buffers
-    __shared__ floatx4 sU[2 * 512];                  // staged B_IK values, two buffers
+    __shared__ u16x8 sW[bf16_buffers(NP, WD) * NP * 64 * 4];   // staged W
+    __shared__ floatx4 sU[bf16_buffers(NP, WD) * 512];          // staged B_IK values
     class_bf16_item<NP, WD>(pd, xcd_contiguous_index(), sTile, sBlk, sTerm, sW, sU);
 }
 
@@ -983,8 +1035,8 @@ void k_batch_bf16(const ProblemDescB *__restrict__ probs, const int32_t *__restr
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[128];
     __shared__ int32_t sTerm[2 * kMaxClassTerms];
-    __shared__ u16x8 sW[2 * NP * 64 * 4];
-    __shared__ floatx4 sU[2 * 512];
+    __shared__ u16x8 sW[bf16_buffers(NP, false) * NP * 64 * 4];
+    __shared__ floatx4 sU[bf16_buffers(NP, false) * 512];
     __shared__ int32_t sItem;
     const int home = blockIdx.x % nq;
     int tried = 0;                       // queues found empty (thread 0)
