@@ -22,7 +22,9 @@ are tabulated before the timed region and the schedule and tile shape are
 autotuned first.
 
 With --op conv a step is one pixel-domain convolution g = B-hat f (FP64) of
-the configuration's grid and beam.
+the configuration's grid and beam.  With --op two_hop a step tabulates the beam
+kernel and samples B^T N^-1 B on the two-hop pattern (every nonzero block of
+the product), in the first of --modes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c5]
                        [--op btnb|conv] [--modes bf16x6,fp64,bf16x3] [--no-cpu-baseline]
@@ -58,7 +60,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c4")
-    ap.add_argument("--op", default="btnb", choices=["btnb", "conv"],
+    ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop"],
                     help="btnb: the D-hat / B-hat^T N^-1 B-hat step (default); conv: the pixel-domain "
                          "convolution g = B-hat f")
     ap.add_argument("--modes", default=None,
@@ -367,6 +369,89 @@ def run_conv(args):
     print(json.dumps(line), flush=True)
 
 
+def run_two_hop(args):
+    """B^T N^-1 B on the two-hop pattern (every nonzero block of the product)."""
+    import torch
+
+    import paper_1504_04653_amd as sp
+    from workloads import synth as S
+
+    cfg = S.CONFIGS[args.config]
+    prec = [m.strip() for m in args.modes.split(",") if m.strip()][0]
+    torch.cuda.set_device(0)
+    g = sp.Grid(cfg.lmax, cfg.k)
+    t0 = time.perf_counter()
+    nblk, nterms = g.pattern_size("two_hop")
+    setup = time.perf_counter() - t0
+    th, ph = g.pixel_theta_phi()
+    ninv_dev = torch.as_tensor(S.ninv_for(cfg, th, ph)).cuda()
+    b_l, R = S.gaussian_beam(cfg.lmax, g.npix, cfg.fwhm_pix)
+    out = torch.empty(nblk * 4096, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    nelem = nblk * 4096
+    alg_flop = 2.0 * 64 ** 3 * nterms
+    print(f"# two-hop {args.config} {prec}: lmax={cfg.lmax} blocks={nblk} (one-hop {g.nblocks}) terms={nterms} "
+          f"output={nelem * 8 / 1e9:.1f} GB pattern_setup={setup:.2f}s", file=sys.stderr, flush=True)
+
+    def step(ev):
+        ev[0].record(stream)
+        kb = sp.Kernel(g, b_l, R, stream=stream)
+        ev[1].record(stream)
+        sp.sample_BtNB_pattern(g, kb, ninv_dev, out, prec, "two_hop", stream=stream)
+        ev[2].record(stream)
+        return kb
+
+    for _ in range(args.warmup):
+        keep = step([torch.cuda.Event(enable_timing=True) for _ in range(3)])
+        torch.cuda.synchronize()
+        del keep
+    evs, keeps = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        keeps.append(step(ev))
+        evs.append(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    keeps.clear()
+    t_C = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms_step = wall * 1000.0 / args.steps
+    mfma = PRODUCTS[prec] * alg_flop / (t_C * 1e-3) / 1e12
+    gbs = nelem * 8 / (t_C * 1e-3) / 1e9
+    t_mfma = PRODUCTS[prec] * alg_flop / (PEAK[prec] * 1e12)
+    t_hbm = nelem * 8 / (HBM_PEAK * 1e9)
+    if t_hbm >= t_mfma:
+        roof = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK, "achieved": gbs, "frac": gbs / HBM_PEAK,
+                "mfma_frac": mfma / PEAK[prec]}
+    else:
+        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec], "achieved": mfma, "frac": mfma / PEAK[prec],
+                "hbm_frac": gbs / HBM_PEAK}
+    roof["kernel"] = KERNEL_NAME[prec]
+    roof["traffic"] = None
+    print(f"# two-hop {prec}: step {ms_step:.2f} ms, contraction {t_C:.2f} ms, {mfma:.1f} TFLOP/s "
+          f"({mfma / PEAK[prec] * 100:.1f}% of {PEAK[prec]} TFLOP/s), {gbs:.0f} GB/s written",
+          file=sys.stderr, flush=True)
+    line = {
+        "metric": "B^T N^-1 B elements/s, two-hop pattern (every nonzero block of the product)",
+        "value": nelem / (ms_step * 1e-3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if prec.startswith("bf16") else ("f64" if prec == "fp64" else "f32"),
+        "data": "synthetic",
+        "config": {"workload": f"sympix lmax={cfg.lmax} k={cfg.k} two-hop blocks, beam FWHM {cfg.fwhm_pix:g} px "
+                               f"cut 3 FWHM, N^-1 {cfg.ninv_kind} seed {cfg.seed}",
+                   "lmax": cfg.lmax, "nblocks": nblk, "nterms": nterms, "precision": prec},
+        "roofline": roof,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -378,6 +463,9 @@ def main():
         return
     if args.op == "conv":
         run_conv(args)
+        return
+    if args.op == "two_hop":
+        run_two_hop(args)
         return
     import torch
 

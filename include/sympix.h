@@ -118,6 +118,24 @@ sympix_status sympix_grid_neighbours(const sympix_grid *g, int64_t *row_ptr, int
 /* Stored blocks as CSR over J: row_ptr[ntiles+1], col[nblocks] = K >= J. */
 sympix_status sympix_grid_blocks(const sympix_grid *g, int64_t *row_ptr, int32_t *col);
 
+/* Stored-block patterns of B-hat^T N^-1 B-hat.  With B-hat local (Section
+ * 4.2: zero unless the two pixels' tiles are the same or neighbours), block
+ * (J, K) of the product is nonzero only where nbr(J) and nbr(K) meet.
+ *   ONE_HOP: K in nbr(J), the pattern of D-hat (what sympix_sample_BtNB and
+ *            sympix_sample_D_BtNB return);
+ *   TWO_HOP: every (J, K) whose neighbourhoods meet, i.e. every nonzero block
+ *            of the product. */
+typedef enum { SYMPIX_PATTERN_ONE_HOP = 0, SYMPIX_PATTERN_TWO_HOP = 1 } sympix_pattern;
+
+/* Blocks (J, K >= J) of a sympix_pattern as CSR over J: *nblocks, *nterms
+ * (contraction terms over all its blocks), row_ptr[ntiles+1] (int64),
+ * col[nblocks] (int32, ascending).  Host buffers, any may be NULL (query
+ * *nblocks first to size col).  The two-hop pattern is built on the first
+ * call that needs it.
+ * Errors: EINVAL (NULL grid, unknown pattern), ENOMEM. */
+sympix_status sympix_grid_pattern_blocks(const sympix_grid *g, int32_t pattern, int64_t *nblocks, int64_t *nterms,
+                                         int64_t *row_ptr, int32_t *col);
+
 /* Symmetry keys (Section 2.3): for every adjacency entry (I, J) in CSR order
  * its unique-block id uid[nadjacency]; and for every id its key
  * (band_I, band_J, delta = (t_J T_I - t_I T_J) mod T_I T_J), arrays of length
@@ -189,6 +207,16 @@ sympix_status sympix_convolve(const sympix_grid *g, const sympix_kernel *b, cons
 sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
                                  int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
                                  void *stream);
+
+/* B-hat^T N^-1 B-hat (Eq. 15) on the blocks of a sympix_pattern, in its
+ * stored-block order; out_len = that pattern's nblocks k^4.  The two-hop
+ * blocks (J, K) not in the one-hop pattern have the terms I in nbr(J) and
+ * nbr(K), one to a few.  Otherwise as sympix_sample_BtNB, which is this call
+ * with SYMPIX_PATTERN_ONE_HOP.
+ * Errors: EINVAL (also an unknown pattern), ESIZE, ENOMEM, EUNSUPPORTED, EHIP. */
+sympix_status sympix_sample_BtNB_pattern(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
+                                         int64_t ninv_len, int32_t prec, int32_t pattern, double *out_dev,
+                                         int64_t out_len, void *stream);
 
 /* Both local operators of Eq. 16 in one call: outD_dev receives the D-hat
  * blocks of kernel d (as sympix_sample_D) and outC_dev the B-hat^T N^-1 B-hat

@@ -135,6 +135,20 @@ def stored_block_list(g: Grid):
     return pairs
 
 
+def two_hop_block_list(g: Grid):
+    """Every block (J, K), K >= J, of B-hat^T N^-1 B-hat that can be nonzero
+    when B-hat is local (Section 4.2): J and K have a common neighbour I
+    (Eq. 15 sums over I in nbr(J) & nbr(K)).  Order: J ascending, then K."""
+    nbr = [set(g.tile_neighbours(t)) for t in range(g.ntiles)]
+    pairs = []
+    for J in range(g.ntiles):
+        ks = set()
+        for I in nbr[J]:
+            ks.update(K for K in nbr[I] if K >= J)
+        pairs.extend((J, K) for K in sorted(ks))
+    return pairs
+
+
 def sample_D(g: Grid, d_l, radius=None, pairs=None):
     """All stored blocks D-hat_JK (Eq. 16, local truncation of Section 4.2)."""
     op = LocalOperator(g, d_l, radius)

@@ -29,6 +29,8 @@ _lib = ctypes.CDLL(_LIB_PATH)
 
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
+PATTERN_ONE_HOP, PATTERN_TWO_HOP = 0, 1
+PATTERNS = {"one_hop": PATTERN_ONE_HOP, "two_hop": PATTERN_TWO_HOP}
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "EINFEASIBLE", -3: "ENOMEM", -4: "EHIP", -5: "ESIZE",
            -6: "EUNSUPPORTED"}
@@ -69,12 +71,15 @@ _grid_rings = _sig("sympix_grid_rings", [_vp, _vp, _vp, _vp, _vp])
 _grid_bands = _sig("sympix_grid_bands", [_vp, _vp, _vp, _vp])
 _grid_neighbours = _sig("sympix_grid_neighbours", [_vp, _vp, _vp])
 _grid_blocks = _sig("sympix_grid_blocks", [_vp, _vp, _vp])
+_grid_pattern_blocks = _sig("sympix_grid_pattern_blocks", [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                                           _vp, _vp])
 _grid_unique = _sig("sympix_grid_unique", [_vp, _vp, _vp, _vp, _vp])
 _kernel_tabulate = _sig("sympix_kernel_tabulate", [_vp, _vp, _i32, _f64, _i32, _vp, ctypes.POINTER(_vp)])
 _kernel_destroy = _sig("sympix_kernel_destroy", [_vp], None)
 _kernel_eval = _sig("sympix_kernel_eval", [_vp, _vp, _vp, _i64, _vp])
 _sample_D = _sig("sympix_sample_D", [_vp, _vp, _vp, _i64, _vp])
 _sample_BtNB = _sig("sympix_sample_BtNB", [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp])
+_sample_BtNB_pattern = _sig("sympix_sample_BtNB_pattern", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _i64, _vp])
 _sample_D_BtNB = _sig("sympix_sample_D_BtNB", [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp, _i64, _vp])
 _convolve = _sig("sympix_convolve", [_vp, _vp, _vp, _i64, _vp, _i64, _vp])
 _last_error = _sig("sympix_last_error", [], ctypes.c_char_p)
@@ -105,9 +110,9 @@ def plan_name(plan):
     return f"{sched}/{tiling}"
 
 EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sympix_grid_rings",
-            "sympix_grid_bands", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_unique",
+            "sympix_grid_bands", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_pattern_blocks", "sympix_grid_unique",
             "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
-            "sympix_sample_BtNB", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
+            "sympix_sample_BtNB", "sympix_sample_BtNB_pattern", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
             "sympix_batch_launch", "sympix_batch_destroy", "sympix_last_error")
 
 
@@ -203,6 +208,24 @@ class Grid:
         _check(_grid_blocks(self._h, _ptr(rp), _ptr(col)))
         return rp, col
 
+    def pattern_size(self, pattern=PATTERN_ONE_HOP):
+        """(blocks, contraction terms) of a stored-block pattern."""
+        if isinstance(pattern, str):
+            pattern = PATTERNS[pattern]
+        n, t = _i64(0), _i64(0)
+        _check(_grid_pattern_blocks(self._h, int(pattern), ctypes.byref(n), ctypes.byref(t), None, None))
+        return n.value, t.value
+
+    def pattern_blocks(self, pattern=PATTERN_ONE_HOP):
+        """(row_ptr, col) of a stored-block pattern (PATTERN_ONE_HOP / TWO_HOP)."""
+        if isinstance(pattern, str):
+            pattern = PATTERNS[pattern]
+        n, _ = self.pattern_size(pattern)
+        rp = np.zeros(self.ntiles + 1, dtype=np.int64)
+        col = np.zeros(n, dtype=np.int32)
+        _check(_grid_pattern_blocks(self._h, int(pattern), None, None, _ptr(rp), _ptr(col)))
+        return rp, col
+
     def unique(self):
         uid = np.zeros(self.nadjacency, dtype=np.int32)
         bi = np.zeros(self.nunique, dtype=np.int32)
@@ -274,6 +297,20 @@ def sample_BtNB(grid: Grid, kernel: Kernel, ninv, out, prec=FP64, stream=None):
     _require_f64_device(out, "out")
     _check(_sample_BtNB(grid.handle, kernel.handle, _ptr(ninv), _numel(ninv), int(prec), _ptr(out),
                         _numel(out), _stream(stream)))
+    return out
+
+
+def sample_BtNB_pattern(grid: Grid, kernel: Kernel, ninv, out, prec=FP64, pattern=PATTERN_ONE_HOP, stream=None):
+    """B-hat^T N^-1 B-hat on the blocks of a stored-block pattern (out holds
+    that pattern's nblocks k^4 values, in the order of grid.pattern_blocks)."""
+    if isinstance(prec, str):
+        prec = PRECISIONS[prec]
+    if isinstance(pattern, str):
+        pattern = PATTERNS[pattern]
+    _require_f64_device(ninv, "ninv")
+    _require_f64_device(out, "out")
+    _check(_sample_BtNB_pattern(grid.handle, kernel.handle, _ptr(ninv), _numel(ninv), int(prec), int(pattern),
+                                _ptr(out), _numel(out), _stream(stream)))
     return out
 
 

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -83,12 +84,32 @@ void free_dev(DevGrid &d) {
     d = DevGrid();
 }
 
+// Device copies of the class tables of a further stored-block pattern.
+struct DevClasses {
+    sympix::DevClass *classes = nullptr;
+    int32_t *class_terms = nullptr;
+    int32_t *class_blk = nullptr;
+    int32_t *class_itab = nullptr;
+    int32_t *mtiles = nullptr;
+};
+
+void free_dev_classes(DevClasses &d) {
+    hipFree(d.classes);
+    hipFree(d.class_terms);
+    hipFree(d.class_blk);
+    hipFree(d.class_itab);
+    hipFree(d.mtiles);
+    d = DevClasses();
+}
+
 }  // namespace
 
 struct sympix_grid {
     Geometry geo;
     mutable std::mutex mu;
     mutable std::map<int, DevGrid> dev;
+    mutable std::unique_ptr<sympix::Pattern> two_hop;    // built on first use
+    mutable std::map<int, DevClasses> dev_two_hop;
 };
 
 struct sympix_kernel {
@@ -140,13 +161,13 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.exp_blk, geo.exp_blk.data(), geo.exp_blk.size());
     if (e == hipSuccess) e = upload(&d.exp_items, geo.exp_items.data(), geo.exp_items.size());
     if (e == hipSuccess)
-        e = upload(&d.classes, reinterpret_cast<const sympix::DevClass *>(geo.classes.data()),
-                   geo.classes.size());
-    if (e == hipSuccess) e = upload(&d.class_terms, geo.class_terms.data(), geo.class_terms.size());
-    if (e == hipSuccess) e = upload(&d.class_blk, geo.class_blk.data(), geo.class_blk.size());
-    if (e == hipSuccess) e = upload(&d.class_itab, geo.class_itab.data(), geo.class_itab.size());
-    if (e == hipSuccess) e = upload(&d.mtiles, geo.mtiles.data(), geo.mtiles.size());
-    if (e == hipSuccess) e = upload(&d.mtiles32, geo.mtiles32.data(), geo.mtiles32.size());
+        e = upload(&d.classes, reinterpret_cast<const sympix::DevClass *>(geo.cls.classes.data()),
+                   geo.cls.classes.size());
+    if (e == hipSuccess) e = upload(&d.class_terms, geo.cls.class_terms.data(), geo.cls.class_terms.size());
+    if (e == hipSuccess) e = upload(&d.class_blk, geo.cls.class_blk.data(), geo.cls.class_blk.size());
+    if (e == hipSuccess) e = upload(&d.class_itab, geo.cls.class_itab.data(), geo.cls.class_itab.size());
+    if (e == hipSuccess) e = upload(&d.mtiles, geo.cls.mtiles.data(), geo.cls.mtiles.size());
+    if (e == hipSuccess) e = upload(&d.mtiles32, geo.cls.mtiles32.data(), geo.cls.mtiles32.size());
     if (e == hipSuccess) e = upload(&d.conv_chunks, geo.conv_chunks.data(), geo.conv_chunks.size());
     if (e == hipSuccess) e = upload(&d.conv_slots, geo.conv_slots.data(), geo.conv_slots.size());
     if (e != hipSuccess) {
@@ -156,6 +177,42 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     }
     auto res = g->dev.emplace(device, d);
     *out = &res.first->second;
+    return SYMPIX_OK;
+}
+
+// The two-hop pattern of grid g (host tables built on first use) and, with
+// device >= 0, its class tables on that device.
+sympix_status two_hop_tables(const sympix_grid *g, int device, const sympix::Pattern **pat,
+                             const DevClasses **dc) {
+    std::lock_guard<std::mutex> lock(g->mu);
+    if (!g->two_hop) {
+        auto p = std::make_unique<sympix::Pattern>();
+        std::string err;
+        const int st = sympix::build_two_hop(g->geo, *p, err);
+        if (st != 0) return fail((sympix_status)st, err);
+        g->two_hop = std::move(p);
+    }
+    *pat = g->two_hop.get();
+    if (device < 0) return SYMPIX_OK;
+    auto it = g->dev_two_hop.find(device);
+    if (it != g->dev_two_hop.end()) {
+        *dc = &it->second;
+        return SYMPIX_OK;
+    }
+    const sympix::ClassTables &ct = g->two_hop->cls;
+    DevClasses d;
+    hipError_t e = upload(&d.classes, reinterpret_cast<const sympix::DevClass *>(ct.classes.data()), ct.classes.size());
+    if (e == hipSuccess) e = upload(&d.class_terms, ct.class_terms.data(), ct.class_terms.size());
+    if (e == hipSuccess) e = upload(&d.class_blk, ct.class_blk.data(), ct.class_blk.size());
+    if (e == hipSuccess) e = upload(&d.class_itab, ct.class_itab.data(), ct.class_itab.size());
+    if (e == hipSuccess) e = upload(&d.mtiles, ct.mtiles.data(), ct.mtiles.size());
+    if (e != hipSuccess) {
+        free_dev_classes(d);
+        return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the two-hop tables failed")
+                                        : hip_fail(e, "uploading the two-hop tables");
+    }
+    auto res = g->dev_two_hop.emplace(device, d);
+    *dc = &res.first->second;
     return SYMPIX_OK;
 }
 
@@ -247,14 +304,25 @@ sympix_status check_kernel_use(const sympix_grid *g, const sympix_kernel *kr) {
 // B-hat^T N^-1 B-hat into out_dev and, with a D-hat kernel d, the D-hat
 // blocks into outD_dev, both written by one class-GEMM launch.
 sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sympix_kernel *b,
-                          const double *ninv_dev, int64_t ninv_len, int32_t prec, double *outD_dev,
-                          int64_t outD_len, double *out_dev, int64_t out_len, void *stream, const char *what) {
+                          const double *ninv_dev, int64_t ninv_len, int32_t prec, int32_t pattern,
+                          double *outD_dev, int64_t outD_len, double *out_dev, int64_t out_len, void *stream,
+                          const char *what) {
     sympix_status s = check_kernel_use(g, b);
     if (s != SYMPIX_OK) return s;
     const Geometry &geo = g->geo;
     if (prec < SYMPIX_FP64 || prec > SYMPIX_BF16X6) return fail(SYMPIX_EINVAL, "unknown precision mode");
+    if (pattern != SYMPIX_PATTERN_ONE_HOP && pattern != SYMPIX_PATTERN_TWO_HOP)
+        return fail(SYMPIX_EINVAL, "unknown block pattern");
     if (ninv_len != geo.npix) return fail(SYMPIX_ESIZE, "ninv_len must be npix");
-    const int64_t want = geo.nblocks() * sympix::kBlockElems;
+    const sympix::Pattern *pat = nullptr;
+    if (pattern == SYMPIX_PATTERN_TWO_HOP) {
+        const DevClasses *unused = nullptr;
+        s = two_hop_tables(g, -1, &pat, &unused);
+        if (s != SYMPIX_OK) return s;
+    }
+    const int64_t nblocks = pat ? pat->nblocks() : geo.nblocks();
+    const sympix::ClassTables &ct = pat ? pat->cls : geo.cls;
+    const int64_t want = nblocks * sympix::kBlockElems;
     if (out_len != want || (d && outD_len != want)) return fail(SYMPIX_ESIZE, "output lengths must be nblocks * k^4");
     if ((geo.npix > 0 && !ninv_dev) || (out_len > 0 && !out_dev) || (d && out_len > 0 && !outD_dev))
         return fail(SYMPIX_EINVAL, "NULL device buffer");
@@ -274,19 +342,30 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
     s = device_tables(g, b->device, &dg);
     if (s != SYMPIX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    if (geo.max_class_terms > sympix::kMaxClassTerms)
+    if (ct.max_class_terms > sympix::kMaxClassTerms)
         return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
     const bool fused = d != nullptr;
     sympix::BtnbArgs a;
     a.u64t = b->u64t;
     a.ut32 = b->ut32;
-    a.classes = dg->classes;
-    a.class_terms = dg->class_terms;
-    a.class_blk = dg->class_blk;
-    a.class_itab = dg->class_itab;
-    a.mtiles = dg->mtiles;
-    a.nmtiles = (int64_t)geo.mtiles.size() / 4;
-    a.nblocks = geo.nblocks();
+    if (pat) {
+        const DevClasses *dc = nullptr;
+        s = two_hop_tables(g, b->device, &pat, &dc);
+        if (s != SYMPIX_OK) return s;
+        a.classes = dc->classes;
+        a.class_terms = dc->class_terms;
+        a.class_blk = dc->class_blk;
+        a.class_itab = dc->class_itab;
+        a.mtiles = dc->mtiles;
+    } else {
+        a.classes = dg->classes;
+        a.class_terms = dg->class_terms;
+        a.class_blk = dg->class_blk;
+        a.class_itab = dg->class_itab;
+        a.mtiles = dg->mtiles;
+    }
+    a.nmtiles = (int64_t)ct.mtiles.size() / 4;
+    a.nblocks = nblocks;
     a.npix = geo.npix;
     a.ninv = ninv_dev;
     a.out = out_dev;
@@ -346,6 +425,7 @@ sympix_status sympix_grid_create(int32_t lmax, int32_t k, double polar_margin, s
 void sympix_grid_destroy(sympix_grid *g) {
     if (!g) return;
     for (auto &kv : g->dev) free_dev(kv.second);
+    for (auto &kv : g->dev_two_hop) free_dev_classes(kv.second);
     delete g;
 }
 
@@ -403,6 +483,30 @@ sympix_status sympix_grid_blocks(const sympix_grid *g, int64_t *row_ptr, int32_t
     const Geometry &s = g->geo;
     if (row_ptr) std::memcpy(row_ptr, s.blk_ptr.data(), s.blk_ptr.size() * sizeof(int64_t));
     if (col) std::memcpy(col, s.blk_col.data(), s.blk_col.size() * sizeof(int32_t));
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_grid_pattern_blocks(const sympix_grid *g, int32_t pattern, int64_t *nblocks, int64_t *nterms,
+                                        int64_t *row_ptr, int32_t *col) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const std::vector<int64_t> *ptr = &g->geo.blk_ptr;
+    const std::vector<int32_t> *cols = &g->geo.blk_col;
+    int64_t nt = (int64_t)g->geo.terms.size();
+    if (pattern == SYMPIX_PATTERN_TWO_HOP) {
+        const sympix::Pattern *pat = nullptr;
+        const DevClasses *unused = nullptr;
+        sympix_status s = two_hop_tables(g, -1, &pat, &unused);
+        if (s != SYMPIX_OK) return s;
+        ptr = &pat->blk_ptr;
+        cols = &pat->blk_col;
+        nt = (int64_t)pat->terms.size();
+    } else if (pattern != SYMPIX_PATTERN_ONE_HOP) {
+        return fail(SYMPIX_EINVAL, "unknown block pattern");
+    }
+    if (nblocks) *nblocks = (int64_t)cols->size();
+    if (nterms) *nterms = nt;
+    if (row_ptr) std::memcpy(row_ptr, ptr->data(), ptr->size() * sizeof(int64_t));
+    if (col) std::memcpy(col, cols->data(), cols->size() * sizeof(int32_t));
     return SYMPIX_OK;
 }
 
@@ -551,7 +655,15 @@ sympix_status sympix_convolve(const sympix_grid *g, const sympix_kernel *b, cons
 sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
                                  int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
                                  void *stream) {
-    return sample_btnb(g, nullptr, b, ninv_dev, ninv_len, prec, nullptr, 0, out_dev, out_len, stream, "sample_BtNB");
+    return sample_btnb(g, nullptr, b, ninv_dev, ninv_len, prec, SYMPIX_PATTERN_ONE_HOP, nullptr, 0, out_dev, out_len,
+                       stream, "sample_BtNB");
+}
+
+sympix_status sympix_sample_BtNB_pattern(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
+                                         int64_t ninv_len, int32_t prec, int32_t pattern, double *out_dev,
+                                         int64_t out_len, void *stream) {
+    return sample_btnb(g, nullptr, b, ninv_dev, ninv_len, prec, pattern, nullptr, 0, out_dev, out_len, stream,
+                       "sample_BtNB_pattern");
 }
 
 sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d, const sympix_kernel *b,
@@ -559,8 +671,8 @@ sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d,
                                    int64_t outD_len, double *outC_dev, int64_t outC_len, void *stream) {
     sympix_status s = check_kernel_use(g, d);
     if (s != SYMPIX_OK) return s;
-    return sample_btnb(g, d, b, ninv_dev, ninv_len, prec, outD_dev, outD_len, outC_dev, outC_len, stream,
-                       "sample_D_BtNB");
+    return sample_btnb(g, d, b, ninv_dev, ninv_len, prec, SYMPIX_PATTERN_ONE_HOP, outD_dev, outD_len, outC_dev,
+                       outC_len, stream, "sample_D_BtNB");
 }
 
 }  // extern "C"
@@ -728,7 +840,7 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
         if (((uintptr_t)p[i].out_dev) % 16 || ((uintptr_t)p[i].ninv_dev) % 8)
             return fail(SYMPIX_EINVAL, "problem " + std::to_string(i) +
                                            ": out_dev must be 16-byte and ninv_dev 8-byte aligned");
-        if (geo.max_class_terms > sympix::kMaxClassTerms)
+        if (geo.cls.max_class_terms > sympix::kMaxClassTerms)
             return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
         if (p[i].out_len > 0)
             spans.emplace_back((uintptr_t)p[i].out_dev, (uintptr_t)(p[i].out_dev + p[i].out_len));
@@ -772,7 +884,7 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
         }
         for (int t = 0; t < SYMPIX_NTILINGS; ++t) {
             const int32_t *dtiles = t == SYMPIX_TILES_64 ? dg->mtiles : dg->mtiles32;
-            const std::vector<int32_t> &tiles = t == SYMPIX_TILES_64 ? geo.mtiles : geo.mtiles32;
+            const std::vector<int32_t> &tiles = t == SYMPIX_TILES_64 ? geo.cls.mtiles : geo.cls.mtiles32;
             sympix::ProblemDesc d{dtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
                                   p[i].b->ut32, nullptr, p[i].out_dev, nullptr, nullptr, nullptr};
             bt->hdesc[t].push_back(d);
@@ -784,7 +896,7 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
             for (int64_t k = 0; k < nmt; ++k) {
                 bt->item_prob[t].push_back(i);
                 bt->item_tile[t].push_back((int32_t)k);
-                bt->item_cost[t].push_back(geo.classes[tiles[4 * k]].nterms * tiles[4 * k + 2]);
+                bt->item_cost[t].push_back(geo.cls.classes[tiles[4 * k]].nterms * tiles[4 * k + 2]);
             }
         }
         bt->ninv.push_back(p[i].ninv_dev);

@@ -161,6 +161,80 @@ int64_t pos_mod(int64_t a, int64_t m) {
     return r < 0 ? r + m : r;
 }
 
+// Block classes of a stored-block pattern: key = the sorted (uid_a, uid_b)
+// pairs of a block's terms; member tiles of 64 rows (a tail of at most 48
+// members in tiles of 32 and / or 16) and, as a second tile shape, of 32.
+void build_classes(const std::vector<int64_t> &term_ptr, const std::vector<Term> &terms, ClassTables &ct) {
+    struct VecHash {
+        size_t operator()(const std::vector<int32_t> &v) const {
+            uint64_t h = 1469598103934665603ull;
+            for (int32_t x : v) h = (h ^ (uint32_t)x) * 1099511628211ull;
+            return (size_t)h;
+        }
+    };
+    const int64_t nblocks = (int64_t)term_ptr.size() - 1;
+    std::unordered_map<std::vector<int32_t>, int32_t, VecHash> index;
+    std::vector<std::vector<int32_t>> members;     // per class: block indices
+    std::vector<std::vector<int32_t>> tiles_of;    // per class: I per (member, term)
+    std::vector<std::vector<int32_t>> keys;
+    std::vector<std::tuple<int32_t, int32_t, int32_t>> tt;
+    std::vector<int32_t> key;
+    for (int64_t n = 0; n < nblocks; ++n) {
+        tt.clear();
+        for (int64_t t = term_ptr[n]; t < term_ptr[n + 1]; ++t)
+            tt.emplace_back(terms[t].uid_a, terms[t].uid_b, terms[t].tile);
+        std::sort(tt.begin(), tt.end());
+        key.clear();
+        for (auto &x : tt) {
+            key.push_back(std::get<0>(x));
+            key.push_back(std::get<1>(x));
+        }
+        auto it = index.find(key);
+        int32_t c;
+        if (it == index.end()) {
+            c = (int32_t)keys.size();
+            index.emplace(key, c);
+            keys.push_back(key);
+            members.emplace_back();
+            tiles_of.emplace_back();
+        } else {
+            c = it->second;
+        }
+        members[c].push_back((int32_t)n);
+        for (auto &x : tt) tiles_of[c].push_back(std::get<2>(x));
+    }
+    for (size_t c = 0; c < keys.size(); ++c) {
+        BlockClass bc;
+        bc.nterms = (int32_t)(keys[c].size() / 2);
+        ct.max_class_terms = std::max(ct.max_class_terms, bc.nterms);
+        bc.nblocks = (int32_t)members[c].size();
+        bc.term0 = (int32_t)(ct.class_terms.size() / 2);
+        bc.blk0 = (int32_t)ct.class_blk.size();
+        bc.itab0 = (int64_t)ct.class_itab.size();
+        ct.class_terms.insert(ct.class_terms.end(), keys[c].begin(), keys[c].end());
+        ct.class_blk.insert(ct.class_blk.end(), members[c].begin(), members[c].end());
+        ct.class_itab.insert(ct.class_itab.end(), tiles_of[c].begin(), tiles_of[c].end());
+        auto tile = [&](int32_t m0, int32_t groups) {
+            ct.mtiles.insert(ct.mtiles.end(), {(int32_t)c, m0, groups, 0});
+        };
+        int32_t m0 = 0;
+        for (; bc.nblocks - m0 > 48; m0 += 64) tile(m0, 4);
+        const int32_t r = bc.nblocks - m0;
+        if (r > 32) {
+            tile(m0, 2);
+            tile(m0 + 32, 1);
+        } else if (r > 16) {
+            tile(m0, 2);
+        } else if (r > 0) {
+            tile(m0, 1);
+        }
+        int32_t mb = 0;
+        for (; bc.nblocks - mb > 16; mb += 32) ct.mtiles32.insert(ct.mtiles32.end(), {(int32_t)c, mb, 2, 0});
+        if (bc.nblocks - mb > 0) ct.mtiles32.insert(ct.mtiles32.end(), {(int32_t)c, mb, 1, 0});
+        ct.classes.push_back(bc);
+    }
+}
+
 }  // namespace
 
 int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::string &err) {
@@ -365,80 +439,7 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
             }
         }
 
-        // block classes: key = sorted (uid_a, uid_b) pairs of the block's terms
-        {
-            struct VecHash {
-                size_t operator()(const std::vector<int32_t> &v) const {
-                    uint64_t h = 1469598103934665603ull;
-                    for (int32_t x : v) h = (h ^ (uint32_t)x) * 1099511628211ull;
-                    return (size_t)h;
-                }
-            };
-            std::unordered_map<std::vector<int32_t>, int32_t, VecHash> index;
-            std::vector<std::vector<int32_t>> members;     // per class: block indices
-            std::vector<std::vector<int32_t>> tiles_of;    // per class: I per (member, term)
-            std::vector<std::vector<int32_t>> keys;
-            std::vector<std::tuple<int32_t, int32_t, int32_t>> tt;
-            std::vector<int32_t> key;
-            for (int64_t n = 0; n < g.nblocks(); ++n) {
-                tt.clear();
-                for (int64_t t = g.term_ptr[n]; t < g.term_ptr[n + 1]; ++t)
-                    tt.emplace_back(g.terms[t].uid_a, g.terms[t].uid_b, g.terms[t].tile);
-                std::sort(tt.begin(), tt.end());
-                key.clear();
-                for (auto &x : tt) {
-                    key.push_back(std::get<0>(x));
-                    key.push_back(std::get<1>(x));
-                }
-                auto it = index.find(key);
-                int32_t c;
-                if (it == index.end()) {
-                    c = (int32_t)keys.size();
-                    index.emplace(key, c);
-                    keys.push_back(key);
-                    members.emplace_back();
-                    tiles_of.emplace_back();
-                } else {
-                    c = it->second;
-                }
-                members[c].push_back((int32_t)n);
-                for (auto &x : tt) tiles_of[c].push_back(std::get<2>(x));
-            }
-            for (size_t c = 0; c < keys.size(); ++c) {
-                BlockClass bc;
-                bc.nterms = (int32_t)(keys[c].size() / 2);
-                g.max_class_terms = std::max(g.max_class_terms, bc.nterms);
-                bc.nblocks = (int32_t)members[c].size();
-                bc.term0 = (int32_t)(g.class_terms.size() / 2);
-                bc.blk0 = (int32_t)g.class_blk.size();
-                bc.itab0 = (int64_t)g.class_itab.size();
-                g.class_terms.insert(g.class_terms.end(), keys[c].begin(), keys[c].end());
-                g.class_blk.insert(g.class_blk.end(), members[c].begin(), members[c].end());
-                g.class_itab.insert(g.class_itab.end(), tiles_of[c].begin(), tiles_of[c].end());
-                // member tiles of 64 rows; a tail of at most 48 members goes
-                // into tiles of 32 and / or 16 rows
-                auto tile = [&](int32_t m0, int32_t groups) {
-                    g.mtiles.insert(g.mtiles.end(), {(int32_t)c, m0, groups, 0});
-                };
-                int32_t m0 = 0;
-                for (; bc.nblocks - m0 > 48; m0 += 64) tile(m0, 4);
-                const int32_t r = bc.nblocks - m0;
-                if (r > 32) {
-                    tile(m0, 2);
-                    tile(m0 + 32, 1);
-                } else if (r > 16) {
-                    tile(m0, 2);
-                } else if (r > 0) {
-                    tile(m0, 1);
-                }
-                // the second tile shape a batch may use: tiles of 32 rows, a
-                // tail of at most 16 members in a tile of 16
-                int32_t mb = 0;
-                for (; bc.nblocks - mb > 16; mb += 32) g.mtiles32.insert(g.mtiles32.end(), {(int32_t)c, mb, 2, 0});
-                if (bc.nblocks - mb > 0) g.mtiles32.insert(g.mtiles32.end(), {(int32_t)c, mb, 1, 0});
-                g.classes.push_back(bc);
-            }
-        }
+        build_classes(g.term_ptr, g.terms, g.cls);
 
         // largest y = 1 - cos(gamma) over every pattern pair: per unique block the
         // largest |phi offset| over the k x k column pairs, then every ring pair
@@ -470,6 +471,55 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
         return 0;
     } catch (const std::bad_alloc &) {
         err = "host allocation failed while building the grid";
+        return -3;
+    }
+}
+
+
+int build_two_hop(const Geometry &g, Pattern &p, std::string &err) {
+    try {
+        p = Pattern();
+        auto uid_of = [&](int64_t I, int64_t J) -> int32_t {
+            auto first = g.adj_col.begin() + g.adj_ptr[I], last = g.adj_col.begin() + g.adj_ptr[I + 1];
+            auto it = std::lower_bound(first, last, (int32_t)J);
+            return g.adj_uid[it - g.adj_col.begin()];
+        };
+        // blocks (J, K >= J) with nbr(J) & nbr(K) non-empty, K ascending; terms
+        // I in nbr(J) & nbr(K), ascending
+        p.blk_ptr.assign(g.ntiles + 1, 0);
+        p.term_ptr.push_back(0);
+        std::vector<int32_t> ks;
+        for (int64_t J = 0; J < g.ntiles; ++J) {
+            ks.clear();
+            for (int64_t e = g.adj_ptr[J]; e < g.adj_ptr[J + 1]; ++e) {
+                const int64_t I = g.adj_col[e];
+                for (int64_t f = g.adj_ptr[I]; f < g.adj_ptr[I + 1]; ++f)
+                    if (g.adj_col[f] >= J) ks.push_back(g.adj_col[f]);
+            }
+            std::sort(ks.begin(), ks.end());
+            ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+            for (int32_t K : ks) {
+                p.blk_col.push_back(K);
+                auto a = g.adj_col.begin() + g.adj_ptr[J], ae = g.adj_col.begin() + g.adj_ptr[J + 1];
+                auto b = g.adj_col.begin() + g.adj_ptr[K], be = g.adj_col.begin() + g.adj_ptr[K + 1];
+                while (a != ae && b != be) {
+                    if (*a < *b) ++a;
+                    else if (*b < *a) ++b;
+                    else {
+                        const int64_t I = *a;
+                        p.terms.push_back(Term{uid_of(I, J), uid_of(I, K), (int32_t)I, 0});
+                        ++a;
+                        ++b;
+                    }
+                }
+                p.term_ptr.push_back((int64_t)p.terms.size());
+            }
+            p.blk_ptr[J + 1] = (int64_t)p.blk_col.size();
+        }
+        build_classes(p.term_ptr, p.terms, p.cls);
+        return 0;
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed building the two-hop pattern";
         return -3;
     }
 }

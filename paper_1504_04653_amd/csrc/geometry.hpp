@@ -26,6 +26,30 @@ struct BlockClass {
     int64_t itab0;   // first entry in class_itab (nblocks * nterms, block-major)
 };
 
+// The contraction of a stored-block pattern in class-GEMM form.
+struct ClassTables {
+    std::vector<BlockClass> classes;
+    std::vector<int32_t> class_terms;   // 2 per term: uid_a, uid_b
+    std::vector<int32_t> class_blk;     // stored-block index of each class member
+    std::vector<int32_t> class_itab;    // tile I of each (member, term)
+    std::vector<int32_t> mtiles;        // 4 per member tile: class, first member,
+                                        // 16-row groups (1, 2 or 4), 0
+    std::vector<int32_t> mtiles32;      // the same with tiles of at most 32 rows
+                                        // (groups 1 or 2): a tile shape for batches
+    int32_t max_class_terms = 0;
+};
+
+// A further stored-block pattern of B-hat^T N^-1 B-hat: blocks (J, K >= J) as
+// CSR over J, their contraction terms (CSR, I ascending) and classes.
+struct Pattern {
+    std::vector<int64_t> blk_ptr;
+    std::vector<int32_t> blk_col;
+    std::vector<int64_t> term_ptr;
+    std::vector<Term> terms;
+    ClassTables cls;
+    int64_t nblocks() const { return (int64_t)blk_col.size(); }
+};
+
 struct Geometry {
     int32_t lmax = 0, k = 0, nrings = 0, nbands_hemi = 0;
     double margin = 0.0;
@@ -70,15 +94,7 @@ struct Geometry {
     std::vector<Term> terms;
 
     // block classes for the GEMM form of the contraction, and its m-tiles
-    std::vector<BlockClass> classes;
-    std::vector<int32_t> class_terms;   // 2 per term: uid_a, uid_b
-    std::vector<int32_t> class_blk;     // stored-block index of each class member
-    std::vector<int32_t> class_itab;    // tile I of each (member, term)
-    std::vector<int32_t> mtiles;        // 4 per member tile: class, first member,
-                                        // 16-row groups (1, 2 or 4), 0
-    std::vector<int32_t> mtiles32;      // the same with tiles of at most 32 rows
-                                        // (groups 1 or 2): a tile shape for batches
-    int32_t max_class_terms = 0;
+    ClassTables cls;
 
     // convolution g = B-hat f: chunks of up to 16 consecutive output tiles of
     // one band {first tile, tiles, first slot, slots}; per slot a unique block
@@ -94,5 +110,9 @@ struct Geometry {
 
 // Status codes follow sympix_status. On failure err holds a message.
 int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::string &err);
+
+// The two-hop pattern: every (J, K >= J) whose neighbourhoods intersect, i.e.
+// every block of B-hat^T N^-1 B-hat that is not zero when B-hat is local.
+int build_two_hop(const Geometry &g, Pattern &p, std::string &err);
 
 }  // namespace sympix

@@ -65,6 +65,21 @@ def test_layout_bit_exact_against_oracle(lmax, k, margin):
     assert g.nterms == nterms
 
 
+@pytest.mark.parametrize("lmax,k,margin", LAYOUT_CASES)
+def test_two_hop_pattern_bit_exact_against_oracle(lmax, k, margin):
+    """The library's two-hop block pattern (every J, K >= J with a common
+    neighbour) equals the oracle's, built from its own neighbour lists."""
+    og = G.make_grid(lmax, k, polar_margin=margin)
+    g = sp.Grid(lmax, k, margin)
+    rp, col = g.pattern_blocks("two_hop")
+    ref = O.two_hop_block_list(og)
+    got = [(J, int(K)) for J in range(g.ntiles) for K in col[rp[J]:rp[J + 1]]]
+    assert got == ref
+    rp1, col1 = g.pattern_blocks("one_hop")
+    brp, bcol = g.blocks()
+    assert np.array_equal(rp1, brp) and np.array_equal(col1, bcol)
+
+
 @pytest.mark.parametrize("lmax,k,margin", [(64, 8, None), (34, 2, 2.0), (100, 8, None)])
 def test_pattern_max_separation(lmax, k, margin):
     """The table domain: max y over all pairs in neighbouring tiles."""

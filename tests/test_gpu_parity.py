@@ -285,6 +285,98 @@ def test_full_size_sampled(name, modes, n_random):
     torch.cuda.empty_cache()
 
 
+# --- the two-hop pattern: every nonzero block of the product -------------------
+
+def two_hop_index(g):
+    """Per one-hop stored block, its position in the two-hop output."""
+    rp1, col1 = g.pattern_blocks("one_hop")
+    rp2, col2 = g.pattern_blocks("two_hop")
+    idx = []
+    for J in range(g.ntiles):
+        row = col2[rp2[J]:rp2[J + 1]]
+        pos = np.searchsorted(row, col1[rp1[J]:rp1[J + 1]])
+        assert np.array_equal(row[pos], col1[rp1[J]:rp1[J + 1]])
+        idx.extend((rp2[J] + pos).tolist())
+    return np.asarray(idx, dtype=np.int64)
+
+
+@pytest.mark.parametrize("lmax", [1, 16, 64, 256])
+def test_two_hop_pattern_all_blocks(lmax):
+    """Every two-hop block against the oracle in all modes; the blocks the
+    one-hop pattern also holds are bitwise equal to sample_BtNB's."""
+    og = G.make_grid(lmax, 8)
+    g = sp.Grid(lmax, 8)
+    rng = np.random.default_rng(2000 + lmax)
+    ninv = rng.uniform(0.5, 2.0, g.npix)
+    ninv[rng.random(g.npix) < 0.1] = 0.0
+    b_l, R = S.gaussian_beam(lmax, g.npix, 3.0)
+    pairs = O.two_hop_block_list(og)
+    rows = [J for J, _ in pairs]
+    n2 = len(pairs)
+    say(f"[two-hop {lmax}] blocks: one-hop {g.nblocks}, two-hop {n2}")
+    kb = sp.Kernel(g, b_l, R)
+    Cref = O.sample_BtNB(og, b_l, ninv, R, pairs)
+    n_dev = dev(ninv)
+    idx = torch.as_tensor(two_hop_index(g), device="cuda")
+    for prec in ("fp64", "fp32", "bf16x6", "bf16x3"):
+        out = torch.full((n2 * 4096,), float("nan"), dtype=torch.float64, device="cuda")
+        sp.sample_BtNB_pattern(g, kb, n_dev, out, prec, "two_hop")
+        torch.cuda.synchronize()
+        C = out.view(n2, 64, 64)
+        rep = error_report(C.cpu().numpy(), Cref, rows)
+        say(f"[two-hop {lmax}] {prec}: {rep}")
+        assert rep["gate"] <= GATE[prec]
+        one = run_BtNB(g, kb, n_dev, prec)
+        assert torch.equal(C[idx], one), f"lmax {lmax} {prec}: one-hop blocks differ from sample_BtNB"
+
+
+def test_two_hop_pattern_full_size_sampled():
+    cfg = S.CONFIGS["c3"]
+    og = G.make_grid(cfg.lmax, cfg.k)
+    g = sp.Grid(cfg.lmax, cfg.k)
+    ninv, b_l, R, _ = config_inputs(cfg, og)
+    rp, col = g.pattern_blocks("two_hop")
+    n2 = len(col)
+    rows = sample_rows(og, 8, seed=cfg.seed + 2)
+    pairs, idx = [], []
+    for J in rows:
+        for n in range(rp[J], rp[J + 1]):
+            pairs.append((J, int(col[n])))
+            idx.append(n)
+    say(f"[two-hop {cfg.lmax}] blocks: one-hop {g.nblocks}, two-hop {n2}; sampled {len(pairs)}")
+    kb = sp.Kernel(g, b_l, R)
+    op = O.LocalOperator(og, b_l, R)
+    Cref = np.stack([O.btnb_block(op, ninv, J, K) for J, K in pairs])
+    n_dev = dev(ninv)
+    idx_t = torch.as_tensor(idx, device="cuda")
+    for prec in ("fp64", "bf16x6"):
+        out = torch.full((n2 * 4096,), float("nan"), dtype=torch.float64, device="cuda")
+        sp.sample_BtNB_pattern(g, kb, n_dev, out, prec, "two_hop")
+        torch.cuda.synchronize()
+        assert not bool(torch.isnan(out).any()), f"{prec}: a two-hop block was not written"
+        rep = error_report(out.view(n2, 64, 64)[idx_t].cpu().numpy(), Cref, [J for J, _ in pairs])
+        say(f"[two-hop {cfg.lmax}] {prec}: {rep}")
+        assert rep["gate"] <= GATE[prec]
+        del out
+        torch.cuda.empty_cache()
+
+
+def test_two_hop_pattern_errors(c1):
+    g, kb = c1["g"], c1["kb"]
+    n = dev(c1["ninv"])
+    rp, col = g.pattern_blocks("two_hop")
+    out = torch.empty(len(col) * 4096, dtype=torch.float64, device="cuda")
+    with pytest.raises(sp.SympixError) as e:
+        sp.sample_BtNB_pattern(g, kb, n, out, "fp64", 2)
+    assert e.value.code == "EINVAL"
+    with pytest.raises(sp.SympixError) as e:
+        sp.sample_BtNB_pattern(g, kb, n, out[:-4096], "fp64", "two_hop")
+    assert e.value.code == "ESIZE"
+    with pytest.raises(sp.SympixError) as e:                      # the one-hop length for the two-hop call
+        sp.sample_BtNB_pattern(g, kb, n, out[:g.out_len], "fp64", "two_hop")
+    assert e.value.code == "ESIZE"
+
+
 # --- pixel-domain convolution g = B-hat f (Section 4.1) --------------------------
 
 def run_convolve(g, kern, f_dev):

@@ -53,6 +53,26 @@ def test_btnb_and_D_match_dense_brute_force(lmax, k, margin):
             assert j // k2 in two_hop[i // k2]
 
 
+@pytest.mark.parametrize("lmax,k,margin", TRANSITION_GRIDS)
+def test_two_hop_blocks_match_dense_brute_force(lmax, k, margin):
+    """The two-hop list covers every nonzero of the brute-force product, and
+    the oracle's blocks on it (one-hop blocks included) equal the product's."""
+    g = G.make_grid(lmax, k, polar_margin=margin)
+    ninv, b_l, R = _inputs(g, seed=11)
+    pairs = O.two_hop_block_list(g)
+    assert set(O.stored_block_list(g)) <= set(pairs)
+    M = BR.btnb_sparse(g, b_l, ninv, R)
+    C = O.sample_BtNB(g, b_l, ninv, R, pairs)
+    assert _gate(C, BR.extract_blocks(M, g, pairs), pairs) < 1e-12
+    k2 = k * k
+    listed = set(pairs)
+    Mc = M.tocoo()
+    for i, j, v in zip(Mc.row, Mc.col, Mc.data):
+        J, K = i // k2, j // k2
+        if v != 0.0 and K >= J:
+            assert (J, K) in listed
+
+
 def test_c1_btnb_matches_sparse_brute_force(c1_grid):
     g = c1_grid
     cfg = S.CONFIGS["c1"]
