@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "geometry.hpp"
+
 namespace sympix {
 
 // Geometry of one unique block: rows are the k^2 pixels of a representative
@@ -48,7 +50,7 @@ hipError_t launch_unique_eval(KTable kt, const UInfo *uinfo, int64_t nunique, co
 // block uid into the stored blocks exp_blk[first .. first + count)
 hipError_t launch_expand(const double *u64, const int32_t *items, int64_t nitems, const int32_t *exp_blk,
                          double *out, hipStream_t st);
-// pixel-domain convolution g = B-hat f over chunks of 16 output tiles
+// pixel-domain convolution g = B-hat f over chunks of kConvTiles output tiles
 hipError_t launch_convolve(const double *u64, const int32_t *chunks, int64_t nchunks, const int32_t *slots,
                            const double *f, double *g, hipStream_t st);
 // a9: B-hat^T N^-1 B-hat contraction

@@ -408,33 +408,33 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
                     g.exp_items.insert(g.exp_items.end(), {(int32_t)u, f, std::min(64, cnt[u + 1] - f), 0});
         }
 
-        // convolution chunks: 16 consecutive tiles of one band; a slot per unique
+        // convolution chunks: kConvTiles consecutive tiles of one band; a slot per unique
         // block used, listing the input tile of every output tile (a tile uses a
         // unique block with at most one neighbour, else a further slot is made)
         {
             const int nb = (int)g.band_tiles.size();
             for (int b = 0; b < nb; ++b) {
                 const int32_t T = g.band_tiles[b];
-                for (int32_t c0 = 0; c0 < T; c0 += 16) {
-                    const int32_t J0 = (int32_t)g.band_tile0[b] + c0, n = std::min(16, T - c0);
-                    const int32_t slot0 = (int32_t)(g.conv_slots.size() / 17);
-                    std::vector<int32_t> slots;          // 17 per slot
+                for (int32_t c0 = 0; c0 < T; c0 += kConvTiles) {
+                    const int32_t J0 = (int32_t)g.band_tile0[b] + c0, n = std::min(kConvTiles, T - c0);
+                    const int32_t slot0 = (int32_t)(g.conv_slots.size() / (1 + kConvTiles));
+                    std::vector<int32_t> slots;          // 1 + kConvTiles per slot
                     for (int32_t j = 0; j < n; ++j) {
                         const int64_t J = J0 + j;
                         for (int64_t e = g.adj_ptr[J]; e < g.adj_ptr[J + 1]; ++e) {
                             const int32_t u = g.adj_uid[e], K = g.adj_col[e];
                             size_t sidx = 0;
-                            for (; sidx < slots.size(); sidx += 17)
+                            for (; sidx < slots.size(); sidx += 1 + kConvTiles)
                                 if (slots[sidx] == u && slots[sidx + 1 + j] < 0) break;
                             if (sidx == slots.size()) {
                                 slots.push_back(u);
-                                slots.insert(slots.end(), 16, -1);
+                                slots.insert(slots.end(), kConvTiles, -1);
                             }
                             slots[sidx + 1 + j] = K;
                         }
                     }
                     g.conv_slots.insert(g.conv_slots.end(), slots.begin(), slots.end());
-                    g.conv_chunks.insert(g.conv_chunks.end(), {J0, n, slot0, (int32_t)(slots.size() / 17)});
+                    g.conv_chunks.insert(g.conv_chunks.end(), {J0, n, slot0, (int32_t)(slots.size() / (1 + kConvTiles))});
                 }
             }
         }

@@ -9,6 +9,8 @@
 namespace sympix {
 
 // One contraction term of an output block (J, K): C_JK += B_IJ^T diag(w_I) B_IK.
+constexpr int kConvTiles = 32;   // output tiles per convolution chunk
+
 struct Term {
     int32_t uid_a;  // unique block of (I -> J)
     int32_t uid_b;  // unique block of (I -> K)
@@ -96,11 +98,11 @@ struct Geometry {
     // block classes for the GEMM form of the contraction, and its m-tiles
     ClassTables cls;
 
-    // convolution g = B-hat f: chunks of up to 16 consecutive output tiles of
-    // one band {first tile, tiles, first slot, slots}; per slot a unique block
-    // and, for each of the 16 tiles, the input tile K it multiplies (-1: none)
+    // convolution g = B-hat f: chunks of up to kConvTiles consecutive output
+    // tiles of one band {first tile, tiles, first slot, slots}; per slot a
+    // unique block and, for each tile, the input tile K it multiplies (-1: none)
     std::vector<int32_t> conv_chunks;   // 4 per chunk
-    std::vector<int32_t> conv_slots;    // 17 per slot: uid, K[16]
+    std::vector<int32_t> conv_slots;    // 1 + kConvTiles per slot: uid, K[]
 
     double y_pattern_max = 0.0;   // max 1 - cos(gamma) over all pattern pairs
 

@@ -7,7 +7,7 @@
 //                  row-major and FP64 / FP32 copies transposed via LDS
 //   k_expand       D-hat: streams each stored block from its unique block
 //   k_convolve     pixel-domain convolution g = B-hat f, one FP64 GEMM per
-//                  unique block over 16 output tiles
+//                  unique block over 32 output tiles
 //   k_class_f64    B-hat^T N^-1 B-hat (Eq. 15) in FP64 as one GEMM per class of
 //                  blocks that share their contraction pattern; the class
 //                  kernels' <true> instantiations also copy D-hat (combined call)
@@ -183,53 +183,93 @@ __global__ __launch_bounds__(256) void k_expand(const double *__restrict__ u64,
 
 // ---------------------------------------------------------------------------
 // Pixel-domain convolution g = B-hat f (Section 4.1): g_J = sum_{K in nbr(J)}
-// B_JK f_K.  One workgroup per chunk of 16 consecutive output tiles of a band,
-// wave i computing output rows 16 i .. 16 i + 15 of all 16 tiles.  For
-// every unique block u the chunk uses, one FP64 GEMM C += U_u F_u with
-// C[p][j] the outputs of tile J0 + j and F_u[q][j] = f of the input tile that
-// tile J0 + j multiplies with u (zero when it does not), so each unique block
-// is read once per 16 tiles.  MFMA 16x16x4 FP64, MFMA m = 2 x + t with
-// contraction index q = 8 x + 2 lk + t: lane (lr, lk) holds U[16 i + lr][q] and
-// F[q][lr]; its result holds rows 16 i + lk + 4 v of column lr.
+// B_JK f_K.  One workgroup per chunk of kConvTiles (32) consecutive output
+// tiles of a band, wave i computing output rows 16 i .. 16 i + 15 of all of
+// them, as two 16-column MFMA tiles.  For every unique block u the chunk uses
+// (a slot), one FP64 GEMM C += U_u F_u with C[p][j] the outputs of tile J0 + j
+// and F_u[q][j] = f of the input tile that tile J0 + j multiplies with u
+// (zero when it does not), so each unique block is read once per 32 tiles.
+// F_u (32 tiles x 64 values) is loaded once by the workgroup into one of two
+// LDS buffers, one barrier per slot; each wave loads only its own 16 rows of
+// U_u.  Loads of the next slot go out before the current slot's MFMAs.  MFMA
+// 16x16x4 FP64, MFMA m = 2 x + t with contraction index q = 8 x + 2 lk + t:
+// lane (lr, lk) holds U[16 i + lr][q] and F[q][16 cg + lr]; its result holds
+// rows 16 i + lk + 4 v of column 16 cg + lr.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64, const int32_t *__restrict__ chunks,
                                                   const int32_t *__restrict__ slots, const double *__restrict__ f,
                                                   double *__restrict__ g) {
+    constexpr int NT = kConvTiles, SW = 1 + kConvTiles;   // tiles per chunk, ints per slot
+    static_assert(NT == 32, "two 16-column MFMA tiles per chunk");
+    // F of one slot: tile t's 64 values as 32 chunks of 16 bytes, chunk c at
+    // 32 t + (c ^ (t & 15)), so each 16-lane read phase (16 tiles, one c)
+    // touches 16 different bank groups
+    __shared__ doublex2 sF[2][NT * 32];
     const int ch = xcd_contiguous_index();
     const int J0 = chunks[4 * ch], n = chunks[4 * ch + 1];
     const int s0 = chunks[4 * ch + 2], ns = chunks[4 * ch + 3];
-    const int i = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's rows 16 i .. 16 i + 15
-    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-    struct Ops { doublex2 a[8], b[8]; };
+    const int tid = threadIdx.x;
+    const int i = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's rows 16 i .. 16 i + 15
+    const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    // F staging: thread tid takes chunks tid + 256 r (r < 4): tile (tid >> 5) + 8 r, chunk tid & 31
+    const int ft = tid >> 5, fc = tid & 31;
+    struct Ops { doublex2 a[8], fs[4]; };
     auto load = [&](int sl, Ops &o) {
-        const int32_t *slot = slots + 17 * (int64_t)(s0 + min(sl, ns - 1));
-        const int K = slot[1 + lr];
-        // chunk x of a row holds q = 8 x + 2 lk, 8 x + 2 lk + 1: the four lanes of a
-        // row read 64 contiguous bytes per load
+        const int32_t *slot = slots + SW * (int64_t)(s0 + min(sl, ns - 1));
         const doublex2 *up = (const doublex2 *)(u64 + (int64_t)slot[0] * kBlockElems + (16 * i + lr) * 64 + 2 * lk);
-        const doublex2 *fp = (const doublex2 *)(f + (int64_t)max(K, 0) * 64 + 2 * lk);
 #pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            o.a[x] = up[4 * x];
-            o.b[x] = K >= 0 ? fp[4 * x] : doublex2{0.0, 0.0};
+        for (int x = 0; x < 8; ++x) o.a[x] = up[4 * x];   // the four lanes of a row read 64 contiguous bytes
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int K = slot[1 + ft + 8 * r];
+            o.fs[r] = K >= 0 ? *(const doublex2 *)(f + (int64_t)K * 64 + 2 * fc) : doublex2{0.0, 0.0};
         }
     };
-    doublex4 c = doublex4{0.0, 0.0, 0.0, 0.0};
+    auto stage = [&](const Ops &o, int buf) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int t = ft + 8 * r;
+            sF[buf][32 * t + (fc ^ (t & 15))] = o.fs[r];
+        }
+    };
+    doublex4 c[2] = {doublex4{0.0, 0.0, 0.0, 0.0}, doublex4{0.0, 0.0, 0.0, 0.0}};
+    auto mfmas = [&](const Ops &o, int buf) {
+#pragma unroll
+        for (int cg = 0; cg < 2; ++cg) {
+            const int t = 16 * cg + lr;
+#pragma unroll
+            for (int x = 0; x < 8; ++x) {
+                const doublex2 bf = sF[buf][32 * t + ((4 * x + lk) ^ (t & 15))];
+                c[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[x][0], bf[0], c[cg], 0, 0, 0);
+                c[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[x][1], bf[1], c[cg], 0, 0, 0);
+            }
+        }
+    };
     Ops o0, o1;
     load(0, o0);
-    for (int sl = 0; sl < ns; sl += 2) {      // the operands of the next slot load during the MFMAs
+    stage(o0, 0);
+    __syncthreads();
+    // slot sl computes from buffer sl & 1 with its U rows in registers; the
+    // next slot's loads go out first and its F is staged after the MFMAs
+    for (int sl = 0; sl < ns; sl += 2) {
         load(sl + 1, o1);
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks) c = __builtin_amdgcn_mfma_f64_16x16x4f64(o0.a[ks >> 1][ks & 1], o0.b[ks >> 1][ks & 1], c, 0, 0, 0);
+        mfmas(o0, 0);
+        stage(o1, 1);
+        __syncthreads();
         if (sl + 1 >= ns) break;
         load(sl + 2, o0);
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks) c = __builtin_amdgcn_mfma_f64_16x16x4f64(o1.a[ks >> 1][ks & 1], o1.b[ks >> 1][ks & 1], c, 0, 0, 0);
+        mfmas(o1, 1);
+        stage(o0, 0);
+        __syncthreads();
     }
-    if (lr < n) {
-        double *o = g + (int64_t)(J0 + lr) * 64 + 16 * i + lk;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) o[4 * v] = c[v];
+    for (int cg = 0; cg < 2; ++cg) {
+        const int j = 16 * cg + lr;
+        if (j < n) {
+            double *o = g + (int64_t)(J0 + j) * 64 + 16 * i + lk;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[4 * v] = c[cg][v];
+        }
     }
 }
 
