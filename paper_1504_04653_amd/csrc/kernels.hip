@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64
                                                   const int32_t *__restrict__ slots, const double *__restrict__ f,
                                                   double *__restrict__ g) {
     constexpr int NT = kConvTiles, SW = 1 + kConvTiles;   // tiles per chunk, ints per slot
-    static_assert(NT == 32, "two 16-column MFMA tiles per chunk");
+    constexpr int NCG = NT / 16, NFR = NT / 8;             // 16-column MFMA tiles, F chunks per thread
+    static_assert(NT % 16 == 0 && NT <= 64, "16-column MFMA tiles, at most 64 KiB of staged F");
     // F of one slot: tile t's 64 values as 32 chunks of 16 bytes, chunk c at
     // 32 t + (c ^ (t & 15)), so each 16-lane read phase (16 tiles, one c)
     // touches 16 different bank groups
@@ -211,31 +212,33 @@ __global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64
     const int tid = threadIdx.x;
     const int i = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's rows 16 i .. 16 i + 15
     const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-    // F staging: thread tid takes chunks tid + 256 r (r < 4): tile (tid >> 5) + 8 r, chunk tid & 31
+    // F staging: thread tid takes chunks tid + 256 r (r < NT / 8): tile (tid >> 5) + 8 r, chunk tid & 31
     const int ft = tid >> 5, fc = tid & 31;
-    struct Ops { doublex2 a[8], fs[4]; };
+    struct Ops { doublex2 a[8], fs[NFR]; };
     auto load = [&](int sl, Ops &o) {
         const int32_t *slot = slots + SW * (int64_t)(s0 + min(sl, ns - 1));
         const doublex2 *up = (const doublex2 *)(u64 + (int64_t)slot[0] * kBlockElems + (16 * i + lr) * 64 + 2 * lk);
 #pragma unroll
         for (int x = 0; x < 8; ++x) o.a[x] = up[4 * x];   // the four lanes of a row read 64 contiguous bytes
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NFR; ++r) {
             const int K = slot[1 + ft + 8 * r];
             o.fs[r] = K >= 0 ? *(const doublex2 *)(f + (int64_t)K * 64 + 2 * fc) : doublex2{0.0, 0.0};
         }
     };
     auto stage = [&](const Ops &o, int buf) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NFR; ++r) {
             const int t = ft + 8 * r;
             sF[buf][32 * t + (fc ^ (t & 15))] = o.fs[r];
         }
     };
-    doublex4 c[2] = {doublex4{0.0, 0.0, 0.0, 0.0}, doublex4{0.0, 0.0, 0.0, 0.0}};
+    doublex4 c[NCG];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) c[cg] = doublex4{0.0, 0.0, 0.0, 0.0};
     auto mfmas = [&](const Ops &o, int buf) {
 #pragma unroll
-        for (int cg = 0; cg < 2; ++cg) {
+        for (int cg = 0; cg < NCG; ++cg) {
             const int t = 16 * cg + lr;
 #pragma unroll
             for (int x = 0; x < 8; ++x) {
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(256) void k_convolve(const double *__restrict__ u64
         __syncthreads();
     }
 #pragma unroll
-    for (int cg = 0; cg < 2; ++cg) {
+    for (int cg = 0; cg < NCG; ++cg) {
         const int j = 16 * cg + lr;
         if (j < n) {
             double *o = g + (int64_t)(J0 + j) * 64 + 16 * i + lk;
