@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--separate", action="store_true",
                     help="sample D-hat and B^T N^-1 B with the two separate calls (default: the combined "
                          "call, one launch)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="tabulate each step's kernels on the main stream, after the previous step (default: on a "
+                         "second stream, while the previous step's sampling launch runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -536,26 +539,76 @@ def main():
         ev[3].record(stream)
         return kb, kd
 
+    # Pipelined steps (default): the kernels of step s + 1 are tabulated on a
+    # second stream (default priority) while step s samples on the main
+    # stream; the main stream waits for them before sampling.  Every step still
+    # tabulates both kernels and writes both outputs.
+    tab_stream = torch.cuda.Stream()
+
+    def tabulate(st):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
+        kb = sp.Kernel(g, b_l, R, stream=st)
+        kd = sp.Kernel(g, d_l, 0.0, stream=st)
+        ev1.record(st)
+        return kb, kd, ev0, ev1
+
+    def sample(prec, kb, kd, ev):
+        fused = fused_mode(prec)
+        ev[1].record(stream)
+        if not fused:
+            sp.sample_D(g, kd, out_D, stream=stream)
+            ev[2].record(stream)
+            sp.sample_BtNB(g, kb, ninv_dev, out_C, prec, stream=stream)
+        else:
+            sp.sample_D_BtNB(g, kd, kb, ninv_dev, out_D, out_C, prec, stream=stream)
+            ev[2].record(stream)
+        ev[3].record(stream)
+
+    def run_overlapped(prec, nsteps):
+        evs, keeps = [], []
+        nxt = tabulate(tab_stream)
+        for s_ in range(nsteps):
+            kb, kd, t0, t1 = nxt
+            stream.wait_event(t1)
+            ev = [t0] + [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            if s_ + 1 < nsteps:                 # queued behind this step's tabulation on its stream
+                nxt = tabulate(tab_stream)
+            sample(prec, kb, kd, ev)
+            keeps.append((kb, kd))
+            evs.append((ev, t1))
+        return evs, keeps
+
     results = {}
     for prec in modes:
-        for _ in range(args.warmup):
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-            keep = step(prec, ev)
-            torch.cuda.synchronize()
-            del keep
+        if args.no_overlap:
+            for _ in range(args.warmup):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                keep = step(prec, ev)
+                torch.cuda.synchronize()
+                del keep
+        else:
+            run_overlapped(prec, max(1, args.warmup))
         evs = []
         keeps = []
         torch.cuda.synchronize()
         t_start = time.perf_counter()
-        for _ in range(args.steps):
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-            keeps.append(step(prec, ev))   # kernel handles are freed after the final synchronisation
-            evs.append(ev)
+        if args.no_overlap:
+            for _ in range(args.steps):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                keeps.append(step(prec, ev))   # kernel handles are freed after the final synchronisation
+                evs.append(ev)
+        else:
+            evo, keeps = run_overlapped(prec, args.steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
         keeps.clear()
-        seg = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
-                         e[0].elapsed_time(e[3])] for e in evs])   # ms
+        if args.no_overlap:
+            seg = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                             e[0].elapsed_time(e[3])] for e in evs])   # ms
+        else:   # tabulation: its own stream's events; the step: sampling (the tabulation overlaps)
+            seg = np.array([[e[0].elapsed_time(t1), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                             e[1].elapsed_time(e[3])] for e, t1 in evo])
         t_tab, t_a, t_b, t_step = seg.mean(axis=0)
         # separate calls: t_a = D-hat, t_b = contraction; combined call: t_a =
         # both outputs (one launch)
@@ -567,6 +620,7 @@ def main():
             "ms_per_step": ms_step,
             "step_events_ms": t_step,
             "tabulate_ms": t_tab,
+            "tabulation_overlapped": not args.no_overlap,
             "D_and_btnb_one_launch": fused,
             "btnb_ms": t_C,
             "btnb_elements_per_s": nelem / (t_C * 1e-3),
