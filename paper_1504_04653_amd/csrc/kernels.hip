@@ -749,15 +749,11 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // hm, mh, hl, lh, mm (smallest first), NP = 2 keeps hh, hm, mh.  MFMA
 // 16x16x32 BF16: lane (lr, lk) holds W[16 i + lr][p0 + 8 lk + 0..7] and
 // M[p0 + 8 lk + 0..7][16 j + lr]; the result holds members 16 i + 4 lk + v.
-// Two waves run on each SIMD: a wave's own VALU work (forming and splitting M,
-// the FP64 accumulation) does not overlap its MFMAs, but it does overlap those
-// of the other wave on its SIMD.  Each wave holds half the columns of its
-// output rows.  Without D-hat (NW = 4) a workgroup of 4 waves takes a member
-// tile, wave w the rows a = w mod 2 and the column half w / 2, and two such
-// workgroups share a CU, so the two waves of a SIMD belong to different
-// workgroups and their steps drift apart.  With D-hat (NW = 8) one workgroup
-// of 8 waves takes the tile, wave w the rows a = w mod 4 and the column half
-// w / 4; there the copies run better with the larger workgroup.  The operands all waves share (W of the tile's
+// Eight waves per member tile, two on each SIMD: a wave's own VALU work
+// (forming and splitting M, the FP64 accumulation) does not overlap its
+// MFMAs, but it does overlap those of the other wave on its SIMD.  Wave w
+// takes the output rows a = w mod 4 and the column half w / 4, so each wave
+// holds half the columns of its rows.  The operands all waves share (W of the tile's
 // rows, the B_IK values of a step) are staged through LDS.  A step is 32
 // pixels (half a term); a term's FP32 sums are added to the FP64 accumulators
 // after its second step.
@@ -766,12 +762,6 @@ __global__ __launch_bounds__(256) void k_split_ninv(const double *__restrict__ n
 // and step (loaded with one step's loads, stored after the next step's), so
 // that these writes proceed under the contraction's arithmetic; chunks left
 // after the last step are copied at the end of the tile.
-// LDS staging buffers of the split-BF16 kernels: four (operands staged two
-// steps ahead, one barrier per term) where they fit, else two (one step
-// ahead, one barrier per step).  Two 4-wave BF16x6 workgroups per CU would
-// need 2 x 85 KB with four.
-__host__ __device__ constexpr int bf16_buffers(int np, bool wd) { return wd || np == 2 ? 4 : 2; }
-
 template <int NP, int NI, bool WD>
 __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item, int32_t *sTile,
                                                 int32_t *sBlk, int32_t *sTerm, u16x8 *sW, floatx4 *sU) {
@@ -781,7 +771,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     const DevClass cl = pd.classes[cls];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    constexpr int NW = WD ? 8 : 4, NT = 64 * NW;     // waves, threads
+    constexpr int NW = 8, NT = 64 * NW;              // waves, threads
     constexpr int RP = NW / 2, RPW = 64 / RP;          // row phases, rows per wave
     const int rw = wave % RP, ch = wave / RP;          // row phase, column half
     const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
@@ -886,12 +876,11 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     // next read meanwhile; (3) the next step's staged operands written to the
     // other buffer, and one barrier.
     // One step, in three scheduling regions: (1) the loads of the staged
-    // operands of a later step (two ahead with four buffers, else the next)
-    // and of this wave's B_IJ values of the next step; (2) the MFMAs of this
-    // step from LDS buffer buf (W fragments, and M formed from the staged B_IK
-    // values and this wave's B_IJ values), with the addresses the next step
-    // needs read meanwhile; (3) the staged operands written to buffer sbuf,
-    // and a barrier where the schedule needs one.
+    // operands of the step two ahead and of this wave's B_IJ values of the
+    // next step; (2) the MFMAs of this step from LDS buffer buf (W fragments,
+    // and M formed from the staged B_IK values and this wave's B_IJ values),
+    // with the addresses the next step needs read meanwhile; (3) the staged
+    // operands written to buffer sbuf, and, at the end of a term, a barrier.
     auto step = [&](const Own &oc, int buf, const SAddr &sa, const OAddr &oa, int sbuf, Stage &stn, Own &on,
                     bool first, bool bar, int nse, int nsh, int noa, int noe, int noh, SAddr &sa_n, OAddr &oa_n,
                     int stp, DCopy &dprev) {
@@ -955,13 +944,11 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         __builtin_amdgcn_sched_barrier(0);
     };
 
-    // With four buffers, iteration it (one term of one row) computes from
+    // Four LDS buffers: iteration it (one term of one row) computes from
     // buffers 2 (it & 1) + h, fills the other pair for iteration it + 1, and
-    // ends with the only barrier of the term.  With two, step h computes from
-    // buffer h and fills the other one for the next step, and every step ends
-    // with a barrier.  Cursors: row index x (a = rw + RP x) and term e; past
-    // the last row they repeat (harmless reloads into buffers no step reads).
-    constexpr bool AHEAD2 = bf16_buffers(NP, WD) == 4;
+    // ends with the only barrier of the term.  Cursors: row index x
+    // (a = rw + RP x) and term e; past the last row they repeat (harmless
+    // reloads into buffers no step reads).
     auto next = [&](int cx, int ce, int &nx, int &ne) {
         ne = ce + 1;
         nx = cx;
@@ -979,21 +966,15 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     int x = 0, e = 0;
     int x1, e1;
     next(0, 0, x1, e1);
-    SAddr sa;
     {
-        Stage t0;
+        Stage t0, t1;
         stage_load(saddr(0, 0), t0);
+        stage_load(saddr(0, 1), t1);
         own_load(oaddr(rw, 0, 0), o0);
-        if constexpr (AHEAD2) {
-            Stage t1;
-            stage_load(saddr(0, 1), t1);
-            stage_store(t1, 1);
-            sa = saddr(e1, 0);
-        } else {
-            sa = saddr(0, 1);
-        }
         stage_store(t0, 0);
+        stage_store(t1, 1);
     }
+    SAddr sa = saddr(e1, 0);
     OAddr oa = oaddr(rw, 0, 1);
     DCopy dpend;                           // D-hat chunks loaded, not yet stored
     dpend.dst[0] = dpend.dst[1] = nullptr;
@@ -1001,16 +982,11 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     for (int it = 0; it < RPW * nterms; ++it) {
         next(x, e, x1, e1);
         const int a = rw + RP * x, a1 = rw + RP * x1;
-        if constexpr (AHEAD2) {
-            int x2, e2;
-            next(x1, e1, x2, e2);
-            const int ib = 2 * (it & 1), nb = 2 - ib;
-            step(o0, ib, sa, oa, nb, s1, o1, true, false, e1, 1, a1, e1, 0, sa, oa, 2 * it, dpend);
-            step(o1, ib + 1, sa, oa, nb + 1, s0, o0, false, true, e2, 0, a1, e1, 1, sa, oa, 2 * it + 1, dpend);
-        } else {
-            step(o0, 0, sa, oa, 1, s1, o1, true, true, e1, 0, a1, e1, 0, sa, oa, 2 * it, dpend);
-            step(o1, 1, sa, oa, 0, s0, o0, false, true, e1, 1, a1, e1, 1, sa, oa, 2 * it + 1, dpend);
-        }
+        int x2, e2;
+        next(x1, e1, x2, e2);
+        const int ib = 2 * (it & 1), nb = 2 - ib;
+        step(o0, ib, sa, oa, nb, s1, o1, true, false, e1, 1, a1, e1, 0, sa, oa, 2 * it, dpend);
+        step(o1, ib + 1, sa, oa, nb + 1, s0, o0, false, true, e2, 0, a1, e1, 1, sa, oa, 2 * it + 1, dpend);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -1059,27 +1035,27 @@ __device__ __forceinline__ void class_bf16_item(const ProblemDescB &pd, int item
 }
 
 template <int NP, bool WD>
-__global__ __launch_bounds__(WD ? 512 : 256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
-    __shared__ u16x8 sW[bf16_buffers(NP, WD) * NP * 64 * 4];   // staged W
-    __shared__ floatx4 sU[bf16_buffers(NP, WD) * 512];          // staged B_IK values
+    __shared__ u16x8 sW[4 * NP * 64 * 4];            // staged W, four buffers
+    __shared__ floatx4 sU[4 * 512];                  // staged B_IK values, four buffers
     class_bf16_item<NP, WD>(pd, xcd_contiguous_index(), sTile, sBlk, sTerm, sW, sU);
 }
 
 // Many problems in one persistent launch, split BF16 (the queues and their
-// draining as in k_batch_f32; two workgroups of 4 waves per CU).
+// draining as in k_batch_f32; one 8-wave workgroup per CU).
 template <int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_batch_bf16(const ProblemDescB *__restrict__ probs, const int32_t *__restrict__ items,
                   const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
     __shared__ int32_t sBlk[128];
     __shared__ int32_t sTerm[2 * kMaxClassTerms];
-    __shared__ u16x8 sW[bf16_buffers(NP, false) * NP * 64 * 4];
-    __shared__ floatx4 sU[bf16_buffers(NP, false) * 512];
+    __shared__ u16x8 sW[4 * NP * 64 * 4];
+    __shared__ floatx4 sU[4 * 512];
     __shared__ int32_t sItem;
     const int home = blockIdx.x % nq;
     int tried = 0;                       // queues found empty (thread 0)
@@ -1165,8 +1141,8 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
         if (prec == 2) hipLaunchKernelGGL((k_class_bf16<2, true>), grid, dim3(512), 0, st, pd);
         else hipLaunchKernelGGL((k_class_bf16<3, true>), grid, dim3(512), 0, st, pd);
     } else {
-        if (prec == 2) hipLaunchKernelGGL((k_class_bf16<2, false>), grid, dim3(256), 0, st, pd);
-        else hipLaunchKernelGGL((k_class_bf16<3, false>), grid, dim3(256), 0, st, pd);
+        if (prec == 2) hipLaunchKernelGGL((k_class_bf16<2, false>), grid, dim3(512), 0, st, pd);
+        else hipLaunchKernelGGL((k_class_bf16<3, false>), grid, dim3(512), 0, st, pd);
     }
     return hipGetLastError();
 }
@@ -1190,9 +1166,9 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
             if (!bf16)
                 hipLaunchKernelGGL(k_batch_f32, g, dim3(256), 0, st, b.desc, b.items, b.qb, b.nq, b.counters);
             else if (b.prec == 2)
-                hipLaunchKernelGGL(k_batch_bf16<2>, g, dim3(256), 0, st, b.descb, b.items, b.qb, b.nq, b.counters);
+                hipLaunchKernelGGL(k_batch_bf16<2>, g, dim3(512), 0, st, b.descb, b.items, b.qb, b.nq, b.counters);
             else
-                hipLaunchKernelGGL(k_batch_bf16<3>, g, dim3(256), 0, st, b.descb, b.items, b.qb, b.nq, b.counters);
+                hipLaunchKernelGGL(k_batch_bf16<3>, g, dim3(512), 0, st, b.descb, b.items, b.qb, b.nq, b.counters);
         }
     } else {
         for (int p = 0; p < b.nprob; ++p) {
@@ -1201,9 +1177,9 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
             if (!bf16)
                 hipLaunchKernelGGL(k_class_f32<false>, g, dim3(256), 0, st, b.host_desc[p]);
             else if (b.prec == 2)
-                hipLaunchKernelGGL((k_class_bf16<2, false>), g, dim3(256), 0, st, b.host_descb[p]);
+                hipLaunchKernelGGL((k_class_bf16<2, false>), g, dim3(512), 0, st, b.host_descb[p]);
             else
-                hipLaunchKernelGGL((k_class_bf16<3, false>), g, dim3(256), 0, st, b.host_descb[p]);
+                hipLaunchKernelGGL((k_class_bf16<3, false>), g, dim3(512), 0, st, b.host_descb[p]);
         }
     }
     return hipGetLastError();
@@ -1211,8 +1187,8 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
 
 hipError_t batch_occupancy(int prec, int *workgroups_per_cu) {
     if (prec == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f32, 256, 0);
-    if (prec == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<2>, 256, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<3>, 256, 0);
+    if (prec == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<2>, 512, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<3>, 512, 0);
 }
 
 hipError_t launch_convolve(const double *u64, const int32_t *chunks, int64_t nchunks, const int32_t *slots,
