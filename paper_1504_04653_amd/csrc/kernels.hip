@@ -472,13 +472,14 @@ void k_class_f64(ProblemDesc64 pd) {
 // a9, FP32 MFMA class GEMM.  Same decomposition as the split-BF16 form below:
 // C[m][(a,b)] = sum_(e,p) W[m][(e,p)] M[(e,p)][(a,b)], W = N^-1 rounded to FP32,
 // M = B_IJ[p][a] B_IK[p][b] formed as the FP32 product of the FP32 copies.
-// MFMA 16x16x4: lane (lr, lk) holds W[16 i + lr][p] and M[p][16 j + lr] for
-// p = 16 g + 4 lk + t, one MFMA per (i, j, t); the result lane holds members
-// 16 i + 4 lk + v of column b = 16 j + lr.  Four waves share one 64-member tile
-// and take every fourth output row a, so their W and B_IK reads coincide in L1.
-// Each step is 16 pixels of one term; its operands are loaded one step ahead.
-// A term's FP32 sum over its 64 pixels is added to FP64 accumulators, which are
-// stored and cleared at the end of every row a.
+// The same schedule as the split-BF16 kernel: eight waves per member tile,
+// wave w the output rows a = w mod 4 and the column half w / 4, two waves per
+// SIMD; W and the B_IK values of a step (32 pixels) staged through four LDS
+// buffers two steps ahead, one barrier per term.  MFMA 16x16x4 FP32, MFMA g
+// of a step taking the pixels 8 lk + g; the result lane holds members
+// 16 i + 4 lk + v of column b = 16 j + lr.  A term's FP32 sum over its 64
+// pixels is added to FP64 accumulators, which are stored and cleared at the
+// end of every row a.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_ninv_f32(const double *__restrict__ ninv, int64_t n,
                                                   float *__restrict__ wf) {
@@ -487,144 +488,200 @@ __global__ __launch_bounds__(256) void k_ninv_f32(const double *__restrict__ nin
 }
 
 // One member tile (item) of one problem with NI groups of 16 member rows; all
-// 256 threads of the workgroup take part.  sTile / sBlk are the workgroup's
-// LDS tables.
+// 512 threads of the workgroup take part.  sTile / sBlk / sTerm are the
+// workgroup's LDS tables, sW / sU its four staging buffers.
 template <int NI, bool WD>
 __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, int32_t *sTile,
-                                               int32_t *sBlk, int32_t *sTerm) {
+                                               int32_t *sBlk, int32_t *sTerm, floatx4 *sW, floatx4 *sU) {
     const float *__restrict__ ut32 = pd.ut32;
-    const float *__restrict__ wf = pd.wf;
     double *__restrict__ out = pd.out;
+    constexpr int NW = 8, NT = 64 * NW, RP = NW / 2, RPW = 64 / RP;
     const int cls = pd.mtiles[4 * item], m0 = pd.mtiles[4 * item + 1];
     const DevClass cl = pd.classes[cls];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rw = wave % RP, ch = wave / RP;          // row phase, column half
+    const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
     const int32_t *terms = pd.cterms + 2 * cl.term0;
 
-    for (int x = threadIdx.x; x < 16 * NI * nterms; x += 256) {
+    for (int x = tid; x < 16 * NI * nterms; x += NT) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
         sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
-    if (threadIdx.x < 64) {
+    if (tid < 64) {
         const int blk = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
         sBlk[lane] = blk;
         if constexpr (WD) sBlk[64 + lane] = blk >= 0 ? pd.blk_uid[blk] : 0;   // D-hat source block
     }
-    if (threadIdx.x < 2 * nterms) sTerm[threadIdx.x] = terms[threadIdx.x];   // unique-block pairs of the class
+    if (tid < 2 * nterms) sTerm[tid] = terms[tid];   // unique-block pairs of the class
     __syncthreads();
 
-    // operand addresses of one term for output row a (lane part included)
-    struct Ptrs { const float *w[NI], *u1, *u2; };
-    auto ptrs = [&](int a, int e, Ptrs &q) {
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-            q.w[i] = wf + (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 4 * lk;
-        q.u1 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 4 * lk;
-        q.u2 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + lr * 64 + 4 * lk;
+    // Staging of one step (32 pixels of a term): W of the tile's 64 rows and
+    // the B_IK values of its 64 columns, FP32, 8 chunks of 16 bytes per row
+    // each; thread t takes W chunk t (row t >> 3) and B_IK chunk t.  Rows past
+    // the tile's 16 NI members load the last member's values into LDS rows no
+    // wave reads.  LDS row r keeps its chunk c at 8 r + (c ^ usw(r)).
+    auto usw = [](int b) { return ((b >> 1) ^ (b << 2)) & 7; };
+    const int srow = tid >> 3, sch = tid & 7;
+    const int wrow = min(srow, 16 * NI - 1) * kMaxClassTerms;
+    const int sdst = srow * 8 + (sch ^ usw(srow));
+    struct SAddr { int64_t wo; const float *u2; };
+    struct OAddr { const float *p1; };
+    auto saddr = [&](int e, int h) {
+        SAddr r;
+        r.wo = (int64_t)sTile[wrow + e] * 64 + 32 * h + 4 * sch;
+        r.u2 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + 32 * h;
+        return r;
     };
-    struct Frag { floatx4 w[NI], u1, u2[4]; };
-    auto load = [&](const Ptrs &q, int g, Frag &f) {
-#pragma unroll
-        for (int i = 0; i < NI; ++i) f.w[i] = *(const floatx4 *)(q.w[i] + 16 * g);
-        f.u1 = *(const floatx4 *)(q.u1 + 16 * g);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) f.u2[j] = *(const floatx4 *)(q.u2 + 16 * j * 64 + 16 * g);
+    // this lane's B_IJ values of row a: pixels 32 h + 8 lk + g, g = 0..7
+    auto oaddr = [&](int a, int e, int h) {
+        OAddr r;
+        r.p1 = ut32 + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 32 * h + 8 * lk;
+        return r;
     };
+    struct Stage { floatx4 w, u; };
+    struct Own { floatx4 u1[2]; };
+    auto stage_load = [&](const SAddr &ad, Stage &st) {
+        st.w = *(const floatx4 *)(pd.wf + ad.wo);
+        st.u = *(const floatx4 *)(ad.u2 + srow * 64 + 4 * sch);
+    };
+    auto own_load = [&](const OAddr &ad, Own &o) {
+        o.u1[0] = *(const floatx4 *)ad.p1;
+        o.u1[1] = *(const floatx4 *)(ad.p1 + 4);
+    };
+    auto stage_store = [&](const Stage &st, int buf) {
+        sW[buf * 512 + sdst] = st.w;
+        sU[buf * 512 + sdst] = st.u;
+    };
+    constexpr int kDChunks = 16 * NI * 2048;   // D-hat chunks of the tile
 
-    doublex4 acc[NI][4];
-    floatx4 part[NI][4];
+    doublex4 acc[NI][2];
+    floatx4 part[NI][2];
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-    // One step: issue the next step's loads, then this step's products and
-    // MFMAs; the first step of a term starts its MFMA sums from zero.  The
-    // scheduling barrier keeps the next step's arithmetic (which waits on
-    // those loads) out of this step.
-    constexpr int kDChunks = 16 * NI * 2048;   // D-hat chunks of the tile
-    auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn, bool first, int stp, DCopy &dprev) {
-        load(qn, gn, fn);
+        for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    // One step, in three scheduling regions as in the split-BF16 form.  MFMA
+    // g (g = 0..7) of a step takes the pixels 8 lk + g: lane (lr, lk) holds
+    // W[16 i + lr][8 lk + g] and M[8 lk + g][16 j + lr].
+    auto step = [&](const Own &oc, int buf, const SAddr &sa, const OAddr &oa, int sbuf, Stage &stn, Own &on,
+                    bool first, bool bar, int nse, int nsh, int noa, int noe, int noh, SAddr &sa_n, OAddr &oa_n,
+                    int stp, DCopy &dprev) {
+        stage_load(sa, stn);
+        own_load(oa, on);
         if constexpr (WD) {
             DCopy dc;
-            dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_load<NT>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
             dcopy_store(dprev, lane);
             dprev = dc;
         }
-        __builtin_amdgcn_sched_group_barrier(0x020, NI + 5, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        floatx4 wfr[NI][2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            float bv[4];
+        for (int i = 0; i < NI; ++i) {
+            const int r = 16 * i + lr;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = f.u1[t] * f.u2[j][t];
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        f.w[i][t], bv[j], (first && t == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][j], 0, 0, 0);
+            for (int hh = 0; hh < 2; ++hh) wfr[i][hh] = sW[buf * 512 + r * 8 + ((2 * lk + hh) ^ usw(r))];
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);   // products of pixel t
-            __builtin_amdgcn_sched_group_barrier(0x008, 4 * NI, 0);  // their MFMAs
+        for (int jj = 0; jj < 2; ++jj) {
+            const int b = 32 * ch + 16 * jj + lr;
+            float m[8];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const floatx4 u2 = sU[buf * 512 + b * 8 + ((2 * lk + hh) ^ usw(b))];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) m[4 * hh + t] = oc.u1[hh][t] * u2[t];
+            }
+#pragma unroll
+            for (int g = 0; g < 8; ++g)
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+                    part[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        wfr[i][g >> 2][g & 3], m[g], (first && g == 0) ? floatx4{0.f, 0.f, 0.f, 0.f} : part[i][jj], 0, 0, 0);
         }
+        sa_n = saddr(nse, nsh);
+        oa_n = oaddr(noa, noe, noh);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_store(stn, sbuf);
+        if (bar) __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
     };
 
-    Frag f0, f1;
-    Ptrs qc, qn;
-    int x = 0, e = 0;                    // row index (a = wave + 4 x) and term of this step
-    ptrs(wave, 0, qc);
-    load(qc, 0, f0);
-    DCopy dpend;                         // D-hat chunks loaded, not yet stored
-    dpend.dst[0] = dpend.dst[1] = nullptr;
-    for (int it = 0; it < 16 * nterms; ++it) {
-        int ne = e + 1, nx = x;
+    // Four LDS buffers: iteration it (one term of one row) computes from
+    // buffers 2 (it & 1) + h, fills the other pair for iteration it + 1, and
+    // ends with the only barrier of the term.
+    auto next = [&](int cx, int ce, int &nx, int &ne) {
+        ne = ce + 1;
+        nx = cx;
         if (ne == nterms) {
             ne = 0;
             ++nx;
         }
-        const int a = wave + 4 * x;
-        if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
-        else qn = qc;                    // past the last row: a harmless reload
-        step(f0, qc, 1, f1, true, 4 * it, dpend);
-        step(f1, qc, 2, f0, false, 4 * it + 1, dpend);
-        step(f0, qc, 3, f1, false, 4 * it + 2, dpend);
-        step(f1, qn, 0, f0, false, 4 * it + 3, dpend);
+        if (nx >= RPW) {
+            nx = cx;
+            ne = ce;
+        }
+    };
+    Stage s0, s1;
+    Own o0, o1;
+    int x = 0, e = 0;
+    int x1, e1;
+    next(0, 0, x1, e1);
+    {
+        Stage t0, t1;
+        stage_load(saddr(0, 0), t0);
+        stage_load(saddr(0, 1), t1);
+        own_load(oaddr(rw, 0, 0), o0);
+        stage_store(t0, 0);
+        stage_store(t1, 1);
+    }
+    SAddr sa = saddr(e1, 0);
+    OAddr oa = oaddr(rw, 0, 1);
+    DCopy dpend;                           // D-hat chunks loaded, not yet stored
+    dpend.dst[0] = dpend.dst[1] = nullptr;
+    __syncthreads();
+    for (int it = 0; it < RPW * nterms; ++it) {
+        next(x, e, x1, e1);
+        const int a = rw + RP * x, a1 = rw + RP * x1;
+        int x2, e2;
+        next(x1, e1, x2, e2);
+        const int ib = 2 * (it & 1), nb = 2 - ib;
+        step(o0, ib, sa, oa, nb, s1, o1, true, false, e1, 1, a1, e1, 0, sa, oa, 2 * it, dpend);
+        step(o1, ib + 1, sa, oa, nb + 1, s0, o0, false, true, e2, 0, a1, e1, 1, sa, oa, 2 * it + 1, dpend);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
-        if (ne == 0) {                       // end of output row a: store, clear
+        if (e == nterms - 1) {           // end of output row a: store, clear
 #pragma unroll
             for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int blk = sBlk[16 * i + 4 * lk + v];
                     if (blk >= 0) {
-                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + lr;
+                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + 32 * ch + lr;
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
+                        for (int j = 0; j < 2; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
                     }
                 }
 #pragma unroll
             for (int i = 0; i < NI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+                for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
         }
-        x = nx;
-        e = ne;
-        qc = qn;
+        x = x1;
+        e = e1;
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
         dcopy_store(dpend, lane);
-        for (int stp = 64 * nterms; 512 * stp < kDChunks; ++stp) {
+        for (int stp = 2 * RPW * nterms; 2 * NT * stp < kDChunks; ++stp) {
             DCopy dc;
-            dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
+            dcopy_load<NT>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
             dcopy_store(dc, lane);
         }
     }
@@ -632,20 +689,22 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
 
 template <bool WD>
 __device__ __forceinline__ void class_f32_item(const ProblemDesc &pd, int item, int32_t *sTile, int32_t *sBlk,
-                                               int32_t *sTerm) {
+                                               int32_t *sTerm, floatx4 *sW, floatx4 *sU) {
     const int groups = pd.mtiles[4 * item + 2];
-    if (groups == 4) class_f32_tile<4, WD>(pd, item, sTile, sBlk, sTerm);
-    else if (groups == 2) class_f32_tile<2, WD>(pd, item, sTile, sBlk, sTerm);
-    else class_f32_tile<1, WD>(pd, item, sTile, sBlk, sTerm);
+    if (groups == 4) class_f32_tile<4, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    else if (groups == 2) class_f32_tile<2, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
+    else class_f32_tile<1, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
 }
 
 template <bool WD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_class_f32(ProblemDesc pd) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
     __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
-    class_f32_item<WD>(pd, xcd_contiguous_index(), sTile, sBlk, sTerm);
+    __shared__ floatx4 sW[4 * 512];                  // staged W, four buffers
+    __shared__ floatx4 sU[4 * 512];                  // staged B_IK values, four buffers
+    class_f32_item<WD>(pd, xcd_contiguous_index(), sTile, sBlk, sTerm, sW, sU);
 }
 
 // ---------------------------------------------------------------------------
@@ -660,12 +719,14 @@ __global__ __launch_bounds__(64) void k_fill_i32(int32_t *p, int32_t n, int32_t 
     for (int i = threadIdx.x; i < n; i += 64) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restrict__ items,
                  const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
     __shared__ int32_t sTile[64 * kMaxClassTerms];
-    __shared__ int32_t sBlk[64];
+    __shared__ int32_t sBlk[128];
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
+    __shared__ floatx4 sW[4 * 512];
+    __shared__ floatx4 sU[4 * 512];
     __shared__ int32_t sItem;
     const int home = blockIdx.x % nq;
     int tried = 0;                       // queues found empty (thread 0)
@@ -688,7 +749,7 @@ void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restric
         __syncthreads();                 // every thread has read sItem before it changes
         if (it < 0) break;
         const ProblemDesc pd = probs[items[2 * it]];
-        class_f32_item<false>(pd, items[2 * it + 1], sTile, sBlk, sTerm);
+        class_f32_item<false>(pd, items[2 * it + 1], sTile, sBlk, sTerm, sW, sU);
     }
 }
 
@@ -1128,8 +1189,8 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
                            a.npix, a.wf32);
         ProblemDesc pd{a.mtiles, a.classes, a.class_terms, a.class_blk, a.class_itab, a.ut32, a.wf32, a.out,
                        a.du64, a.blk_uid, a.outD};
-        if (a.outD) hipLaunchKernelGGL(k_class_f32<true>, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
-        else hipLaunchKernelGGL(k_class_f32<false>, dim3((unsigned)a.nmtiles), dim3(256), 0, st, pd);
+        if (a.outD) hipLaunchKernelGGL(k_class_f32<true>, dim3((unsigned)a.nmtiles), dim3(512), 0, st, pd);
+        else hipLaunchKernelGGL(k_class_f32<false>, dim3((unsigned)a.nmtiles), dim3(512), 0, st, pd);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_split_ninv, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0, st, a.ninv,
@@ -1164,7 +1225,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
         if (b.nitems > 0) {
             const dim3 g((unsigned)b.nworkgroups);
             if (!bf16)
-                hipLaunchKernelGGL(k_batch_f32, g, dim3(256), 0, st, b.desc, b.items, b.qb, b.nq, b.counters);
+                hipLaunchKernelGGL(k_batch_f32, g, dim3(512), 0, st, b.desc, b.items, b.qb, b.nq, b.counters);
             else if (b.prec == 2)
                 hipLaunchKernelGGL(k_batch_bf16<2>, g, dim3(512), 0, st, b.descb, b.items, b.qb, b.nq, b.counters);
             else
@@ -1175,7 +1236,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
             if (b.nmtiles[p] == 0) continue;
             const dim3 g((unsigned)b.nmtiles[p]);
             if (!bf16)
-                hipLaunchKernelGGL(k_class_f32<false>, g, dim3(256), 0, st, b.host_desc[p]);
+                hipLaunchKernelGGL(k_class_f32<false>, g, dim3(512), 0, st, b.host_desc[p]);
             else if (b.prec == 2)
                 hipLaunchKernelGGL((k_class_bf16<2, false>), g, dim3(512), 0, st, b.host_descb[p]);
             else
@@ -1186,7 +1247,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
 }
 
 hipError_t batch_occupancy(int prec, int *workgroups_per_cu) {
-    if (prec == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f32, 256, 0);
+    if (prec == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f32, 512, 0);
     if (prec == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<2>, 512, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<3>, 512, 0);
 }
