@@ -14,7 +14,7 @@ value = stored B^T N^-1 B elements / step time in the headline precision mode
 (split BF16, 6 products); FP64 and the other modes are timed the same way and
 reported side by side under "modes".
 
-With --config c5 a step is one launch of the captured graph that contracts
+With --config batch32 a step is one launch of the captured graph that contracts
 all 32 problems of the batched workload (lmax 256/512/1024/2048; split BF16x6
 and FP32 MFMA, FP64 accumulation across contraction tiles; 172 GB of output),
 one batch per mode, the first reported as the headline; the beam kernels
@@ -26,7 +26,7 @@ the configuration's grid and beam.  With --op two_hop a step tabulates the beam
 kernel and samples B^T N^-1 B on the two-hop pattern (every nonzero block of
 the product), in the first of --modes.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config lmax3000|batch32]
                        [--op btnb|conv] [--modes bf16x6,fp64,bf16x3] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -59,13 +59,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c4")
+    ap.add_argument("--config", default="lmax3000")
     ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop"],
                     help="btnb: the D-hat / B-hat^T N^-1 B-hat step (default); conv: the pixel-domain "
                          "convolution g = B-hat f")
     ap.add_argument("--modes", default=None,
                     help="precision modes, the first is the headline (default bf16x6,fp64,bf16x3; "
-                         "for --config c5 bf16x6,fp32)")
+                         "for --config batch32 bf16x6,fp32)")
     ap.add_argument("--separate", action="store_true",
                     help="sample D-hat and B^T N^-1 B with the two separate calls (default: the combined "
                          "call, one launch)")
@@ -79,7 +79,7 @@ def parse():
                          "kernel of known traffic for HBM counter runs)")
     args = ap.parse_args()
     if args.modes is None:
-        args.modes = "bf16x6,fp32" if args.config == "c5" else "bf16x6,fp64,bf16x3"
+        args.modes = "bf16x6,fp32" if args.config == "batch32" else "bf16x6,fp64,bf16x3"
     return args
 
 
@@ -219,7 +219,7 @@ def run_batch(args):
     nelem = sum(pr["g"].nblocks for pr in probs) * 4096
     alg_flop = sum(2.0 * 64 ** 3 * pr["g"].nterms for pr in probs)
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
-    print(f"# workload c5: 32 problems, npix={sum(pr['g'].npix for pr in probs)} "
+    print(f"# workload batch32: 32 problems, npix={sum(pr['g'].npix for pr in probs)} "
           f"nblocks={nelem // 4096} output={nelem * 8 / 1e9:.1f} GB setup={setup:.1f}s", file=sys.stderr, flush=True)
     results = {}
     for prec in modes:
@@ -249,9 +249,9 @@ def run_batch(args):
             "schedule": sched, "tune_ms": [round(t, 3) for t in tune_ms],
             "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec], "achieved": achieved,
                          "frac": achieved / PEAK[prec], "kernel": kern,
-                         "traffic": recorded_traffic(prec, "c5")},
+                         "traffic": recorded_traffic(prec, "batch32")},
         }
-        print(f"# c5 batch {prec} ({sched}; tune ms {[round(t, 2) for t in tune_ms]}): step {ms_step:.2f} ms wall, "
+        print(f"# batch32 batch {prec} ({sched}; tune ms {[round(t, 2) for t in tune_ms]}): step {ms_step:.2f} ms wall, "
               f"{ms.mean():.2f} ms per graph launch, {achieved:.1f} TFLOP/s "
               f"({achieved / PEAK[prec] * 100:.1f}% of {PEAK[prec]} TFLOP/s)", file=sys.stderr, flush=True)
     head = results[modes[0]]
@@ -458,10 +458,10 @@ def run_two_hop(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the sampling path runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding the grid by band pairs across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
-    if args.config == "c5":
+    if args.config == "batch32":
         run_batch(args)
         return
     if args.op == "conv":

@@ -14,6 +14,6 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def c1_grid():
+def lmax64_grid():
     from oracle import grid as G
     return G.make_grid(64, 8)

@@ -26,9 +26,9 @@ def test_default_arguments():
     try:
         sys.argv = ["bench.py"]
         a = bench.parse()
-        assert (a.gpus, a.config, a.op) == (1, "c4", "btnb")
+        assert (a.gpus, a.config, a.op) == (1, "lmax3000", "btnb")
         assert a.modes.split(",")[0] == "bf16x6"
-        sys.argv = ["bench.py", "--config", "c5"]
+        sys.argv = ["bench.py", "--config", "batch32"]
         assert bench.parse().modes.split(",")[0] == "bf16x6"
     finally:
         sys.argv = old
@@ -39,10 +39,10 @@ def test_traffic_rows_count_only_for_the_current_kernel_source(tmp_path, monkeyp
     prof.mkdir()
     h = bench.kernels_hash()
     (prof / "pmc_traffic.md").write_text(
-        f"| bf16x6 | c4 | {h} | 1.0e+08 | 2.0e+09 |\n"
-        f"| fp64 | c4 | 0000000000000000 | 5.0e+08 | 6.0e+09 |\n")
+        f"| bf16x6 | lmax3000 | {h} | 1.0e+08 | 2.0e+09 |\n"
+        f"| fp64 | lmax3000 | 0000000000000000 | 5.0e+08 | 6.0e+09 |\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernels_hash", lambda: h)
-    assert bench.recorded_traffic("bf16x6", "c4") == pytest.approx(2.1e9)
-    assert bench.recorded_traffic("fp64", "c4") is None        # taken on another source
-    assert bench.recorded_traffic("bf16x6", "c5") is None      # no row
+    assert bench.recorded_traffic("bf16x6", "lmax3000") == pytest.approx(2.1e9)
+    assert bench.recorded_traffic("fp64", "lmax3000") is None        # taken on another source
+    assert bench.recorded_traffic("bf16x6", "batch32") is None      # no row

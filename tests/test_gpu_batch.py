@@ -182,10 +182,10 @@ def test_c5_full_batch_sampled(prec):
     spec = [(S.BATCH_LMAX[p % 4], p) for p in range(32)]
     probs = make_problems(spec)
     total = sum(p["g"].nblocks for p in probs) * 4096 * 8
-    say(f"[c5 {prec}] 32 problems, {sum(p['g'].npix for p in probs)} pixels, output {total / 1e9:.1f} GB")
+    say(f"[batch32 {prec}] 32 problems, {sum(p['g'].npix for p in probs)} pixels, output {total / 1e9:.1f} GB")
     bt = sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"]) for p in probs], prec=prec)
     chosen, ms = bt.tune()
-    say(f"[c5 {prec}] tune: chosen {sp.plan_name(chosen)}, ms per plan {[round(t, 2) for t in ms]}")
+    say(f"[batch32 {prec}] tune: chosen {sp.plan_name(chosen)}, ms per plan {[round(t, 2) for t in ms]}")
     for p in probs:
         p["out"].fill_(float("nan"))
     bt.launch()
@@ -201,10 +201,10 @@ def test_c5_full_batch_sampled(prec):
         C = p["out"].view(-1, 64, 64)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
         rep = error_report(C, Cref, [J for J, _ in pairs])
         worst = max(worst, rep["gate"])
-        say(f"[c5 {prec}] problem {i} lmax {g.lmax}: {len(idx)} blocks, {rep}")
+        say(f"[batch32 {prec}] problem {i} lmax {g.lmax}: {len(idx)} blocks, {rep}")
         assert rep["gate"] <= GATE[prec]
         assert not bool(torch.isnan(p["out"]).any()), f"problem {i}: a block was not written"
-    say(f"[c5 {prec}] worst gate {worst:.3e}")
+    say(f"[batch32 {prec}] worst gate {worst:.3e}")
     bt.close()
     for p in probs:
         del p["out"]

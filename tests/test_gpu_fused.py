@@ -88,7 +88,7 @@ def test_fused_equals_separate_calls(lmax):
 
 
 def test_fused_full_size_against_oracle_and_separate_calls():
-    cfg = S.CONFIGS["c4"]
+    cfg = S.CONFIGS["lmax3000"]
     og = G.make_grid(cfg.lmax, cfg.k)
     g = sp.Grid(cfg.lmax, cfg.k)
     ninv, b_l, R, d_l = config_inputs(cfg, og)
@@ -103,20 +103,20 @@ def test_fused_full_size_against_oracle_and_separate_calls():
     op = O.LocalOperator(og, b_l, R)
     Cref = np.stack([O.btnb_block(op, ninv, J, K) for J, K in pairs])
     Dref = O.sample_D(og, d_l, None, pairs)
-    say(f"[fused c4] npix={g.npix} nblocks={g.nblocks} sampled rows={len(rows)} blocks={len(idx)}")
+    say(f"[fused lmax3000] npix={g.npix} nblocks={g.nblocks} sampled rows={len(rows)} blocks={len(idx)}")
     for prec in ("bf16x6", "fp32"):
         D1, C1 = fused(g, kd, kb, n_dev, prec)
         rep_c = error_report(C1.view(-1, 64, 64)[idx_t].cpu().numpy(), Cref, jrow)
         rep_d = error_report(D1.view(-1, 64, 64)[idx_t].cpu().numpy(), Dref, jrow)
-        say(f"[fused c4] {prec}: C {rep_c}; D {rep_d}")
+        say(f"[fused lmax3000] {prec}: C {rep_c}; D {rep_d}")
         assert rep_c["gate"] <= GATE[prec]
         assert rep_d["gate"] <= GATE["fp64"]
         assert not bool(torch.isnan(D1).any()), f"{prec}: a D-hat block was not written"
         assert not bool(torch.isnan(C1).any()), f"{prec}: a B^T N^-1 B block was not written"
         D0, C0 = separate(g, kd, kb, n_dev, prec)
-        assert torch.equal(D1, D0), f"c4 {prec}: D-hat differs from sample_D"
-        assert torch.equal(C1, C0), f"c4 {prec}: B^T N^-1 B differs from sample_BtNB"
-        say(f"[fused c4] {prec}: both outputs bitwise equal to the separate calls")
+        assert torch.equal(D1, D0), f"lmax3000 {prec}: D-hat differs from sample_D"
+        assert torch.equal(C1, C0), f"lmax3000 {prec}: B^T N^-1 B differs from sample_BtNB"
+        say(f"[fused lmax3000] {prec}: both outputs bitwise equal to the separate calls")
         del D0, C0, D1, C1
         torch.cuda.empty_cache()
 

@@ -61,25 +61,25 @@ def run_BtNB(g, kern, ninv_dev, prec):
 # --- C1: lmax 64, every block against the oracle ----------------------------
 
 @pytest.fixture(scope="module")
-def c1():
-    cfg = S.CONFIGS["c1"]
+def lmax64():
+    cfg = S.CONFIGS["lmax64"]
     og = G.make_grid(cfg.lmax, cfg.k)
     g = sp.Grid(cfg.lmax, cfg.k)
     ninv, b_l, R, d_l = config_inputs(cfg, og)
     pairs = stored_pairs(og)
     rows = [J for J, _ in pairs]
-    say(f"[c1] npix={g.npix} nblocks={g.nblocks} nterms={g.nterms} nunique={g.nunique}")
+    say(f"[lmax64] npix={g.npix} nblocks={g.nblocks} nterms={g.nterms} nunique={g.nunique}")
     return dict(og=og, g=g, ninv=ninv, b_l=b_l, R=R, d_l=d_l, pairs=pairs, rows=rows,
                 kb=sp.Kernel(g, b_l, R), kd=sp.Kernel(g, d_l, 0.0))
 
 
-def test_c1_kernel_table_interpolation(c1):
+def test_lmax64_kernel_table_interpolation(lmax64):
     """The table's 4-point interpolation against the oracle's direct sum at
     random y over the whole domain: <= 1e-12 of the kernel's peak."""
-    g = c1["g"]
+    g = lmax64["g"]
     rng = np.random.default_rng(1)
-    for name, coef, R in (("beam", c1["b_l"], c1["R"]), ("prior", c1["d_l"], None)):
-        kern = c1["kb"] if name == "beam" else c1["kd"]
+    for name, coef, R in (("beam", lmax64["b_l"], lmax64["R"]), ("prior", lmax64["d_l"], None)):
+        kern = lmax64["kb"] if name == "beam" else lmax64["kd"]
         ydom = g.y_pattern_max if R is None else min(g.y_pattern_max, 2 * math.sin(R / 2) ** 2)
         y = np.concatenate([[0.0], rng.uniform(0, ydom, 4000), ydom * rng.uniform(0, 1e-4, 200)])
         out = torch.empty(y.size, dtype=torch.float64, device="cuda")
@@ -87,53 +87,53 @@ def test_c1_kernel_table_interpolation(c1):
         ref = OK.legendre_series_in_y(coef, y)
         peak = abs(OK.legendre_series_in_y(coef, np.array([0.0]))[0])
         err = np.abs(out.cpu().numpy() - ref).max() / peak
-        say(f"[c1] table {name}: max err / peak = {err:.3e}")
+        say(f"[lmax64] table {name}: max err / peak = {err:.3e}")
         assert err <= 1e-12
 
 
-def test_c1_D_and_B_blocks(c1):
-    og, g, pairs, rows = c1["og"], c1["g"], c1["pairs"], c1["rows"]
-    D = run_D(g, c1["kd"]).cpu().numpy()
-    Dref = O.sample_D(og, c1["d_l"], None, pairs)
+def test_lmax64_D_and_B_blocks(lmax64):
+    og, g, pairs, rows = lmax64["og"], lmax64["g"], lmax64["pairs"], lmax64["rows"]
+    D = run_D(g, lmax64["kd"]).cpu().numpy()
+    Dref = O.sample_D(og, lmax64["d_l"], None, pairs)
     rep = error_report(D, Dref, rows)
-    say(f"[c1] D fp64: {rep}")
+    say(f"[lmax64] D fp64: {rep}")
     assert rep["gate"] <= GATE["fp64"]
-    B = run_D(g, c1["kb"]).cpu().numpy()
-    Bref = O.sample_D(og, c1["b_l"], c1["R"], pairs)
+    B = run_D(g, lmax64["kb"]).cpu().numpy()
+    Bref = O.sample_D(og, lmax64["b_l"], lmax64["R"], pairs)
     rep = error_report(B, Bref, rows)
-    say(f"[c1] B fp64: {rep}")
+    say(f"[lmax64] B fp64: {rep}")
     assert rep["gate"] <= GATE["fp64"]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x3"])
-def test_c1_btnb(c1, prec):
-    og, g, pairs, rows = c1["og"], c1["g"], c1["pairs"], c1["rows"]
-    if "Cref" not in c1:
-        c1["Cref"] = O.sample_BtNB(og, c1["b_l"], c1["ninv"], c1["R"], pairs)
-    C = run_BtNB(g, c1["kb"], dev(c1["ninv"]), prec).cpu().numpy()
-    rep = error_report(C, c1["Cref"], rows)
-    say(f"[c1] BtNB {prec}: {rep}")
+def test_lmax64_btnb(lmax64, prec):
+    og, g, pairs, rows = lmax64["og"], lmax64["g"], lmax64["pairs"], lmax64["rows"]
+    if "Cref" not in lmax64:
+        lmax64["Cref"] = O.sample_BtNB(og, lmax64["b_l"], lmax64["ninv"], lmax64["R"], pairs)
+    C = run_BtNB(g, lmax64["kb"], dev(lmax64["ninv"]), prec).cpu().numpy()
+    rep = error_report(C, lmax64["Cref"], rows)
+    say(f"[lmax64] BtNB {prec}: {rep}")
     assert rep["gate"] <= GATE[prec]
 
 
-def test_c1_fp64_is_bitwise_reproducible(c1):
-    g = c1["g"]
-    n = dev(c1["ninv"])
-    a = run_BtNB(g, c1["kb"], n, "fp64").clone()
-    b = run_BtNB(g, c1["kb"], n, "fp64")
+def test_lmax64_fp64_is_bitwise_reproducible(lmax64):
+    g = lmax64["g"]
+    n = dev(lmax64["ninv"])
+    a = run_BtNB(g, lmax64["kb"], n, "fp64").clone()
+    b = run_BtNB(g, lmax64["kb"], n, "fp64")
     assert torch.equal(a, b)
 
 
-def test_c1_delta_map_and_linearity(c1):
+def test_lmax64_delta_map_and_linearity(lmax64):
     """N^-1 = e_p gives rank-one blocks B(p, J_a) B(p, K_b); the result is linear
     in N^-1 (Eq. 15 closed forms, checked on the GPU output alone)."""
-    g = c1["g"]
-    Bblk = run_D(g, c1["kb"]).cpu().numpy()                 # local B-hat blocks
+    g = lmax64["g"]
+    Bblk = run_D(g, lmax64["kb"]).cpu().numpy()                 # local B-hat blocks
     brp, bcol = g.blocks()
     p = 5 * 64 + 17                                           # a pixel of tile 5
     w = np.zeros(g.npix)
     w[p] = 1.0
-    C = run_BtNB(g, c1["kb"], dev(w), "fp64").cpu().numpy()
+    C = run_BtNB(g, lmax64["kb"], dev(w), "fp64").cpu().numpy()
     rows = np.repeat(np.arange(g.ntiles), np.diff(brp))
     Bfull = {}
     for n, (J, K) in enumerate(zip(rows, bcol)):
@@ -147,15 +147,15 @@ def test_c1_delta_map_and_linearity(c1):
         assert np.max(np.abs(C[n] - np.outer(u, v))) <= 1e-13 * peak
     n1 = np.random.default_rng(2).uniform(0.5, 2, g.npix)
     n2 = np.random.default_rng(3).uniform(0.5, 2, g.npix)
-    C1 = run_BtNB(g, c1["kb"], dev(n1), "fp64")
-    C2 = run_BtNB(g, c1["kb"], dev(n2), "fp64")
-    C12 = run_BtNB(g, c1["kb"], dev(2.5 * n1 - 0.5 * n2), "fp64")
+    C1 = run_BtNB(g, lmax64["kb"], dev(n1), "fp64")
+    C2 = run_BtNB(g, lmax64["kb"], dev(n2), "fp64")
+    C12 = run_BtNB(g, lmax64["kb"], dev(2.5 * n1 - 0.5 * n2), "fp64")
     assert torch.max(torch.abs(C12 - (2.5 * C1 - 0.5 * C2))).item() <= 1e-13 * torch.max(torch.abs(C12)).item()
 
 
-def test_c1_errors_through_the_abi(c1):
-    g, kb = c1["g"], c1["kb"]
-    n = dev(c1["ninv"])
+def test_lmax64_errors_through_the_abi(lmax64):
+    g, kb = lmax64["g"], lmax64["kb"]
+    n = dev(lmax64["ninv"])
     bad = torch.empty(g.out_len - 1, dtype=torch.float64, device="cuda")
     with pytest.raises(sp.SympixError) as e:
         sp.sample_BtNB(g, kb, n, bad, "fp64")
@@ -251,9 +251,9 @@ def test_tiny_grids_all_blocks(lmax):
 
 # --- full-size configurations, sampled block-rows ------------------------------
 
-@pytest.mark.parametrize("name,modes,n_random", [("c2", ("fp64", "bf16x6"), 24),
-                                                 ("c3", ("fp64", "fp32", "bf16x6", "bf16x3"), 16),
-                                                 ("c4", ("fp64", "fp32", "bf16x6", "bf16x3"), 12)])
+@pytest.mark.parametrize("name,modes,n_random", [("lmax512", ("fp64", "bf16x6"), 24),
+                                                 ("lmax1500", ("fp64", "fp32", "bf16x6", "bf16x3"), 16),
+                                                 ("lmax3000", ("fp64", "fp32", "bf16x6", "bf16x3"), 12)])
 def test_full_size_sampled(name, modes, n_random):
     cfg = S.CONFIGS[name]
     og = G.make_grid(cfg.lmax, cfg.k)
@@ -331,7 +331,7 @@ def test_two_hop_pattern_all_blocks(lmax):
 
 
 def test_two_hop_pattern_full_size_sampled():
-    cfg = S.CONFIGS["c3"]
+    cfg = S.CONFIGS["lmax1500"]
     og = G.make_grid(cfg.lmax, cfg.k)
     g = sp.Grid(cfg.lmax, cfg.k)
     ninv, b_l, R, _ = config_inputs(cfg, og)
@@ -361,9 +361,9 @@ def test_two_hop_pattern_full_size_sampled():
         torch.cuda.empty_cache()
 
 
-def test_two_hop_pattern_errors(c1):
-    g, kb = c1["g"], c1["kb"]
-    n = dev(c1["ninv"])
+def test_two_hop_pattern_errors(lmax64):
+    g, kb = lmax64["g"], lmax64["kb"]
+    n = dev(lmax64["ninv"])
     rp, col = g.pattern_blocks("two_hop")
     out = torch.empty(len(col) * 4096, dtype=torch.float64, device="cuda")
     with pytest.raises(sp.SympixError) as e:
@@ -412,7 +412,7 @@ def test_convolution_every_tile(lmax):
 
 
 def test_convolution_full_size_sampled():
-    cfg = S.CONFIGS["c4"]
+    cfg = S.CONFIGS["lmax3000"]
     og = G.make_grid(cfg.lmax, cfg.k)
     g = sp.Grid(cfg.lmax, cfg.k)
     rng = np.random.default_rng(4040)
@@ -423,13 +423,13 @@ def test_convolution_full_size_sampled():
     tiles = sample_rows(og, 48, seed=cfg.seed)
     ref = O.convolve(og, b_l, f, R, tiles=tiles)
     gate = conv_gate(got[tiles], ref)
-    say(f"[conv c4] {len(tiles)} sampled tiles, gate {gate:.3e}")
+    say(f"[conv lmax3000] {len(tiles)} sampled tiles, gate {gate:.3e}")
     assert gate <= GATE["fp64"]
     assert np.isfinite(got).all()
 
 
-def test_convolution_errors(c1):
-    g, kb = c1["g"], c1["kb"]
+def test_convolution_errors(lmax64):
+    g, kb = lmax64["g"], lmax64["kb"]
     f = torch.zeros(g.npix, dtype=torch.float64, device="cuda")
     short = torch.zeros(g.npix - 1, dtype=torch.float64, device="cuda")
     with pytest.raises(sp.SympixError) as ei:

@@ -98,7 +98,7 @@ def test_min_m_matches_quadratic_root():
         assert G.min_m_eq3(lmax, s, c, thr) == _m_closed_form(lmax, s, c, thr)
 
 
-def test_c1_closed_form_layout():
+def test_lmax64_closed_form_layout():
     """lmax = 64, k = 8, margin 100: Eq. 3 never holds (sqrt(...) <= 64 < 100),
     so every band needs 2*64+1 = 129 pixels, alpha = 17, T_0 = 18 (smallest
     5-smooth >= 17) and every band keeps 18 tiles: 80 rings of 144 pixels."""

@@ -73,9 +73,9 @@ def test_two_hop_blocks_match_dense_brute_force(lmax, k, margin):
             assert (J, K) in listed
 
 
-def test_c1_btnb_matches_sparse_brute_force(c1_grid):
-    g = c1_grid
-    cfg = S.CONFIGS["c1"]
+def test_lmax64_btnb_matches_sparse_brute_force(lmax64_grid):
+    g = lmax64_grid
+    cfg = S.CONFIGS["lmax64"]
     ring, pin, nr, phi = g.pixel_coords()
     ninv = S.ninv_for(cfg, g.theta[ring], phi)
     b_l, R = S.gaussian_beam(cfg.lmax, g.npix, cfg.fwhm_pix)
@@ -113,10 +113,10 @@ def test_linearity_in_ninv():
     assert np.max(np.abs(C12 - (0.3 * C1 - 1.7 * C2))) < 1e-14 * np.abs(C12).max() * 10
 
 
-def test_blocks_are_symmetric_across_the_diagonal(c1_grid):
+def test_blocks_are_symmetric_across_the_diagonal(lmax64_grid):
     """D_JK = D_KJ^T and C_JK = C_KJ^T, with the (K, J) blocks built from their
     own symmetry keys."""
-    g = c1_grid
+    g = lmax64_grid
     rng = np.random.default_rng(3)
     ninv = rng.uniform(0.5, 2.0, g.npix)
     b_l, R = S.gaussian_beam(g.lmax, g.npix, 3.0)
@@ -209,8 +209,8 @@ def test_convolution_matches_sparse_brute_force(lmax, k, margin):
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
 
 
-def test_c1_convolution_matches_sparse_brute_force(c1_grid):
-    g = c1_grid
+def test_lmax64_convolution_matches_sparse_brute_force(lmax64_grid):
+    g = lmax64_grid
     rng = np.random.default_rng(5)
     f = rng.uniform(-1.0, 1.0, g.npix)
     b_l, R = S.gaussian_beam(g.lmax, g.npix, 3.0)

@@ -30,10 +30,10 @@ class Config:
 
 
 CONFIGS = {
-    "c1": Config("c1", 64, 8, 3.0, "uniform", 101),
-    "c2": Config("c2", 512, 8, 3.0, "dipole_mask", 202),
-    "c3": Config("c3", 1500, 8, 3.0, "dipole_mask", 303),
-    "c4": Config("c4", 3000, 8, 3.0, "scan_lognormal", 404),
+    "lmax64": Config("lmax64", 64, 8, 3.0, "uniform", 101),
+    "lmax512": Config("lmax512", 512, 8, 3.0, "dipole_mask", 202),
+    "lmax1500": Config("lmax1500", 1500, 8, 3.0, "dipole_mask", 303),
+    "lmax3000": Config("lmax3000", 3000, 8, 3.0, "scan_lognormal", 404),
 }
 
 BATCH_LMAX = (256, 512, 1024, 2048)
