@@ -2,24 +2,30 @@
 
 A step is one pass of the whole device path on one synthetic problem:
 tabulate the beam and prior kernels (each with its unique-block evaluation),
-expand D-hat, and contract B-hat^T N^-1 B-hat.  Grid construction is host work
-done once per resolution and is timed separately (setup_s).  Inputs are
-resident in device memory before the timed region.
+then write the D-hat blocks and contract B-hat^T N^-1 B-hat (one launch, the
+combined call).  Grid construction is host work done once per resolution and
+is timed separately (grid_setup_s).  Inputs are resident in device memory
+before the timed region.
 
 Default workload: lmax = 3000, k = 8 (13.0M pixels, 1,013,648 stored 64x64
 blocks), Gaussian beam FWHM 3 pixels cut at 3 FWHM, prior d_l = (l+1)^2,
 N^-1 = log-normal scan-stripe pattern with 20% of the sky masked.
 
-value = stored B^T N^-1 B elements / step time in the headline precision mode
-(split BF16, 6 products); FP64 and the other modes are timed the same way and
-reported side by side under "modes".
+value = stored B^T N^-1 B elements / step time in plain FP64 (the paper's
+arithmetic); the mixed-precision modes (split BF16 with 6 or 3 products, FP32
+MFMA) are timed the same way and reported under "modes", each with its error
+against the FP64 oracle ("gate": max |GPU - oracle| / M_J on sampled block
+rows, M_J the largest oracle value of block-row J) and its speed relative to
+FP64.  The oracle runs only in the cpu_baseline leg: it computes the sampled
+block-rows there (that is the baseline's timed work), and the same rows are
+then compared with every mode's last timed output.
 
 With --config batch32 a step is one launch of the captured graph that contracts
-all 32 problems of the batched workload (lmax 256/512/1024/2048; split BF16x6
-and FP32 MFMA, FP64 accumulation across contraction tiles; 172 GB of output),
-one batch per mode, the first reported as the headline; the beam kernels
-are tabulated before the timed region and the schedule and tile shape are
-autotuned first.
+all 32 problems of the batched workload (lmax 256/512/1024/2048; FP32 MFMA
+with FP64 accumulation across contraction tiles first, then split BF16x6 and
+plain FP64; 172 GB of output), one batch per mode, the first reported as
+value; the beam kernels are tabulated before the timed region and the schedule
+and tile shape are autotuned first.
 
 With --op conv a step is one pixel-domain convolution g = B-hat f (FP64) of
 the configuration's grid and beam.  With --op two_hop a step tabulates the beam
@@ -27,7 +33,8 @@ kernel and samples B^T N^-1 B on the two-hop pattern (every nonzero block of
 the product), in the first of --modes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config lmax3000|batch32]
-                       [--op btnb|conv] [--modes bf16x6,fp64,bf16x3] [--no-cpu-baseline]
+                       [--op btnb|conv|two_hop] [--modes fp64,bf16x6,fp32,bf16x3]
+                       [--no-cpu-baseline] [--no-batch-compare]
 """
 from __future__ import annotations
 
@@ -45,13 +52,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "B^T N^-1 B elements/s at lmax=3000: FP64 vs split-BF16 MFMA at <=1e-6 rel err"
-HEADLINE = "bf16x6"
+HEADLINE = "fp64"
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}     # TFLOP/s, dense
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}                   # MFMA products per term
+BOUND = {"fp64": 1e-10, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 2.0 ** -15}  # gate each mode is held to
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x6": "bf16", "bf16x3": "bf16"}
 HBM_PEAK = 8000.0                                                              # GB/s
-HBM_PEAK_GBS = 8000.0
 KERNEL_NAME = {"fp64": "k_class_f64<false>", "fp32": "k_class_f32<false>", "bf16x3": "k_class_bf16<2, false>",
                "bf16x6": "k_class_bf16<3, false>"}
+BATCH_KERNEL = {"fp64": "k_batch_f64", "fp32": "k_batch_f32", "bf16x6": "k_batch_bf16<3>",
+                "bf16x3": "k_batch_bf16<2>"}
 
 
 def parse():
@@ -62,24 +72,29 @@ def parse():
     ap.add_argument("--config", default="lmax3000")
     ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop"],
                     help="btnb: the D-hat / B-hat^T N^-1 B-hat step (default); conv: the pixel-domain "
-                         "convolution g = B-hat f")
+                         "convolution g = B-hat f; two_hop: B^T N^-1 B on every nonzero block of the product")
     ap.add_argument("--modes", default=None,
-                    help="precision modes, the first is the headline (default bf16x6,fp64,bf16x3; "
-                         "for --config batch32 bf16x6,fp32)")
+                    help="precision modes, the first is reported as value (default fp64,bf16x6,fp32,bf16x3; "
+                         "for --config batch32 fp32,bf16x6,fp64)")
     ap.add_argument("--separate", action="store_true",
                     help="sample D-hat and B^T N^-1 B with the two separate calls (default: the combined "
                          "call, one launch)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="tabulate each step's kernels on the main stream, after the previous step (default: on a "
                          "second stream, while the previous step's sampling launch runs)")
+    ap.add_argument("--no-batch-compare", action="store_true",
+                    help="skip the untimed comparison of the contraction alone in the class-kernel grid and "
+                         "as a one-problem persistent batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds-1t", type=float, default=6.0,
+                    help="budget of the single-BLAS-thread oracle run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES bytes (a reference "
                          "kernel of known traffic for HBM counter runs)")
     args = ap.parse_args()
     if args.modes is None:
-        args.modes = "bf16x6,fp32" if args.config == "batch32" else "bf16x6,fp64,bf16x3"
+        args.modes = "fp32,bf16x6,fp64" if args.config == "batch32" else "fp64,bf16x6,fp32,bf16x3"
     return args
 
 
@@ -102,38 +117,169 @@ def recorded_traffic(mode, config):
     return None
 
 
-def cpu_baseline(cfg, budget_s):
-    """The oracle as it stands, on a bounded sample of the same workload: whole
-    block-rows of B^T N^-1 B at random tiles until the time budget is spent."""
+def host_info():
+    """Host cores, CPU model and the BLAS library numpy calls (vendor,
+    version, threads)."""
+    info = {"nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0))}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if blas:
+            info["blas"] = {"vendor": blas[0].get("internal_api"), "version": blas[0].get("version"),
+                            "threads": int(blas[0].get("num_threads", 1))}
+    except Exception:  # pragma: no cover
+        pass
+    return info
+
+
+def blas_threads(info):
+    return int(info.get("blas", {}).get("threads", 1))
+
+
+def gate(C, ref, rows):
+    """max |C - ref| / M_J over the blocks compared, M_J the largest |ref| of
+    block-row J (rows[n] = J of block n); infinite if anything is not finite."""
+    if not (np.isfinite(C).all() and np.isfinite(ref).all()):
+        return float("inf")
+    mj = {}
+    for n, J in enumerate(rows):
+        mj[J] = max(mj.get(J, 0.0), float(np.abs(ref[n]).max()))
+    worst = 0.0
+    for n, J in enumerate(rows):
+        d = float(np.abs(C[n] - ref[n]).max())
+        worst = max(worst, d / mj[J] if mj[J] > 0 else d)
+    return worst
+
+
+def error_summary(C, ref, rows):
+    """Gate plus the per-element |C - ref| / max(|ref|, 1e-8 M_J) median / p99 / max."""
+    mj = {}
+    for n, J in enumerate(rows):
+        mj[J] = max(mj.get(J, 0.0), float(np.abs(ref[n]).max()))
+    scale = np.array([mj[J] for J in rows])[:, None, None]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rel = np.abs(C - ref) / np.maximum(np.maximum(np.abs(ref), 1e-8 * scale), 1e-300)
+    return {"gate": gate(C, ref, rows), "median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
+            "max": float(np.max(rel))}
+
+
+def sampled_rows(tiles, n_random, seed):
+    """Block-rows J to check: the first tile of the two polar bands, of the two
+    equatorial bands and of up to four bands whose tile count differs from a
+    neighbour's, then random tiles (in that order)."""
+    tiles = np.asarray(tiles)
+    t0 = np.concatenate([[0], np.cumsum(tiles)[:-1]])
+    nb = len(tiles)
+    nh = nb // 2
+    special = list(dict.fromkeys([0, 1, nb - 2, nb - 1]))
+    ntrans = 0
+    for b in range(nb):
+        i, south = divmod(b, 2)
+        nbrs = [2 * (i - 1) + south] if i > 0 else []
+        nbrs.append(2 * (i + 1) + south if i < nh - 1 else 2 * i + 1 - south)
+        if b not in special and ntrans < 4 and any(tiles[x] != tiles[b] for x in nbrs):
+            special.append(b)
+            ntrans += 1
+    rows = []
+    for b in special:
+        if int(t0[b]) not in rows:
+            rows.append(int(t0[b]))
+    rng = np.random.default_rng(seed)
+    ntiles = int(tiles.sum())
+    target = min(ntiles, len(rows) + n_random)
+    while len(rows) < target:
+        J = int(rng.integers(ntiles))
+        if J not in rows:
+            rows.append(J)
+    return rows
+
+
+def row_blocks(blk_ptr, blk_col, rows):
+    """Library stored-block indices and (J, K) pairs of the given rows."""
+    idx, pairs = [], []
+    for J in rows:
+        for n in range(int(blk_ptr[J]), int(blk_ptr[J + 1])):
+            idx.append(n)
+            pairs.append((J, int(blk_col[n])))
+    return np.asarray(idx, dtype=np.int64), pairs
+
+
+def cpu_baseline(cfg, g, budget_s, budget_1t, sampled):
+    """The oracle as it stands, timed on the sampled block-rows of the same
+    workload (in order, until the budget is spent; unique blocks evaluated on
+    first use inside the timed region), first with numpy's BLAS threads, then
+    on one BLAS thread.  The rows it computed are then compared with every
+    mode's GPU output of those rows (sampled = {"rows", "pairs", "modes":
+    {mode: {"C": blocks, "D": blocks or None}}})."""
     from oracle import grid as G
     from oracle import operators as O
     from workloads import synth as S
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = 1
+    info = host_info()
     og = G.make_grid(cfg.lmax, cfg.k)
-    ring, pin, nr, phi = og.pixel_coords()
+    ring, _, _, phi = og.pixel_coords()
     ninv = S.ninv_for(cfg, og.theta[ring], phi)
     b_l, R = S.gaussian_beam(cfg.lmax, og.npix, cfg.fwhm_pix)
-    op = O.LocalOperator(og, b_l, R)
-    rng = np.random.default_rng(7)
-    t0 = time.perf_counter()
-    nblk = 0
-    nrows = 0
-    while time.perf_counter() - t0 < budget_s:
-        J = int(rng.integers(og.ntiles))
-        for K in og.tile_neighbours(J):
-            if K >= J:
-                O.btnb_block(op, ninv, J, K)
-                nblk += 1
-        nrows += 1
-    dt = time.perf_counter() - t0
-    return {"value": nblk * 4096 / dt, "unit": "elements/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{nrows} random block-rows ({nblk} stored 64x64 blocks of B^T N^-1 B, "
-                      f"unique blocks evaluated on first use) of the lmax={cfg.lmax} workload, "
-                      f"{dt:.1f} s wall"}
+    rows, pairs = sampled["rows"], sampled["pairs"]
+    # the library's stored-block rows must list the oracle's neighbours K >= J
+    layout_ok = all([K for J2, K in pairs if J2 == J] == [K for K in og.tile_neighbours(J) if K >= J]
+                    for J in rows)
+    by_row = {}
+    for n, (J, K) in enumerate(pairs):
+        by_row.setdefault(J, []).append((n, K))
+
+    def run(budget):
+        op = O.LocalOperator(og, b_l, R)
+        done, out = [], []
+        t0 = time.perf_counter()
+        for J in rows:
+            if done and time.perf_counter() - t0 >= budget:
+                break
+            for n, K in by_row[J]:
+                out.append(O.btnb_block(op, ninv, J, K))
+                done.append(n)
+        return time.perf_counter() - t0, done, out
+
+    dt, done, Cref = run(budget_s)
+    res = {"value": len(done) * 4096 / dt, "unit": "elements/s", "cores": blas_threads(info), "kind": "oracle",
+           "sample": f"{len(set(pairs[n][0] for n in done))} block-rows ({len(done)} stored 64x64 blocks of "
+                     f"B^T N^-1 B: polar, equatorial and ratio-transition bands, then random tiles) of the "
+                     f"lmax={cfg.lmax} workload, unique blocks evaluated on first use, {dt:.1f} s wall, "
+                     f"numpy FP64 with {blas_threads(info)} BLAS threads",
+           "host": info, "layout_matches_oracle": bool(layout_ok)}
+    if budget_1t > 0:
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="blas"):
+                dt1, done1, _ = run(budget_1t)
+            res["single_thread"] = {"value": len(done1) * 4096 / dt1, "unit": "elements/s", "cores": 1,
+                                    "sample": f"the first {len(done1)} of the same blocks, {dt1:.1f} s wall"}
+        except Exception as e:  # pragma: no cover
+            res["single_thread"] = {"error": str(e)}
+    # the same rows against every mode's last timed output
+    Cref = np.stack(Cref)
+    jrow = [pairs[n][0] for n in done]
+    Dref = None
+    gates = {}
+    for mode, m in sampled["modes"].items():
+        r = {"C": error_summary(m["C"][done], Cref, jrow), "bound": BOUND[mode]}
+        if m.get("D") is not None:
+            if Dref is None:
+                Dref = O.sample_D(og, S.prior(cfg.lmax), None, [pairs[n] for n in done])
+            r["D"] = error_summary(m["D"][done], Dref, jrow)
+        r["blocks"] = len(done)
+        if not layout_ok:
+            r["C"]["gate"] = float("inf")          # the blocks compared are not the oracle's
+        gates[mode] = r
+    return res, gates
+
+
 
 
 def batch_inputs(sp, S):
@@ -151,22 +297,19 @@ def batch_inputs(sp, S):
     return probs
 
 
-def cpu_baseline_batch(probs, budget_s):
-    """The oracle on random block-rows drawn across the batch's problems until
-    the time budget is spent."""
+def cpu_baseline_batch(probs, budget_s, sampled):
+    """The oracle on sampled block-rows of the batch's problems (two per
+    problem, problems in turn) until the budget is spent; the rows it computed
+    are then compared with every mode's GPU output of those rows."""
     from oracle import grid as G
     from oracle import operators as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = 1
-    rng = np.random.default_rng(11)
+    info = host_info()
     grids, ops = {}, {}
     t0 = time.perf_counter()
-    nblk = nrows = 0
-    while time.perf_counter() - t0 < budget_s:
-        i = int(rng.integers(len(probs)))
+    done = []                     # (problem, J, Cref blocks)
+    for i, J in sampled["order"]:
+        if done and time.perf_counter() - t0 >= budget_s:
+            break
         pr = probs[i]
         lmax = pr["g"].lmax
         if lmax not in grids:
@@ -174,16 +317,28 @@ def cpu_baseline_batch(probs, budget_s):
         og = grids[lmax]
         if i not in ops:
             ops[i] = O.LocalOperator(og, pr["b_l"], pr["R"])
-        J = int(rng.integers(og.ntiles))
-        for K in og.tile_neighbours(J):
-            if K >= J:
-                O.btnb_block(ops[i], pr["ninv"], J, K)
-                nblk += 1
-        nrows += 1
+        ks = [K for K in og.tile_neighbours(J) if K >= J]
+        done.append((i, J, ks, np.stack([O.btnb_block(ops[i], pr["ninv"], J, K) for K in ks])))
     dt = time.perf_counter() - t0
-    return {"value": nblk * 4096 / dt, "unit": "elements/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{nrows} random block-rows ({nblk} stored blocks) across the 32 problems, "
-                      f"grids and unique blocks built on first use inside the {dt:.1f} s wall"}
+    nblk = sum(len(d[2]) for d in done)
+    res = {"value": nblk * 4096 / dt, "unit": "elements/s", "cores": blas_threads(info), "kind": "oracle",
+           "sample": f"{len(done)} block-rows ({nblk} stored blocks) drawn two per problem across the 32 "
+                     f"problems, grids and unique blocks built on first use inside the {dt:.1f} s wall",
+           "host": info}
+    gates = {}
+    for mode, per in sampled["modes"].items():
+        worst, per_prob = 0.0, {}
+        for i, J, ks, Cref in done:
+            got = per[(i, J)]
+            if got["ks"] != ks:
+                g_ = float("inf")                      # layout differs from the oracle's neighbours
+            else:
+                g_ = gate(got["C"], Cref, [J] * len(ks))
+            per_prob[i] = max(per_prob.get(i, 0.0), g_)
+            worst = max(worst, g_)
+        gates[mode] = {"gate": worst, "bound": BOUND[mode], "per_problem": {str(k): v for k, v in per_prob.items()},
+                       "rows": len(done)}
+    return res, gates
 
 
 def copy_calibration(torch, nbytes):
@@ -219,6 +374,17 @@ def run_batch(args):
     nelem = sum(pr["g"].nblocks for pr in probs) * 4096
     alg_flop = sum(2.0 * 64 ** 3 * pr["g"].nterms for pr in probs)
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    # sampled rows, two per problem: the first tile and a random one
+    rng = np.random.default_rng(11)
+    order = []
+    for i, pr in enumerate(probs):
+        order.append((i, 0))
+        order.append((i, int(rng.integers(1, pr["g"].ntiles))))
+    order = [order[2 * i] for i in range(32)] + [order[2 * i + 1] for i in range(32)]
+    blocks = {}
+    for i, pr in enumerate(probs):
+        blocks[i] = pr["g"].blocks()
+    sampled = {"order": order, "modes": {}}
     print(f"# workload batch32: 32 problems, npix={sum(pr['g'].npix for pr in probs)} "
           f"nblocks={nelem // 4096} output={nelem * 8 / 1e9:.1f} GB setup={setup:.1f}s", file=sys.stderr, flush=True)
     results = {}
@@ -238,12 +404,18 @@ def run_batch(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
         bt.close()
+        per = {}
+        for i, J in order:
+            rp, col = blocks[i]
+            n0, n1 = int(rp[J]), int(rp[J + 1])
+            per[(i, J)] = {"ks": [int(k) for k in col[n0:n1]],
+                           "C": probs[i]["out"].view(-1, 64, 64)[n0:n1].cpu().numpy()}
+        sampled["modes"][prec] = per
         ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
         ms_step = wall * 1000.0 / args.steps
         achieved = PRODUCTS[prec] * alg_flop / (ms.mean() * 1e-3) / 1e12
-        kern = {"fp32": ("k_batch_f32", "k_class_f32"), "bf16x6": ("k_batch_bf16<3>", "k_class_bf16<3, false>"),
-                "bf16x3": ("k_batch_bf16<2>", "k_class_bf16<2, false>")}[prec][
-            1 if chosen % len(sp.SCHEDULES) == sp.SCHED_PER_PROBLEM else 0]
+        kern = (BATCH_KERNEL[prec] if chosen % len(sp.SCHEDULES) != sp.SCHED_PER_PROBLEM
+                else KERNEL_NAME[prec])
         results[prec] = {
             "elements_per_s": nelem / (ms_step * 1e-3), "ms_per_step": ms_step, "graph_launch_ms": ms.mean(),
             "schedule": sched, "tune_ms": [round(t, 3) for t in tune_ms],
@@ -254,6 +426,9 @@ def run_batch(args):
         print(f"# batch32 batch {prec} ({sched}; tune ms {[round(t, 2) for t in tune_ms]}): step {ms_step:.2f} ms wall, "
               f"{ms.mean():.2f} ms per graph launch, {achieved:.1f} TFLOP/s "
               f"({achieved / PEAK[prec] * 100:.1f}% of {PEAK[prec]} TFLOP/s)", file=sys.stderr, flush=True)
+    if "fp64" in results:
+        for prec, r in results.items():
+            r["speed_vs_fp64"] = r["elements_per_s"] / results["fp64"]["elements_per_s"]
     head = results[modes[0]]
     line = {
         "metric": "B^T N^-1 B elements/s, 32-problem batch in one graph launch",
@@ -266,7 +441,7 @@ def run_batch(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if modes[0].startswith("bf16") else "f32",
+        "dtype": DTYPE[modes[0]],
         "data": "synthetic",
         "config": {"workload": "sympix batch: 32 problems, lmax 256/512/1024/2048 (8 each), "
                                "beam FWHM U[2,5] px cut 3 FWHM, N^-1 U[0.5,2] x cap mask U[0,0.3], "
@@ -278,7 +453,10 @@ def run_batch(args):
         "modes": results,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_batch(probs, args.cpu_seconds)
+        base, gates = cpu_baseline_batch(probs, args.cpu_seconds, sampled)
+        line["cpu_baseline"] = base
+        for prec, gr in gates.items():
+            results[prec]["error_vs_oracle"] = gr
     print(json.dumps(line), flush=True)
 
 
@@ -287,11 +465,8 @@ def cpu_baseline_conv(cfg, budget_s):
     from oracle import grid as G
     from oracle import operators as O
     from workloads import synth as S
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = 1
+    info = host_info()
+    threads = blas_threads(info)
     og = G.make_grid(cfg.lmax, cfg.k)
     f = np.random.default_rng(1).standard_normal(og.npix)
     b_l, R = S.gaussian_beam(cfg.lmax, og.npix, cfg.fwhm_pix)
@@ -309,7 +484,7 @@ def cpu_baseline_conv(cfg, budget_s):
     dt = time.perf_counter() - t0
     return {"value": ntiles * k2 / dt, "unit": "pixels/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{ntiles} random output tiles of the lmax={cfg.lmax} convolution, "
-                      f"unique blocks evaluated on first use, {dt:.1f} s wall"}
+                      f"unique blocks evaluated on first use, {dt:.1f} s wall", "host": info}
 
 
 def run_conv(args):
@@ -445,7 +620,7 @@ def run_two_hop(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if prec.startswith("bf16") else ("f64" if prec == "fp64" else "f32"),
+        "dtype": DTYPE[prec],
         "data": "synthetic",
         "config": {"workload": f"sympix lmax={cfg.lmax} k={cfg.k} two-hop blocks, beam FWHM {cfg.fwhm_pix:g} px "
                                f"cut 3 FWHM, N^-1 {cfg.ninv_kind} seed {cfg.seed}",
@@ -494,6 +669,12 @@ def main():
     alg_flop = 2.0 * 64 ** 3 * g.nterms
     print(f"# workload {args.config}: lmax={cfg.lmax} npix={g.npix} nblocks={g.nblocks} "
           f"nterms={g.nterms} nunique={g.nunique} grid_setup={setup_grid:.2f}s", file=sys.stderr, flush=True)
+    # block-rows whose outputs are kept for the comparison with the oracle
+    blk_ptr, blk_col = g.blocks()
+    rows = sampled_rows(g.bands()[0], 160, seed=cfg.seed + 7)
+    sidx, spairs = row_blocks(blk_ptr, blk_col, rows)
+    sidx_t = torch.as_tensor(sidx, device="cuda")
+    sampled = {"rows": rows, "pairs": spairs, "modes": {}}
 
     copy_calibration(torch, args.copy_calibration)
 
@@ -517,8 +698,7 @@ def main():
         r_mfma["hbm_frac"] = r_hbm["frac"]
         return r_mfma
 
-    def fused_mode(prec):
-        return not args.separate
+    fused = not args.separate
 
     # One step: tabulate the beam and prior kernels (with their unique
     # blocks), then sample D-hat and B^T N^-1 B.  Events: 0 start, 1 kernels
@@ -529,14 +709,7 @@ def main():
         kb = sp.Kernel(g, b_l, R, stream=stream)
         kd = sp.Kernel(g, d_l, 0.0, stream=stream)
         ev[1].record(stream)
-        if not fused_mode(prec):
-            sp.sample_D(g, kd, out_D, stream=stream)
-            ev[2].record(stream)
-            sp.sample_BtNB(g, kb, ninv_dev, out_C, prec, stream=stream)
-        else:
-            sp.sample_D_BtNB(g, kd, kb, ninv_dev, out_D, out_C, prec, stream=stream)
-            ev[2].record(stream)
-        ev[3].record(stream)
+        sample(prec, kb, kd, ev, first=False)
         return kb, kd
 
     # Pipelined steps (default): the kernels of step s + 1 are tabulated on a
@@ -553,9 +726,9 @@ def main():
         ev1.record(st)
         return kb, kd, ev0, ev1
 
-    def sample(prec, kb, kd, ev):
-        fused = fused_mode(prec)
-        ev[1].record(stream)
+    def sample(prec, kb, kd, ev, first=True):
+        if first:
+            ev[1].record(stream)
         if not fused:
             sp.sample_D(g, kd, out_D, stream=stream)
             ev[2].record(stream)
@@ -578,6 +751,28 @@ def main():
             keeps.append((kb, kd))
             evs.append((ev, t1))
         return evs, keeps
+
+    def contraction_alone(prec, kb, n=3):
+        """Untimed comparison: the contraction alone in the class-kernel grid
+        (sample_BtNB) and as a one-problem persistent batch in one captured
+        graph (tuned over its schedules and tile shapes)."""
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+            e[0].record(stream)
+            for i in range(n):
+                fn()
+                e[i + 1].record(stream)
+            torch.cuda.synchronize()
+            return float(np.mean([e[i].elapsed_time(e[i + 1]) for i in range(n)]))
+        t_grid = timed(lambda: sp.sample_BtNB(g, kb, ninv_dev, out_C, prec, stream=stream))
+        bt = sp.Batch([(g, kb, ninv_dev, out_C)], prec=prec, stream=stream)
+        chosen, _ = bt.tune(stream)
+        t_batch = timed(lambda: bt.launch(stream))
+        bt.close()
+        return {"class_grid_ms": t_grid, "persistent_batch_ms": t_batch, "batch_plan": sp.plan_name(chosen),
+                "class_grid_kernel": KERNEL_NAME[prec], "batch_kernel": BATCH_KERNEL[prec]}
 
     results = {}
     for prec in modes:
@@ -602,7 +797,10 @@ def main():
             evo, keeps = run_overlapped(prec, args.steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
-        keeps.clear()
+        # the sampled rows of this mode's last timed outputs, for the oracle comparison
+        sampled["modes"][prec] = {"C": out_C.view(-1, 64, 64)[sidx_t].cpu().numpy(),
+                                  "D": out_D.view(-1, 64, 64)[sidx_t].cpu().numpy() if fused else None}
+        kb_last = keeps[-1][0]
         if args.no_overlap:
             seg = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
                              e[0].elapsed_time(e[3])] for e in evs])   # ms
@@ -612,7 +810,6 @@ def main():
         t_tab, t_a, t_b, t_step = seg.mean(axis=0)
         # separate calls: t_a = D-hat, t_b = contraction; combined call: t_a =
         # both outputs (one launch)
-        fused = fused_mode(prec)
         t_D, t_C = (None, t_a) if fused else (t_a, t_b)
         ms_step = wall * 1000.0 / args.steps
         r = {
@@ -632,20 +829,30 @@ def main():
         else:
             r["D_ms"] = t_D
             r["D_hbm_GBs"] = nelem * 8 / (t_D * 1e-3) / 1e9
+        if not args.no_batch_compare:
+            r["contraction_alone"] = contraction_alone(prec, kb_last)
+        keeps.clear()
+        del kb_last
         results[prec] = r
         dpart = (f"D-hat in the same launch ({r['hbm_write_GBs']:.0f} GB/s written)" if fused
                  else f"D {t_D:.2f} ms ({r['D_hbm_GBs']:.0f} GB/s)")
         rf = r["btnb_roofline"]
+        ca = r.get("contraction_alone")
+        cpart = (f"; contraction alone {ca['class_grid_ms']:.2f} ms in the class grid, "
+                 f"{ca['persistent_batch_ms']:.2f} ms as a persistent batch ({ca['batch_plan']})" if ca else "")
         print(f"# {prec}: step {ms_step:.2f} ms, btnb {t_C:.2f} ms "
               f"({rf['frac'] * 100:.1f}% of {rf['peak']} {rf['unit']}"
               f"{', MFMA %.1f%%' % (rf['mfma_frac'] * 100) if 'mfma_frac' in rf else ''}), {dpart}, "
-              f"tabulate {t_tab:.2f} ms, step by events {t_step:.2f} ms",
+              f"tabulate {t_tab:.2f} ms, step by events {t_step:.2f} ms{cpart}",
               file=sys.stderr, flush=True)
 
     head = HEADLINE if HEADLINE in results else modes[0]
     hr = results[head]
+    if "fp64" in results:
+        for prec, r in results.items():
+            r["speed_vs_fp64"] = r["elements_per_s"] / results["fp64"]["elements_per_s"]
     # the committed counter rows are taken on the default step (combined call)
-    traffic = recorded_traffic(head, args.config) if not args.separate else None
+    traffic = recorded_traffic(head, args.config) if fused else None
     roof = dict(hr["btnb_roofline"])
     roof["kernel"] = KERNEL_NAME[head]
     if hr["D_and_btnb_one_launch"]:
@@ -664,7 +871,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if head.startswith("bf16") else ("f64" if head == "fp64" else "f32"),
+        "dtype": DTYPE[head],
         "data": "synthetic",
         "config": {"workload": f"sympix lmax={cfg.lmax} k={cfg.k} beam FWHM {cfg.fwhm_pix:g} px "
                                f"cut 3 FWHM, prior (l+1)^2, N^-1 {cfg.ninv_kind} seed {cfg.seed}",
@@ -675,7 +882,14 @@ def main():
         "modes": results,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        base, gates = cpu_baseline(cfg, g, args.cpu_seconds, args.cpu_seconds_1t, sampled)
+        line["cpu_baseline"] = base
+        line["gates"] = {m: gr["C"]["gate"] for m, gr in gates.items()}
+        for prec, gr in gates.items():
+            results[prec]["error_vs_oracle"] = gr
+        print("# gates against the oracle: " + ", ".join(
+            f"{m} {gr['C']['gate']:.2e} (bound {gr['bound']:.0e})" + (f", D {gr['D']['gate']:.2e}" if "D" in gr else "")
+            for m, gr in gates.items()), file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -109,13 +109,28 @@ sympix_status sympix_grid_rings(const sympix_grid *g, double *theta, double *wei
 sympix_status sympix_grid_bands(const sympix_grid *g, int32_t *tiles, int32_t *alpha,
                                 int32_t *first_ring);
 
+/* Colatitude theta and longitude phi of every pixel, in pixel order (host
+ * buffers of npix values; either may be NULL).  Section 2.4 layout: pixel p of
+ * a ring of n pixels sits at phi = 2 pi (p + 1/2) / n, the first one half a
+ * pixel step from phi = 0 (Section 2.3), on the ring's Gauss-Legendre
+ * colatitude (Section 2.1).  Errors: EINVAL (NULL grid). */
+sympix_status sympix_grid_pixels(const sympix_grid *g, double *theta, double *phi);
+
 /* Full tile adjacency as CSR: row_ptr[ntiles+1] (int64), col[nadjacency]
- * (int32, ascending, the tile itself included).  Same band: t-1, t, t+1 mod T;
- * neighbouring band (N_i-N_i+1, S_i-S_i+1, N_{n-1}-S_{n-1}): closed phi
- * intervals that meet.  Host buffers. */
+ * (int32, ascending, the tile itself included).  These are the "neighbouring
+ * tiles" of Section 2.2 (the partner points a pixel needs lie in its own tile
+ * and the tiles around it) and of the truncation in Section 4.2.  Same band:
+ * t-1, t, t+1 mod T; neighbouring band (N_i-N_i+1, S_i-S_i+1, N_{n-1}-S_{n-1}):
+ * closed phi intervals that meet; no neighbour across a pole.  Host buffers.
+ * Errors: EINVAL (NULL grid). */
 sympix_status sympix_grid_neighbours(const sympix_grid *g, int64_t *row_ptr, int32_t *col);
 
-/* Stored blocks as CSR over J: row_ptr[ntiles+1], col[nblocks] = K >= J. */
+/* Stored blocks as CSR over J: row_ptr[ntiles+1], col[nblocks] = K >= J.
+ * Section 4.2 keeps an element of D-hat or B-hat only when its two pixels lie
+ * in the same or in neighbouring tiles, so the local part of either operator
+ * is the blocks (J, K) with K in nbr(J); by symmetry the pairs K >= J are
+ * stored and the rest are their transposes.  Host buffers, NULL skips.
+ * Errors: EINVAL (NULL grid). */
 sympix_status sympix_grid_blocks(const sympix_grid *g, int64_t *row_ptr, int32_t *col);
 
 /* Stored-block patterns of B-hat^T N^-1 B-hat.  With B-hat local (Section
@@ -235,17 +250,18 @@ sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d,
 
 /* ---- Batches: many B-hat^T N^-1 B-hat problems in one graph launch ----------
  * Eq. 15 evaluated for n independent problems (own grid, beam kernel, N^-1 and
- * output each) by one captured HIP graph: a persistent contraction in FP32
- * MFMA or split-BF16 MFMA (FP64 accumulation across contraction tiles, as the
- * single-problem modes) pulls (problem, 64-block tile) work items from
- * per-XCD queues.  Results are bitwise identical to sympix_sample_BtNB(...,
- * prec, ...) per problem, under every schedule. */
+ * output each) by one captured HIP graph: a persistent contraction in FP64
+ * MFMA, FP32 MFMA or split-BF16 MFMA (the latter two with FP64 accumulation
+ * across contraction tiles, as the single-problem modes) pulls (problem,
+ * 64-block tile) work items from per-XCD queues.  Results are bitwise
+ * identical to sympix_sample_BtNB(..., prec, ...) per problem, under every
+ * schedule and tile shape. */
 typedef struct sympix_batch sympix_batch;
 
 typedef struct {
     const sympix_grid *g;
     const sympix_kernel *b;   /* beam kernel tabulated for g */
-    const double *ninv_dev;   /* device, float64, npix values, 8-byte aligned */
+    const double *ninv_dev;   /* device, float64, npix values, 8-byte aligned (32-byte for SYMPIX_FP64) */
     int64_t ninv_len;         /* must be npix */
     double *out_dev;          /* device, float64, nblocks k^4 values, 16-byte aligned */
     int64_t out_len;          /* must be nblocks k^4 */
@@ -270,23 +286,28 @@ typedef enum {
 
 /* Build a batch over problems p[0..n) (copied; the buffers they point to must
  * stay allocated, and the grids and kernels alive, until the batch is
- * destroyed) and capture its graph with the default schedule.  prec:
- * SYMPIX_FP32, SYMPIX_BF16X3 or SYMPIX_BF16X6.  The batch owns its device
- * tables and its N^-1 operand scratch (4 npix bytes per problem in FP32, 6 in
- * the split-BF16 modes).  stream: the call synchronises it once while
- * uploading tables.
+ * destroyed) and capture its graph with the default schedule (or the plan the
+ * tuner chose earlier in this process for the same problems and mode).  prec:
+ * any sympix_precision.  The batch owns its device tables and its N^-1
+ * operand scratch (none in FP64, which reads N^-1 directly; 4 npix bytes per
+ * problem in FP32, 6 in the split-BF16 modes).  stream: the call synchronises
+ * it once while uploading tables.
  * Errors: EINVAL (NULL, n < 1, misaligned or overlapping outputs, problems on
- * another device), ESIZE (a length mismatch), EUNSUPPORTED (prec SYMPIX_FP64,
- * k != 8), ENOMEM, EHIP. */
+ * another device, unknown prec), ESIZE (a length mismatch), EUNSUPPORTED
+ * (k != 8), ENOMEM, EHIP. */
 sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t prec, void *stream,
                                   sympix_batch **out);
 
 /* Re-capture the batch's graph with schedule s (a sympix_schedule), keeping
- * its tile shape. */
+ * its tile shape.  Re-capturing rewrites the batch's work-item tables, so the
+ * call first waits on the host for the batch's last launch (on any stream) to
+ * complete; a launch made on another thread while this call runs is not
+ * allowed. */
 sympix_status sympix_batch_set_schedule(sympix_batch *bt, int32_t s);
 
 /* Re-capture the batch's graph with tile shape t (a sympix_tiling), keeping
- * its schedule. */
+ * its schedule.  Waits for the batch's last launch as
+ * sympix_batch_set_schedule does. */
 sympix_status sympix_batch_set_tiling(sympix_batch *bt, int32_t t);
 
 /* Autotune: time one launch of every plan (schedule and tile shape) on stream
@@ -294,12 +315,14 @@ sympix_status sympix_batch_set_tiling(sympix_batch *bt, int32_t t);
  * fastest and report its plan in *chosen and the times in
  * ms_out[SYMPIX_NSCHED * SYMPIX_NTILINGS], indexed by plan (either may be
  * NULL).  The choice is remembered for batches of the same problems and mode
- * in this process. */
+ * in this process.  Each re-capture first waits for the batch's previous
+ * launch, so the call may follow sympix_batch_launch on any stream. */
 sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen, double *ms_out);
 
 /* Enqueue the batch's graph on stream: converts every N^-1 to the operand
- * format (FP32, or BF16 parts) and writes every output.  Launches on one device must not overlap in time (they share
- * the batch's queue counters and scratch). */
+ * format (FP32, or BF16 parts; FP64 reads it as given) and writes every
+ * output.  Launches of one batch must not overlap in time (they share its
+ * queue counters and scratch): launch it on one stream, or order the streams. */
 sympix_status sympix_batch_launch(sympix_batch *bt, void *stream);
 
 /* Free a batch. NULL is ignored.  No launch of it may be in flight. */

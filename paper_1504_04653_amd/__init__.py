@@ -69,6 +69,7 @@ _grid_destroy = _sig("sympix_grid_destroy", [_vp], None)
 _grid_dims = _sig("sympix_grid_dims", [_vp, ctypes.POINTER(Dims)])
 _grid_rings = _sig("sympix_grid_rings", [_vp, _vp, _vp, _vp, _vp])
 _grid_bands = _sig("sympix_grid_bands", [_vp, _vp, _vp, _vp])
+_grid_pixels = _sig("sympix_grid_pixels", [_vp, _vp, _vp])
 _grid_neighbours = _sig("sympix_grid_neighbours", [_vp, _vp, _vp])
 _grid_blocks = _sig("sympix_grid_blocks", [_vp, _vp, _vp])
 _grid_pattern_blocks = _sig("sympix_grid_pattern_blocks", [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
@@ -110,7 +111,7 @@ def plan_name(plan):
     return f"{sched}/{tiling}"
 
 EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sympix_grid_rings",
-            "sympix_grid_bands", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_pattern_blocks", "sympix_grid_unique",
+            "sympix_grid_bands", "sympix_grid_pixels", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_pattern_blocks", "sympix_grid_unique",
             "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
             "sympix_sample_BtNB", "sympix_sample_BtNB_pattern", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
             "sympix_batch_launch", "sympix_batch_destroy", "sympix_last_error")
@@ -235,18 +236,10 @@ class Grid:
         return uid, bi, bj, de
 
     def pixel_theta_phi(self):
-        """Colatitude and longitude of every pixel in pixel order (host arrays),
-        from the ring tables and the Section 2.4 layout."""
-        theta, _, npix_ring, first = self.rings()
-        k = self.k
+        """Colatitude and longitude of every pixel in pixel order (host arrays)."""
         th = np.empty(self.npix)
         ph = np.empty(self.npix)
-        for j in range(self.nrings):
-            n = int(npix_ring[j])
-            p = np.arange(n)
-            idx = first[j] + (p // k) * k * k + (p % k) * k
-            th[idx] = theta[j]
-            ph[idx] = 2.0 * np.pi * (p + 0.5) / n
+        _check(_grid_pixels(self._h, _ptr(th), _ptr(ph)))
         return th, ph
 
     @property
@@ -341,7 +334,7 @@ def raw_call(name):
 
 
 class Batch:
-    """Many B-hat^T N^-1 B-hat problems (FP32 or split-BF16 mode) in one captured graph.
+    """Many B-hat^T N^-1 B-hat problems (any precision mode) in one captured graph.
 
     problems: sequence of (grid, kernel, ninv, out) with ninv / out contiguous
     float64 CUDA tensors.  The batch keeps references to all of them."""

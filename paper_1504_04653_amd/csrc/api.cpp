@@ -25,6 +25,8 @@ namespace {
 
 thread_local std::string g_last_error;
 
+constexpr double kPi = 3.14159265358979323846;
+
 sympix_status fail(sympix_status s, const std::string &msg) {
     g_last_error = msg;
     return s;
@@ -470,6 +472,25 @@ sympix_status sympix_grid_bands(const sympix_grid *g, int32_t *tiles, int32_t *a
     return SYMPIX_OK;
 }
 
+sympix_status sympix_grid_pixels(const sympix_grid *g, double *theta, double *phi) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const Geometry &s = g->geo;
+    const int64_t k = s.k;
+    for (size_t b = 0; b < s.band_tiles.size(); ++b) {
+        const int64_t n = k * s.band_tiles[b];          // pixels on each ring of the band
+        const int64_t pix0 = s.band_tile0[b] * k * k;
+        for (int64_t r = 0; r < k; ++r) {
+            const double th = s.theta[s.band_ring0[b] + r];
+            for (int64_t p = 0; p < n; ++p) {
+                const int64_t idx = pix0 + (p / k) * k * k + (p % k) * k + r;   // tile, column, ring
+                if (theta) theta[idx] = th;
+                if (phi) phi[idx] = 2.0 * kPi * ((double)p + 0.5) / (double)n;
+            }
+        }
+    }
+    return SYMPIX_OK;
+}
+
 sympix_status sympix_grid_neighbours(const sympix_grid *g, int64_t *row_ptr, int32_t *col) {
     if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
     const Geometry &s = g->geo;
@@ -689,6 +710,7 @@ struct sympix_batch {
     int32_t nworkgroups = 0;
     // per tile shape (sympix_tiling): problem descriptors, tile counts, work
     // items in natural order
+    std::vector<sympix::ProblemDesc64> hdesc64[SYMPIX_NTILINGS]; // FP64
     std::vector<sympix::ProblemDesc> hdesc[SYMPIX_NTILINGS];     // FP32
     std::vector<sympix::ProblemDescB> hdescb[SYMPIX_NTILINGS];   // split BF16
     std::vector<int64_t> nmtiles[SYMPIX_NTILINGS];
@@ -696,6 +718,7 @@ struct sympix_batch {
     std::vector<uint16_t *> wsplit;                // split BF16: 3 N^-1 parts per problem
     std::vector<const double *> ninv;
     std::vector<int64_t> npix;
+    sympix::ProblemDesc64 *d_desc64[SYMPIX_NTILINGS] = {};
     sympix::ProblemDesc *d_desc[SYMPIX_NTILINGS] = {};
     int32_t *d_items = nullptr;
     int32_t *d_qb = nullptr;
@@ -704,6 +727,8 @@ struct sympix_batch {
     sympix::ProblemDescB *d_descb[SYMPIX_NTILINGS] = {};
     uint16_t *d_wsplit = nullptr;
     hipStream_t cap = nullptr;
+    hipEvent_t done = nullptr;          // recorded after every launch of the graph
+    bool launched = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string shape;
@@ -720,7 +745,9 @@ void free_batch(sympix_batch *bt) {
     if (bt->exec) hipGraphExecDestroy(bt->exec);
     if (bt->graph) hipGraphDestroy(bt->graph);
     if (bt->cap) hipStreamDestroy(bt->cap);
+    if (bt->done) hipEventDestroy(bt->done);
     for (int t = 0; t < SYMPIX_NTILINGS; ++t) {
+        hipFree(bt->d_desc64[t]);
         hipFree(bt->d_desc[t]);
         hipFree(bt->d_descb[t]);
     }
@@ -735,6 +762,14 @@ void free_batch(sympix_batch *bt) {
 // Order the work items of tile shape t and bound the queues for schedule s,
 // then capture the batch's launches into a fresh graph.
 sympix_status capture_batch(sympix_batch *bt, int32_t s, int32_t t) {
+    // the tables below are rewritten with blocking copies on the null stream,
+    // which do not wait for a launch on a non-blocking stream: wait for the
+    // batch's last launch first, whichever stream it was queued on
+    if (bt->launched) {
+        hipError_t ew = hipEventSynchronize(bt->done);
+        if (ew != hipSuccess) return hip_fail(ew, "waiting for the batch's last launch");
+        bt->launched = false;
+    }
     const std::vector<int32_t> &item_prob = bt->item_prob[t], &item_tile = bt->item_tile[t],
                                &item_cost = bt->item_cost[t];
     const int64_t nitems = (int64_t)item_prob.size();
@@ -777,6 +812,8 @@ sympix_status capture_batch(sympix_batch *bt, int32_t s, int32_t t) {
     sympix::BatchLaunch bl;
     bl.nprob = bt->nprob;
     bl.prec = bt->prec;
+    bl.host_desc64 = bt->hdesc64[t].data();
+    bl.desc64 = bt->d_desc64[t];
     bl.host_desc = bt->hdesc[t].data();
     bl.host_descb = bt->hdescb[t].data();
     bl.wsplit = bt->wsplit.data();
@@ -824,8 +861,8 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!p || n < 1) return fail(SYMPIX_EINVAL, "need at least one problem");
-    if (prec != SYMPIX_FP32 && prec != SYMPIX_BF16X3 && prec != SYMPIX_BF16X6)
-        return fail(SYMPIX_EUNSUPPORTED, "batches run in SYMPIX_FP32, SYMPIX_BF16X3 or SYMPIX_BF16X6");
+    if (prec < SYMPIX_FP64 || prec > SYMPIX_BF16X6) return fail(SYMPIX_EINVAL, "unknown precision mode");
+    const size_t ninv_align = prec == SYMPIX_FP64 ? 32 : 8;   // FP64 loads N^-1 in 32-byte vectors
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int32_t i = 0; i < n; ++i) {
         sympix_status s = check_kernel_use(p[i].g, p[i].b);
@@ -837,9 +874,9 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
             return fail(SYMPIX_ESIZE, "problem " + std::to_string(i) + ": out_len must be nblocks * k^4");
         if ((geo.npix > 0 && !p[i].ninv_dev) || (p[i].out_len > 0 && !p[i].out_dev))
             return fail(SYMPIX_EINVAL, "problem " + std::to_string(i) + ": NULL device buffer");
-        if (((uintptr_t)p[i].out_dev) % 16 || ((uintptr_t)p[i].ninv_dev) % 8)
-            return fail(SYMPIX_EINVAL, "problem " + std::to_string(i) +
-                                           ": out_dev must be 16-byte and ninv_dev 8-byte aligned");
+        if (((uintptr_t)p[i].out_dev) % 16 || ((uintptr_t)p[i].ninv_dev) % ninv_align)
+            return fail(SYMPIX_EINVAL, "problem " + std::to_string(i) + ": out_dev must be 16-byte and ninv_dev " +
+                                           std::to_string(ninv_align) + "-byte aligned");
         if (geo.cls.max_class_terms > sympix::kMaxClassTerms)
             return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
         if (p[i].out_len > 0)
@@ -854,7 +891,8 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     bt->device = p[0].b->device;
     bt->nprob = n;
     bt->prec = prec;
-    const bool bf16 = prec != SYMPIX_FP32;
+    const bool f64 = prec == SYMPIX_FP64;
+    const bool bf16 = prec == SYMPIX_BF16X3 || prec == SYMPIX_BF16X6;
     hipError_t e = hipSuccess;
     int64_t wf_total = 0;
     std::string shape;
@@ -865,7 +903,8 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
             free_batch(bt);
             return hip_fail(e, "hipGetDeviceProperties");
         }
-        shape = std::string(prop.gcnArchName) + (bf16 ? (prec == SYMPIX_BF16X3 ? "|bf16x3" : "|bf16x6") : "|fp32");
+        static const char *mode_name[] = {"|fp64", "|fp32", "|bf16x3", "|bf16x6"};
+        shape = std::string(prop.gcnArchName) + mode_name[prec];
         int occ = 0;
         e = sympix::batch_occupancy(prec, &occ);
         if (e != hipSuccess) {
@@ -885,6 +924,9 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
         for (int t = 0; t < SYMPIX_NTILINGS; ++t) {
             const int32_t *dtiles = t == SYMPIX_TILES_64 ? dg->mtiles : dg->mtiles32;
             const std::vector<int32_t> &tiles = t == SYMPIX_TILES_64 ? geo.cls.mtiles : geo.cls.mtiles32;
+            sympix::ProblemDesc64 d64{dtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
+                                      p[i].b->u64t, p[i].ninv_dev, p[i].out_dev, nullptr, nullptr, nullptr};
+            bt->hdesc64[t].push_back(d64);
             sympix::ProblemDesc d{dtiles, dg->classes, dg->class_terms, dg->class_blk, dg->class_itab,
                                   p[i].b->ut32, nullptr, p[i].out_dev, nullptr, nullptr, nullptr};
             bt->hdesc[t].push_back(d);
@@ -911,7 +953,8 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
         return fail(SYMPIX_ESIZE, "too many work items for one batch");
     }
     for (int t = 0; t < SYMPIX_NTILINGS && e == hipSuccess; ++t) {
-        e = hipMalloc((void **)&bt->d_desc[t], n * sizeof(sympix::ProblemDesc));
+        if (f64) e = hipMalloc((void **)&bt->d_desc64[t], n * sizeof(sympix::ProblemDesc64));
+        else e = hipMalloc((void **)&bt->d_desc[t], n * sizeof(sympix::ProblemDesc));
         if (e == hipSuccess && bf16) e = hipMalloc((void **)&bt->d_descb[t], n * sizeof(sympix::ProblemDescB));
     }
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_items, std::max<int64_t>(1, 2 * nitems) * sizeof(int32_t));
@@ -920,7 +963,7 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     if (bf16) {
         if (e == hipSuccess)
             e = hipMalloc((void **)&bt->d_wsplit, std::max<int64_t>(1, 3 * wf_total) * sizeof(uint16_t));
-    } else if (e == hipSuccess) {
+    } else if (!f64 && e == hipSuccess) {
         e = hipMalloc((void **)&bt->d_wf, std::max<int64_t>(1, wf_total) * sizeof(float));
     }
     if (e != hipSuccess) {
@@ -934,19 +977,24 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
         for (int t = 0; t < SYMPIX_NTILINGS; ++t) {
             if (bf16)
                 for (int k = 0; k < 3; ++k) bt->hdescb[t][i].w[k] = bt->wsplit[3 * i + k];
-            else
+            else if (!f64)
                 bt->hdesc[t][i].wf = bt->d_wf + off;
         }
         off += bt->npix[i];
     }
     for (int t = 0; t < SYMPIX_NTILINGS && e == hipSuccess; ++t) {
-        e = hipMemcpy(bt->d_desc[t], bt->hdesc[t].data(), n * sizeof(sympix::ProblemDesc), hipMemcpyHostToDevice);
+        if (f64)
+            e = hipMemcpy(bt->d_desc64[t], bt->hdesc64[t].data(), n * sizeof(sympix::ProblemDesc64),
+                          hipMemcpyHostToDevice);
+        else
+            e = hipMemcpy(bt->d_desc[t], bt->hdesc[t].data(), n * sizeof(sympix::ProblemDesc), hipMemcpyHostToDevice);
         if (e == hipSuccess && bf16)
             e = hipMemcpy(bt->d_descb[t], bt->hdescb[t].data(), n * sizeof(sympix::ProblemDescB),
                           hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->done, hipEventDisableTiming);
     if (e != hipSuccess) {
         free_batch(bt);
         return hip_fail(e, "batch set-up");
@@ -985,7 +1033,10 @@ sympix_status sympix_batch_launch(sympix_batch *bt, void *stream) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev != bt->device) return fail(SYMPIX_EINVAL, "batch lives on another device than the current one");
     hipStream_t st = (hipStream_t)stream;
-    return after_launch(hipGraphLaunch(bt->exec, st), st, "batch launch");
+    e = hipGraphLaunch(bt->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(bt->done, st);
+    if (e == hipSuccess) bt->launched = true;
+    return after_launch(e, st, "batch launch");
 }
 
 sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen, double *ms_out) {
@@ -1008,6 +1059,8 @@ sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen,
         if (e == hipSuccess) e = hipEventRecord(e0, st);
         if (e == hipSuccess) e = hipGraphLaunch(bt->exec, st);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventRecord(bt->done, st);
+        if (e == hipSuccess) bt->launched = true;
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);

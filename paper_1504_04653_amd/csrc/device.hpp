@@ -113,14 +113,17 @@ struct ProblemDesc {
     double *outD;             // D-hat output, or nullptr
 };
 
-// a10: one batched launch.  host_desc / host_descb / ninv / npix / nmtiles /
-// wsplit are host arrays of nprob entries (wsplit: 3 per problem); desc,
-// descb, items, qb and counters live on the device.  prec: 1 FP32 (desc,
+// a10: one batched launch.  host_desc / host_descb / host_desc64 / ninv /
+// npix / nmtiles / wsplit are host arrays of nprob entries (wsplit: 3 per
+// problem); desc, descb, desc64, items, qb and counters live on the device.
+// prec: 0 FP64 (desc64, host_desc64; N^-1 read as given), 1 FP32 (desc,
 // host_desc), 2 or 3 split BF16 with that many parts (descb, host_descb, and
 // the N^-1 parts in wsplit).
 struct BatchLaunch {
     int32_t nprob;
     int32_t prec;
+    const ProblemDesc64 *host_desc64;
+    const ProblemDesc64 *desc64;
     const ProblemDesc *host_desc;
     const ProblemDescB *host_descb;
     uint16_t *const *wsplit;

@@ -14,8 +14,9 @@
 //   k_ninv_f32     N^-1 rounded to FP32
 //   k_class_f32    FP32-MFMA contraction as one GEMM per class of blocks that
 //                  share their contraction pattern, FP64 accumulation across tiles
-//   k_batch_f32    the FP32 class GEMM of many problems in one persistent
+//   k_batch_f64    the FP64 class GEMM of many problems in one persistent
 //                  launch fed by per-XCD work queues
+//   k_batch_f32    the same in FP32
 //   k_split_ninv   N^-1 split into BF16 parts
 //   k_class_bf16   the same GEMM in split BF16
 //   k_batch_bf16   many problems in one persistent launch, split BF16
@@ -468,6 +469,51 @@ void k_class_f64(ProblemDesc64 pd) {
     else class_f64_tile<1, WD>(pd, item, sTile, sBlk, sTerm);
 }
 
+// Queue draining shared by the persistent batch kernels: thread 0 takes the
+// next item from queue home, then steals from the others in order; -1 once
+// every queue is empty.  Counters only grow, so every workgroup leaves.
+__device__ __forceinline__ int batch_next_item(const int32_t *__restrict__ qb, int32_t nq,
+                                               int32_t *__restrict__ counters, int home, int &tried) {
+    int it = -1;
+    while (tried < nq) {
+        const int q = (home + tried) % nq;
+        const int c = atomicAdd(&counters[q], 1);
+        if (c < qb[q + 1] - qb[q]) {
+            it = qb[q] + c;
+            break;
+        }
+        ++tried;
+    }
+    return it;
+}
+
+// a10 in FP64: the FP64 class GEMM of many problems in one persistent launch
+// (one 4-wave workgroup per CU, as k_class_f64), fed by the same queues as the
+// FP32 and split-BF16 batch kernels below.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_batch_f64(const ProblemDesc64 *__restrict__ probs, const int32_t *__restrict__ items,
+                 const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
+    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sBlk[128];
+    __shared__ int32_t sTerm[2 * kMaxClassTerms];
+    __shared__ int32_t sItem;
+    const int home = blockIdx.x % nq;
+    int tried = 0;                       // queues found empty (thread 0)
+    for (;;) {
+        if (threadIdx.x == 0) sItem = batch_next_item(qb, nq, counters, home, tried);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(sItem);   // uniform: descriptors in scalar registers
+        __syncthreads();                 // every thread has read sItem before it changes
+        if (it < 0) break;
+        const ProblemDesc64 pd = probs[items[2 * it]];
+        const int item = items[2 * it + 1];
+        const int groups = pd.mtiles[4 * item + 2];
+        if (groups == 4) class_f64_tile<4, false>(pd, item, sTile, sBlk, sTerm);
+        else if (groups == 2) class_f64_tile<2, false>(pd, item, sTile, sBlk, sTerm);
+        else class_f64_tile<1, false>(pd, item, sTile, sBlk, sTerm);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a9, FP32 MFMA class GEMM.  Same decomposition as the split-BF16 form below:
 // C[m][(a,b)] = sum_(e,p) W[m][(e,p)] M[(e,p)][(a,b)], W = N^-1 rounded to FP32,
@@ -731,19 +777,7 @@ void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restric
     const int home = blockIdx.x % nq;
     int tried = 0;                       // queues found empty (thread 0)
     for (;;) {
-        if (threadIdx.x == 0) {
-            int it = -1;
-            while (tried < nq) {
-                const int q = (home + tried) % nq;
-                const int c = atomicAdd(&counters[q], 1);
-                if (c < qb[q + 1] - qb[q]) {
-                    it = qb[q] + c;
-                    break;
-                }
-                ++tried;
-            }
-            sItem = it;
-        }
+        if (threadIdx.x == 0) sItem = batch_next_item(qb, nq, counters, home, tried);
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(sItem);   // uniform: descriptors in scalar registers
         __syncthreads();                 // every thread has read sItem before it changes
@@ -1121,19 +1155,7 @@ void k_batch_bf16(const ProblemDescB *__restrict__ probs, const int32_t *__restr
     const int home = blockIdx.x % nq;
     int tried = 0;                       // queues found empty (thread 0)
     for (;;) {
-        if (threadIdx.x == 0) {
-            int it = -1;
-            while (tried < nq) {
-                const int q = (home + tried) % nq;
-                const int c = atomicAdd(&counters[q], 1);
-                if (c < qb[q + 1] - qb[q]) {
-                    it = qb[q] + c;
-                    break;
-                }
-                ++tried;
-            }
-            sItem = it;
-        }
+        if (threadIdx.x == 0) sItem = batch_next_item(qb, nq, counters, home, tried);
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(sItem);   // uniform: descriptors in scalar registers
         __syncthreads();                 // every thread has read sItem before it changes
@@ -1210,6 +1232,19 @@ hipError_t launch_btnb(int prec, const BtnbArgs &a, hipStream_t st) {
 
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.counters, b.nq, 0);
+    if (b.prec == 0) {                   // FP64: N^-1 is read as given
+        if (b.persistent) {
+            if (b.nitems > 0)
+                hipLaunchKernelGGL(k_batch_f64, dim3((unsigned)b.nworkgroups), dim3(256), 0, st, b.desc64, b.items,
+                                   b.qb, b.nq, b.counters);
+        } else {
+            for (int p = 0; p < b.nprob; ++p)
+                if (b.nmtiles[p] > 0)
+                    hipLaunchKernelGGL(k_class_f64<false>, dim3((unsigned)b.nmtiles[p]), dim3(256), 0, st,
+                                       b.host_desc64[p]);
+        }
+        return hipGetLastError();
+    }
     const bool bf16 = b.prec != 1;
     for (int p = 0; p < b.nprob; ++p) {
         if (b.npix[p] == 0) continue;
@@ -1247,6 +1282,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
 }
 
 hipError_t batch_occupancy(int prec, int *workgroups_per_cu) {
+    if (prec == 0) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f64, 256, 0);
     if (prec == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_f32, 512, 0);
     if (prec == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<2>, 512, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(workgroups_per_cu, k_batch_bf16<3>, 512, 0);

@@ -93,13 +93,19 @@ def test_pattern_max_separation(lmax, k, margin):
     assert abs(g.y_pattern_max - ymax) <= 1e-13 * ymax
 
 
-def test_pixel_coordinates_match_oracle():
-    og = G.make_grid(100, 8)
-    g = sp.Grid(100, 8)
+@pytest.mark.parametrize("lmax,k,margin", LAYOUT_CASES)
+def test_pixel_coordinates_match_oracle(lmax, k, margin):
+    """sympix_grid_pixels: every pixel on its ring's colatitude (the library's
+    own ring table) at phi = 2 pi (p + 1/2) / n, bit for bit the oracle's
+    layout (ring and ring-local index of every pixel)."""
+    og = G.make_grid(lmax, k, polar_margin=margin)
+    g = sp.Grid(lmax, k, margin)
     th, ph = g.pixel_theta_phi()
     ring, pin, nr, phi = og.pixel_coords()
-    assert np.array_equal(th, og.theta[ring])
-    assert np.allclose(ph, phi, rtol=0, atol=1e-15)
+    theta_lib = g.rings()[0]
+    assert np.array_equal(th, theta_lib[ring])
+    assert np.array_equal(ph, phi)
+    assert sp.raw_call("sympix_grid_pixels")(None, None, None) == -1
 
 
 def test_default_margin_and_dims():

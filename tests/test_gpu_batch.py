@@ -1,6 +1,6 @@
-"""GPU parity of batched launches: many B-hat^T N^-1 B-hat problems (FP32 or
-split-BF16 MFMA, FP64 accumulation across contraction tiles) in one captured
-graph.
+"""GPU parity of batched launches: many B-hat^T N^-1 B-hat problems (FP64,
+FP32 or split-BF16 MFMA; the latter two with FP64 accumulation across
+contraction tiles) in one captured graph.
 
 Every schedule must give results bitwise identical to the single-problem path
 of the same mode (each work item is computed by the same arithmetic whichever
@@ -24,8 +24,8 @@ from _parity import block_index, error_report, stored_pairs
 
 pytestmark = pytest.mark.gpu
 
-GATE = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 2.0 ** -15}
-BATCH_MODES = ["fp32", "bf16x6", "bf16x3"]
+GATE = {"fp64": 1e-10, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 2.0 ** -15}
+BATCH_MODES = ["fp64", "fp32", "bf16x6", "bf16x3"]
 
 # (lmax, problem index whose beam / mask draws are used): mixed sizes, with
 # two problems on one grid
@@ -140,12 +140,43 @@ def test_tune_picks_a_plan_and_keeps_results(small):
     launch_and_check(small, "after tune")
 
 
+def test_launch_then_retune_on_a_side_stream(small):
+    """A launch queued on a non-blocking stream, followed at once by a tile
+    shape change, a schedule change and a tune (each re-captures the graph
+    and rewrites the work-item tables): the re-capture waits for the launch,
+    and every result stays bitwise equal to the single-problem path."""
+    side = torch.cuda.Stream()
+    for p in small["probs"]:
+        p["out"].fill_(float("nan"))
+    torch.cuda.synchronize()
+    small["bt"].set_tiling("tiles64")
+    small["bt"].set_schedule("xcd_queues")
+    small["bt"].launch(side)
+    small["bt"].set_tiling("tiles32")           # no host synchronisation in between
+    small["bt"].launch(side)
+    small["bt"].set_schedule("global_lpt")
+    small["bt"].launch(side)
+    small["bt"].tune(side)
+    side.synchronize()
+    for i, (p, r) in enumerate(zip(small["probs"], small["ref"])):
+        assert torch.equal(p["out"], r), f"problem {i} differs after launch-then-retune on a side stream"
+    launch_and_check(small, "after retune")
+    say(f"[batch {small['prec']}] launch / re-capture / tune on a side stream: results unchanged")
+
+
 def test_batch_argument_errors(small):
     p = small["probs"][0]
     q = small["probs"][2]                   # same grid as p
     with pytest.raises(sp.SympixError) as ei:
-        sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"])], prec="fp64")
-    assert ei.value.code == "EUNSUPPORTED"
+        sp.Batch([(p["g"], p["kb"], p["ninv_dev"], p["out"])], prec=7)
+    assert ei.value.code == "EINVAL"
+    buf = torch.zeros(p["g"].npix + 8, dtype=torch.float64, device="cuda")
+    off = 1 if (buf.data_ptr() // 8) % 4 == 0 else 0          # an 8-byte but not 32-byte aligned view
+    misaligned = buf[off:off + p["g"].npix]
+    assert misaligned.data_ptr() % 32 != 0
+    with pytest.raises(sp.SympixError) as ei:                  # FP64 reads N^-1 in 32-byte vectors
+        sp.Batch([(p["g"], p["kb"], misaligned, p["out"])], prec="fp64")
+    assert ei.value.code == "EINVAL"
     short = torch.empty(p["g"].out_len - 1, dtype=torch.float64, device="cuda")
     with pytest.raises(sp.SympixError) as ei:
         sp.Batch([(p["g"], p["kb"], p["ninv_dev"], short)])
@@ -177,7 +208,7 @@ def c5_rows(og, seed):
     return sorted(rows)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "fp64"])
 def test_c5_full_batch_sampled(prec):
     spec = [(S.BATCH_LMAX[p % 4], p) for p in range(32)]
     probs = make_problems(spec)

@@ -104,7 +104,7 @@ def test_fused_full_size_against_oracle_and_separate_calls():
     Cref = np.stack([O.btnb_block(op, ninv, J, K) for J, K in pairs])
     Dref = O.sample_D(og, d_l, None, pairs)
     say(f"[fused lmax3000] npix={g.npix} nblocks={g.nblocks} sampled rows={len(rows)} blocks={len(idx)}")
-    for prec in ("bf16x6", "fp32"):
+    for prec in MODES:
         D1, C1 = fused(g, kd, kb, n_dev, prec)
         rep_c = error_report(C1.view(-1, 64, 64)[idx_t].cpu().numpy(), Cref, jrow)
         rep_d = error_report(D1.view(-1, 64, 64)[idx_t].cpu().numpy(), Dref, jrow)

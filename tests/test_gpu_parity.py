@@ -91,6 +91,32 @@ def test_lmax64_kernel_table_interpolation(lmax64):
         assert err <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["lmax512", "lmax1500", "lmax3000"])
+def test_kernel_table_interpolation_full_size(name):
+    """The 2^16-node table of the beam and of the prior d_l = (l+1)^2 (which
+    oscillates fastest at high lmax) against the oracle's direct Legendre sum
+    in y, at random y over the whole table domain and near y = 0: <= 1e-13 of
+    the kernel's peak."""
+    cfg = S.CONFIGS[name]
+    g = sp.Grid(cfg.lmax, cfg.k)
+    b_l, R = S.gaussian_beam(cfg.lmax, g.npix, cfg.fwhm_pix)
+    rng = np.random.default_rng(cfg.seed + 5)
+    for kname, coef, rad in (("beam", b_l, R), ("prior", S.prior(cfg.lmax), None)):
+        kern = sp.Kernel(g, coef, 0.0 if rad is None else rad)
+        ydom = g.y_pattern_max if rad is None else min(g.y_pattern_max, 2 * math.sin(rad / 2) ** 2)
+        y = np.concatenate([[0.0], rng.uniform(0, ydom, 1500), ydom * rng.uniform(0, 1e-3, 100),
+                            ydom * (1.0 - rng.uniform(0, 1e-3, 20))])
+        out = torch.empty(y.size, dtype=torch.float64, device="cuda")
+        kern.eval(dev(y), out)
+        torch.cuda.synchronize()
+        ref = OK.legendre_series_in_y(coef, y)
+        peak = abs(OK.legendre_series_in_y(coef, np.array([0.0]))[0])
+        err = np.abs(out.cpu().numpy() - ref).max() / peak
+        say(f"[{name}] table {kname}: max err / peak = {err:.3e} over {y.size} points")
+        assert err <= 1e-13
+        del kern
+
+
 def test_lmax64_D_and_B_blocks(lmax64):
     og, g, pairs, rows = lmax64["og"], lmax64["g"], lmax64["pairs"], lmax64["rows"]
     D = run_D(g, lmax64["kd"]).cpu().numpy()
@@ -204,7 +230,7 @@ def test_transition_grid_all_blocks():
     say(f"[t256] npix={g.npix} nblocks={g.nblocks} tiles={og.tiles_north[:8]}")
     kb = sp.Kernel(g, b_l, R)
     Cref = O.sample_BtNB(og, b_l, ninv, R, pairs)
-    for prec in ("fp64", "fp32", "bf16x6"):
+    for prec in ("fp64", "fp32", "bf16x6", "bf16x3"):
         C = run_BtNB(g, kb, dev(ninv), prec).cpu().numpy()
         rep = error_report(C, Cref, rows)
         say(f"[t256] BtNB {prec}: {rep}")
