@@ -6,14 +6,18 @@ per band (Fig. 3, Eqs. 4-5, Section 2.5), the memory layout of Section 2.4 and
 the neighbouring-tile relation of Section 2.2.
 
 Where the paper is ambiguous the reading used is a field of ``Readings``; the
-defaults are the readings the build uses.  No combination of the readings
-reproduces the SymPix pixel counts printed in Table 1 (the nearest values are
-recorded in tests/golden/table1_npix.txt), so the defaults follow Fig. 3
-literally, except that band 1 may differ from band 0 as the caption of Fig. 3
-allows.  The tile-count optimisation is therefore "parity unpinned" against
-Table 1; it is pinned instead by a closed form (every band at the same count
-when Eq. 3 never holds), by brute force with the run rule switched off, and by
-the structural rules of Section 2.3.
+defaults are the readings the build uses.  No combination of the readings, at
+any margin of Eq. 3 in [-30, 120], reproduces the SymPix pixel counts printed
+in Table 1: tests/golden/make_grid_readings.py (which calls only this module)
+records every reading's sizes next to the printed ones in
+tests/golden/table1_npix.txt.  With the paper's margin, 2 k^2 sum(alpha_i)
+alone exceeds each printed count, so no tile programme over these alpha can
+reach them.  The defaults follow Fig. 3 literally, except that band 1 may
+differ from band 0 as the caption of Fig. 3 allows (taken literally, the
+sentinel makes every printed case infeasible).  The tile-count optimisation is
+therefore "parity unpinned" against Table 1; it is pinned instead by a closed
+form (every band at the same count when Eq. 3 never holds), by brute force
+with the run rule switched off, and by the structural rules of Section 2.3.
 """
 from __future__ import annotations
 
