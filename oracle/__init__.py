@@ -15,6 +15,8 @@ kernel     the Legendre-series kernel of Eq. 10, evaluated by direct sum.
 operators  pair geometry, the local blocks of D-hat and B-hat (Eq. 16 and
            the tile truncation of Section 4.2), and the blockwise product
            B-hat^T N^-1 B-hat (Eq. 15).
+twogrid    B-hat = Y_2 B Y_1^T between an auxiliary grid and the grid of the
+           unknowns (Eqs. 13 and 16) and its B-hat^T N_2^-1 B-hat.
 brute      pattern-level brute force without any symmetry reuse (tests only).
 
 Every function is plain and slow on purpose: the point is that a reader can

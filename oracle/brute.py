@@ -63,3 +63,54 @@ def extract_blocks(M, g: Grid, pairs):
     for n, (J, K) in enumerate(pairs):
         out[n] = M[J * k2:(J + 1) * k2, K * k2:(K + 1) * k2].toarray()
     return out
+
+
+# ---------------------------------------------------------------------------
+# Two grids (Eqs. 13 and 16): B-hat = Y_2 B Y_1^T element by element
+# ---------------------------------------------------------------------------
+
+def tile_rectangles(g: Grid):
+    """Per tile, its closed rectangle in units of (pi, one turn):
+    [theta_lo, theta_hi, phi_lo, phi_hi], in floating point (each end is a
+    correctly rounded ratio of small integers, so equal ratios give equal
+    values)."""
+    rect = np.zeros((g.ntiles, 4))
+    n, k, R = g.nbands_hemi, g.k, g.nrings
+    for b in range(len(g.band_tiles)):
+        i, south = divmod(b, 2)
+        lo, hi = (i * k / R, (i + 1) * k / R) if not south else ((R - (i + 1) * k) / R, (R - i * k) / R)
+        T = g.band_tiles[b]
+        for t in range(T):
+            rect[g.band_tile0[b] + t] = (lo, hi, t / T, (t + 1) / T)
+    return rect
+
+
+def cross_relation_dense(g2: Grid, g1: Grid):
+    """Boolean ntiles_2 x ntiles_1 matrix: tile rectangles meet (phi modulo one
+    turn), tested on every pair in floating point."""
+    r2 = tile_rectangles(g2)[:, None, :]
+    r1 = tile_rectangles(g1)[None, :, :]
+    th = (r2[..., 0] <= r1[..., 1]) & (r1[..., 0] <= r2[..., 1])
+    ph = np.zeros(th.shape, dtype=bool)
+    for s in (-1.0, 0.0, 1.0):
+        ph |= (r2[..., 2] + s <= r1[..., 3]) & (r1[..., 2] <= r2[..., 3] + s)
+    return th & ph
+
+
+def cross_operator_dense(g2: Grid, g1: Grid, coef_l, radius=None):
+    """Dense Npix_2 x Npix_1 B-hat: every element evaluated directly from 3-D
+    unit vectors, kept where the two pixels' tiles meet (and within radius);
+    the kernel sums l <= min(lmax_1, lmax_2)."""
+    L = min(g1.lmax, g2.lmax)
+    coef = np.zeros(L + 1)
+    c = np.asarray(coef_l, dtype=np.float64)[:L + 1]
+    coef[:c.size] = c
+    v2, v1 = unit_vectors(g2), unit_vectors(g1)
+    diff = v2[:, None, :] - v1[None, :, :]
+    y = 0.5 * np.einsum("ijk,ijk->ij", diff, diff)
+    val = legendre_series_in_y(coef, y.ravel()).reshape(y.shape)
+    rel = cross_relation_dense(g2, g1)
+    keep = np.repeat(np.repeat(rel, g2.k ** 2, axis=0), g1.k ** 2, axis=1)
+    if radius is not None and radius > 0:
+        keep &= y <= 2.0 * np.sin(0.5 * radius) ** 2
+    return np.where(keep, val, 0.0)

@@ -55,6 +55,12 @@ def tile_pixel_geometry(g: Grid, tile: int):
 def pair_y(g: Grid, ring1, p1, n1, ring2, p2, n2):
     """y = 1 - cos(gamma) for pixel pairs given by (ring, ring-local index, ring
     length); all integer arrays broadcast together."""
+    return pair_y_two(g, ring1, p1, n1, g, ring2, p2, n2)
+
+
+def pair_y_two(g1: Grid, ring1, p1, n1, g2: Grid, ring2, p2, n2):
+    """The same with the first pixel of each pair on grid g1 and the second on
+    grid g2 (the rings' colatitudes come from each pixel's own grid)."""
     ring1, p1, n1, ring2, p2, n2 = np.broadcast_arrays(
         *(np.asarray(v, dtype=np.int64) for v in (ring1, p1, n1, ring2, p2, n2)))
     M = n1 * n2
@@ -62,10 +68,10 @@ def pair_y(g: Grid, ring1, p1, n1, ring2, p2, n2):
     N = np.mod(N, 2 * M)
     N = np.where(N > M, N - 2 * M, N)
     dphi = np.pi * N.astype(np.float64) / M.astype(np.float64)
-    th1 = g.theta[ring1]
-    th2 = g.theta[ring2]
-    s1 = g.sin_theta[ring1]
-    s2 = g.sin_theta[ring2]
+    th1 = g1.theta[ring1]
+    th2 = g2.theta[ring2]
+    s1 = g1.sin_theta[ring1]
+    s2 = g2.sin_theta[ring2]
     return 2.0 * (np.sin(0.5 * (th1 - th2)) ** 2 + s1 * s2 * np.sin(0.5 * dphi) ** 2)
 
 
