@@ -223,6 +223,29 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
                                  int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
                                  void *stream);
 
+/* sympix_sample_BtNB without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The same arguments, kernels and results
+ * (bitwise equal to sympix_sample_BtNB in every mode); the N^-1 operand
+ * scratch of the FP32 and split-BF16 modes is a static device array of the
+ * library (96 MiB per device, held until the process ends) instead of a
+ * stream-ordered allocation, and FP64 needs none.
+ * Limits and rules:
+ *   - FP32 / BF16X3 / BF16X6: npix <= 16777216 (2^24; lmax 3000 at k = 8 has
+ *     13,038,976), else ESIZE.  FP64: any size.
+ *   - The grid's device tables must already exist on the current device
+ *     (they do once a kernel of this grid has been tabulated there).
+ *   - Every allocation-free call on a device shares that device's array:
+ *     calls whose launches overlap in time on one device race and give
+ *     undefined results; order them on one stream (or with events).  The
+ *     array keeps the last call's contents; each call rewrites the part it
+ *     reads before reading it.
+ * Errors: as sympix_sample_BtNB, plus ESIZE for a grid beyond the limit and
+ * EINVAL when the grid's tables are not on the device. */
+sympix_status sympix_sample_BtNB_noalloc(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
+                                         int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
+                                         void *stream);
+
 /* B-hat^T N^-1 B-hat (Eq. 15) on the blocks of a sympix_pattern, in its
  * stored-block order; out_len = that pattern's nblocks k^4.  The two-hop
  * blocks (J, K) not in the one-hop pattern have the terms I in nbr(J) and

@@ -80,6 +80,7 @@ _kernel_destroy = _sig("sympix_kernel_destroy", [_vp], None)
 _kernel_eval = _sig("sympix_kernel_eval", [_vp, _vp, _vp, _i64, _vp])
 _sample_D = _sig("sympix_sample_D", [_vp, _vp, _vp, _i64, _vp])
 _sample_BtNB = _sig("sympix_sample_BtNB", [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp])
+_sample_BtNB_noalloc = _sig("sympix_sample_BtNB_noalloc", [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp])
 _sample_BtNB_pattern = _sig("sympix_sample_BtNB_pattern", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _i64, _vp])
 _sample_D_BtNB = _sig("sympix_sample_D_BtNB", [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp, _i64, _vp])
 _convolve = _sig("sympix_convolve", [_vp, _vp, _vp, _i64, _vp, _i64, _vp])
@@ -113,7 +114,7 @@ def plan_name(plan):
 EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sympix_grid_rings",
             "sympix_grid_bands", "sympix_grid_pixels", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_pattern_blocks", "sympix_grid_unique",
             "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
-            "sympix_sample_BtNB", "sympix_sample_BtNB_pattern", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
+            "sympix_sample_BtNB", "sympix_sample_BtNB_noalloc", "sympix_sample_BtNB_pattern", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
             "sympix_batch_launch", "sympix_batch_destroy", "sympix_last_error")
 
 
@@ -290,6 +291,19 @@ def sample_BtNB(grid: Grid, kernel: Kernel, ninv, out, prec=FP64, stream=None):
     _require_f64_device(out, "out")
     _check(_sample_BtNB(grid.handle, kernel.handle, _ptr(ninv), _numel(ninv), int(prec), _ptr(out),
                         _numel(out), _stream(stream)))
+    return out
+
+
+def sample_BtNB_noalloc(grid: Grid, kernel: Kernel, ninv, out, prec=FP64, stream=None):
+    """sample_BtNB without any device allocation (static N^-1 scratch of the
+    library; at most 2^24 pixels outside FP64; overlapping calls on one device
+    race)."""
+    if isinstance(prec, str):
+        prec = PRECISIONS[prec]
+    _require_f64_device(ninv, "ninv")
+    _require_f64_device(out, "out")
+    _check(_sample_BtNB_noalloc(grid.handle, kernel.handle, _ptr(ninv), _numel(ninv), int(prec), _ptr(out),
+                                _numel(out), _stream(stream)))
     return out
 
 

@@ -130,14 +130,16 @@ struct sympix_kernel {
 namespace {
 
 // Upload the grid's tables to the current device once (blocking copies, so
-// every stream sees them afterwards).
-sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **out) {
+// every stream sees them afterwards).  With create = false only an existing
+// upload is returned (EINVAL if there is none): nothing is allocated.
+sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **out, bool create = true) {
     std::lock_guard<std::mutex> lock(g->mu);
     auto it = g->dev.find(device);
     if (it != g->dev.end()) {
         *out = &it->second;
         return SYMPIX_OK;
     }
+    if (!create) return fail(SYMPIX_EINVAL, "the grid's tables are not on this device (tabulate a kernel first)");
     const Geometry &geo = g->geo;
     std::vector<UInfo> uinfo(geo.nunique());
     for (int64_t u = 0; u < geo.nunique(); ++u) {
@@ -304,11 +306,13 @@ sympix_status check_kernel_use(const sympix_grid *g, const sympix_kernel *kr) {
 }
 
 // B-hat^T N^-1 B-hat into out_dev and, with a D-hat kernel d, the D-hat
-// blocks into outD_dev, both written by one class-GEMM launch.
+// blocks into outD_dev, both written by one class-GEMM launch.  With noalloc
+// the N^-1 operand scratch is the library's static device array and nothing
+// is allocated (the grid's tables must already be on the device).
 sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sympix_kernel *b,
                           const double *ninv_dev, int64_t ninv_len, int32_t prec, int32_t pattern,
                           double *outD_dev, int64_t outD_len, double *out_dev, int64_t out_len, void *stream,
-                          const char *what) {
+                          const char *what, bool noalloc = false) {
     sympix_status s = check_kernel_use(g, b);
     if (s != SYMPIX_OK) return s;
     const Geometry &geo = g->geo;
@@ -316,6 +320,10 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
     if (pattern != SYMPIX_PATTERN_ONE_HOP && pattern != SYMPIX_PATTERN_TWO_HOP)
         return fail(SYMPIX_EINVAL, "unknown block pattern");
     if (ninv_len != geo.npix) return fail(SYMPIX_ESIZE, "ninv_len must be npix");
+    if (noalloc && prec != SYMPIX_FP64 && geo.npix > sympix::kNoAllocMaxPix)
+        return fail(SYMPIX_ESIZE, "the allocation-free call holds N^-1 operands for at most " +
+                                      std::to_string(sympix::kNoAllocMaxPix) + " pixels (this grid has " +
+                                      std::to_string(geo.npix) + "); use sympix_sample_BtNB");
     const sympix::Pattern *pat = nullptr;
     if (pattern == SYMPIX_PATTERN_TWO_HOP) {
         const DevClasses *unused = nullptr;
@@ -341,7 +349,7 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
     }
     if (d && d->device != b->device) return fail(SYMPIX_EINVAL, "the two kernels live on different devices");
     const DevGrid *dg = nullptr;
-    s = device_tables(g, b->device, &dg);
+    s = device_tables(g, b->device, &dg, !noalloc);
     if (s != SYMPIX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     if (ct.max_class_terms > sympix::kMaxClassTerms)
@@ -378,14 +386,23 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
     a.outD = fused ? outD_dev : nullptr;
     hipError_t e = hipSuccess;
     void *scratch = nullptr;
+    bool owned = false;
     if (prec != SYMPIX_FP64) {
-        // stream-ordered scratch for N^-1 in the MFMA operand format (FP32, or
-        // three BF16 parts): concurrent calls stay independent
-        const size_t bytes = (size_t)geo.npix * (prec == SYMPIX_FP32 ? sizeof(float) : 3 * sizeof(uint16_t));
-        e = hipMallocAsync(&scratch, bytes, st);
-        if (e != hipSuccess)
-            return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 operands")
-                                            : hip_fail(e, "hipMallocAsync");
+        if (noalloc) {
+            // the static array: shared by every allocation-free call on this
+            // device, fully rewritten (npix values per part) before it is read
+            e = sympix::noalloc_scratch(b->device, &scratch);
+            if (e != hipSuccess) return hip_fail(e, "address of the static N^-1 scratch");
+        } else {
+            // stream-ordered scratch for N^-1 in the MFMA operand format (FP32,
+            // or three BF16 parts): concurrent calls stay independent
+            const size_t bytes = (size_t)geo.npix * (prec == SYMPIX_FP32 ? sizeof(float) : 3 * sizeof(uint16_t));
+            e = hipMallocAsync(&scratch, bytes, st);
+            if (e != hipSuccess)
+                return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 operands")
+                                                : hip_fail(e, "hipMallocAsync");
+            owned = true;
+        }
         if (prec == SYMPIX_FP32) {
             a.wf32 = (float *)scratch;
         } else {
@@ -395,7 +412,7 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
         }
     }
     e = sympix::launch_btnb(prec, a, st);
-    if (scratch) {
+    if (owned) {
         hipError_t ef = hipFreeAsync(scratch, st);
         if (e == hipSuccess) e = ef;
     }
@@ -678,6 +695,13 @@ sympix_status sympix_sample_BtNB(const sympix_grid *g, const sympix_kernel *b, c
                                  void *stream) {
     return sample_btnb(g, nullptr, b, ninv_dev, ninv_len, prec, SYMPIX_PATTERN_ONE_HOP, nullptr, 0, out_dev, out_len,
                        stream, "sample_BtNB");
+}
+
+sympix_status sympix_sample_BtNB_noalloc(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,
+                                         int64_t ninv_len, int32_t prec, double *out_dev, int64_t out_len,
+                                         void *stream) {
+    return sample_btnb(g, nullptr, b, ninv_dev, ninv_len, prec, SYMPIX_PATTERN_ONE_HOP, nullptr, 0, out_dev, out_len,
+                       stream, "sample_BtNB_noalloc", true);
 }
 
 sympix_status sympix_sample_BtNB_pattern(const sympix_grid *g, const sympix_kernel *b, const double *ninv_dev,

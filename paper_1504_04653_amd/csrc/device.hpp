@@ -141,6 +141,14 @@ struct BatchLaunch {
     int32_t nworkgroups;
 };
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t st);
+
+// The allocation-free sampling call keeps N^-1 in the MFMA operand format in a
+// file-scope device array of 3 * kNoAllocMaxPix BF16 words (96 MiB): up to
+// kNoAllocMaxPix pixels in every mode.  noalloc_scratch returns the array's
+// address on `device`, which must be current (looked up once per device).
+constexpr int64_t kNoAllocMaxPix = int64_t(1) << 24;
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_scratch(int device, void **ptr);
 hipError_t batch_occupancy(int prec, int *workgroups_per_cu);
 
 }  // namespace sympix

@@ -22,6 +22,8 @@
 //   k_batch_bf16   many problems in one persistent launch, split BF16
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device.hpp"
 
 namespace sympix {
@@ -1165,7 +1167,34 @@ void k_batch_bf16(const ProblemDescB *__restrict__ probs, const int32_t *__restr
     }
 }
 
+// Scratch of the allocation-free entry point: N^-1 in the MFMA operand format
+// (three BF16 parts or FP32) for up to kNoAllocMaxPix pixels.  Each device
+// that loads this code object holds one copy until the process ends.
+static __device__ __align__(256) uint16_t scratch[3 * kNoAllocMaxPix];
+
 }  // namespace
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    // the array's name is a host-side stand-in: its device address comes from
+    // the runtime, once per device, with that device current
+    static std::mutex mu;
+    static void *addr[kNoAllocMaxDevices] = {};
+    if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_tabulate(const double *coef, int32_t lmax, double h, double *table,
                            int32_t n_nodes, hipStream_t st) {
