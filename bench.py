@@ -30,10 +30,12 @@ and tile shape are autotuned first.
 With --op conv a step is one pixel-domain convolution g = B-hat f (FP64) of
 the configuration's grid and beam.  With --op two_hop a step tabulates the beam
 kernel and samples B^T N^-1 B on the two-hop pattern (every nonzero block of
-the product), in the first of --modes.
+the product), in the first of --modes.  With --op two_grid a step tabulates
+the beam kernel between the configuration's grid Y_1 and an auxiliary grid Y_2
+(--lmax2, default twice lmax) and samples B^T N_2^-1 B with N_2^-1 on Y_2.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config lmax3000|batch32]
-                       [--op btnb|conv|two_hop] [--modes fp64,bf16x6,fp32,bf16x3]
+                       [--op btnb|conv|two_hop|two_grid] [--lmax2 L] [--modes fp64,bf16x6,fp32,bf16x3]
                        [--no-cpu-baseline] [--no-batch-compare]
 """
 from __future__ import annotations
@@ -70,9 +72,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="lmax3000")
-    ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop"],
+    ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop", "two_grid"],
                     help="btnb: the D-hat / B-hat^T N^-1 B-hat step (default); conv: the pixel-domain "
-                         "convolution g = B-hat f; two_hop: B^T N^-1 B on every nonzero block of the product")
+                         "convolution g = B-hat f; two_hop: B^T N^-1 B on every nonzero block of the product; "
+                         "two_grid: B^T N_2^-1 B with N_2^-1 on an auxiliary grid (--lmax2, default twice)")
+    ap.add_argument("--lmax2", type=int, default=0, help="band limit of the auxiliary grid for --op two_grid")
     ap.add_argument("--modes", default=None,
                     help="precision modes, the first is reported as value (default fp64,bf16x6,fp32,bf16x3; "
                          "for --config batch32 fp32,bf16x6,fp64)")
@@ -630,6 +634,83 @@ def run_two_hop(args):
     print(json.dumps(line), flush=True)
 
 
+def run_two_grid(args):
+    """B^T N_2^-1 B with N_2^-1 on an auxiliary grid Y_2 of twice the band limit
+    (Eq. 13; Section 4.2's "twice that of Y_1"): a step tabulates the two-grid
+    beam kernel and contracts, in the first of --modes."""
+    import torch
+
+    import paper_1504_04653_amd as sp
+    from workloads import synth as S
+
+    cfg = S.CONFIGS[args.config]
+    lmax2 = args.lmax2 or 2 * cfg.lmax
+    prec = [m.strip() for m in args.modes.split(",") if m.strip()][0]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g1, g2 = sp.Grid(cfg.lmax, cfg.k), sp.Grid(lmax2, cfg.k)
+    x = sp.Cross(g2, g1)
+    setup = time.perf_counter() - t0
+    th2, ph2 = g2.pixel_theta_phi()
+    ninv2 = torch.as_tensor(S.ninv_for(cfg, th2, ph2)).cuda()
+    b_l, R = S.gaussian_beam(cfg.lmax, g1.npix, cfg.fwhm_pix)
+    out = torch.empty(x.out_len, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    nelem = x.nblocks * 4096
+    alg_flop = 2.0 * 64 ** 3 * x.nterms
+    print(f"# two-grid {args.config}: lmax1={cfg.lmax} lmax2={lmax2} npix2={g2.npix} blocks={x.nblocks} "
+          f"terms={x.nterms} (max {x.max_terms}) unique={x.nunique} setup={setup:.2f}s", file=sys.stderr, flush=True)
+
+    def step(ev):
+        ev[0].record(stream)
+        kb = sp.CrossKernel(x, b_l, R, stream=stream)
+        ev[1].record(stream)
+        sp.sample_BtNB_cross(x, kb, ninv2, out, prec, stream=stream)
+        ev[2].record(stream)
+        return kb
+
+    for _ in range(args.warmup):
+        keep = step([torch.cuda.Event(enable_timing=True) for _ in range(3)])
+        torch.cuda.synchronize()
+        del keep
+    evs, keeps = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        keeps.append(step(ev))
+        evs.append(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    keeps.clear()
+    t_C = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    t_T = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    ms_step = wall * 1000.0 / args.steps
+    mfma = PRODUCTS[prec] * alg_flop / (t_C * 1e-3) / 1e12
+    print(f"# two-grid {prec}: step {ms_step:.2f} ms, contraction {t_C:.2f} ms ({mfma:.1f} TFLOP/s, "
+          f"{mfma / PEAK[prec] * 100:.1f}% of {PEAK[prec]}), tabulation {t_T:.2f} ms", file=sys.stderr, flush=True)
+    line = {
+        "metric": "B^T N_2^-1 B elements/s, N_2^-1 on an auxiliary grid of twice the band limit",
+        "value": nelem / (ms_step * 1e-3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[prec],
+        "data": "synthetic",
+        "config": {"workload": f"sympix Y_1 lmax={cfg.lmax}, Y_2 lmax={lmax2}, k={cfg.k}, beam FWHM "
+                               f"{cfg.fwhm_pix:g} px of Y_1 cut 3 FWHM, N_2^-1 {cfg.ninv_kind} seed {cfg.seed} on Y_2",
+                   "lmax1": cfg.lmax, "lmax2": lmax2, "nblocks": x.nblocks, "nterms": x.nterms, "precision": prec,
+                   "tabulate_ms": t_T, "contraction_ms": t_C},
+        "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec], "achieved": mfma,
+                     "frac": mfma / PEAK[prec], "kernel": KERNEL_NAME[prec], "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -644,6 +725,9 @@ def main():
         return
     if args.op == "two_hop":
         run_two_hop(args)
+        return
+    if args.op == "two_grid":
+        run_two_grid(args)
         return
     import torch
 

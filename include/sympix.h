@@ -271,6 +271,87 @@ sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d,
                                    const double *ninv_dev, int64_t ninv_len, int32_t prec, double *outD_dev,
                                    int64_t outD_len, double *outC_dev, int64_t outC_len, void *stream);
 
+/* ---- Two grids: B-hat = Y_2 B Y_1^T (Eqs. 13 and 16) --------------------------
+ * Eq. 13 moves N^-1 onto an auxiliary SymPix grid Y_2, which may differ from
+ * the grid Y_1 of the unknowns (Section 4.2: with Y_2 at twice the band limit
+ * of Y_1 the substitution holds to about 1e-10); B-hat = Y_2 B Y_1^T then has
+ * a row per pixel of Y_2 and a column per pixel of Y_1, and Eq. 15 asks for
+ * B-hat^T N_2^-1 B-hat on the stored blocks of Y_1.  An element of B-hat is
+ * b(n_i . n_j) with the Eq. 10 kernel summed over l <= min(lmax_1, lmax_2).
+ * Section 4.2's truncation ("same or neighbouring tiles") needs a relation
+ * between tiles of two grids, which the paper does not give; this library
+ * places each tile of Y_2 in the tile of Y_1 that contains its centre
+ * (centres and band ranges [ik/R, (i+1)k/R] pi as exact rationals, half-open
+ * to the south and east) and pairs it with that tile's neighbours, so the
+ * truncation reaches as far as on one grid.  With Y_2 = Y_1 every table, and
+ * every result, is bitwise that of the one-grid calls.  Both grids must have
+ * the same k (8 for device sampling); blocks are k^2 x k^2. */
+typedef struct sympix_cross sympix_cross;   /* opaque, library-owned; refers to both grids */
+
+typedef struct {
+    int32_t lmax_eff;        /* min(lmax_1, lmax_2): band limit of the kernel series */
+    int32_t max_terms;       /* largest number of contraction terms of one stored block */
+    int64_t nadjacency;      /* blocks of B-hat kept: pairs (tile I of Y_2, tile J of Y_1) */
+    int64_t nunique;         /* distinct (band of I, band of J, phi offset) keys */
+    int64_t nblocks;         /* stored blocks of B-hat^T N_2^-1 B-hat (those of Y_1) */
+    int64_t nterms;          /* sum over stored blocks of the tiles I of Y_2 they share */
+    double y_pattern_max;    /* largest 1 - cos(gamma) over the kept pairs */
+} sympix_cross_sizes;
+
+/* Tables of the pair (g2 = Y_2 auxiliary, g1 = Y_1); host only.  Both grids
+ * must outlive the pair.  Errors: EINVAL (NULL), EUNSUPPORTED (different k),
+ * ENOMEM. */
+sympix_status sympix_cross_create(const sympix_grid *g2, const sympix_grid *g1, sympix_cross **out);
+
+/* Free a pair and its device tables.  NULL is ignored; its kernels must be
+ * destroyed first. */
+void sympix_cross_destroy(sympix_cross *x);
+
+/* Sizes of the pair.  Errors: EINVAL. */
+sympix_status sympix_cross_dims(const sympix_cross *x, sympix_cross_sizes *out);
+
+/* The tile relation (host buffers, NULL skips): container[ntiles_2] = the tile
+ * of Y_1 holding each tile's centre; CSR over the tiles I of Y_2,
+ * row_ptr[ntiles_2 + 1], col[nadjacency] = tiles J of Y_1 (ascending), and
+ * uid[nadjacency] = each block's unique id.  Errors: EINVAL. */
+sympix_status sympix_cross_neighbours(const sympix_cross *x, int32_t *container, int64_t *row_ptr, int32_t *col,
+                                      int32_t *uid);
+
+/* Key of every unique block: (band of I in Y_2, band of J in Y_1,
+ * delta = (t_J T_I - t_I T_J) mod T_I T_J), arrays of nunique.  NULL skips. */
+sympix_status sympix_cross_unique(const sympix_cross *x, int32_t *key_band_i, int32_t *key_band_j,
+                                  int64_t *key_delta);
+
+/* sympix_kernel_tabulate for the pair: the Eq. 10 kernel of coef_l up to
+ * lmax_eff, tabulated over the pair's pattern, and every unique block of
+ * B-hat = Y_2 B Y_1^T.  The handle serves sympix_sample_B_cross,
+ * sympix_sample_BtNB_cross, sympix_kernel_eval and sympix_kernel_destroy.
+ * Arguments and errors as sympix_kernel_tabulate. */
+sympix_status sympix_kernel_tabulate_cross(const sympix_cross *x, const double *coef_l, int32_t ncoef,
+                                           double radius, int32_t n_nodes, void *stream, sympix_kernel **out);
+
+/* The kept blocks of B-hat (Eq. 16 with the truncation above): out_dev
+ * (device, float64, nadjacency k^4 values, 16-byte aligned) receives block
+ * (I, J) for each relation entry in CSR order, row a = local pixel of I (on
+ * Y_2), column b = local pixel of J (on Y_1), row-major.
+ * Errors: EINVAL (NULL, kernel of another pair), ESIZE, EUNSUPPORTED (k != 8),
+ * EHIP. */
+sympix_status sympix_sample_B_cross(const sympix_cross *x, const sympix_kernel *b, double *out_dev, int64_t out_len,
+                                    void *stream);
+
+/* B-hat^T N_2^-1 B-hat (Eq. 15) on the stored blocks of Y_1:
+ *   C_JK = sum_{I of Y_2 related to J and K} B_IJ^T diag(ninv2_I) B_IK,
+ * ninv2_dev (device, float64, npix of Y_2 in its pixel order, 32-byte
+ * aligned), out_dev (device, float64, nblocks k^4 in the stored-block order of
+ * Y_1, 16-byte aligned, not overlapping ninv2_dev); prec any
+ * sympix_precision, on the same kernels as sympix_sample_BtNB.
+ * Errors: EINVAL (NULL, misalignment, overlap, kernel of another pair, unknown
+ * prec), ESIZE (ninv2_len != npix of Y_2, out_len != nblocks k^4),
+ * EUNSUPPORTED (k != 8, more than 128 terms in a block), ENOMEM, EHIP. */
+sympix_status sympix_sample_BtNB_cross(const sympix_cross *x, const sympix_kernel *b, const double *ninv2_dev,
+                                       int64_t ninv2_len, int32_t prec, double *out_dev, int64_t out_len,
+                                       void *stream);
+
 /* ---- Batches: many B-hat^T N^-1 B-hat problems in one graph launch ----------
  * Eq. 15 evaluated for n independent problems (own grid, beam kernel, N^-1 and
  * output each) by one captured HIP graph: a persistent contraction in FP64
@@ -338,9 +419,18 @@ sympix_status sympix_batch_set_tiling(sympix_batch *bt, int32_t t);
  * fastest and report its plan in *chosen and the times in
  * ms_out[SYMPIX_NSCHED * SYMPIX_NTILINGS], indexed by plan (either may be
  * NULL).  The choice is remembered for batches of the same problems and mode
- * in this process.  Each re-capture first waits for the batch's previous
- * launch, so the call may follow sympix_batch_launch on any stream. */
+ * in this process and, when the environment variable SYMPIX_TUNE_CACHE names
+ * a file, in that file (one "<shape>\t<plan>" line per batch shape, keyed by
+ * the gfx architecture, HIP runtime version, mode and every problem's lmax
+ * and block count), where sympix_batch_create of a later process finds it.
+ * Each re-capture first waits for the batch's previous launch, so the call
+ * may follow sympix_batch_launch on any stream.
+ * Errors: EINVAL (NULL, the cache file cannot be written), EHIP. */
 sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen, double *ms_out);
+
+/* The plan the batch's graph was captured with (schedule + SYMPIX_NSCHED *
+ * tiling).  Errors: EINVAL (NULL). */
+sympix_status sympix_batch_plan(const sympix_batch *bt, int32_t *plan);
 
 /* Enqueue the batch's graph on stream: converts every N^-1 to the operand
  * format (FP32, or BF16 parts; FP64 reads it as given) and writes every

@@ -69,38 +69,48 @@ def extract_blocks(M, g: Grid, pairs):
 # Two grids (Eqs. 13 and 16): B-hat = Y_2 B Y_1^T element by element
 # ---------------------------------------------------------------------------
 
-def tile_rectangles(g: Grid):
-    """Per tile, its closed rectangle in units of (pi, one turn):
-    [theta_lo, theta_hi, phi_lo, phi_hi], in floating point (each end is a
-    correctly rounded ratio of small integers, so equal ratios give equal
-    values)."""
-    rect = np.zeros((g.ntiles, 4))
-    n, k, R = g.nbands_hemi, g.k, g.nrings
+def tile_centres(g: Grid):
+    """Per tile, its centre as (colatitude / pi, longitude / turn) in floating
+    point: the middle of its band's range [i k/R, (i+1) k/R] (mirrored in the
+    south) and of [t/T, (t+1)/T]."""
+    out = np.zeros((g.ntiles, 2))
+    k, R = g.k, g.nrings
     for b in range(len(g.band_tiles)):
         i, south = divmod(b, 2)
-        lo, hi = (i * k / R, (i + 1) * k / R) if not south else ((R - (i + 1) * k) / R, (R - i * k) / R)
+        lo, hi = (i * k, (i + 1) * k) if not south else (R - (i + 1) * k, R - i * k)
         T = g.band_tiles[b]
         for t in range(T):
-            rect[g.band_tile0[b] + t] = (lo, hi, t / T, (t + 1) / T)
-    return rect
+            out[g.band_tile0[b] + t] = ((lo + hi) / (2 * R), (2 * t + 1) / (2 * T))
+    return out
 
 
 def cross_relation_dense(g2: Grid, g1: Grid):
-    """Boolean ntiles_2 x ntiles_1 matrix: tile rectangles meet (phi modulo one
-    turn), tested on every pair in floating point."""
-    r2 = tile_rectangles(g2)[:, None, :]
-    r1 = tile_rectangles(g1)[None, :, :]
-    th = (r2[..., 0] <= r1[..., 1]) & (r1[..., 0] <= r2[..., 1])
-    ph = np.zeros(th.shape, dtype=bool)
-    for s in (-1.0, 0.0, 1.0):
-        ph |= (r2[..., 2] + s <= r1[..., 3]) & (r1[..., 2] <= r2[..., 3] + s)
-    return th & ph
+    """Boolean ntiles_2 x ntiles_1 matrix of the two-grid tile relation, built
+    in floating point: each tile centre of g2 located in g1 by sorted band
+    edges and a floor, then the one-grid neighbours of the tile found."""
+    k, R = g1.k, g1.nrings
+    # band edges of g1 from the north pole, with the storage band of each interval
+    edges, bands = [], []
+    for i in range(g1.nbands_hemi):
+        edges.append(i * k / R)
+        bands.append(2 * i)
+    for i in reversed(range(g1.nbands_hemi)):
+        edges.append((R - (i + 1) * k) / R)
+        bands.append(2 * i + 1)
+    edges = np.array(edges)
+    rel = np.zeros((g2.ntiles, g1.ntiles), dtype=bool)
+    for I, (th, ph) in enumerate(tile_centres(g2)):
+        b = bands[int(np.searchsorted(edges, th, side="right")) - 1]
+        T = g1.band_tiles[b]
+        J0 = g1.band_tile0[b] + int(np.floor(ph * T))
+        rel[I, g1.tile_neighbours(J0)] = True
+    return rel
 
 
 def cross_operator_dense(g2: Grid, g1: Grid, coef_l, radius=None):
     """Dense Npix_2 x Npix_1 B-hat: every element evaluated directly from 3-D
-    unit vectors, kept where the two pixels' tiles meet (and within radius);
-    the kernel sums l <= min(lmax_1, lmax_2)."""
+    unit vectors, kept where the two pixels' tiles are related (and within
+    radius); the kernel sums l <= min(lmax_1, lmax_2)."""
     L = min(g1.lmax, g2.lmax)
     coef = np.zeros(L + 1)
     c = np.asarray(coef_l, dtype=np.float64)[:L + 1]

@@ -19,18 +19,23 @@ Definitions followed
   k_2^2 x k_1^2 (rectangular when the grids' tile sizes differ).
 
 Reading (the paper does not say when a tile of Y_2 and a tile of Y_1 are
-"neighbouring"): every tile covers a closed rectangle in (theta, phi), and two
-tiles of the two grids are neighbours when their rectangles meet (touching
-counts).  A tile's phi range is [t/T, (t+1)/T] of a turn; its band's
-colatitude range is [i k/R, (i+1) k/R] pi for north band i of a grid with R
-rings (the mirror image for south band i).  The j-th Gauss-Legendre ring lies
+"neighbouring"): the tile organisation that truncates is that of Y_1, the grid
+of the unknowns.  A tile of Y_2 is placed in the tile of Y_1 that contains its
+centre, and tile I of Y_2 neighbours tile J of Y_1 when that tile is J or one
+of J's neighbours (the one-grid relation of Section 2.2).  The truncation then
+reaches as far from J as it does on one grid, whatever the resolution of Y_2.
+Centres and ranges are exact rationals: band i of a grid with R rings spans
+the colatitudes [i k/R, (i+1) k/R] pi in the north (the mirror image in the
+south) and tile t of a band of T tiles the longitudes [t/T, (t+1)/T] of a turn;
+a tile's centre is the middle of both.  The j-th Gauss-Legendre ring lies
 strictly inside [j/R, (j+1)/R] pi (the zeros of P_R obey
 (j + 1/2)/(R + 1/2) < theta_j / pi < (j + 1)/(R + 1/2)), so each band's rings
-lie inside its range.  On one grid, bands that follow each other share an edge
-(the two equatorial bands meet at pi/2) and no others meet, so with Y_2 = Y_1
-the relation is the single-grid one (same band t-1, t, t+1; neighbouring bands
-by closed phi intervals): the two-grid operator then equals the one-grid
-operator exactly.  Everything is compared in integers (rational range ends).
+lie inside its range.  A centre on a boundary of Y_1 belongs to the band or
+tile on its south or east side (half-open ranges).  With Y_2 = Y_1 every tile
+contains its own centre and the relation is the one-grid one, so the two-grid
+operator then equals the one-grid operator exactly.  Which pairs are kept does
+not change any block's values: a kept block depends only on the two bands and
+the exact phi offset between the tiles, as on one grid.
 """
 from __future__ import annotations
 
@@ -50,50 +55,64 @@ def band_colatitude(g: Grid, b: int):
     return (i * k, (i + 1) * k, R)
 
 
-def ranges_meet(e1, e2) -> bool:
-    """Closed rational ranges [a1/d1, b1/d1] and [a2/d2, b2/d2] meet."""
-    a1, b1, d1 = e1
-    a2, b2, d2 = e2
-    return a1 * d2 <= b2 * d1 and a2 * d1 <= b1 * d2
+def containing_tile(g1: Grid, th_num: int, th_den: int, ph_num: int, ph_den: int) -> int:
+    """The tile of g1 containing the point of colatitude (th_num/th_den) pi and
+    longitude ph_num/ph_den of a turn (half-open ranges, exact integers)."""
+    for b in range(len(g1.band_tiles)):
+        lo, hi, den = band_colatitude(g1, b)
+        if lo * th_den <= th_num * den < hi * th_den:
+            T = g1.band_tiles[b]
+            return g1.band_tile0[b] + (ph_num * T) // ph_den
+    raise ValueError("colatitude outside [0, pi)")
 
 
-def phi_meet(t1: int, T1: int, t2: int, T2: int) -> bool:
-    """Closed phi intervals [t1/T1, (t1+1)/T1] and [t2/T2, (t2+1)/T2] meet
-    modulo one turn (integers after scaling by T1 T2)."""
-    M = T1 * T2
-    lo1, hi1 = t1 * T2, (t1 + 1) * T2
-    lo2, hi2 = t2 * T1, (t2 + 1) * T1
-    return any(lo1 <= hi2 + s and lo2 + s <= hi1 for s in (-M, 0, M))
+def tile_centre_container(g2: Grid, g1: Grid, I: int) -> int:
+    """The tile of g1 that contains the centre of tile I of g2."""
+    b = g2.tile_band(I)
+    lo, hi, den = band_colatitude(g2, b)
+    T = g2.band_tiles[b]
+    t = I - g2.band_tile0[b]
+    return containing_tile(g1, lo + hi, 2 * den, 2 * t + 1, 2 * T)
 
 
-def cross_neighbours(g2: Grid, g1: Grid, J: int):
-    """Sorted tiles of g2 whose rectangle meets that of tile J of g1."""
-    bJ = g1.tile_band(J)
-    eJ = band_colatitude(g1, bJ)
-    TJ = g1.band_tiles[bJ]
-    tJ = J - g1.band_tile0[bJ]
-    out = []
-    for b2 in range(len(g2.band_tiles)):
-        if not ranges_meet(band_colatitude(g2, b2), eJ):
-            continue
-        T2 = g2.band_tiles[b2]
-        for t2 in range(T2):
-            if phi_meet(t2, T2, tJ, TJ):
-                out.append(g2.band_tile0[b2] + t2)
-    return sorted(out)
+def centre_containers(g2: Grid, g1: Grid):
+    """containing_tile for the centre of every tile of g2 at once (the same
+    half-open tests, over the bands of g1 in turn)."""
+    lo2 = np.zeros(g2.ntiles, dtype=np.int64)
+    den2 = np.zeros(g2.ntiles, dtype=np.int64)
+    ph_num = np.zeros(g2.ntiles, dtype=np.int64)
+    ph_den = np.zeros(g2.ntiles, dtype=np.int64)
+    for b in range(len(g2.band_tiles)):
+        lo, hi, den = band_colatitude(g2, b)
+        T = g2.band_tiles[b]
+        sl = slice(g2.band_tile0[b], g2.band_tile0[b] + T)
+        lo2[sl], den2[sl] = lo + hi, 2 * den
+        ph_num[sl], ph_den[sl] = 2 * np.arange(T) + 1, 2 * T
+    out = np.full(g2.ntiles, -1, dtype=np.int64)
+    for b in range(len(g1.band_tiles)):
+        lo, hi, den = band_colatitude(g1, b)
+        inside = (lo * den2 <= lo2 * den) & (lo2 * den < hi * den2)
+        T = g1.band_tiles[b]
+        out[inside] = g1.band_tile0[b] + (ph_num[inside] * T) // ph_den[inside]
+    assert (out >= 0).all()
+    return out
 
 
 def cross_adjacency(g2: Grid, g1: Grid):
-    """The relation as CSR over the tiles I of g2: for each, the tiles J of g1
-    it neighbours (ascending)."""
-    rows = [[] for _ in range(g2.ntiles)]
-    for J in range(g1.ntiles):
-        for I in cross_neighbours(g2, g1, J):
-            rows[I].append(J)
+    """The relation as CSR over the tiles I of g2: the tiles J of g1 it
+    neighbours, ascending (the neighbours of the tile of g1 holding I's
+    centre, itself included)."""
+    rows = [g1.tile_neighbours(tile_centre_container(g2, g1, I)) for I in range(g2.ntiles)]
     rp = np.zeros(g2.ntiles + 1, dtype=np.int64)
     rp[1:] = np.cumsum([len(r) for r in rows])
     col = np.fromiter((c for r in rows for c in r), dtype=np.int32, count=int(rp[-1]))
     return rp, col
+
+
+def cross_neighbours(g2: Grid, g1: Grid, J: int):
+    """Sorted tiles of g2 neighbouring tile J of g1."""
+    nj = set(g1.tile_neighbours(J))
+    return [I for I in range(g2.ntiles) if tile_centre_container(g2, g1, I) in nj]
 
 
 def cross_key(g2: Grid, I: int, g1: Grid, J: int):
@@ -126,11 +145,15 @@ class CrossOperator:
         self.y_cut = radius_to_y(radius)
         self.cache = {}
         self._nbr = {}
+        self._container = None
 
     def neighbours(self, J: int):
         """Tiles of Y_2 neighbouring tile J of Y_1."""
         if J not in self._nbr:
-            self._nbr[J] = cross_neighbours(self.g2, self.g1, J)
+            if self._container is None:
+                self._container = centre_containers(self.g2, self.g1)
+            nj = np.array(self.g1.tile_neighbours(J))
+            self._nbr[J] = [int(I) for I in np.flatnonzero(np.isin(self._container, nj))]
         return self._nbr[J]
 
     def block(self, I: int, J: int):

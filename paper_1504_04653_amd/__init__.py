@@ -87,6 +87,22 @@ _convolve = _sig("sympix_convolve", [_vp, _vp, _vp, _i64, _vp, _i64, _vp])
 _last_error = _sig("sympix_last_error", [], ctypes.c_char_p)
 
 
+class CrossSizes(ctypes.Structure):
+    _fields_ = [("lmax_eff", ctypes.c_int32), ("max_terms", ctypes.c_int32), ("nadjacency", ctypes.c_int64),
+                ("nunique", ctypes.c_int64), ("nblocks", ctypes.c_int64), ("nterms", ctypes.c_int64),
+                ("y_pattern_max", ctypes.c_double)]
+
+
+_cross_create = _sig("sympix_cross_create", [_vp, _vp, ctypes.POINTER(_vp)])
+_cross_destroy = _sig("sympix_cross_destroy", [_vp], None)
+_cross_dims = _sig("sympix_cross_dims", [_vp, ctypes.POINTER(CrossSizes)])
+_cross_neighbours = _sig("sympix_cross_neighbours", [_vp, _vp, _vp, _vp, _vp])
+_cross_unique = _sig("sympix_cross_unique", [_vp, _vp, _vp, _vp])
+_kernel_tabulate_cross = _sig("sympix_kernel_tabulate_cross", [_vp, _vp, _i32, _f64, _i32, _vp, ctypes.POINTER(_vp)])
+_sample_B_cross = _sig("sympix_sample_B_cross", [_vp, _vp, _vp, _i64, _vp])
+_sample_BtNB_cross = _sig("sympix_sample_BtNB_cross", [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp])
+
+
 class Problem(ctypes.Structure):
     _fields_ = [("g", _vp), ("b", _vp), ("ninv_dev", _vp), ("ninv_len", _i64), ("out_dev", _vp),
                 ("out_len", _i64)]
@@ -97,6 +113,7 @@ _batch_set_schedule = _sig("sympix_batch_set_schedule", [_vp, _i32])
 _batch_set_tiling = _sig("sympix_batch_set_tiling", [_vp, _i32])
 _batch_tune = _sig("sympix_batch_tune", [_vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64)])
 _batch_launch = _sig("sympix_batch_launch", [_vp, _vp])
+_batch_plan = _sig("sympix_batch_plan", [_vp, ctypes.POINTER(_i32)])
 _batch_destroy = _sig("sympix_batch_destroy", [_vp], None)
 
 SCHED_XCD_QUEUES, SCHED_GLOBAL_LPT, SCHED_PER_PROBLEM = 0, 1, 2
@@ -115,7 +132,9 @@ EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sy
             "sympix_grid_bands", "sympix_grid_pixels", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_pattern_blocks", "sympix_grid_unique",
             "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
             "sympix_sample_BtNB", "sympix_sample_BtNB_noalloc", "sympix_sample_BtNB_pattern", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
-            "sympix_batch_launch", "sympix_batch_destroy", "sympix_last_error")
+            "sympix_batch_launch", "sympix_batch_plan", "sympix_batch_destroy", "sympix_last_error",
+            "sympix_cross_create", "sympix_cross_destroy", "sympix_cross_dims", "sympix_cross_neighbours",
+            "sympix_cross_unique", "sympix_kernel_tabulate_cross", "sympix_sample_B_cross", "sympix_sample_BtNB_cross")
 
 
 def _check(status):
@@ -342,6 +361,86 @@ def convolve(grid: Grid, kernel: Kernel, f, out, stream=None):
     return out
 
 
+class Cross:
+    """The pair of grids (g2 = Y_2 auxiliary, g1 = Y_1) of B-hat = Y_2 B Y_1^T."""
+
+    def __init__(self, g2: Grid, g1: Grid):
+        h = _vp()
+        _check(_cross_create(g2.handle, g1.handle, ctypes.byref(h)))
+        self._h = h
+        self.g2, self.g1 = g2, g1          # the pair refers to both grids
+        d = CrossSizes()
+        _check(_cross_dims(self._h, ctypes.byref(d)))
+        for f, _ in CrossSizes._fields_:
+            setattr(self, f, getattr(d, f))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _cross_destroy is not None:
+            _cross_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def neighbours(self):
+        """(container[ntiles_2], row_ptr, col, uid) of the tile relation."""
+        cont = np.zeros(self.g2.ntiles, dtype=np.int32)
+        rp = np.zeros(self.g2.ntiles + 1, dtype=np.int64)
+        col = np.zeros(self.nadjacency, dtype=np.int32)
+        uid = np.zeros(self.nadjacency, dtype=np.int32)
+        _check(_cross_neighbours(self._h, _ptr(cont), _ptr(rp), _ptr(col), _ptr(uid)))
+        return cont, rp, col, uid
+
+    def unique(self):
+        bi = np.zeros(self.nunique, dtype=np.int32)
+        bj = np.zeros(self.nunique, dtype=np.int32)
+        de = np.zeros(self.nunique, dtype=np.int64)
+        _check(_cross_unique(self._h, _ptr(bi), _ptr(bj), _ptr(de)))
+        return bi, bj, de
+
+    @property
+    def out_len(self):
+        return self.nblocks * self.g1.k ** 4
+
+    @property
+    def b_len(self):
+        return self.nadjacency * self.g1.k ** 4
+
+
+class CrossKernel(Kernel):
+    """Eq. 10 kernel tabulated for a pair of grids, with every unique block of
+    B-hat = Y_2 B Y_1^T."""
+
+    def __init__(self, cross: Cross, coef_l, radius: float = 0.0, n_nodes: int = 65536, stream=None):
+        coef = np.ascontiguousarray(coef_l, dtype=np.float64)
+        h = _vp()
+        self.grid = None
+        self.cross = cross
+        _check(_kernel_tabulate_cross(cross.handle, _ptr(coef), int(coef.size), float(radius), int(n_nodes),
+                                      _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+
+def sample_B_cross(cross: Cross, kernel: CrossKernel, out, stream=None):
+    """The kept blocks of B-hat = Y_2 B Y_1^T in the relation's CSR order."""
+    _require_f64_device(out, "out")
+    _check(_sample_B_cross(cross.handle, kernel.handle, _ptr(out), _numel(out), _stream(stream)))
+    return out
+
+
+def sample_BtNB_cross(cross: Cross, kernel: CrossKernel, ninv2, out, prec=FP64, stream=None):
+    """B-hat^T N_2^-1 B-hat on the stored blocks of Y_1, N_2^-1 on Y_2."""
+    if isinstance(prec, str):
+        prec = PRECISIONS[prec]
+    _require_f64_device(ninv2, "ninv2")
+    _require_f64_device(out, "out")
+    _check(_sample_BtNB_cross(cross.handle, kernel.handle, _ptr(ninv2), _numel(ninv2), int(prec), _ptr(out),
+                              _numel(out), _stream(stream)))
+    return out
+
+
 def raw_call(name):
     """The ctypes function of an exported symbol (for ABI-level tests)."""
     return getattr(_lib, name)
@@ -395,4 +494,10 @@ class Batch:
 
     def launch(self, stream=None):
         _check(_batch_launch(self._h, _stream(stream)))
+
+    def plan(self):
+        """The plan (schedule + len(SCHEDULES) * tiling) the graph was captured with."""
+        p = _i32(-1)
+        _check(_batch_plan(self._h, ctypes.byref(p)))
+        return p.value
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -13,6 +14,8 @@
 #include <numeric>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "../../include/sympix.h"
 #include "device.hpp"
@@ -39,6 +42,30 @@ sympix_status hip_fail(hipError_t e, const char *what) {
 bool sync_mode() {
     const char *v = std::getenv("SYMPIX_SYNC");
     return v && v[0] == '1';
+}
+
+// Allocation-failure injection for tests of the error paths: with the
+// environment variable SYMPIX_FAIL_ALLOC=n, the n-th host allocation point
+// reached since the variable took its current value (counting from 1) fails
+// as an allocation would: the call returns ENOMEM and creates no handle.
+// Allocation points: every handle the library allocates and every table build
+// (grid, two-hop pattern, two-grid pair, kernel, batch).
+bool injected_alloc_failure() {
+    static std::mutex mu;
+    static std::string last;
+    static long count = 0;
+    const char *v = std::getenv("SYMPIX_FAIL_ALLOC");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!v || !*v) {
+        last.clear();
+        count = 0;
+        return false;
+    }
+    if (last != v) {
+        last = v;
+        count = 0;
+    }
+    return ++count == std::strtol(v, nullptr, 10);
 }
 
 // Device copies of the grid tables, one set per device that used the grid.
@@ -114,8 +141,11 @@ struct sympix_grid {
     mutable std::map<int, DevClasses> dev_two_hop;
 };
 
+struct sympix_cross;
+
 struct sympix_kernel {
-    const sympix_grid *g = nullptr;
+    const sympix_grid *g = nullptr;       // owner: one grid, or
+    const sympix_cross *x = nullptr;      // a pair of grids (B-hat = Y_2 B Y_1^T)
     int device = 0;
     int32_t n_nodes = 0;
     double h = 0.0, inv_h = 0.0, y_cut = 0.0;
@@ -190,6 +220,7 @@ sympix_status two_hop_tables(const sympix_grid *g, int device, const sympix::Pat
                              const DevClasses **dc) {
     std::lock_guard<std::mutex> lock(g->mu);
     if (!g->two_hop) {
+        if (injected_alloc_failure()) return fail(SYMPIX_ENOMEM, "host allocation failed building the two-hop pattern");
         auto p = std::make_unique<sympix::Pattern>();
         std::string err;
         const int st = sympix::build_two_hop(g->geo, *p, err);
@@ -305,6 +336,48 @@ sympix_status check_kernel_use(const sympix_grid *g, const sympix_kernel *kr) {
     return SYMPIX_OK;
 }
 
+// Launch a contraction whose tables are set in a (all but the N^-1 operand
+// scratch): the scratch is the library's static array (noalloc) or a
+// stream-ordered allocation of a.npix values in the operand format.
+sympix_status launch_contraction(sympix::BtnbArgs &a, int device, int32_t prec, bool noalloc, hipStream_t st,
+                                 const char *what) {
+    a.wsplit[0] = a.wsplit[1] = a.wsplit[2] = nullptr;
+    a.wf32 = nullptr;
+    hipError_t e = hipSuccess;
+    void *scratch = nullptr;
+    bool owned = false;
+    if (prec != SYMPIX_FP64) {
+        if (noalloc) {
+            // the static array: shared by every allocation-free call on this
+            // device, fully rewritten (npix values per part) before it is read
+            e = sympix::noalloc_scratch(device, &scratch);
+            if (e != hipSuccess) return hip_fail(e, "address of the static N^-1 scratch");
+        } else {
+            // stream-ordered scratch for N^-1 in the MFMA operand format (FP32,
+            // or three BF16 parts): concurrent calls stay independent
+            const size_t bytes = (size_t)a.npix * (prec == SYMPIX_FP32 ? sizeof(float) : 3 * sizeof(uint16_t));
+            e = hipMallocAsync(&scratch, bytes, st);
+            if (e != hipSuccess)
+                return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 operands")
+                                                : hip_fail(e, "hipMallocAsync");
+            owned = true;
+        }
+        if (prec == SYMPIX_FP32) {
+            a.wf32 = (float *)scratch;
+        } else {
+            a.wsplit[0] = (uint16_t *)scratch;
+            a.wsplit[1] = a.wsplit[0] + a.npix;
+            a.wsplit[2] = a.wsplit[1] + a.npix;
+        }
+    }
+    e = sympix::launch_btnb(prec, a, st);
+    if (owned) {
+        hipError_t ef = hipFreeAsync(scratch, st);
+        if (e == hipSuccess) e = ef;
+    }
+    return after_launch(e, st, what);
+}
+
 // B-hat^T N^-1 B-hat into out_dev and, with a D-hat kernel d, the D-hat
 // blocks into outD_dev, both written by one class-GEMM launch.  With noalloc
 // the N^-1 operand scratch is the library's static device array and nothing
@@ -379,44 +452,92 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
     a.npix = geo.npix;
     a.ninv = ninv_dev;
     a.out = out_dev;
-    a.wsplit[0] = a.wsplit[1] = a.wsplit[2] = nullptr;
-    a.wf32 = nullptr;
     a.du64 = fused ? d->u64 : nullptr;
     a.blk_uid = fused ? dg->blk_uid : nullptr;
     a.outD = fused ? outD_dev : nullptr;
-    hipError_t e = hipSuccess;
-    void *scratch = nullptr;
-    bool owned = false;
-    if (prec != SYMPIX_FP64) {
-        if (noalloc) {
-            // the static array: shared by every allocation-free call on this
-            // device, fully rewritten (npix values per part) before it is read
-            e = sympix::noalloc_scratch(b->device, &scratch);
-            if (e != hipSuccess) return hip_fail(e, "address of the static N^-1 scratch");
-        } else {
-            // stream-ordered scratch for N^-1 in the MFMA operand format (FP32,
-            // or three BF16 parts): concurrent calls stay independent
-            const size_t bytes = (size_t)geo.npix * (prec == SYMPIX_FP32 ? sizeof(float) : 3 * sizeof(uint16_t));
-            e = hipMallocAsync(&scratch, bytes, st);
-            if (e != hipSuccess)
-                return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device scratch for N^-1 operands")
-                                                : hip_fail(e, "hipMallocAsync");
-            owned = true;
-        }
-        if (prec == SYMPIX_FP32) {
-            a.wf32 = (float *)scratch;
-        } else {
-            a.wsplit[0] = (uint16_t *)scratch;
-            a.wsplit[1] = a.wsplit[0] + geo.npix;
-            a.wsplit[2] = a.wsplit[1] + geo.npix;
-        }
+    return launch_contraction(a, b->device, prec, noalloc, st, what);
+}
+
+// What a kernel tabulation needs from its owner (one grid or a pair): the band
+// limit of the series, the largest y between paired pixels, and the unique
+// blocks with their ring tables on the device.
+struct TabSource {
+    int32_t lmax;
+    double y_pattern_max;
+    int64_t nunique;
+    const UInfo *uinfo;
+    const double *ring_theta, *ring_sin;
+};
+
+sympix_status tabulate(const TabSource &src, const sympix_grid *g, const sympix_cross *x, int device,
+                       const double *coef_l, int32_t ncoef, double radius, int32_t n_nodes, hipStream_t st,
+                       sympix_kernel **out) {
+    if (ncoef < 1) return fail(SYMPIX_ESIZE, "ncoef must be >= 1");
+    if (n_nodes == 0) n_nodes = 65536;
+    if (n_nodes < 64) return fail(SYMPIX_EINVAL, "n_nodes must be >= 64");
+    if (!(radius == radius)) return fail(SYMPIX_EINVAL, "radius is NaN");
+    for (int32_t l = 0; l < ncoef; ++l)
+        if (!std::isfinite(coef_l[l])) return fail(SYMPIX_EINVAL, "coefficients must be finite");
+    sympix_kernel *kr = injected_alloc_failure() ? nullptr : new (std::nothrow) sympix_kernel();
+    if (!kr) return fail(SYMPIX_ENOMEM, "host allocation failed");
+    kr->g = g;
+    kr->x = x;
+    kr->device = device;
+    kr->n_nodes = n_nodes;
+    double y_dom = src.y_pattern_max;
+    kr->y_cut = INFINITY;
+    if (radius > 0) {
+        const double sr = std::sin(0.5 * radius);
+        kr->y_cut = 2.0 * sr * sr;
+        if (kr->y_cut < y_dom) y_dom = kr->y_cut;
     }
-    e = sympix::launch_btnb(prec, a, st);
-    if (owned) {
-        hipError_t ef = hipFreeAsync(scratch, st);
-        if (e == hipSuccess) e = ef;
+    // nodes uniform in s = sqrt(y) up to the domain end plus a little slack for
+    // device rounding of y; the last interval keeps one spare node
+    const double s_top = std::fmax(std::sqrt(y_dom) * (1.0 + 1e-6), 1e-300);
+    kr->h = s_top / (double)(n_nodes - 5);
+    kr->inv_h = 1.0 / kr->h;
+
+    const int32_t lmax = src.lmax;
+    std::vector<double> coef(lmax + 1, 0.0);
+    for (int32_t l = 0; l <= lmax && l < ncoef; ++l) coef[l] = coef_l[l];
+    const size_t nu = (size_t)src.nunique * sympix::kBlockElems;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_table = up(coef.size() * sizeof(double));
+    const size_t o_u64 = o_table + up((size_t)n_nodes * sizeof(double));
+    const size_t o_u64t = o_u64 + up(nu * sizeof(double));
+    const size_t o_ut32 = o_u64t + up(nu * sizeof(double));
+    const size_t total = o_ut32 + up(nu * sizeof(float));
+    hipError_t e = hipMallocAsync(&kr->block, total, st);
+    if (e != hipSuccess) {
+        kr->block = nullptr;
+        free_kernel(kr);
+        return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the kernel failed")
+                                        : hip_fail(e, "hipMallocAsync");
     }
-    return after_launch(e, st, what);
+    char *base = (char *)kr->block;
+    kr->coef = (double *)base;
+    kr->table = (double *)(base + o_table);
+    kr->u64 = (double *)(base + o_u64);
+    kr->u64t = (double *)(base + o_u64t);
+    kr->ut32 = (float *)(base + o_ut32);
+    e = upload_coefficients(device, coef, kr->coef, st);
+    if (e != hipSuccess) {
+        hipStreamSynchronize(st);
+        free_kernel(kr);
+        return hip_fail(e, "copying coefficients");
+    }
+    e = sympix::launch_tabulate(kr->coef, lmax, kr->h, kr->table, n_nodes, st);
+    if (e == hipSuccess)
+        e = sympix::launch_unique_eval(ktable(kr), src.uinfo, src.nunique, src.ring_theta, src.ring_sin, kr->u64,
+                                       kr->u64t, kr->ut32, st);
+    sympix_status s = after_launch(e, st, "tabulate / unique-block evaluation");
+    if (s != SYMPIX_OK) {
+        hipStreamSynchronize(st);
+        free_kernel(kr);
+        return s;
+    }
+    *out = kr;
+    return SYMPIX_OK;
 }
 
 }  // namespace
@@ -428,10 +549,11 @@ const char *sympix_last_error(void) { return g_last_error.c_str(); }
 sympix_status sympix_grid_create(int32_t lmax, int32_t k, double polar_margin, sympix_grid **out) {
     if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
     *out = nullptr;
-    sympix_grid *g = new (std::nothrow) sympix_grid();
+    sympix_grid *g = injected_alloc_failure() ? nullptr : new (std::nothrow) sympix_grid();
     if (!g) return fail(SYMPIX_ENOMEM, "host allocation failed");
     std::string err;
-    int rc = sympix::build_geometry(lmax, k, polar_margin, g->geo, err);
+    int rc = injected_alloc_failure() ? (err = "host allocation failed while building the grid (injected)", -3)
+                                      : sympix::build_geometry(lmax, k, polar_margin, g->geo, err);
     if (rc != 0) {
         delete g;
         return fail((sympix_status)rc, err);
@@ -565,80 +687,15 @@ sympix_status sympix_kernel_tabulate(const sympix_grid *g, const double *coef_l,
     if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!g || !coef_l) return fail(SYMPIX_EINVAL, "NULL grid or coefficients");
-    if (ncoef < 1) return fail(SYMPIX_ESIZE, "ncoef must be >= 1");
-    if (n_nodes == 0) n_nodes = 65536;
-    if (n_nodes < 64) return fail(SYMPIX_EINVAL, "n_nodes must be >= 64");
-    if (!(radius == radius)) return fail(SYMPIX_EINVAL, "radius is NaN");
-    for (int32_t l = 0; l < ncoef; ++l)
-        if (!std::isfinite(coef_l[l])) return fail(SYMPIX_EINVAL, "coefficients must be finite");
-    const Geometry &geo = g->geo;
-    hipStream_t st = (hipStream_t)stream;
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     const DevGrid *dg = nullptr;
     sympix_status s = device_tables(g, device, &dg);
     if (s != SYMPIX_OK) return s;
-
-    sympix_kernel *kr = new (std::nothrow) sympix_kernel();
-    if (!kr) return fail(SYMPIX_ENOMEM, "host allocation failed");
-    kr->g = g;
-    kr->device = device;
-    kr->n_nodes = n_nodes;
-    double y_dom = geo.y_pattern_max;
-    kr->y_cut = INFINITY;
-    if (radius > 0) {
-        const double sr = std::sin(0.5 * radius);
-        kr->y_cut = 2.0 * sr * sr;
-        if (kr->y_cut < y_dom) y_dom = kr->y_cut;
-    }
-    // nodes uniform in s = sqrt(y) up to the domain end plus a little slack for
-    // device rounding of y; the last interval keeps one spare node
-    const double s_top = std::fmax(std::sqrt(y_dom) * (1.0 + 1e-6), 1e-300);
-    kr->h = s_top / (double)(n_nodes - 5);
-    kr->inv_h = 1.0 / kr->h;
-
-    const int32_t lmax = geo.lmax;
-    std::vector<double> coef(lmax + 1, 0.0);
-    for (int32_t l = 0; l <= lmax && l < ncoef; ++l) coef[l] = coef_l[l];
-    const size_t nu = (size_t)geo.nunique() * sympix::kBlockElems;
-    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t o_table = up(coef.size() * sizeof(double));
-    const size_t o_u64 = o_table + up((size_t)n_nodes * sizeof(double));
-    const size_t o_u64t = o_u64 + up(nu * sizeof(double));
-    const size_t o_ut32 = o_u64t + up(nu * sizeof(double));
-    const size_t total = o_ut32 + up(nu * sizeof(float));
-    e = hipMallocAsync(&kr->block, total, st);
-    if (e != hipSuccess) {
-        kr->block = nullptr;
-        free_kernel(kr);
-        return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the kernel failed")
-                                        : hip_fail(e, "hipMallocAsync");
-    }
-    char *base = (char *)kr->block;
-    kr->coef = (double *)base;
-    kr->table = (double *)(base + o_table);
-    kr->u64 = (double *)(base + o_u64);
-    kr->u64t = (double *)(base + o_u64t);
-    kr->ut32 = (float *)(base + o_ut32);
-    e = upload_coefficients(device, coef, kr->coef, st);
-    if (e != hipSuccess) {
-        hipStreamSynchronize(st);
-        free_kernel(kr);
-        return hip_fail(e, "copying coefficients");
-    }
-    e = sympix::launch_tabulate(kr->coef, lmax, kr->h, kr->table, n_nodes, st);
-    if (e == hipSuccess)
-        e = sympix::launch_unique_eval(ktable(kr), dg->uinfo, geo.nunique(), dg->ring_theta, dg->ring_sin,
-                                       kr->u64, kr->u64t, kr->ut32, st);
-    s = after_launch(e, st, "tabulate / unique-block evaluation");
-    if (s != SYMPIX_OK) {
-        hipStreamSynchronize(st);
-        free_kernel(kr);
-        return s;
-    }
-    *out = kr;
-    return SYMPIX_OK;
+    const Geometry &geo = g->geo;
+    TabSource src{geo.lmax, geo.y_pattern_max, geo.nunique(), dg->uinfo, dg->ring_theta, dg->ring_sin};
+    return tabulate(src, g, nullptr, device, coef_l, ncoef, radius, n_nodes, (hipStream_t)stream, out);
 }
 
 void sympix_kernel_destroy(sympix_kernel *kr) {
@@ -764,6 +821,51 @@ constexpr int kBatchQueues = 8;   // one per XCD
 
 std::mutex g_tune_mu;
 std::map<std::string, int32_t> g_tune_cache;   // batch shape -> plan (schedule + NSCHED tiling)
+
+// On-disk tuner cache: with SYMPIX_TUNE_CACHE=<file>, plans chosen by
+// sympix_batch_tune are kept in that text file, one "<key>\t<plan>" line per
+// batch shape (key: the gfx architecture, the HIP runtime version, the mode
+// and every problem's lmax and block count), and sympix_batch_create starts
+// from a plan found there.  The file is rewritten whole on every update
+// (write to a temporary file, then rename); concurrent writers: last one wins.
+std::string tune_cache_file() {
+    const char *v = std::getenv("SYMPIX_TUNE_CACHE");
+    return v ? std::string(v) : std::string();
+}
+
+std::map<std::string, int32_t> read_tune_file(const std::string &path) {
+    std::map<std::string, int32_t> out;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return out;
+    char line[4096];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        const size_t tab = l.rfind('\t');
+        if (tab == std::string::npos || tab == 0) continue;
+        char *end = nullptr;
+        const long plan = std::strtol(l.c_str() + tab + 1, &end, 10);
+        if (end == l.c_str() + tab + 1 || *end != '\0') continue;
+        if (plan < 0 || plan >= SYMPIX_NSCHED * SYMPIX_NTILINGS) continue;
+        out[l.substr(0, tab)] = (int32_t)plan;
+    }
+    std::fclose(f);
+    return out;
+}
+
+bool write_tune_file(const std::string &path, const std::string &key, int32_t plan) {
+    std::map<std::string, int32_t> all = read_tune_file(path);
+    all[key] = plan;
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    bool ok = true;
+    for (auto &kv : all) ok = ok && std::fprintf(f, "%s\t%d\n", kv.first.c_str(), kv.second) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    if (ok) ok = std::rename(tmp.c_str(), path.c_str()) == 0;
+    if (!ok) std::remove(tmp.c_str());
+    return ok;
+}
 
 void free_batch(sympix_batch *bt) {
     if (bt->exec) hipGraphExecDestroy(bt->exec);
@@ -910,7 +1012,7 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     for (size_t i = 1; i < spans.size(); ++i)
         if (spans[i].first < spans[i - 1].second) return fail(SYMPIX_EINVAL, "problem outputs overlap");
 
-    sympix_batch *bt = new (std::nothrow) sympix_batch();
+    sympix_batch *bt = injected_alloc_failure() ? nullptr : new (std::nothrow) sympix_batch();
     if (!bt) return fail(SYMPIX_ENOMEM, "host allocation");
     bt->device = p[0].b->device;
     bt->nprob = n;
@@ -928,7 +1030,9 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
             return hip_fail(e, "hipGetDeviceProperties");
         }
         static const char *mode_name[] = {"|fp64", "|fp32", "|bf16x3", "|bf16x6"};
-        shape = std::string(prop.gcnArchName) + mode_name[prec];
+        int rt = 0;
+        if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+        shape = std::string(prop.gcnArchName) + "|hip" + std::to_string(rt) + mode_name[prec];
         int occ = 0;
         e = sympix::batch_occupancy(prec, &occ);
         if (e != hipSuccess) {
@@ -1027,7 +1131,19 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tune_cache.find(bt->shape);
-        if (it != g_tune_cache.end()) plan = it->second;
+        if (it != g_tune_cache.end()) {
+            plan = it->second;
+        } else {
+            const std::string path = tune_cache_file();
+            if (!path.empty()) {
+                const std::map<std::string, int32_t> disk = read_tune_file(path);
+                auto d = disk.find(bt->shape);
+                if (d != disk.end()) {
+                    plan = d->second;
+                    g_tune_cache[bt->shape] = plan;
+                }
+            }
+        }
     }
     sympix_status s = capture_batch(bt, plan % SYMPIX_NSCHED, plan / SYMPIX_NSCHED);
     if (s != SYMPIX_OK) {
@@ -1106,13 +1222,268 @@ sympix_status sympix_batch_tune(sympix_batch *bt, void *stream, int32_t *chosen,
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tune_cache[bt->shape] = best;
+        const std::string path = tune_cache_file();
+        if (!path.empty() && !write_tune_file(path, bt->shape, best))
+            return fail(SYMPIX_EINVAL, "could not write the tuner cache file " + path);
     }
     if (chosen) *chosen = best;
     return SYMPIX_OK;
 }
 
+sympix_status sympix_batch_plan(const sympix_batch *bt, int32_t *plan) {
+    if (!bt || !plan) return fail(SYMPIX_EINVAL, "NULL argument");
+    *plan = bt->schedule + SYMPIX_NSCHED * bt->tiling;
+    return SYMPIX_OK;
+}
+
 void sympix_batch_destroy(sympix_batch *bt) {
     if (bt) free_batch(bt);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Two grids: B-hat = Y_2 B Y_1^T (Eqs. 13, 16) and B-hat^T N_2^-1 B-hat.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Device copies of a pair's tables: ring tables of g1 then g2, unique-block
+// descriptors, class tables of the contraction, and the B-hat expansion list.
+struct DevCross {
+    double *ring_theta = nullptr;
+    double *ring_sin = nullptr;
+    UInfo *uinfo = nullptr;
+    sympix::DevClass *classes = nullptr;
+    int32_t *class_terms = nullptr;
+    int32_t *class_blk = nullptr;
+    int32_t *class_itab = nullptr;
+    int32_t *mtiles = nullptr;
+    int32_t *exp_items = nullptr;
+    int32_t *exp_blk = nullptr;
+};
+
+void free_dev_cross(DevCross &d) {
+    hipFree(d.ring_theta);
+    hipFree(d.ring_sin);
+    hipFree(d.uinfo);
+    hipFree(d.classes);
+    hipFree(d.class_terms);
+    hipFree(d.class_blk);
+    hipFree(d.class_itab);
+    hipFree(d.mtiles);
+    hipFree(d.exp_items);
+    hipFree(d.exp_blk);
+    d = DevCross();
+}
+
+}  // namespace
+
+struct sympix_cross {
+    const sympix_grid *g2 = nullptr;      // auxiliary grid: rows of B-hat, N_2^-1
+    const sympix_grid *g1 = nullptr;      // grid of the unknowns: columns, stored blocks
+    sympix::CrossGeometry x;
+    mutable std::mutex mu;
+    mutable std::map<int, DevCross> dev;
+};
+
+namespace {
+
+sympix_status cross_tables(const sympix_cross *c, int device, const DevCross **out) {
+    std::lock_guard<std::mutex> lock(c->mu);
+    auto it = c->dev.find(device);
+    if (it != c->dev.end()) {
+        *out = &it->second;
+        return SYMPIX_OK;
+    }
+    const Geometry &g1 = c->g1->geo, &g2 = c->g2->geo;
+    const sympix::CrossGeometry &x = c->x;
+    std::vector<double> th(g1.theta), sn(g1.sin_theta);
+    th.insert(th.end(), g2.theta.begin(), g2.theta.end());
+    sn.insert(sn.end(), g2.sin_theta.begin(), g2.sin_theta.end());
+    std::vector<UInfo> uinfo(x.nunique());
+    for (int64_t u = 0; u < x.nunique(); ++u) {
+        const int64_t I = x.rep_i[u], J = x.rep_j[u];
+        const int bI = g2.tile_band[I], bJ = g1.tile_band[J];
+        UInfo f;
+        f.ring0_i = g1.nrings + g2.band_ring0[bI];   // rows: rings of g2, after those of g1
+        f.ring0_j = g1.band_ring0[bJ];
+        f.n_i = g2.k * g2.band_tiles[bI];
+        f.n_j = g1.k * g1.band_tiles[bJ];
+        f.p0_i = (int32_t)((I - g2.band_tile0[bI]) * g2.k);
+        f.p0_j = (int32_t)((J - g1.band_tile0[bJ]) * g1.k);
+        f.pad0 = f.pad1 = 0;
+        uinfo[u] = f;
+    }
+    DevCross d;
+    hipError_t e = upload(&d.ring_theta, th.data(), th.size());
+    if (e == hipSuccess) e = upload(&d.ring_sin, sn.data(), sn.size());
+    if (e == hipSuccess) e = upload(&d.uinfo, uinfo.data(), uinfo.size());
+    if (e == hipSuccess)
+        e = upload(&d.classes, reinterpret_cast<const sympix::DevClass *>(x.cls.classes.data()), x.cls.classes.size());
+    if (e == hipSuccess) e = upload(&d.class_terms, x.cls.class_terms.data(), x.cls.class_terms.size());
+    if (e == hipSuccess) e = upload(&d.class_blk, x.cls.class_blk.data(), x.cls.class_blk.size());
+    if (e == hipSuccess) e = upload(&d.class_itab, x.cls.class_itab.data(), x.cls.class_itab.size());
+    if (e == hipSuccess) e = upload(&d.mtiles, x.cls.mtiles.data(), x.cls.mtiles.size());
+    if (e == hipSuccess) e = upload(&d.exp_items, x.exp_items.data(), x.exp_items.size());
+    if (e == hipSuccess) e = upload(&d.exp_blk, x.exp_blk.data(), x.exp_blk.size());
+    if (e != hipSuccess) {
+        free_dev_cross(d);
+        return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the two-grid tables failed")
+                                        : hip_fail(e, "uploading the two-grid tables");
+    }
+    auto res = c->dev.emplace(device, d);
+    *out = &res.first->second;
+    return SYMPIX_OK;
+}
+
+sympix_status check_cross_kernel(const sympix_cross *c, const sympix_kernel *kr) {
+    if (!c || !kr) return fail(SYMPIX_EINVAL, "NULL pair or kernel");
+    if (kr->x != c) return fail(SYMPIX_EINVAL, "kernel was not tabulated for this pair of grids");
+    if (c->g1->geo.k != 8) return fail(SYMPIX_EUNSUPPORTED, "device sampling is implemented for k = 8 only");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != kr->device) return fail(SYMPIX_EINVAL, "kernel lives on another device than the current one");
+    return SYMPIX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sympix_status sympix_cross_create(const sympix_grid *g2, const sympix_grid *g1, sympix_cross **out) {
+    if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g2 || !g1) return fail(SYMPIX_EINVAL, "NULL grid");
+    sympix_cross *c = injected_alloc_failure() ? nullptr : new (std::nothrow) sympix_cross();
+    if (!c) return fail(SYMPIX_ENOMEM, "host allocation failed");
+    c->g2 = g2;
+    c->g1 = g1;
+    std::string err;
+    const int rc = injected_alloc_failure() ? (err = "host allocation failed building the two-grid tables (injected)", -3)
+                                            : sympix::build_cross(g2->geo, g1->geo, c->x, err);
+    if (rc != 0) {
+        delete c;
+        return fail((sympix_status)rc, err);
+    }
+    *out = c;
+    return SYMPIX_OK;
+}
+
+void sympix_cross_destroy(sympix_cross *c) {
+    if (!c) return;
+    for (auto &kv : c->dev) free_dev_cross(kv.second);
+    delete c;
+}
+
+sympix_status sympix_cross_dims(const sympix_cross *c, sympix_cross_sizes *out) {
+    if (!c || !out) return fail(SYMPIX_EINVAL, "NULL argument");
+    const sympix::CrossGeometry &x = c->x;
+    out->lmax_eff = x.lmax_eff;
+    out->max_terms = x.cls.max_class_terms;
+    out->nadjacency = (int64_t)x.adj_col.size();
+    out->nunique = x.nunique();
+    out->nblocks = c->g1->geo.nblocks();
+    out->nterms = (int64_t)x.terms.size();
+    out->y_pattern_max = x.y_pattern_max;
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_cross_neighbours(const sympix_cross *c, int32_t *container, int64_t *row_ptr, int32_t *col,
+                                      int32_t *uid) {
+    if (!c) return fail(SYMPIX_EINVAL, "NULL pair");
+    const sympix::CrossGeometry &x = c->x;
+    if (container) std::memcpy(container, x.container.data(), x.container.size() * sizeof(int32_t));
+    if (row_ptr) std::memcpy(row_ptr, x.adj_ptr.data(), x.adj_ptr.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, x.adj_col.data(), x.adj_col.size() * sizeof(int32_t));
+    if (uid) std::memcpy(uid, x.adj_uid.data(), x.adj_uid.size() * sizeof(int32_t));
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_cross_unique(const sympix_cross *c, int32_t *key_band_i, int32_t *key_band_j,
+                                  int64_t *key_delta) {
+    if (!c) return fail(SYMPIX_EINVAL, "NULL pair");
+    const sympix::CrossGeometry &x = c->x;
+    if (key_band_i) std::memcpy(key_band_i, x.key_band_i.data(), x.key_band_i.size() * sizeof(int32_t));
+    if (key_band_j) std::memcpy(key_band_j, x.key_band_j.data(), x.key_band_j.size() * sizeof(int32_t));
+    if (key_delta) std::memcpy(key_delta, x.key_delta.data(), x.key_delta.size() * sizeof(int64_t));
+    return SYMPIX_OK;
+}
+
+sympix_status sympix_kernel_tabulate_cross(const sympix_cross *c, const double *coef_l, int32_t ncoef,
+                                           double radius, int32_t n_nodes, void *stream, sympix_kernel **out) {
+    if (!out) return fail(SYMPIX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !coef_l) return fail(SYMPIX_EINVAL, "NULL pair or coefficients");
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const DevCross *dx = nullptr;
+    sympix_status s = cross_tables(c, device, &dx);
+    if (s != SYMPIX_OK) return s;
+    TabSource src{c->x.lmax_eff, c->x.y_pattern_max, c->x.nunique(), dx->uinfo, dx->ring_theta, dx->ring_sin};
+    return tabulate(src, nullptr, c, device, coef_l, ncoef, radius, n_nodes, (hipStream_t)stream, out);
+}
+
+sympix_status sympix_sample_B_cross(const sympix_cross *c, const sympix_kernel *b, double *out_dev, int64_t out_len,
+                                    void *stream) {
+    sympix_status s = check_cross_kernel(c, b);
+    if (s != SYMPIX_OK) return s;
+    const sympix::CrossGeometry &x = c->x;
+    if (out_len != (int64_t)x.adj_col.size() * sympix::kBlockElems)
+        return fail(SYMPIX_ESIZE, "out_len must be nadjacency * k^4");
+    if (out_len > 0 && !out_dev) return fail(SYMPIX_EINVAL, "out_dev is NULL");
+    if (((uintptr_t)out_dev) % 16) return fail(SYMPIX_EINVAL, "out_dev must be 16-byte aligned");
+    const DevCross *dx = nullptr;
+    s = cross_tables(c, b->device, &dx);
+    if (s != SYMPIX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    return after_launch(sympix::launch_expand(b->u64, dx->exp_items, (int64_t)x.exp_items.size() / 4, dx->exp_blk,
+                                              out_dev, st),
+                        st, "sample_B_cross");
+}
+
+sympix_status sympix_sample_BtNB_cross(const sympix_cross *c, const sympix_kernel *b, const double *ninv2_dev,
+                                       int64_t ninv2_len, int32_t prec, double *out_dev, int64_t out_len,
+                                       void *stream) {
+    sympix_status s = check_cross_kernel(c, b);
+    if (s != SYMPIX_OK) return s;
+    const Geometry &g1 = c->g1->geo, &g2 = c->g2->geo;
+    const sympix::CrossGeometry &x = c->x;
+    if (prec < SYMPIX_FP64 || prec > SYMPIX_BF16X6) return fail(SYMPIX_EINVAL, "unknown precision mode");
+    if (ninv2_len != g2.npix) return fail(SYMPIX_ESIZE, "ninv2_len must be npix of the auxiliary grid");
+    const int64_t nblocks = g1.nblocks();
+    if (out_len != nblocks * sympix::kBlockElems) return fail(SYMPIX_ESIZE, "out_len must be nblocks * k^4");
+    if ((g2.npix > 0 && !ninv2_dev) || (out_len > 0 && !out_dev)) return fail(SYMPIX_EINVAL, "NULL device buffer");
+    if (((uintptr_t)out_dev) % 16 || ((uintptr_t)ninv2_dev) % 32)
+        return fail(SYMPIX_EINVAL, "out_dev must be 16-byte and ninv2_dev 32-byte aligned");
+    if (out_len > 0) {
+        const char *o = (const char *)out_dev, *w = (const char *)ninv2_dev;
+        const size_t ob = (size_t)out_len * sizeof(double), nb = (size_t)ninv2_len * sizeof(double);
+        if (o < w + nb && w < o + ob) return fail(SYMPIX_EINVAL, "the output overlaps ninv2_dev");
+    }
+    if (x.cls.max_class_terms > sympix::kMaxClassTerms)
+        return fail(SYMPIX_EUNSUPPORTED, "a block has more contraction tiles than the class GEMM supports");
+    const DevCross *dx = nullptr;
+    s = cross_tables(c, b->device, &dx);
+    if (s != SYMPIX_OK) return s;
+    sympix::BtnbArgs a;
+    a.u64t = b->u64t;
+    a.ut32 = b->ut32;
+    a.classes = dx->classes;
+    a.class_terms = dx->class_terms;
+    a.class_blk = dx->class_blk;
+    a.class_itab = dx->class_itab;
+    a.mtiles = dx->mtiles;
+    a.nmtiles = (int64_t)x.cls.mtiles.size() / 4;
+    a.nblocks = nblocks;
+    a.npix = g2.npix;
+    a.ninv = ninv2_dev;
+    a.out = out_dev;
+    a.du64 = nullptr;
+    a.blk_uid = nullptr;
+    a.outD = nullptr;
+    return launch_contraction(a, b->device, prec, false, (hipStream_t)stream, "sample_BtNB_cross");
 }
 
 }  // extern "C"

@@ -35,7 +35,10 @@ struct KTable {
 
 constexpr int kBlockDim = 64;              // k^2 for k = 8
 constexpr int kBlockElems = 64 * 64;
-constexpr int kMaxClassTerms = 16;      // member-tile table width in the class GEMM
+constexpr int kMaxClassTerms = 128;     // contraction terms a class may have (two-grid blocks have up to ~4x
+                                        // the one-grid count when Y_2 has twice Y_1's resolution)
+constexpr int kTileStride = kMaxClassTerms + 1;   // LDS row stride of the member-tile table (odd: no bank
+                                                  // conflicts when the lanes of a wave read 16 rows)
 
 // a6: table of sum_l c_l P_l(1 - s^2), c_l = (2l+1) coef_l / 4 pi
 hipError_t launch_tabulate(const double *coef, int32_t lmax, double h, double *table,

@@ -237,6 +237,39 @@ void build_classes(const std::vector<int64_t> &term_ptr, const std::vector<Term>
 
 }  // namespace
 
+// Largest y = 1 - cos(gamma) over every pair of a set of blocks: per block
+// the largest |phi offset| over the k x k column pairs, then every ring pair.
+// Rows on grid gi (tile I), columns on grid gj (tile J).
+static double blocks_y_max(const Geometry &gi, const Geometry &gj, const std::vector<int32_t> &rep_i,
+                           const std::vector<int32_t> &rep_j) {
+    const int k = gj.k;
+    double ymax = 0.0;
+    for (size_t u = 0; u < rep_i.size(); ++u) {
+        const int64_t I = rep_i[u], J = rep_j[u];
+        const int bI = gi.tile_band[I], bJ = gj.tile_band[J];
+        const int64_t nI = (int64_t)k * gi.band_tiles[bI], nJ = (int64_t)k * gj.band_tiles[bJ];
+        const int64_t pI0 = (I - gi.band_tile0[bI]) * k, pJ0 = (J - gj.band_tile0[bJ]) * k;
+        const int64_t M = nI * nJ;
+        int64_t nmax = 0;
+        for (int c = 0; c < k; ++c)
+            for (int c2 = 0; c2 < k; ++c2) {
+                int64_t N = pos_mod((2 * (pJ0 + c2) + 1) * nI - (2 * (pI0 + c) + 1) * nJ, 2 * M);
+                if (N > M) N -= 2 * M;
+                nmax = std::max(nmax, N < 0 ? -N : N);
+            }
+        const double sh = std::sin(0.5 * (kPi * (double)nmax / (double)M));
+        const double hmax = sh * sh;
+        for (int r = 0; r < k; ++r)
+            for (int r2 = 0; r2 < k; ++r2) {
+                const int j1 = gi.band_ring0[bI] + r, j2 = gj.band_ring0[bJ] + r2;
+                const double sd = std::sin(0.5 * (gi.theta[j1] - gj.theta[j2]));
+                const double y = 2.0 * (sd * sd + gi.sin_theta[j1] * gj.sin_theta[j2] * hmax);
+                ymax = std::max(ymax, y);
+            }
+    }
+    return ymax;
+}
+
 int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::string &err) {
     try {
         if (lmax < 1 || k < 1 || k > 64 || lmax > 100000) {
@@ -441,33 +474,7 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
 
         build_classes(g.term_ptr, g.terms, g.cls);
 
-        // largest y = 1 - cos(gamma) over every pattern pair: per unique block the
-        // largest |phi offset| over the k x k column pairs, then every ring pair
-        double ymax = 0.0;
-        for (int64_t u = 0; u < g.nunique(); ++u) {
-            const int64_t I = g.rep_i[u], J = g.rep_j[u];
-            const int bI = g.tile_band[I], bJ = g.tile_band[J];
-            const int64_t nI = (int64_t)k * g.band_tiles[bI], nJ = (int64_t)k * g.band_tiles[bJ];
-            const int64_t pI0 = (I - g.band_tile0[bI]) * k, pJ0 = (J - g.band_tile0[bJ]) * k;
-            const int64_t M = nI * nJ;
-            int64_t nmax = 0;
-            for (int c = 0; c < k; ++c)
-                for (int c2 = 0; c2 < k; ++c2) {
-                    int64_t N = pos_mod((2 * (pJ0 + c2) + 1) * nI - (2 * (pI0 + c) + 1) * nJ, 2 * M);
-                    if (N > M) N -= 2 * M;
-                    nmax = std::max(nmax, N < 0 ? -N : N);
-                }
-            const double sh = std::sin(0.5 * (kPi * (double)nmax / (double)M));
-            const double hmax = sh * sh;
-            for (int r = 0; r < k; ++r)
-                for (int r2 = 0; r2 < k; ++r2) {
-                    const int j1 = g.band_ring0[bI] + r, j2 = g.band_ring0[bJ] + r2;
-                    const double sd = std::sin(0.5 * (g.theta[j1] - g.theta[j2]));
-                    const double y = 2.0 * (sd * sd + g.sin_theta[j1] * g.sin_theta[j2] * hmax);
-                    ymax = std::max(ymax, y);
-                }
-        }
-        g.y_pattern_max = ymax;
+        g.y_pattern_max = blocks_y_max(g, g, g.rep_i, g.rep_j);
         return 0;
     } catch (const std::bad_alloc &) {
         err = "host allocation failed while building the grid";
@@ -520,6 +527,129 @@ int build_two_hop(const Geometry &g, Pattern &p, std::string &err) {
         return 0;
     } catch (const std::bad_alloc &) {
         err = "host allocation failed building the two-hop pattern";
+        return -3;
+    }
+}
+
+int build_cross(const Geometry &g2, const Geometry &g1, CrossGeometry &x, std::string &err) {
+    try {
+        x = CrossGeometry();
+        if (g1.k != g2.k) {
+            err = "the two grids must have the same tile size k";
+            return -6;
+        }
+        x.lmax_eff = std::min(g1.lmax, g2.lmax);
+        const int64_t k = g1.k, R1 = g1.nrings;
+        // the tile of g1 holding the centre of every tile of g2: colatitude
+        // (lo + hi) / (2 R2) pi, longitude (2t + 1) / (2T) turn; half-open
+        // band ranges [ik, (i+1)k) / R1 north, [R1 - (i+1)k, R1 - ik) / R1 south
+        x.container.resize(g2.ntiles);
+        for (size_t b = 0; b < g2.band_tiles.size(); ++b) {
+            const int64_t i2 = (int64_t)b / 2, south2 = (int64_t)b % 2, R2 = g2.nrings;
+            const int64_t lo = south2 ? R2 - (i2 + 1) * k : i2 * k, hi = lo + k;
+            const int64_t th_num = lo + hi, th_den = 2 * R2;
+            const int64_t xs = th_num * R1;                 // theta R1 = xs / th_den
+            int b1;
+            if (2 * th_num < th_den) {
+                b1 = (int)(2 * (xs / (th_den * k)));
+            } else {
+                const int64_t ys = R1 * th_den - xs;        // (1 - theta) R1 th_den > 0
+                b1 = (int)(2 * ((ys + th_den * k - 1) / (th_den * k) - 1) + 1);
+            }
+            const int64_t T2 = g2.band_tiles[b], T1 = g1.band_tiles[b1];
+            for (int64_t t = 0; t < T2; ++t)
+                x.container[g2.band_tile0[b] + t] = (int32_t)(g1.band_tile0[b1] + ((2 * t + 1) * T1) / (2 * T2));
+        }
+        // adjacency rows: the g1 neighbours of each tile's container; keys in
+        // the one-grid order (I ascending, then J ascending)
+        std::map<std::tuple<int32_t, int32_t, int64_t>, int32_t> keys;
+        x.adj_ptr.assign(g2.ntiles + 1, 0);
+        for (int64_t I = 0; I < g2.ntiles; ++I) {
+            const int64_t C = x.container[I];
+            const int bI = g2.tile_band[I];
+            const int64_t TI = g2.band_tiles[bI], tI = I - g2.band_tile0[bI];
+            for (int64_t e = g1.adj_ptr[C]; e < g1.adj_ptr[C + 1]; ++e) {
+                const int64_t J = g1.adj_col[e];
+                const int bJ = g1.tile_band[J];
+                const int64_t TJ = g1.band_tiles[bJ], tJ = J - g1.band_tile0[bJ];
+                const int64_t delta = pos_mod(tJ * TI - tI * TJ, TI * TJ);
+                auto key = std::make_tuple((int32_t)bI, (int32_t)bJ, delta);
+                auto it = keys.find(key);
+                int32_t uid;
+                if (it == keys.end()) {
+                    uid = (int32_t)x.key_delta.size();
+                    keys.emplace(key, uid);
+                    x.key_band_i.push_back(bI);
+                    x.key_band_j.push_back(bJ);
+                    x.key_delta.push_back(delta);
+                    x.rep_i.push_back((int32_t)I);
+                    x.rep_j.push_back((int32_t)J);
+                } else {
+                    uid = it->second;
+                }
+                x.adj_col.push_back((int32_t)J);
+                x.adj_uid.push_back(uid);
+            }
+            x.adj_ptr[I + 1] = (int64_t)x.adj_col.size();
+        }
+        // transpose: the tiles of g2 neighbouring each tile of g1, ascending
+        x.nbr_ptr.assign(g1.ntiles + 1, 0);
+        for (int32_t J : x.adj_col) ++x.nbr_ptr[J + 1];
+        for (int64_t J = 0; J < g1.ntiles; ++J) x.nbr_ptr[J + 1] += x.nbr_ptr[J];
+        x.nbr_col.assign(x.adj_col.size(), 0);
+        {
+            std::vector<int64_t> pos(x.nbr_ptr.begin(), x.nbr_ptr.end() - 1);
+            for (int64_t I = 0; I < g2.ntiles; ++I)
+                for (int64_t e = x.adj_ptr[I]; e < x.adj_ptr[I + 1]; ++e) x.nbr_col[pos[x.adj_col[e]]++] = (int32_t)I;
+        }
+        auto uid_of = [&](int64_t I, int64_t J) -> int32_t {
+            auto first = x.adj_col.begin() + x.adj_ptr[I], last = x.adj_col.begin() + x.adj_ptr[I + 1];
+            auto it = std::lower_bound(first, last, (int32_t)J);
+            return x.adj_uid[it - x.adj_col.begin()];
+        };
+        // terms of every stored block (J, K) of g1: I in nbr(J) & nbr(K), ascending
+        x.term_ptr.push_back(0);
+        for (int64_t J = 0; J < g1.ntiles; ++J)
+            for (int64_t n = g1.blk_ptr[J]; n < g1.blk_ptr[J + 1]; ++n) {
+                const int64_t K = g1.blk_col[n];
+                auto a = x.nbr_col.begin() + x.nbr_ptr[J], ae = x.nbr_col.begin() + x.nbr_ptr[J + 1];
+                auto b = x.nbr_col.begin() + x.nbr_ptr[K], be = x.nbr_col.begin() + x.nbr_ptr[K + 1];
+                while (a != ae && b != be) {
+                    if (*a < *b) ++a;
+                    else if (*b < *a) ++b;
+                    else {
+                        const int64_t I = *a;
+                        x.terms.push_back(Term{uid_of(I, J), uid_of(I, K), (int32_t)I, 0});
+                        ++a;
+                        ++b;
+                    }
+                }
+                x.term_ptr.push_back((int64_t)x.terms.size());
+            }
+        // B-hat output blocks (one per adjacency entry) grouped by unique
+        // block, work items of at most 64 {uid, first, count, 0}
+        {
+            const int64_t nadj = (int64_t)x.adj_col.size();
+            std::vector<int64_t> cnt(x.nunique() + 1, 0);
+            for (int32_t u : x.adj_uid) ++cnt[u + 1];
+            for (int64_t u = 0; u < x.nunique(); ++u) cnt[u + 1] += cnt[u];
+            if (nadj >= INT32_MAX) {
+                err = "too many B-hat blocks";
+                return -5;
+            }
+            x.exp_blk.assign(nadj, 0);
+            std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+            for (int64_t e = 0; e < nadj; ++e) x.exp_blk[pos[x.adj_uid[e]]++] = (int32_t)e;
+            for (int64_t u = 0; u < x.nunique(); ++u)
+                for (int64_t f = cnt[u]; f < cnt[u + 1]; f += 64)
+                    x.exp_items.insert(x.exp_items.end(),
+                                       {(int32_t)u, (int32_t)f, (int32_t)std::min<int64_t>(64, cnt[u + 1] - f), 0});
+        }
+        build_classes(x.term_ptr, x.terms, x.cls);
+        x.y_pattern_max = blocks_y_max(g2, g1, x.rep_i, x.rep_j);
+        return 0;
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed building the two-grid tables";
         return -3;
     }
 }

@@ -110,11 +110,39 @@ struct Geometry {
     int64_t nunique() const { return (int64_t)key_delta.size(); }
 };
 
+// B-hat between two grids (rows on the auxiliary grid g2, columns on g1) and
+// the contraction terms of B-hat^T N_2^-1 B-hat over the stored blocks of g1.
+// Tile I of g2 neighbours tile J of g1 when the tile of g1 holding I's centre
+// is J or a neighbour of J; blocks are keyed by (band of I in g2, band of J in
+// g1, (t_J T_I - t_I T_J) mod T_I T_J).  With g2 = g1 every table equals the
+// one-grid table it corresponds to.
+struct CrossGeometry {
+    int32_t lmax_eff = 0;                 // min(lmax_1, lmax_2)
+    std::vector<int32_t> container;       // per tile of g2: tile of g1 holding its centre
+    std::vector<int64_t> adj_ptr;         // CSR over tiles I of g2: tiles J of g1, ascending
+    std::vector<int32_t> adj_col;
+    std::vector<int32_t> adj_uid;         // unique-block id of each (I, J) entry
+    std::vector<int32_t> key_band_i, key_band_j;
+    std::vector<int64_t> key_delta;
+    std::vector<int32_t> rep_i, rep_j;    // a representative (I in g2, J in g1) per key
+    std::vector<int64_t> nbr_ptr;         // CSR over tiles J of g1: tiles I of g2, ascending
+    std::vector<int32_t> nbr_col;
+    std::vector<int64_t> term_ptr;        // per stored block of g1, its terms
+    std::vector<Term> terms;              // tile = I of g2 (N_2^-1 pixels [I k^2, (I+1) k^2))
+    ClassTables cls;
+    std::vector<int32_t> exp_blk, exp_items;   // B-hat blocks (adjacency entries) grouped by unique block
+    double y_pattern_max = 0.0;
+    int64_t nunique() const { return (int64_t)key_delta.size(); }
+};
+
 // Status codes follow sympix_status. On failure err holds a message.
 int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::string &err);
 
 // The two-hop pattern: every (J, K >= J) whose neighbourhoods intersect, i.e.
 // every block of B-hat^T N^-1 B-hat that is not zero when B-hat is local.
 int build_two_hop(const Geometry &g, Pattern &p, std::string &err);
+
+// The two-grid tables of B-hat = Y_2 B Y_1^T (g2 auxiliary, g1 the unknowns).
+int build_cross(const Geometry &g2, const Geometry &g1, CrossGeometry &x, std::string &err);
 
 }  // namespace sympix

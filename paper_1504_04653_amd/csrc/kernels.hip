@@ -346,7 +346,7 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
     for (int x = threadIdx.x; x < 16 * NI * nterms; x += 256) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
-        sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
+        sTile[r * kTileStride + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
     if (threadIdx.x < 64) {
         const int blk = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
@@ -360,7 +360,7 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
     auto ptrs = [&](int a, int e, Ptrs &q) {
 #pragma unroll
         for (int i = 0; i < NI; ++i)
-            q.w[i] = wv + (int64_t)sTile[(16 * i + lr) * kMaxClassTerms + e] * 64 + 4 * lk;
+            q.w[i] = wv + (int64_t)sTile[(16 * i + lr) * kTileStride + e] * 64 + 4 * lk;
         q.u1 = ut + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 4 * lk;
         q.u2 = ut + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + lr * 64 + 4 * lk;
     };
@@ -461,7 +461,7 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
 template <bool WD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_class_f64(ProblemDesc64 pd) {
-    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sTile[64 * kTileStride];
     __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     const int item = xcd_contiguous_index();
@@ -495,7 +495,7 @@ __device__ __forceinline__ int batch_next_item(const int32_t *__restrict__ qb, i
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_batch_f64(const ProblemDesc64 *__restrict__ probs, const int32_t *__restrict__ items,
                  const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
-    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sTile[64 * kTileStride];
     __shared__ int32_t sBlk[128];
     __shared__ int32_t sTerm[2 * kMaxClassTerms];
     __shared__ int32_t sItem;
@@ -556,7 +556,7 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     for (int x = tid; x < 16 * NI * nterms; x += NT) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
-        sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
+        sTile[r * kTileStride + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
     if (tid < 64) {
         const int blk = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
@@ -573,7 +573,7 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     // wave reads.  LDS row r keeps its chunk c at 8 r + (c ^ usw(r)).
     auto usw = [](int b) { return ((b >> 1) ^ (b << 2)) & 7; };
     const int srow = tid >> 3, sch = tid & 7;
-    const int wrow = min(srow, 16 * NI - 1) * kMaxClassTerms;
+    const int wrow = min(srow, 16 * NI - 1) * kTileStride;
     const int sdst = srow * 8 + (sch ^ usw(srow));
     struct SAddr { int64_t wo; const float *u2; };
     struct OAddr { const float *p1; };
@@ -747,7 +747,7 @@ __device__ __forceinline__ void class_f32_item(const ProblemDesc &pd, int item, 
 template <bool WD>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_class_f32(ProblemDesc pd) {
-    __shared__ int32_t sTile[64 * kMaxClassTerms];   // tile I of (member row, term)
+    __shared__ int32_t sTile[64 * kTileStride];   // tile I of (member row, term)
     __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ floatx4 sW[4 * 512];                  // staged W, four buffers
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(64) void k_fill_i32(int32_t *p, int32_t n, int32_t 
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_batch_f32(const ProblemDesc *__restrict__ probs, const int32_t *__restrict__ items,
                  const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
-    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sTile[64 * kTileStride];
     __shared__ int32_t sBlk[128];
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ floatx4 sW[4 * 512];
@@ -878,7 +878,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     for (int x = tid; x < 16 * NI * nterms; x += NT) {
         const int r = x / nterms, e = x - r * nterms;
         const int m = min(m0 + r, cl.nblocks - 1);   // rows past the class repeat its last member
-        sTile[r * kMaxClassTerms + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
+        sTile[r * kTileStride + e] = pd.citab[cl.itab0 + (int64_t)m * nterms + e];
     }
     if (tid < 64) {
         const int blk = lane < 16 * NI && m0 + lane < cl.nblocks ? pd.cblk[cl.blk0 + m0 + lane] : -1;
@@ -906,7 +906,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
         if (c >= 256 * NP) c -= 256;
         const int k = __builtin_amdgcn_readfirstlane(c >> 8), q = c & 255, row = q >> 2, sub = q & 3;
         wsrc[r] = pd.w[k] + 8 * sub;
-        wrow[r] = min(row, 16 * NI - 1) * kMaxClassTerms;
+        wrow[r] = min(row, 16 * NI - 1) * kTileStride;
         // LDS layouts, in 16-byte chunks: W row r (64 bytes) keeps its chunk c at
         // 4 r + (c ^ wsw(r)), a B_IK row b (128 bytes) its chunk c at 8 b + (c ^
         // usw(b)); every read and write phase then touches distinct banks,
@@ -1134,7 +1134,7 @@ __device__ __forceinline__ void class_bf16_item(const ProblemDescB &pd, int item
 template <int NP, bool WD>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_class_bf16(ProblemDescB pd) {
-    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sTile[64 * kTileStride];
     __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ u16x8 sW[4 * NP * 64 * 4];            // staged W, four buffers
@@ -1148,7 +1148,7 @@ template <int NP>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_batch_bf16(const ProblemDescB *__restrict__ probs, const int32_t *__restrict__ items,
                   const int32_t *__restrict__ qb, int32_t nq, int32_t *__restrict__ counters) {
-    __shared__ int32_t sTile[64 * kMaxClassTerms];
+    __shared__ int32_t sTile[64 * kTileStride];
     __shared__ int32_t sBlk[128];
     __shared__ int32_t sTerm[2 * kMaxClassTerms];
     __shared__ u16x8 sW[4 * NP * 64 * 4];

@@ -1,5 +1,6 @@
 """Host-side tests of the C ABI (no GPU): exported symbols, grid layout and
 symmetry keys against the oracle bit for bit, and error paths."""
+import ctypes
 import math
 import os
 import re
@@ -167,3 +168,94 @@ def test_one_hip_runtime_in_the_process():
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
 
+
+
+# --- two grids: B-hat = Y_2 B Y_1^T ------------------------------------------
+
+CROSS_CASES = [((128, 8, None), (64, 8, None)), ((512, 8, None), (256, 8, None)), ((300, 8, None), (100, 8, None)),
+               ((64, 8, None), (128, 8, None)), ((34, 2, 2.0), (16, 2, None)), ((32, 2, 0.0), (20, 2, 0.0))]
+
+
+@pytest.mark.parametrize("c2,c1", CROSS_CASES)
+def test_cross_tables_bit_exact_against_oracle(c2, c1):
+    """The library's two-grid relation (centre containers, CSR), block keys and
+    term count equal the oracle's, built from its own integer arithmetic."""
+    from oracle import twogrid as X
+    og2, og1 = G.make_grid(c2[0], c2[1], polar_margin=c2[2]), G.make_grid(c1[0], c1[1], polar_margin=c1[2])
+    g2, g1 = sp.Grid(*c2), sp.Grid(*c1)
+    x = sp.Cross(g2, g1)
+    assert x.lmax_eff == min(c1[0], c2[0]) and x.nblocks == g1.nblocks
+    cont, rp, col, uid = x.neighbours()
+    assert np.array_equal(cont, X.centre_containers(og2, og1))
+    orp, ocol = X.cross_adjacency(og2, og1)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    bi, bj, de = x.unique()
+    keys = set()
+    for I in range(og2.ntiles):
+        for e in range(rp[I], rp[I + 1]):
+            key = X.cross_key(og2, I, og1, int(col[e]))
+            assert (bi[uid[e]], bj[uid[e]], de[uid[e]]) == key
+            keys.add(key)
+    assert len(keys) == x.nunique
+    nbr = [[] for _ in range(og1.ntiles)]
+    for I in range(og2.ntiles):
+        for J in col[rp[I]:rp[I + 1]]:
+            nbr[int(J)].append(I)
+    brp, bcol = g1.blocks()
+    nterms = sum(len(set(nbr[J]) & set(nbr[int(K)])) for J in range(og1.ntiles) for K in bcol[brp[J]:brp[J + 1]])
+    assert x.nterms == nterms
+
+
+@pytest.mark.parametrize("lmax,k,margin", [(64, 8, None), (256, 8, None), (34, 2, 2.0)])
+def test_cross_of_a_grid_with_itself_is_the_one_grid_table(lmax, k, margin):
+    g = sp.Grid(lmax, k, margin)
+    x = sp.Cross(g, g)
+    cont, rp, col, uid = x.neighbours()
+    assert np.array_equal(cont, np.arange(g.ntiles))
+    nrp, ncol = g.neighbours()
+    assert np.array_equal(rp, nrp) and np.array_equal(col, ncol)
+    guid, gbi, gbj, gde = g.unique()
+    assert np.array_equal(uid, guid)
+    bi, bj, de = x.unique()
+    assert np.array_equal(bi, gbi) and np.array_equal(bj, gbj) and np.array_equal(de, gde)
+    assert (x.nterms, x.nunique, x.lmax_eff) == (g.nterms, g.nunique, lmax)
+    assert x.y_pattern_max == g.y_pattern_max
+
+
+def test_cross_errors():
+    with pytest.raises(sp.SympixError) as e:
+        sp.Cross(sp.Grid(64, 8), sp.Grid(40, 4))
+    assert e.value.code == "EUNSUPPORTED"
+    assert sp.raw_call("sympix_cross_dims")(None, None) == -1
+    sp.raw_call("sympix_cross_destroy")(None)
+
+
+def test_injected_allocation_failures_return_enomem(monkeypatch):
+    """SYMPIX_FAIL_ALLOC=n fails the n-th host allocation point reached since
+    the variable took its value: ENOMEM, no handle, message set; the next
+    point (or an unset variable) succeeds, and NULL handles stay destroyable."""
+    create = sp.raw_call("sympix_grid_create")
+    for n, want in ((1, -3), (2, -3), (3, 0)):
+        monkeypatch.setenv("SYMPIX_FAIL_ALLOC", str(n))
+        h = ctypes.c_void_p(1)
+        assert create(64, 8, math.nan, ctypes.byref(h)) == want
+        if want:
+            assert not h.value and b"allocation" in sp.raw_call("sympix_last_error")()
+        else:
+            sp.raw_call("sympix_grid_destroy")(h)
+        monkeypatch.delenv("SYMPIX_FAIL_ALLOC")
+    g = sp.Grid(64, 8)
+    for n in (1, 2):
+        monkeypatch.setenv("SYMPIX_FAIL_ALLOC", str(n))
+        with pytest.raises(sp.SympixError) as e:
+            sp.Cross(g, g)
+        assert e.value.code == "ENOMEM"
+        monkeypatch.delenv("SYMPIX_FAIL_ALLOC")
+    monkeypatch.setenv("SYMPIX_FAIL_ALLOC", "1")
+    with pytest.raises(sp.SympixError) as e:
+        g.pattern_size("two_hop")
+    assert e.value.code == "ENOMEM"
+    monkeypatch.delenv("SYMPIX_FAIL_ALLOC")
+    assert g.pattern_size("two_hop")[0] > g.nblocks           # the pattern builds once the hook is off
+    sp.raw_call("sympix_cross_destroy")(None)
+    sp.raw_call("sympix_grid_destroy")(None)

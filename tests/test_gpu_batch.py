@@ -240,3 +240,50 @@ def test_c5_full_batch_sampled(prec):
     for p in probs:
         del p["out"]
     torch.cuda.empty_cache()
+
+
+TUNE_SCRIPT = r"""
+import sys
+import numpy as np
+import torch
+import paper_1504_04653_amd as sp
+from workloads import synth as S
+torch.cuda.set_device(0)
+keep = []
+for lmax, p in ((64, 0), (128, 1)):
+    g = sp.Grid(lmax, 8)
+    b_l, R = S.gaussian_beam(lmax, g.npix, 3.0)
+    kb = sp.Kernel(g, b_l, R)
+    n = torch.as_tensor(np.random.default_rng(p).uniform(0.5, 2.0, g.npix)).cuda()
+    out = torch.empty(g.out_len, dtype=torch.float64, device="cuda")
+    keep.append((g, kb, n, out))
+bt = sp.Batch(keep, prec="fp32")
+if sys.argv[1] == "tune":
+    chosen, _ = bt.tune()
+    print("PLAN", chosen, flush=True)
+else:
+    print("PLAN", bt.plan(), flush=True)
+bt.close()
+"""
+
+
+def test_tuner_cache_file_carries_the_plan_to_another_process(tmp_path):
+    """SYMPIX_TUNE_CACHE: one process tunes and records its plan in the file;
+    a later process creating a batch of the same problems starts from it."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, SYMPIX_TUNE_CACHE=str(cache), PYTHONPATH=root)
+
+    def run(mode):
+        res = subprocess.run([sys.executable, "-c", TUNE_SCRIPT, mode], capture_output=True, text=True, env=env,
+                             timeout=300, cwd=root)
+        assert res.returncode == 0, res.stderr[-2000:]
+        return int([l for l in res.stdout.splitlines() if l.startswith("PLAN")][0].split()[1])
+
+    chosen = run("tune")
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].endswith("\t%d" % chosen) and "|fp32|" in lines[0]
+    assert run("plan") == chosen
+    say(f"[batch] tuner cache file: plan {sp.plan_name(chosen)} recorded and picked up by a new process")

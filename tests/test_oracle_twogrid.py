@@ -1,6 +1,6 @@
 """Pins for the oracle's two-grid operator B-hat = Y_2 B Y_1^T (Eqs. 13 and
 16) and B-hat^T N_2^-1 B-hat (Eq. 15): the tile relation against an
-independent floating-point rectangle test, every block and the product against
+independent floating-point location of tile centres, every block and the product against
 a dense per-pair brute force on small grid pairs (including tile sizes that
 differ, so the blocks are rectangular), the band limit of the kernel against
 the addition theorem, and the limit Y_2 = Y_1, which must reproduce the
@@ -36,7 +36,7 @@ def _gate(C, ref, pairs):
 
 
 @pytest.mark.parametrize("pair", PAIRS)
-def test_relation_matches_floating_point_rectangles(pair):
+def test_relation_matches_floating_point_centre_location(pair):
     g2, g1 = _grids(pair)
     rp, col = X.cross_adjacency(g2, g1)
     got = np.zeros((g2.ntiles, g1.ntiles), dtype=bool)
@@ -44,6 +44,7 @@ def test_relation_matches_floating_point_rectangles(pair):
         got[I, col[rp[I]:rp[I + 1]]] = True
     assert np.array_equal(got, BR.cross_relation_dense(g2, g1))
     assert got.any(axis=0).all() and got.any(axis=1).all()     # every tile has a partner
+    assert [X.tile_centre_container(g2, g1, I) for I in range(g2.ntiles)] == X.centre_containers(g2, g1).tolist()
 
 
 def test_band_ranges_contain_their_rings():
