@@ -23,6 +23,7 @@ struct UInfo {
 struct DevClass {
     int32_t nterms, nblocks, term0, blk0;
     int64_t itab0;
+    int32_t sym, pad;      // sym: every member block is symmetric
 };
 
 // Tabulated kernel as seen by device code.

@@ -211,6 +211,9 @@ void build_classes(const std::vector<int64_t> &term_ptr, const std::vector<Term>
         bc.term0 = (int32_t)(ct.class_terms.size() / 2);
         bc.blk0 = (int32_t)ct.class_blk.size();
         bc.itab0 = (int64_t)ct.class_itab.size();
+        bc.sym = 1;
+        for (size_t q = 0; q + 1 < keys[c].size(); q += 2) bc.sym &= keys[c][q] == keys[c][q + 1] ? 1 : 0;
+        bc.pad = 0;
         ct.class_terms.insert(ct.class_terms.end(), keys[c].begin(), keys[c].end());
         ct.class_blk.insert(ct.class_blk.end(), members[c].begin(), members[c].end());
         ct.class_itab.insert(ct.class_itab.end(), tiles_of[c].begin(), tiles_of[c].end());

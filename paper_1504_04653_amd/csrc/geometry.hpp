@@ -26,6 +26,9 @@ struct BlockClass {
     int32_t term0;   // first (uid_a, uid_b) pair in class_terms (pairs)
     int32_t blk0;    // first block in class_blk
     int64_t itab0;   // first entry in class_itab (nblocks * nterms, block-major)
+    int32_t sym;     // 1 if every term pairs a unique block with itself: the
+                     // members' blocks are symmetric (C_m[a][b] = C_m[b][a])
+    int32_t pad;
 };
 
 // The contraction of a stored-block pattern in class-GEMM form.

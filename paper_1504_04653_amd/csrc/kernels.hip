@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -364,13 +365,22 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         q.u1 = ut + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 4 * lk;
         q.u2 = ut + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + lr * 64 + 4 * lk;
     };
+    // Symmetric classes (every term pairs a unique block with itself, the
+    // blocks (J, J)): C[a][b] = C[b][a] bit for bit, since the products
+    // B[p][a] B[p][b] are the same numbers either way round.  Row a then
+    // computes only the column groups j >= a / 16 (10 of the 16 16x16 tiles)
+    // and writes the tiles below the diagonal as mirror images.  Wave w's row
+    // x is a = w + 4 x, so a / 16 = x / 4: rows run in four phases with the
+    // first column group JLO fixed at compile time (0 for every row of other
+    // classes).
     struct Frag { doublex4 w[NI], u1, u2[4]; };
-    auto load = [&](const Ptrs &q, int g, Frag &f) {
+    auto load = [&](auto jt, const Ptrs &q, int g, Frag &f) {
+        constexpr int JLO = decltype(jt)::value;
 #pragma unroll
         for (int i = 0; i < NI; ++i) f.w[i] = *(const doublex4 *)(q.w[i] + 16 * g);
         f.u1 = *(const doublex4 *)(q.u1 + 16 * g);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) f.u2[j] = *(const doublex4 *)(q.u2 + 16 * j * 64 + 16 * g);
+        for (int j = JLO; j < 4; ++j) f.u2[j] = *(const doublex4 *)(q.u2 + 16 * j * 64 + 16 * g);
     };
 
     doublex4 acc[NI][4];
@@ -379,8 +389,11 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
     constexpr int kDChunks = 16 * NI * 2048;   // D-hat chunks of the tile
-    auto step = [&](const Frag &f, const Ptrs &qn, int gn, Frag &fn, int stp, DCopy &dprev) {
-        load(qn, gn, fn);
+    // One step of phase JLO: the next step's loads (for groups >= JLO, which
+    // covers every later phase), then this step's products and MFMAs.
+    auto step = [&](auto jt, const Frag &f, const Ptrs &qn, int gn, Frag &fn, int stp, DCopy &dprev) {
+        constexpr int JLO = decltype(jt)::value, NJ = 4 - JLO;
+        load(jt, qn, gn, fn);
         if constexpr (WD) {
             DCopy dc;
             dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
@@ -391,62 +404,83 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         for (int t = 0; t < 4; ++t) {
             double bv[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = f.u1[t] * f.u2[j][t];
+            for (int j = JLO; j < 4; ++j) bv[j] = f.u1[t] * f.u2[j][t];
 #pragma unroll
             for (int i = 0; i < NI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = JLO; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.w[i][t], bv[j], acc[i][j], 0, 0, 0);
         }
-        __builtin_amdgcn_sched_group_barrier(0x020, 2 * (NI + 5), 0);   // loads first
+        __builtin_amdgcn_sched_group_barrier(0x020, 2 * (NI + 1 + NJ), 0);   // loads first
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);          // products of pixel t
-            __builtin_amdgcn_sched_group_barrier(0x008, 4 * NI, 0);     // their MFMAs
+            __builtin_amdgcn_sched_group_barrier(0x002, NJ, 0);          // products of pixel t
+            __builtin_amdgcn_sched_group_barrier(0x008, NJ * NI, 0);     // their MFMAs
         }
         __builtin_amdgcn_sched_barrier(0);
+    };
+    // end of output row a: store groups >= JLO (and their mirror images below
+    // the diagonal in a symmetric class), clear
+    const bool sym = cl.sym != 0;
+    auto store_row = [&](auto jt, int a) {
+        constexpr int JLO = decltype(jt)::value;
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int blk = sBlk[16 * i + lk + 4 * v];
+                if (blk >= 0) {
+                    double *ob = out + (int64_t)blk * kBlockElems;
+#pragma unroll
+                    for (int j = JLO; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &ob[a * 64 + 16 * j + lr]);
+                    if (sym) {
+#pragma unroll
+                        for (int j = JLO + 1; j < 4; ++j)
+                            __builtin_nontemporal_store(acc[i][j][v], &ob[(16 * j + lr) * 64 + a]);
+                    }
+                }
+            }
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = JLO; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
     };
 
     Frag f0, f1;
     Ptrs qc, qn;
-    int x = 0, e = 0;                    // row index (a = wave + 4 x) and term of this step
+    int x = 0, e = 0, it = 0;            // row index (a = wave + 4 x), term and step group of this step
     ptrs(wave, 0, qc);
-    load(qc, 0, f0);
+    load(std::integral_constant<int, 0>(), qc, 0, f0);
     DCopy dpend;                         // D-hat chunks loaded, not yet stored
     dpend.dst[0] = dpend.dst[1] = nullptr;
-    for (int it = 0; it < 16 * nterms; ++it) {
-        int ne = e + 1, nx = x;
-        if (ne == nterms) {
-            ne = 0;
-            ++nx;
+    auto rows = [&](auto jt, int x_end) {
+        while (x < x_end) {
+            int ne = e + 1, nx = x;
+            if (ne == nterms) {
+                ne = 0;
+                ++nx;
+            }
+            const int a = wave + 4 * x;
+            if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
+            else qn = qc;                // past the last row: a harmless reload
+            step(jt, f0, qc, 1, f1, 4 * it, dpend);
+            step(jt, f1, qc, 2, f0, 4 * it + 1, dpend);
+            step(jt, f0, qc, 3, f1, 4 * it + 2, dpend);
+            step(jt, f1, qn, 0, f0, 4 * it + 3, dpend);
+            if (ne == 0) store_row(jt, a);
+            x = nx;
+            e = ne;
+            qc = qn;
+            ++it;
         }
-        const int a = wave + 4 * x;
-        if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
-        else qn = qc;                    // past the last row: a harmless reload
-        step(f0, qc, 1, f1, 4 * it, dpend);
-        step(f1, qc, 2, f0, 4 * it + 1, dpend);
-        step(f0, qc, 3, f1, 4 * it + 2, dpend);
-        step(f1, qn, 0, f0, 4 * it + 3, dpend);
-        if (ne == 0) {                   // end of output row a: store, clear
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int blk = sBlk[16 * i + lk + 4 * v];
-                    if (blk >= 0) {
-                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + lr;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
-                    }
-                }
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-        }
-        x = nx;
-        e = ne;
-        qc = qn;
+    };
+    if (sym) {
+        rows(std::integral_constant<int, 0>(), 4);
+        rows(std::integral_constant<int, 1>(), 8);
+        rows(std::integral_constant<int, 2>(), 12);
+        rows(std::integral_constant<int, 3>(), 16);
+    } else {
+        rows(std::integral_constant<int, 0>(), 16);
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
         dcopy_store(dpend, lane);
