@@ -320,6 +320,27 @@ __device__ __forceinline__ void dcopy_store(const DCopy &dc, int lane) {
         if (dc.dst[r]) __builtin_nontemporal_store(dc.v[r], (doublex2 *)(dc.dst[r] + 2 * lane));
 }
 
+// A class without contraction terms: between two grids, when the auxiliary
+// grid is the coarser one, a stored block (J, K) can have no tile I that
+// neighbours both J and K, so the sum of Eq. 15 is empty and the block is
+// zero.  The workgroup clears the member tile's blocks (and gives them their
+// D-hat copies), without LDS; the caller returns right after.
+template <int NT, bool WD, class PD>
+__device__ __forceinline__ void empty_class_tile(const PD &pd, const DevClass &cl, int m0, int rows) {
+    constexpr int kChunks = kBlockElems / 2;            // 16-byte chunks of a block
+    const int nm = min(rows, cl.nblocks - m0);
+    for (int c = threadIdx.x; c < nm * kChunks; c += NT) {
+        const int m = c / kChunks, q = c - m * kChunks;
+        const int64_t blk = pd.cblk[cl.blk0 + m0 + m];
+        __builtin_nontemporal_store(doublex2{0.0, 0.0}, (doublex2 *)(pd.out + blk * kBlockElems) + q);
+        if constexpr (WD) {
+            const int64_t u = pd.blk_uid[blk];
+            __builtin_nontemporal_store(*((const doublex2 *)(pd.du64 + u * kBlockElems) + q),
+                                        (doublex2 *)(pd.outD + blk * kBlockElems) + q);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a9, FP64 MFMA class GEMM (the class decomposition is described with the
 // FP32 form below).  W = N^-1 as given, M = B_IJ[p][a] B_IK[p][b] formed in
@@ -330,7 +351,26 @@ __device__ __forceinline__ void dcopy_store(const DCopy &dc, int lane) {
 // separate accumulation step; four waves share a member tile and take every
 // fourth row a; each step (16 pixels of one term) loads the next step's
 // operands before its own MFMAs.
+//
+// Symmetric classes (every term pairs a unique block with itself: the blocks
+// (J, J)) give C[a][b] = C[b][a] bit for bit, since the products B[p][a]
+// B[p][b] are the same numbers either way round.  Row a then computes only
+// the column groups j >= a / 16 (10 of the 16 16x16 tiles) and writes the
+// tiles below the diagonal as mirror images.  Wave w's row x is a = w + 4 x,
+// so a / 16 = x / 4: its rows run in four phases with the first column group
+// JLO fixed at compile time (JLO = 0 for every row of other classes).  A step
+// issues one W load per 16 members whatever the number of column groups, so
+// the later phases take R rows a, a + 4, ... at once (R NI (4 - JLO) <= 16
+// accumulators), sharing the W and M-column loads between them: every step
+// keeps 64 MFMAs in a full tile.
 // ---------------------------------------------------------------------------
+template <int NI, int JLO>
+struct F64Phase {
+    static constexpr int NJ = 4 - JLO;
+    static constexpr int R = 4 * NI * NJ <= 16 ? 4 : 2 * NI * NJ <= 16 ? 2 : 1;
+    static_assert(R * NI * NJ <= 16, "a phase holds at most 16 accumulators");
+};
+
 template <int NI, bool WD>
 __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item, int32_t *sTile,
                                                int32_t *sBlk, int32_t *sTerm) {
@@ -343,6 +383,10 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
     const int32_t *terms = pd.cterms + 2 * cl.term0;
+    if (nterms == 0) {
+        empty_class_tile<256, WD>(pd, cl, m0, 16 * NI);
+        return;
+    }
 
     for (int x = threadIdx.x; x < 16 * NI * nterms; x += 256) {
         const int r = x / nterms, e = x - r * nterms;
@@ -357,6 +401,8 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
     if (threadIdx.x < 2 * nterms) sTerm[threadIdx.x] = terms[threadIdx.x];   // unique-block pairs of the class
     __syncthreads();
 
+    // operand pointers of term e for the row group starting at row a (rows
+    // a + 4 r of the group lie 256 r further along u1)
     struct Ptrs { const double *w[NI], *u1, *u2; };
     auto ptrs = [&](int a, int e, Ptrs &q) {
 #pragma unroll
@@ -365,35 +411,33 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         q.u1 = ut + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e]) * kBlockElems + a * 64 + 4 * lk;
         q.u2 = ut + (int64_t)__builtin_amdgcn_readfirstlane(sTerm[2 * e + 1]) * kBlockElems + lr * 64 + 4 * lk;
     };
-    // Symmetric classes (every term pairs a unique block with itself, the
-    // blocks (J, J)): C[a][b] = C[b][a] bit for bit, since the products
-    // B[p][a] B[p][b] are the same numbers either way round.  Row a then
-    // computes only the column groups j >= a / 16 (10 of the 16 16x16 tiles)
-    // and writes the tiles below the diagonal as mirror images.  Wave w's row
-    // x is a = w + 4 x, so a / 16 = x / 4: rows run in four phases with the
-    // first column group JLO fixed at compile time (0 for every row of other
-    // classes).
-    struct Frag { doublex4 w[NI], u1, u2[4]; };
+    struct Frag { doublex4 w[NI], u1[4], u2[4]; };
+    // operands of pixel group g in the shape of phase JL (its R rows, its
+    // column groups >= JL)
     auto load = [&](auto jt, const Ptrs &q, int g, Frag &f) {
-        constexpr int JLO = decltype(jt)::value;
+        constexpr int JL = decltype(jt)::value, RL = F64Phase<NI, JL>::R;
 #pragma unroll
         for (int i = 0; i < NI; ++i) f.w[i] = *(const doublex4 *)(q.w[i] + 16 * g);
-        f.u1 = *(const doublex4 *)(q.u1 + 16 * g);
 #pragma unroll
-        for (int j = JLO; j < 4; ++j) f.u2[j] = *(const doublex4 *)(q.u2 + 16 * j * 64 + 16 * g);
+        for (int r = 0; r < RL; ++r) f.u1[r] = *(const doublex4 *)(q.u1 + 256 * r + 16 * g);
+#pragma unroll
+        for (int j = JL; j < 4; ++j) f.u2[j] = *(const doublex4 *)(q.u2 + 16 * j * 64 + 16 * g);
     };
 
-    doublex4 acc[NI][4];
+    // accumulator of (row r of the group, member group i, column group j) in
+    // phase JLO; every slot is zero between row groups
+    doublex4 acc[16];
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < 16; ++s) acc[s] = doublex4{0.0, 0.0, 0.0, 0.0};
     constexpr int kDChunks = 16 * NI * 2048;   // D-hat chunks of the tile
-    // One step of phase JLO: the next step's loads (for groups >= JLO, which
-    // covers every later phase), then this step's products and MFMAs.
-    auto step = [&](auto jt, const Frag &f, const Ptrs &qn, int gn, Frag &fn, int stp, DCopy &dprev) {
-        constexpr int JLO = decltype(jt)::value, NJ = 4 - JLO;
-        load(jt, qn, gn, fn);
+    // One step of phase JLO: the loads of the next step in the shape of phase
+    // JN (JLO itself, or the next phase for the last step of a phase), then
+    // this step's products and MFMAs.
+    auto step = [&](auto jt, auto jn, const Frag &f, const Ptrs &qn, int gn, Frag &fn, int stp, DCopy &dprev) {
+        constexpr int JLO = decltype(jt)::value, NJ = F64Phase<NI, JLO>::NJ, R = F64Phase<NI, JLO>::R;
+        constexpr int JN = decltype(jn)::value;
+        constexpr int NLOAD = 2 * (NI + F64Phase<NI, JN>::R + F64Phase<NI, JN>::NJ);
+        load(jn, qn, gn, fn);
         if constexpr (WD) {
             DCopy dc;
             dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
@@ -402,89 +446,112 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            double bv[4];
+            double bv[4][4];
 #pragma unroll
-            for (int j = JLO; j < 4; ++j) bv[j] = f.u1[t] * f.u2[j][t];
+            for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int i = 0; i < NI; ++i)
+                for (int j = JLO; j < 4; ++j) bv[r][j] = f.u1[r][t] * f.u2[j][t];
 #pragma unroll
-                for (int j = JLO; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.w[i][t], bv[j], acc[i][j], 0, 0, 0);
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int j = JLO; j < 4; ++j) {
+                        doublex4 &c = acc[(r * NJ + j - JLO) * NI + i];
+                        c = __builtin_amdgcn_mfma_f64_16x16x4f64(f.w[i][t], bv[r][j], c, 0, 0, 0);
+                    }
         }
-        __builtin_amdgcn_sched_group_barrier(0x020, 2 * (NI + 1 + NJ), 0);   // loads first
+        __builtin_amdgcn_sched_group_barrier(0x020, NLOAD, 0);          // loads first
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            __builtin_amdgcn_sched_group_barrier(0x002, NJ, 0);          // products of pixel t
-            __builtin_amdgcn_sched_group_barrier(0x008, NJ * NI, 0);     // their MFMAs
+            __builtin_amdgcn_sched_group_barrier(0x002, R * NJ, 0);      // products of pixel t
+            __builtin_amdgcn_sched_group_barrier(0x008, R * NJ * NI, 0); // their MFMAs
         }
         __builtin_amdgcn_sched_barrier(0);
     };
-    // end of output row a: store groups >= JLO (and their mirror images below
-    // the diagonal in a symmetric class), clear
-    const bool sym = cl.sym != 0;
-    auto store_row = [&](auto jt, int a) {
-        constexpr int JLO = decltype(jt)::value;
+    // end of a row group (first row x): store groups >= JLO of its rows (and
+    // their mirror images below the diagonal in a symmetric class), clear
+    auto store_group = [&](auto jt, auto symt, int x) {
+        constexpr int JLO = decltype(jt)::value, NJ = F64Phase<NI, JLO>::NJ, R = F64Phase<NI, JLO>::R;
+        constexpr bool SYM = decltype(symt)::value;
 #pragma unroll
-        for (int i = 0; i < NI; ++i)
+        for (int r = 0; r < R; ++r) {
+            const int a = wave + 4 * (x + r);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int blk = sBlk[16 * i + lk + 4 * v];
-                if (blk >= 0) {
-                    double *ob = out + (int64_t)blk * kBlockElems;
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
-                    for (int j = JLO; j < 4; ++j) __builtin_nontemporal_store(acc[i][j][v], &ob[a * 64 + 16 * j + lr]);
-                    if (sym) {
+                for (int v = 0; v < 4; ++v) {
+                    const int blk = sBlk[16 * i + lk + 4 * v];
+                    if (blk >= 0) {
+                        double *ob = out + (int64_t)blk * kBlockElems;
 #pragma unroll
-                        for (int j = JLO + 1; j < 4; ++j)
-                            __builtin_nontemporal_store(acc[i][j][v], &ob[(16 * j + lr) * 64 + a]);
+                        for (int j = JLO; j < 4; ++j)
+                            __builtin_nontemporal_store(acc[(r * NJ + j - JLO) * NI + i][v], &ob[a * 64 + 16 * j + lr]);
+                        if constexpr (SYM) {
+#pragma unroll
+                            for (int j = JLO + 1; j < 4; ++j)
+                                __builtin_nontemporal_store(acc[(r * NJ + j - JLO) * NI + i][v],
+                                                            &ob[(16 * j + lr) * 64 + a]);
+                        }
                     }
                 }
-            }
+        }
 #pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int j = JLO; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < R * NJ * NI; ++s) acc[s] = doublex4{0.0, 0.0, 0.0, 0.0};
     };
 
     Frag f0, f1;
     Ptrs qc, qn;
-    int x = 0, e = 0, it = 0;            // row index (a = wave + 4 x), term and step group of this step
-    ptrs(wave, 0, qc);
-    load(std::integral_constant<int, 0>(), qc, 0, f0);
+    int it = 0;                          // (row group, term) iterations done: 4 steps each
     DCopy dpend;                         // D-hat chunks loaded, not yet stored
     dpend.dst[0] = dpend.dst[1] = nullptr;
-    auto rows = [&](auto jt, int x_end) {
-        while (x < x_end) {
-            int ne = e + 1, nx = x;
-            if (ne == nterms) {
-                ne = 0;
-                ++nx;
-            }
-            const int a = wave + 4 * x;
+    // rows x in [xb, xe) of phase JLO in groups of R; JN: the phase after it.
+    // One (row group x, term e) iteration is four steps; the last iteration of
+    // the phase is peeled, so that the operands it loads in the next phase's
+    // shape are live only from there on.
+    auto phase = [&](auto jt, auto jn, auto symt, int xb, int xe) {
+        constexpr int R = F64Phase<NI, decltype(jt)::value>::R;
+        auto iteration = [&](auto jl, int x, int e) {
+            const bool last_term = e + 1 == nterms;
+            const int nx = last_term ? x + R : x, ne = last_term ? 0 : e + 1;
             if (nx < 16) ptrs(wave + 4 * nx, ne, qn);
             else qn = qc;                // past the last row: a harmless reload
-            step(jt, f0, qc, 1, f1, 4 * it, dpend);
-            step(jt, f1, qc, 2, f0, 4 * it + 1, dpend);
-            step(jt, f0, qc, 3, f1, 4 * it + 2, dpend);
-            step(jt, f1, qn, 0, f0, 4 * it + 3, dpend);
-            if (ne == 0) store_row(jt, a);
-            x = nx;
-            e = ne;
+            step(jt, jt, f0, qc, 1, f1, 4 * it, dpend);
+            step(jt, jt, f1, qc, 2, f0, 4 * it + 1, dpend);
+            step(jt, jt, f0, qc, 3, f1, 4 * it + 2, dpend);
+            step(jt, jl, f1, qn, 0, f0, 4 * it + 3, dpend);
+            if (last_term) store_group(jt, symt, x);
             qc = qn;
             ++it;
+        };
+        const int n_iter = (xe - xb) / R * nterms;
+        int x = xb, e = 0;
+        for (int n = 0; n + 1 < n_iter; ++n) {
+            iteration(jt, x, e);
+            if (++e == nterms) {
+                e = 0;
+                x += R;
+            }
         }
+        iteration(jn, x, e);
     };
-    if (sym) {
-        rows(std::integral_constant<int, 0>(), 4);
-        rows(std::integral_constant<int, 1>(), 8);
-        rows(std::integral_constant<int, 2>(), 12);
-        rows(std::integral_constant<int, 3>(), 16);
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    ptrs(wave, 0, qc);
+    load(I0(), qc, 0, f0);
+    if (cl.sym != 0) {
+        phase(I0(), I1(), std::true_type(), 0, 4);
+        phase(I1(), I2(), std::true_type(), 4, 8);
+        phase(I2(), I3(), std::true_type(), 8, 12);
+        phase(I3(), I3(), std::true_type(), 12, 16);
     } else {
-        rows(std::integral_constant<int, 0>(), 16);
+        phase(I0(), I0(), std::false_type(), 0, 16);
     }
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
         dcopy_store(dpend, lane);
-        for (int stp = 64 * nterms; 512 * stp < kDChunks; ++stp) {
+        for (int stp = 4 * it; 512 * stp < kDChunks; ++stp) {
             DCopy dc;
             dcopy_load<256>(pd.du64, pd.outD, sBlk, kDChunks, stp, wave, lane, dc);
             dcopy_store(dc, lane);
@@ -586,6 +653,10 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
     const int32_t *terms = pd.cterms + 2 * cl.term0;
+    if (nterms == 0) {
+        empty_class_tile<NT, WD>(pd, cl, m0, 16 * NI);
+        return;
+    }
 
     for (int x = tid; x < 16 * NI * nterms; x += NT) {
         const int r = x / nterms, e = x - r * nterms;
@@ -908,6 +979,10 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int nterms = cl.nterms;
     const int32_t *terms = pd.cterms + 2 * cl.term0;
+    if (nterms == 0) {
+        empty_class_tile<NT, WD>(pd, cl, m0, 16 * NI);
+        return;
+    }
 
     for (int x = tid; x < 16 * NI * nterms; x += NT) {
         const int r = x / nterms, e = x - r * nterms;

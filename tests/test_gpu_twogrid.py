@@ -78,7 +78,10 @@ def test_equal_grids_are_bitwise_the_one_grid_calls(lmax):
     say(f"[twogrid {lmax}] Y_2 = Y_1: B-hat blocks and B^T N^-1 B in every mode bitwise equal to the one-grid calls")
 
 
-PAIRS = [(128, 64), (100, 64), (64, 128), (512, 256)]
+# (32, 128) and (48, 128): Y_2 coarser than half of Y_1's resolution, where
+# some stored blocks (J, K) have no tile of Y_2 neighbouring both (an empty sum
+# in Eq. 15: zero blocks, a class without terms)
+PAIRS = [(128, 64), (100, 64), (64, 128), (512, 256), (32, 128), (48, 128)]
 
 
 @pytest.mark.parametrize("l2,l1", PAIRS)

@@ -107,6 +107,11 @@ def test_blocks_and_product_match_dense_brute_force(pair):
     ref = np.stack([Cd[J * k12:(J + 1) * k12, K * k12:(K + 1) * k12] for J, K in pairs])
     assert _gate(C, ref, pairs) < 1e-12
     op = X.CrossOperator(g2, g1, b_l, R)
+    # stored blocks with an empty sum (Y_2 the coarser grid) are exact zeros
+    empty = [n for n, (J, K) in enumerate(pairs) if not set(op.neighbours(J)) & set(op.neighbours(K))]
+    assert all(not C[n].any() for n in empty)
+    if g2.lmax < g1.lmax:
+        assert empty, "a coarser auxiliary grid leaves some stored blocks without terms"
     for J in range(g1.ntiles):
         for K in range(g1.ntiles):
             if not set(op.neighbours(J)) & set(op.neighbours(K)):
