@@ -17,6 +17,9 @@ operators  pair geometry, the local blocks of D-hat and B-hat (Eq. 16 and
            B-hat^T N^-1 B-hat (Eq. 15).
 twogrid    B-hat = Y_2 B Y_1^T between an auxiliary grid and the grid of the
            unknowns (Eqs. 13 and 16) and its B-hat^T N_2^-1 B-hat.
+sht        spherical harmonic synthesis, its transpose and the quadrature
+           analysis of Eq. 1 on the SymPix geometry (real orthonormal basis),
+           and the N^-1 degrade theta_2 = W_2 Y_2 Y_obs^T theta of Eq. 14.
 brute      pattern-level brute force without any symmetry reuse (tests only).
 
 Every function is plain and slow on purpose: the point is that a reader can
