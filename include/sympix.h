@@ -441,6 +441,61 @@ sympix_status sympix_batch_launch(sympix_batch *bt, void *stream);
 /* Free a batch. NULL is ignored.  No launch of it may be in flight. */
 void sympix_batch_destroy(sympix_batch *bt);
 
+/* ------------------------------------------------------------------------
+ * Spherical harmonic transforms on the SymPix geometry (Section 2.1, Eq. 1)
+ * and the N^-1 degrade of Eq. 14.
+ *
+ * Basis: real orthonormal harmonics without the Condon-Shortley phase,
+ *   Y_{l,0} = lambda_l0(theta),  Y_{l,m} = sqrt(2) lambda_lm(theta) cos(m phi),
+ *   Y_{l,-m} = sqrt(2) lambda_lm(theta) sin(m phi)  (0 < m <= l <= L),
+ * lambda_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) P_l^m(cos theta), P_l^m >= 0
+ * near the north pole, so that Y (npix x (L+1)^2) is a real matrix and Y^T its
+ * transpose.  Coefficient vectors: float64, (L+1)^2 entries, entry l^2 + l + m
+ * for the coefficient of Y_{l,m}.  Maps: float64, npix values in the grid's
+ * pixel order (sympix_grid_pixels).  W: per pixel, the Gauss-Legendre weight
+ * of its ring times 2 pi / n_ring (the quadrature rule of Eq. 1).  Every mode
+ * m <= L is kept on every ring (no mode is dropped near the poles).
+ * ------------------------------------------------------------------------ */
+typedef struct sympix_sht sympix_sht;
+
+/* Plan for the transforms of band limit lmax_sh on grid g, on the current
+ * device: ring tables, lambda_mm per ring and m, and the plan's work buffers
+ * (about 16 nrings (L+1) + 16 (L+1)(L+2)/2 + 12 (nrings/2)(L+1) bytes).  The
+ * grid must outlive the plan.  Calls that use one plan (the transforms below,
+ * and a degrade naming it) share its work buffers and must not overlap in
+ * time: issue them on one stream, or order the streams.
+ * Errors: EINVAL (NULL, lmax_sh < 0), EUNSUPPORTED (lmax_sh > 4095, a ring
+ * longer than 8192 pixels or not of the form 2^a 3^b 5^c), ENOMEM, EHIP. */
+sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sht **out);
+
+/* Free a plan (after its last call has completed). NULL is ignored. */
+void sympix_sht_destroy(sympix_sht *s);
+
+/* Synthesis map = Y alm: alm_dev (device, (L+1)^2 values), map_dev (device,
+ * npix values); both 8-byte aligned, not overlapping.
+ * Errors: EINVAL (NULL, overlap, plan on another device), ESIZE (alm_len !=
+ * (L+1)^2, map_len != npix), EHIP. */
+sympix_status sympix_sht_synthesis(sympix_sht *s, const double *alm_dev, int64_t alm_len, double *map_dev,
+                                   int64_t map_len, void *stream);
+
+/* Transpose alm = Y^T map (no quadrature weights).  Arguments and errors as
+ * sympix_sht_synthesis. */
+sympix_status sympix_sht_adjoint(sympix_sht *s, const double *map_dev, int64_t map_len, double *alm_dev,
+                                 int64_t alm_len, void *stream);
+
+/* Analysis alm = Y^T W map (Eq. 1).  Arguments and errors as
+ * sympix_sht_synthesis. */
+sympix_status sympix_sht_analysis(sympix_sht *s, const double *map_dev, int64_t map_len, double *alm_dev,
+                                  int64_t alm_len, void *stream);
+
+/* The degrade of Eq. 14, theta_2 = W_2 Y_2 Y_obs^T theta_obs: theta_obs_dev on
+ * the grid of obs (npix_obs values), theta2_dev on the grid of target (npix_2
+ * values); Y_obs^T carries no ring weights, W_2 is the target grid's
+ * quadrature weight.  Both plans must have the same band limit and device.
+ * Errors: EINVAL (NULL, overlap, band limits or devices differ), ESIZE, EHIP. */
+sympix_status sympix_sht_degrade(sympix_sht *obs, sympix_sht *target, const double *theta_obs_dev,
+                                 int64_t obs_len, double *theta2_dev, int64_t target_len, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *sympix_last_error(void);
 

@@ -102,6 +102,13 @@ _kernel_tabulate_cross = _sig("sympix_kernel_tabulate_cross", [_vp, _vp, _i32, _
 _sample_B_cross = _sig("sympix_sample_B_cross", [_vp, _vp, _vp, _i64, _vp])
 _sample_BtNB_cross = _sig("sympix_sample_BtNB_cross", [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp])
 
+_sht_create = _sig("sympix_sht_create", [_vp, _i32, ctypes.POINTER(_vp)])
+_sht_destroy = _sig("sympix_sht_destroy", [_vp], None)
+_sht_synthesis = _sig("sympix_sht_synthesis", [_vp, _vp, _i64, _vp, _i64, _vp])
+_sht_adjoint = _sig("sympix_sht_adjoint", [_vp, _vp, _i64, _vp, _i64, _vp])
+_sht_analysis = _sig("sympix_sht_analysis", [_vp, _vp, _i64, _vp, _i64, _vp])
+_sht_degrade = _sig("sympix_sht_degrade", [_vp, _vp, _vp, _i64, _vp, _i64, _vp])
+
 
 class Problem(ctypes.Structure):
     _fields_ = [("g", _vp), ("b", _vp), ("ninv_dev", _vp), ("ninv_len", _i64), ("out_dev", _vp),
@@ -134,7 +141,9 @@ EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sy
             "sympix_sample_BtNB", "sympix_sample_BtNB_noalloc", "sympix_sample_BtNB_pattern", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
             "sympix_batch_launch", "sympix_batch_plan", "sympix_batch_destroy", "sympix_last_error",
             "sympix_cross_create", "sympix_cross_destroy", "sympix_cross_dims", "sympix_cross_neighbours",
-            "sympix_cross_unique", "sympix_kernel_tabulate_cross", "sympix_sample_B_cross", "sympix_sample_BtNB_cross")
+            "sympix_cross_unique", "sympix_kernel_tabulate_cross", "sympix_sample_B_cross", "sympix_sample_BtNB_cross",
+            "sympix_sht_create", "sympix_sht_destroy", "sympix_sht_synthesis", "sympix_sht_adjoint",
+            "sympix_sht_analysis", "sympix_sht_degrade")
 
 
 def _check(status):
@@ -501,3 +510,49 @@ class Batch:
         _check(_batch_plan(self._h, ctypes.byref(p)))
         return p.value
 
+
+class Sht:
+    """Transform plan of band limit lmax on a grid (the current device):
+    synthesis Y a, transpose Y^T f and analysis Y^T W f in the real
+    orthonormal basis, coefficients at l^2 + l + m (see include/sympix.h)."""
+
+    def __init__(self, g: Grid, lmax: int):
+        h = _vp()
+        _check(_sht_create(g.handle, int(lmax), ctypes.byref(h)))
+        self._h = h
+        self.g = g                          # the plan refers to the grid
+        self.lmax = int(lmax)
+        self.nalm = (self.lmax + 1) ** 2
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _sht_destroy is not None:
+            _sht_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def synthesis(self, alm, out, stream=None):
+        _require_f64_device(alm, "alm")
+        _require_f64_device(out, "out")
+        _check(_sht_synthesis(self._h, _ptr(alm), _numel(alm), _ptr(out), _numel(out), _stream(stream)))
+
+    def adjoint(self, f, out, stream=None):
+        _require_f64_device(f, "f")
+        _require_f64_device(out, "out")
+        _check(_sht_adjoint(self._h, _ptr(f), _numel(f), _ptr(out), _numel(out), _stream(stream)))
+
+    def analysis(self, f, out, stream=None):
+        _require_f64_device(f, "f")
+        _require_f64_device(out, "out")
+        _check(_sht_analysis(self._h, _ptr(f), _numel(f), _ptr(out), _numel(out), _stream(stream)))
+
+
+def degrade(obs: Sht, target: Sht, theta_obs, out, stream=None):
+    """theta_2 = W_2 Y_2 Y_obs^T theta_obs (Eq. 14) onto the target plan's grid."""
+    _require_f64_device(theta_obs, "theta_obs")
+    _require_f64_device(out, "out")
+    _check(_sht_degrade(obs.handle, target.handle, _ptr(theta_obs), _numel(theta_obs), _ptr(out), _numel(out),
+                        _stream(stream)))

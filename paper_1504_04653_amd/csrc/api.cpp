@@ -20,6 +20,7 @@
 #include "../../include/sympix.h"
 #include "device.hpp"
 #include "geometry.hpp"
+#include "sht.hpp"
 
 using sympix::Geometry;
 using sympix::UInfo;
@@ -1484,6 +1485,224 @@ sympix_status sympix_sample_BtNB_cross(const sympix_cross *c, const sympix_kerne
     a.blk_uid = nullptr;
     a.outD = nullptr;
     return launch_contraction(a, b->device, prec, false, (hipStream_t)stream, "sample_BtNB_cross");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Spherical harmonic transforms on the SymPix geometry (Eq. 1) and the
+// degrade of Eq. 14.
+// ---------------------------------------------------------------------------
+struct sympix_sht {
+    const sympix_grid *g = nullptr;
+    int32_t lmax = 0;
+    int device = 0;
+    sympix::ShtDesc d{};
+    double *fbuf = nullptr;      // nrings (L+1) 2: Legendre <-> Fourier stage
+    double *ac = nullptr;        // m-major cos coefficients
+    double *as = nullptr;        // m-major sin coefficients
+    void *block = nullptr;       // one allocation holding the tables and buffers
+};
+
+namespace {
+
+// FFT passes of a ring of n = 2^a 3^b 5^c pixels: radix 4 first, then 2, 3, 5
+bool ring_radices(int32_t n, int8_t out[16]) {
+    int np = 0;
+    for (int r : {4, 2, 3, 5})
+        while (n % r == 0 && np < 15) {
+            out[1 + np++] = (int8_t)r;
+            n /= r;
+        }
+    out[0] = (int8_t)np;
+    return n == 1;
+}
+
+sympix_status sht_check(const sympix_sht *s, const void *in, int64_t in_len, int64_t want_in, const void *out,
+                        int64_t out_len, int64_t want_out) {
+    if (!s) return fail(SYMPIX_EINVAL, "NULL plan");
+    if (in_len != want_in || out_len != want_out) return fail(SYMPIX_ESIZE, "buffer length does not match the plan");
+    if ((want_in > 0 && !in) || (want_out > 0 && !out)) return fail(SYMPIX_EINVAL, "NULL device buffer");
+    if (((uintptr_t)in) % 8 || ((uintptr_t)out) % 8) return fail(SYMPIX_EINVAL, "buffers must be 8-byte aligned");
+    const char *a = (const char *)in, *b = (const char *)out;
+    if (a < b + out_len * 8 && b < a + in_len * 8) return fail(SYMPIX_EINVAL, "input and output overlap");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != s->device)
+        return fail(SYMPIX_EINVAL, "the plan lives on another device");
+    return SYMPIX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sht **out) {
+    if (!g || !out) return fail(SYMPIX_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (lmax_sh < 0) return fail(SYMPIX_EINVAL, "lmax_sh must be >= 0");
+    if (lmax_sh > sympix::kShtMaxL) return fail(SYMPIX_EUNSUPPORTED, "lmax_sh above 4095");
+    const Geometry &geo = g->geo;
+    const int32_t L = lmax_sh, nr = geo.nrings, nh = nr / 2, k = geo.k;
+    // ring tables: band of each ring, its length, first pixel and weight
+    std::vector<int32_t> rn(nr, 0);
+    std::vector<int64_t> pix0(nr, 0);
+    std::vector<double> rw(nr, 0.0);
+    std::vector<int8_t> rad((size_t)nr * 16, 0);
+    int32_t max_ring = 0;
+    for (size_t b = 0; b < geo.band_tiles.size(); ++b) {
+        const int32_t n = k * geo.band_tiles[b];
+        for (int32_t r = 0; r < k; ++r) {
+            const int32_t j = geo.band_ring0[b] + r;
+            rn[j] = n;
+            pix0[j] = geo.band_tile0[b] * (int64_t)k * k + r;
+            rw[j] = geo.weight[j] * 2.0 * kPi / (double)n;
+            if (!ring_radices(n, &rad[(size_t)j * 16]))
+                return fail(SYMPIX_EUNSUPPORTED, "a ring length is not of the form 2^a 3^b 5^c");
+        }
+        max_ring = std::max(max_ring, n);
+    }
+    if (max_ring > sympix::kShtMaxRing) return fail(SYMPIX_EUNSUPPORTED, "a ring is longer than 8192 pixels");
+    // lambda_mm of the northern rings: the product recurrence lambda_mm =
+    // lambda_{m-1,m-1} sqrt((2m+1)/(2m)) sin(theta) from 1/sqrt(4 pi), kept as
+    // mant * 2^exp with mant >= 2^-300
+    std::vector<double> mant((size_t)(L + 1) * nh), ring_cos(nh);
+    std::vector<int32_t> ex((size_t)(L + 1) * nh);
+    for (int32_t r = 0; r < nh; ++r) {
+        ring_cos[r] = geo.cos_theta[r];
+        const double st = geo.sin_theta[r];
+        double v = 1.0 / std::sqrt(4.0 * kPi);
+        int32_t e = 0;
+        for (int32_t m = 0; m <= L; ++m) {
+            if (m > 0) {
+                v *= std::sqrt((2.0 * m + 1.0) / (2.0 * m)) * st;
+                if (v < 0x1p-300) {
+                    v *= 0x1p300;
+                    e -= 300;
+                }
+            }
+            mant[(size_t)m * nh + r] = v;
+            ex[(size_t)m * nh + r] = e;
+        }
+    }
+    sympix_sht *s = injected_alloc_failure() ? nullptr : new (std::nothrow) sympix_sht();
+    if (!s) return fail(SYMPIX_ENOMEM, "host allocation failed");
+    s->g = g;
+    s->lmax = L;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "hipGetDevice");
+    }
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t nmm = (size_t)(L + 1) * (L + 2) / 2;
+    size_t o = 0;
+    const size_t o_cos = o;   o += up(sizeof(double) * nh);
+    const size_t o_mant = o;  o += up(sizeof(double) * mant.size());
+    const size_t o_exp = o;   o += up(sizeof(int32_t) * ex.size());
+    const size_t o_n = o;     o += up(sizeof(int32_t) * nr);
+    const size_t o_pix = o;   o += up(sizeof(int64_t) * nr);
+    const size_t o_w = o;     o += up(sizeof(double) * nr);
+    const size_t o_rad = o;   o += up(rad.size());
+    const size_t o_f = o;     o += up(sizeof(double) * 2 * (size_t)nr * (L + 1));
+    const size_t o_ac = o;    o += up(sizeof(double) * nmm);
+    const size_t o_as = o;    o += up(sizeof(double) * nmm);
+    e = injected_alloc_failure() ? hipErrorOutOfMemory : hipMalloc(&s->block, o);
+    if (e != hipSuccess) {
+        s->block = nullptr;
+        delete s;
+        return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the transform plan failed")
+                                        : hip_fail(e, "hipMalloc");
+    }
+    char *base = (char *)s->block;
+    auto put = [&](size_t off, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
+    };
+    put(o_cos, ring_cos.data(), sizeof(double) * nh);
+    put(o_mant, mant.data(), sizeof(double) * mant.size());
+    put(o_exp, ex.data(), sizeof(int32_t) * ex.size());
+    put(o_n, rn.data(), sizeof(int32_t) * nr);
+    put(o_pix, pix0.data(), sizeof(int64_t) * nr);
+    put(o_w, rw.data(), sizeof(double) * nr);
+    put(o_rad, rad.data(), rad.size());
+    if (e == hipSuccess) e = sympix::sht_prepare(L, max_ring);
+    if (e != hipSuccess) {
+        hipFree(s->block);
+        delete s;
+        return hip_fail(e, "uploading the transform plan");
+    }
+    sympix::ShtDesc &d = s->d;
+    d.lmax = L;
+    d.nrings = nr;
+    d.nhalf = nh;
+    d.k = k;
+    d.max_ring = max_ring;
+    d.pad = 0;
+    d.ring_cos = (const double *)(base + o_cos);
+    d.lmm_mant = (const double *)(base + o_mant);
+    d.lmm_exp = (const int32_t *)(base + o_exp);
+    d.ring_n = (const int32_t *)(base + o_n);
+    d.ring_pix0 = (const int64_t *)(base + o_pix);
+    d.ring_w = (const double *)(base + o_w);
+    d.ring_rad = (const int8_t *)(base + o_rad);
+    s->fbuf = (double *)(base + o_f);
+    s->ac = (double *)(base + o_ac);
+    s->as = (double *)(base + o_as);
+    *out = s;
+    return SYMPIX_OK;
+}
+
+void sympix_sht_destroy(sympix_sht *s) {
+    if (!s) return;
+    hipFree(s->block);
+    delete s;
+}
+
+sympix_status sympix_sht_synthesis(sympix_sht *s, const double *alm_dev, int64_t alm_len, double *map_dev,
+                                   int64_t map_len, void *stream) {
+    if (!s) return fail(SYMPIX_EINVAL, "NULL plan");
+    const int64_t nalm = (int64_t)(s->lmax + 1) * (s->lmax + 1);
+    sympix_status st = sht_check(s, alm_dev, alm_len, nalm, map_dev, map_len, s->g->geo.npix);
+    if (st != SYMPIX_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    return after_launch(sympix::sht_synthesis(s->d, alm_dev, s->ac, s->as, s->fbuf, map_dev, false, hs), hs,
+                        "sht_synthesis");
+}
+
+static sympix_status sht_transpose(sympix_sht *s, const double *map_dev, int64_t map_len, double *alm_dev,
+                                   int64_t alm_len, void *stream, bool weighted, const char *what) {
+    if (!s) return fail(SYMPIX_EINVAL, "NULL plan");
+    const int64_t nalm = (int64_t)(s->lmax + 1) * (s->lmax + 1);
+    sympix_status st = sht_check(s, map_dev, map_len, s->g->geo.npix, alm_dev, alm_len, nalm);
+    if (st != SYMPIX_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    return after_launch(sympix::sht_adjoint(s->d, map_dev, s->fbuf, s->ac, s->as, alm_dev, weighted, hs), hs, what);
+}
+
+sympix_status sympix_sht_adjoint(sympix_sht *s, const double *map_dev, int64_t map_len, double *alm_dev,
+                                 int64_t alm_len, void *stream) {
+    return sht_transpose(s, map_dev, map_len, alm_dev, alm_len, stream, false, "sht_adjoint");
+}
+
+sympix_status sympix_sht_analysis(sympix_sht *s, const double *map_dev, int64_t map_len, double *alm_dev,
+                                  int64_t alm_len, void *stream) {
+    return sht_transpose(s, map_dev, map_len, alm_dev, alm_len, stream, true, "sht_analysis");
+}
+
+sympix_status sympix_sht_degrade(sympix_sht *obs, sympix_sht *target, const double *theta_obs_dev,
+                                 int64_t obs_len, double *theta2_dev, int64_t target_len, void *stream) {
+    if (!obs || !target) return fail(SYMPIX_EINVAL, "NULL plan");
+    if (obs->lmax != target->lmax) return fail(SYMPIX_EINVAL, "the two plans have different band limits");
+    if (obs->device != target->device) return fail(SYMPIX_EINVAL, "the two plans live on different devices");
+    sympix_status st = sht_check(obs, theta_obs_dev, obs_len, obs->g->geo.npix, theta2_dev, target_len,
+                                 target->g->geo.npix);
+    if (st != SYMPIX_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    // Y_obs^T theta into the observation plan's m-major buffers, then W_2 Y_2
+    // of them on the target grid
+    hipError_t e = sympix::sht_adjoint(obs->d, theta_obs_dev, obs->fbuf, obs->ac, obs->as, nullptr, false, hs);
+    if (e == hipSuccess)
+        e = sympix::sht_synthesis(target->d, nullptr, obs->ac, obs->as, target->fbuf, theta2_dev, true, hs);
+    return after_launch(e, hs, "sht_degrade");
 }
 
 }  // extern "C"

@@ -1,0 +1,40 @@
+// Spherical harmonic transforms on the SymPix geometry: device tables of a
+// transform plan and the launch functions (sht.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sympix {
+
+constexpr int kShtMaxRing = 8192;   // longest ring the LDS FFT holds (complex FP64)
+constexpr int kShtMaxL = 4095;      // largest band limit (LDS of the Legendre kernels)
+
+// Device tables of one plan (grid, band limit L).  Rings j = 0 .. nrings-1
+// from the north pole; ring nrings-1-j mirrors ring j, so the Legendre part
+// runs over the nhalf = nrings/2 northern rings.
+struct ShtDesc {
+    int32_t lmax, nrings, nhalf, k, max_ring, pad;
+    const double *ring_cos;     // [nhalf] cos(theta) of the northern rings
+    const double *lmm_mant;     // [L+1][nhalf] lambda_mm = mant * 2^exp
+    const int32_t *lmm_exp;     // [L+1][nhalf]
+    const int32_t *ring_n;      // [nrings] pixels on the ring
+    const int64_t *ring_pix0;   // [nrings] pixel of ring position 0 (ring position j:
+                                // + (j / k) k^2 + (j % k) k)
+    const double *ring_w;       // [nrings] quadrature weight of each of the ring's pixels
+    const int8_t *ring_rad;     // [nrings][16] FFT passes: count, then radices
+};
+
+// map = Y a (alm in the l^2 + l + m layout; nullptr: the m-major ac / as are
+// already filled); with weighted, map = W Y a.  fbuf: nrings (L+1) 2 doubles.
+hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double *as, double *fbuf, double *map,
+                         bool weighted, hipStream_t st);
+// alm = Y^T map (weighted: Y^T W map); alm == nullptr leaves the result in the
+// m-major ac / as.  gbuf: nrings (L+1) 2 doubles.
+hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double *ac, double *as, double *alm,
+                       bool weighted, hipStream_t st);
+// Allow the kernels the LDS a plan of band limit L and longest ring max_ring needs.
+hipError_t sht_prepare(int lmax, int max_ring);
+
+}  // namespace sympix

@@ -1,0 +1,170 @@
+"""GPU parity of the spherical harmonic transforms on the SymPix geometry
+(Eq. 1) and the degrade of Eq. 14 through the C ABI, against the FP64 oracle
+(oracle.sht): every pixel and coefficient on small grids (several tile sizes,
+band limits below and at the grid's lmax), the degrade between two grids,
+sampled rings at lmax 512, and at the full sizes (lmax 1500 and 3000) the
+properties that hold at any size: analysis inverts synthesis on this build's
+grids (to the level the oracle shows at lmax 128 and 512) and Y^T is the
+transpose of Y (<Y a, f> = <a, Y^T f>)."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1504_04653_amd as sp
+from oracle import grid as G
+from oracle import sht as H
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12          # FP64 both sides; FFT against direct sums, relative to the largest value
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def rel(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+CASES = [(16, 2, 16), (40, 4, 30), (64, 8, 64), (128, 8, 128), (100, 8, 60)]
+
+
+@pytest.mark.parametrize("lmax,k,L", CASES)
+def test_transforms_against_oracle(lmax, k, L):
+    og, g = G.make_grid(lmax, k), sp.Grid(lmax, k)
+    s = sp.Sht(g, L)
+    rng = np.random.default_rng(lmax + 7 * k + L)
+    a = rng.standard_normal((L + 1) ** 2)
+    f = rng.standard_normal(g.npix)
+    out_map = torch.full((g.npix,), float("nan"), dtype=torch.float64, device="cuda")
+    out_alm = torch.full(((L + 1) ** 2,), float("nan"), dtype=torch.float64, device="cuda")
+    s.synthesis(dev(a), out_map)
+    torch.cuda.synchronize()
+    e_syn = rel(out_map.cpu().numpy(), H.synthesis(og, a, L))
+    s.adjoint(dev(f), out_alm)
+    torch.cuda.synchronize()
+    e_adj = rel(out_alm.cpu().numpy(), H.adjoint(og, f, L))
+    s.analysis(dev(f), out_alm)
+    torch.cuda.synchronize()
+    e_ana = rel(out_alm.cpu().numpy(), H.analysis(og, f, L))
+    say(f"[sht lmax={lmax} k={k} L={L}] npix={g.npix} synthesis {e_syn:.2e} adjoint {e_adj:.2e} analysis {e_ana:.2e}")
+    assert max(e_syn, e_adj, e_ana) <= TOL
+
+
+@pytest.mark.parametrize("obs,target,L", [((64, 8), (32, 4), 32), ((48, 4), (64, 8), 40)])
+def test_degrade_against_oracle(obs, target, L):
+    og_o, og_t = G.make_grid(*obs), G.make_grid(*target)
+    g_o, g_t = sp.Grid(*obs), sp.Grid(*target)
+    s_o, s_t = sp.Sht(g_o, L), sp.Sht(g_t, L)
+    rng = np.random.default_rng(L)
+    th = rng.uniform(0.5, 2.0, g_o.npix)
+    th[rng.random(g_o.npix) < 0.2] = 0.0                # masked pixels
+    out = torch.full((g_t.npix,), float("nan"), dtype=torch.float64, device="cuda")
+    sp.degrade(s_o, s_t, dev(th), out)
+    torch.cuda.synchronize()
+    e = rel(out.cpu().numpy(), H.degrade(og_o, og_t, th, L))
+    say(f"[degrade {obs} -> {target} L={L}] {e:.2e}")
+    assert e <= TOL
+
+
+def test_sampled_rings_at_lmax512():
+    """Synthesis on every pixel of two polar and two equatorial rings, and
+    analysis of a band-limited map, against the oracle at lmax 512."""
+    lmax = L = 512
+    og, g = G.make_grid(lmax, 8), sp.Grid(lmax, 8)
+    s = sp.Sht(g, L)
+    rng = np.random.default_rng(512)
+    a = rng.standard_normal((L + 1) ** 2) / np.sqrt(np.repeat(np.arange(L + 1), 2 * np.arange(L + 1) + 1) + 1.0)
+    out = torch.empty(g.npix, dtype=torch.float64, device="cuda")
+    s.synthesis(dev(a), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ring, pin, nr, phi = og.pixel_coords()
+    rings = [0, 5, og.nrings // 2 - 1, og.nrings - 3]
+    lam = H.lambda_table(L, og.theta[rings])
+    worst = 0.0
+    for q, r in enumerate(rings):
+        pix = np.nonzero(ring == r)[0]
+        ref = np.zeros(pix.size)
+        for m in range(L + 1):
+            ls = np.arange(m, L + 1)
+            Fc = a[ls * ls + ls + m] @ lam[m:, m, q]
+            if m == 0:
+                ref += Fc
+            else:
+                Fs = a[ls * ls + ls - m] @ lam[m:, m, q]
+                ref += np.sqrt(2.0) * (Fc * np.cos(m * phi[pix]) + Fs * np.sin(m * phi[pix]))
+        worst = max(worst, np.abs(got[pix] - ref).max() / np.abs(got).max())
+    back = torch.empty((L + 1) ** 2, dtype=torch.float64, device="cuda")
+    s.analysis(out, back)
+    torch.cuda.synchronize()
+    e_rt = float(np.abs(back.cpu().numpy() - a).max() / np.abs(a).max())
+    say(f"[sht lmax=512] sampled rings {worst:.2e}, analysis of the synthesised map {e_rt:.2e}")
+    assert worst <= TOL
+    assert e_rt <= 1e-11
+
+
+@pytest.mark.parametrize("lmax", [1500, 3000])
+def test_full_size_round_trip_and_transpose(lmax):
+    L = lmax
+    g = sp.Grid(lmax, 8)
+    s = sp.Sht(g, L)
+    rng = np.random.default_rng(lmax)
+    ell = np.repeat(np.arange(L + 1), 2 * np.arange(L + 1) + 1)
+    a = dev(rng.standard_normal((L + 1) ** 2) / np.sqrt(ell + 1.0))
+    f = torch.empty(g.npix, dtype=torch.float64, device="cuda")
+    back = torch.empty_like(a)
+    s.synthesis(a, f)
+    s.analysis(f, back)
+    torch.cuda.synchronize()
+    e_rt = float((back - a).abs().max() / a.abs().max())
+    x = dev(rng.standard_normal(g.npix))
+    yt = torch.empty_like(a)
+    s.adjoint(x, yt)
+    torch.cuda.synchronize()
+    lhs, rhs = float(f @ x), float(a @ yt)
+    e_tr = abs(lhs - rhs) / (float(f.abs().sum()) * float(x.abs().max()))
+    assert bool(torch.isfinite(f).all()) and bool(torch.isfinite(yt).all())
+    say(f"[sht lmax={lmax}] npix={g.npix}: analysis of synthesis {e_rt:.2e}; <Ya,x> vs <a,Y^T x> {e_tr:.2e}")
+    assert e_rt <= 1e-10
+    assert e_tr <= 1e-12
+
+
+def test_sht_errors():
+    g, g2 = sp.Grid(32, 4), sp.Grid(48, 4)
+    s, s2, s3 = sp.Sht(g, 20), sp.Sht(g2, 20), sp.Sht(g2, 24)
+    alm = torch.zeros(21 ** 2, dtype=torch.float64, device="cuda")
+    m = torch.zeros(g.npix, dtype=torch.float64, device="cuda")
+    m2 = torch.zeros(g2.npix, dtype=torch.float64, device="cuda")
+    for bad, code in ((lambda: s.synthesis(alm[:-1], m), "ESIZE"),
+                      (lambda: s.synthesis(alm, m[:-1]), "ESIZE"),
+                      (lambda: s.analysis(m2, alm), "ESIZE"),
+                      (lambda: sp.degrade(s, s3, m, m2), "EINVAL"),
+                      (lambda: sp.degrade(s, s2, m, m), "ESIZE")):
+        with pytest.raises(sp.SympixError) as ei:
+            bad()
+        assert ei.value.code == code
+    with pytest.raises(sp.SympixError) as ei:
+        sp.Sht(g, -1)
+    assert ei.value.code == "EINVAL"
+    with pytest.raises(sp.SympixError) as ei:
+        sp.Sht(g, 5000)
+    assert ei.value.code == "EUNSUPPORTED"
