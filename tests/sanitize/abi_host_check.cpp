@@ -131,6 +131,18 @@ int main() {
     CHECK(sympix_grid_pattern_blocks(a, SYMPIX_PATTERN_TWO_HOP, &nb, nullptr, nullptr, nullptr) == SYMPIX_ENOMEM);
     unsetenv("SYMPIX_FAIL_ALLOC");
     CHECK(sympix_grid_pattern_blocks(a, SYMPIX_PATTERN_TWO_HOP, &nb, nullptr, nullptr, nullptr) == SYMPIX_OK);
+    // transform plans: argument errors and the host allocation are checked
+    // before any device call
+    sympix_sht *sh = (sympix_sht *)0x1;
+    CHECK(sympix_sht_create(nullptr, 10, &sh) == SYMPIX_EINVAL && sh == (sympix_sht *)0x1);
+    CHECK(sympix_sht_create(a, -1, &sh) == SYMPIX_EINVAL && sh == nullptr);
+    CHECK(sympix_sht_create(a, 5000, &sh) == SYMPIX_EUNSUPPORTED && sh == nullptr);
+    setenv("SYMPIX_FAIL_ALLOC", "1", 1);
+    CHECK(sympix_sht_create(a, 64, &sh) == SYMPIX_ENOMEM && sh == nullptr);
+    unsetenv("SYMPIX_FAIL_ALLOC");
+    CHECK(sympix_sht_synthesis(nullptr, nullptr, 0, nullptr, 0, nullptr) == SYMPIX_EINVAL);
+    CHECK(sympix_sht_degrade(nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr) == SYMPIX_EINVAL);
+    sympix_sht_destroy(nullptr);
     sympix_grid_destroy(a);
     sympix_grid_destroy(b);
     sympix_grid_destroy(nullptr);

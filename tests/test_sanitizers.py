@@ -26,7 +26,7 @@ FLAGS = ["-std=c++17", "-O1", "-g", "-fPIC", "--offload-arch=gfx950",
 def test_host_abi_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     if not (os.path.exists(HIPCC) or shutil.which("hipcc")):
         pytest.skip("hipcc not available")
-    srcs = [os.path.join(CSRC, "geometry.cpp"), os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "kernels.hip"),
+    srcs = [os.path.join(CSRC, "geometry.cpp"), os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "sht.hip"),
             os.path.join(ROOT, "tests", "sanitize", "abi_host_check.cpp")]
     objs = []
     for src in srcs:
