@@ -87,21 +87,32 @@ __device__ __forceinline__ void rec_factors(int l, int m, double &alpha, double 
 // ---------------------------------------------------------------------------
 // Legendre synthesis.  Workgroup m; thread t takes the ring pairs t + 512 q
 // (R of them at a time, interleaved for latency).  LDS: (alpha, gamma) and
-// (a_cos, a_sin) per degree of this m.
+// (a_cos, a_sin) per degree of this m, padded by kLegPad entries so that the
+// loop reads ahead without a bound check.  Degrees go in pairs (odd i = l -
+// m, then even), so that the parity of each is fixed; the test for the 2^300
+// rescale is made once per pair (two steps of the recurrence grow a value by
+// far less than the 2^723 left to the top of the double range).
 // ---------------------------------------------------------------------------
+constexpr int kLegPad = 8;
+
+__device__ __forceinline__ void leg_fill(int m, int L, int nl, const double *ac, const double *as, double2 *sF,
+                                         double2 *sA) {
+    const int64_t off = mm_off(L, m);
+    for (int i = threadIdx.x; i < nl + kLegPad; i += kShtThreads) {
+        double al = 0.0, ga = 0.0;
+        if (i > 0 && i < nl) rec_factors(m + i, m, al, ga);
+        sF[i] = double2{al, ga};
+        if (sA) sA[i] = i < nl ? double2{ac[off + i], as[off + i]} : double2{0.0, 0.0};
+    }
+}
+
 template <int R>
 __global__ __launch_bounds__(kShtThreads) void k_leg_syn(ShtDesc d, const double *__restrict__ ac,
                                                          const double *__restrict__ as, double *__restrict__ fbuf) {
     extern __shared__ double2 sh[];
     const int m = blockIdx.x, L = d.lmax, nl = L - m + 1;
-    double2 *sF = sh, *sA = sh + nl;                  // (alpha, gamma), (a_cos, a_sin)
-    const int64_t off = mm_off(L, m);
-    for (int i = threadIdx.x; i < nl; i += kShtThreads) {
-        double al = 0.0, ga = 0.0;
-        if (i > 0) rec_factors(m + i, m, al, ga);
-        sF[i] = double2{al, ga};
-        sA[i] = double2{ac[off + i], as[off + i]};
-    }
+    double2 *sF = sh, *sA = sh + nl + kLegPad;        // (alpha, gamma), (a_cos, a_sin)
+    leg_fill(m, L, nl, ac, as, sF, sA);
     __syncthreads();
     for (int rp0 = threadIdx.x; rp0 < d.nhalf; rp0 += kShtThreads * R) {
         double ct[R], x[R], xp[R], ec[R], es[R], oc[R], os[R];
@@ -117,32 +128,33 @@ __global__ __launch_bounds__(kShtThreads) void k_leg_syn(ShtDesc d, const double
             es[q] = sA[0].y * x[q];
             oc[q] = os[q] = 0.0;
         }
-        // degrees l = m + i: odd i adds to (oc, os), even i to (ec, es)
-        for (int i = 1; i < nl; ++i) {
-            const double2 f = sF[i], a = sA[i];
-            const bool odd = (i & 1) != 0;
+        double2 f1 = sF[1], a1 = sA[1], f2 = sF[2], a2 = sA[2];
+        for (int i = 1; i < nl; i += 2) {
+            const double2 g1 = sF[i + 2], b1 = sA[i + 2], g2 = sF[i + 3], b2 = sA[i + 3];
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                double xn = f.x * ct[q] * x[q] - f.y * xp[q];
-                if (fabs(xn) > kBig) {                // rescale the recurrence and its sums
-                    xn *= kSmall;
+                const double x1 = fma(f1.x * ct[q], x[q], -f1.y * xp[q]);      // odd degree
+                oc[q] = fma(a1.x, x1, oc[q]);
+                os[q] = fma(a1.y, x1, os[q]);
+                const double x2 = fma(f2.x * ct[q], x1, -f2.y * x[q]);       // even degree (zero past L)
+                ec[q] = fma(a2.x, x2, ec[q]);
+                es[q] = fma(a2.y, x2, es[q]);
+                xp[q] = x1;
+                x[q] = x2;
+                if (fabs(x2) > kBig) {                // rescale the recurrence and its sums
                     x[q] *= kSmall;
+                    xp[q] *= kSmall;
                     ec[q] *= kSmall;
                     es[q] *= kSmall;
                     oc[q] *= kSmall;
                     os[q] *= kSmall;
                     e[q] += 300;
                 }
-                xp[q] = x[q];
-                x[q] = xn;
-                if (odd) {
-                    oc[q] = fma(a.x, xn, oc[q]);
-                    os[q] = fma(a.y, xn, os[q]);
-                } else {
-                    ec[q] = fma(a.x, xn, ec[q]);
-                    es[q] = fma(a.y, xn, es[q]);
-                }
             }
+            f1 = g1;
+            a1 = b1;
+            f2 = g2;
+            a2 = b2;
         }
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -160,10 +172,12 @@ __global__ __launch_bounds__(kShtThreads) void k_leg_syn(ShtDesc d, const double
 }
 
 // ---------------------------------------------------------------------------
-// Legendre transpose.  Workgroup m; thread t takes ring pairs as above and
-// adds lambda_lm (G(north) +- G(south)) over them for eight degrees at a time;
-// the workgroup then sums the 512 partials of each of the 16 values (cos, sin
-// x 8 degrees) through LDS and wave shuffles.
+// Legendre transpose.  Workgroup m; thread t carries ring pairs t + 512 q (q <
+// R) and adds lambda_lm (G(north) +- G(south)) over them, eight degrees at a
+// time (four pairs, parities fixed as above); the workgroup then sums the
+// 512 partials of each of the 16 values (cos, sin x 8 degrees) through LDS
+// (row w read by 32 threads at consecutive addresses) and wave shuffles.
+// Degrees past L read zero factors and are not written.
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ __launch_bounds__(kShtThreads) void k_leg_adj(ShtDesc d, const double *__restrict__ gbuf,
@@ -171,16 +185,11 @@ __global__ __launch_bounds__(kShtThreads) void k_leg_adj(ShtDesc d, const double
     constexpr int CH = 8;
     extern __shared__ double2 sh[];
     const int m = blockIdx.x, L = d.lmax, nl = L - m + 1;
-    double2 *sF = sh;                                  // (alpha, gamma) per degree
-    double *sRed = (double *)(sh + nl);                // [2 CH][512]
+    const int nch = (nl + CH - 1) / CH;
+    double2 *sF = sh;                                  // (alpha, gamma) per degree, zero past L
+    double *sRed = (double *)(sh + nl + kLegPad);      // [2 CH][512]
+    leg_fill(m, L, nl, nullptr, nullptr, sF, nullptr);  // nch CH <= nl + 7 < nl + kLegPad
     const int64_t off = mm_off(L, m);
-    for (int i = threadIdx.x; i < nl; i += kShtThreads) {
-        double al = 0.0, ga = 0.0;
-        if (i > 0) rec_factors(m + i, m, al, ga);
-        sF[i] = double2{al, ga};
-    }
-    // this thread's ring pairs (all of them, R at a time in turn would need
-    // the reduction per pass; the thread instead carries up to R pairs)
     double ct[R], x[R], xp[R], fsc[R], pc[R], mc[R], ps[R], ms[R];
     int e[R];
 #pragma unroll
@@ -202,37 +211,37 @@ __global__ __launch_bounds__(kShtThreads) void k_leg_adj(ShtDesc d, const double
         ms[q] = gn[1] - gs[1];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    for (int i0 = 0; i0 < nl; i0 += CH) {
+    for (int c = 0; c < nch; ++c) {
+        const int i0 = c * CH;
         double vc[CH], vs[CH];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int i = i0 + j;
-            vc[j] = vs[j] = 0.0;
-            if (i >= nl) continue;
-            const bool odd = (i & 1) != 0;
+        for (int j = 0; j < CH; ++j) vc[j] = vs[j] = 0.0;
+#pragma unroll
+        for (int j = 0; j < CH; j += 2) {
+            // degrees i0 + j (even i) and i0 + j + 1 (odd); i = 0 is lambda_mm itself
+            const double2 f0 = sF[i0 + j], f1 = sF[i0 + j + 1];
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                if (i > 0) {
-                    const double2 f = sF[i];
-                    double xn = f.x * ct[q] * x[q] - f.y * xp[q];
-                    if (fabs(xn) > kBig) {
-                        xn *= kSmall;
-                        x[q] *= kSmall;
-                        e[q] += 300;
-                        fsc[q] = ldexp(1.0, e[q]);
-                    }
-                    xp[q] = x[q];
-                    x[q] = xn;
+                double x0 = x[q];
+                if (i0 + j > 0) x0 = fma(f0.x * ct[q], x[q], -f0.y * xp[q]);
+                const double x1 = fma(f1.x * ct[q], x0, -f1.y * x[q]);
+                const double v0 = x0 * fsc[q], v1 = x1 * fsc[q];
+                vc[j] = fma(v0, pc[q], vc[j]);
+                vs[j] = fma(v0, ps[q], vs[j]);
+                vc[j + 1] = fma(v1, mc[q], vc[j + 1]);
+                vs[j + 1] = fma(v1, ms[q], vs[j + 1]);
+                // carry (x0, x1) as (x_{i-1}, x_i) of the next pair: the next
+                // even degree needs x_{i0+j+1} and x_{i0+j}
+                xp[q] = x0;
+                x[q] = x1;
+                if (fabs(x1) > kBig) {
+                    x[q] *= kSmall;
+                    xp[q] *= kSmall;
+                    e[q] += 300;
+                    fsc[q] = ldexp(1.0, e[q]);
                 }
-                const double v = x[q] * fsc[q];
-                vc[j] = fma(v, odd ? mc[q] : pc[q], vc[j]);
-                vs[j] = fma(v, odd ? ms[q] : ps[q], vs[j]);
             }
         }
-        // sum the 2 CH values over the workgroup: row w = 0..15 (cos rows
-        // first), thread t sums 16 of row t / 32's partials, then the 32
-        // threads of a row (half a wave) combine by shuffles
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             sRed[j * kShtThreads + threadIdx.x] = vc[j];
@@ -240,19 +249,18 @@ __global__ __launch_bounds__(kShtThreads) void k_leg_adj(ShtDesc d, const double
         }
         __syncthreads();
         const int row = threadIdx.x >> 5, seg = threadIdx.x & 31;
-        double s = 0.0;
+        double sum = 0.0;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) s += sRed[row * kShtThreads + seg * 16 + t];
+        for (int t = 0; t < 16; ++t) sum += sRed[row * kShtThreads + t * 32 + seg];   // 32 threads: 32 banks
 #pragma unroll
-        for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        for (int o = 16; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
         if (seg == 0) {
-            const int j = row & (CH - 1), i = i0 + j;
+            const int i = i0 + (row & (CH - 1));
             if (i < nl) {
-                if (row < CH) ac[off + i] = s;
-                else as[off + i] = m == 0 ? 0.0 : s;
+                if (row < CH) ac[off + i] = sum;
+                else as[off + i] = m == 0 ? 0.0 : sum;
             }
         }
-        (void)lane;
         __syncthreads();
     }
 }
@@ -426,8 +434,8 @@ __global__ __launch_bounds__(kShtThreads) void k_ring_adj(ShtDesc d, const doubl
 }  // namespace
 
 hipError_t sht_prepare(int lmax, int max_ring) {
-    const int leg_syn = 2 * (lmax + 1) * (int)sizeof(double2);
-    const int leg_adj = (lmax + 1) * (int)sizeof(double2) + 16 * kShtThreads * (int)sizeof(double);
+    const int leg_syn = 2 * (lmax + 1 + kLegPad) * (int)sizeof(double2);
+    const int leg_adj = (lmax + 1 + kLegPad) * (int)sizeof(double2) + 16 * kShtThreads * (int)sizeof(double);
     const int ring = max_ring * (int)sizeof(double2);
     hipError_t e = hipSuccess;
     auto set = [&](const void *f, int bytes) {
@@ -449,7 +457,7 @@ hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double
     const int L = d.lmax;
     const int64_t nalm = (int64_t)(L + 1) * (L + 1);
     if (alm) hipLaunchKernelGGL(k_alm_to_mm, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, st, alm, L, ac, as);
-    const size_t lds_leg = (size_t)2 * (L + 1) * sizeof(double2);
+    const size_t lds_leg = (size_t)2 * (L + 1 + kLegPad) * sizeof(double2);
     if (d.nhalf > 2 * kShtThreads)
         hipLaunchKernelGGL(k_leg_syn<3>, dim3(L + 1), dim3(kShtThreads), lds_leg, st, d, ac, as, fbuf);
     else if (d.nhalf > kShtThreads)
@@ -466,7 +474,7 @@ hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double
     const int L = d.lmax;
     const size_t lds_ring = (size_t)d.max_ring * sizeof(double2);
     hipLaunchKernelGGL(k_ring_adj, dim3(d.nrings), dim3(kShtThreads), lds_ring, st, d, map, gbuf, weighted ? 1 : 0);
-    const size_t lds_leg = (size_t)(L + 1) * sizeof(double2) + (size_t)16 * kShtThreads * sizeof(double);
+    const size_t lds_leg = (size_t)(L + 1 + kLegPad) * sizeof(double2) + (size_t)16 * kShtThreads * sizeof(double);
     if (d.nhalf > 2 * kShtThreads)
         hipLaunchKernelGGL(k_leg_adj<3>, dim3(L + 1), dim3(kShtThreads), lds_leg, st, d, gbuf, ac, as);
     else if (d.nhalf > kShtThreads)
