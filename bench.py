@@ -60,6 +60,7 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}                   # 
 BOUND = {"fp64": 1e-10, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 2.0 ** -15}  # gate each mode is held to
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x6": "bf16", "bf16x3": "bf16"}
 HBM_PEAK = 8000.0                                                              # GB/s
+FP64_VECTOR = 78.6     # TFLOP/s: FP64 FMA on the vector ALUs (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)
 KERNEL_NAME = {"fp64": "k_class_f64<false>", "fp32": "k_class_f32<false>", "bf16x3": "k_class_bf16<2, false>",
                "bf16x6": "k_class_bf16<3, false>"}
 BATCH_KERNEL = {"fp64": "k_batch_f64", "fp32": "k_batch_f32", "bf16x6": "k_batch_bf16<3>",
@@ -72,10 +73,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="lmax3000")
-    ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop", "two_grid"],
+    ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop", "two_grid", "sht"],
                     help="btnb: the D-hat / B-hat^T N^-1 B-hat step (default); conv: the pixel-domain "
                          "convolution g = B-hat f; two_hop: B^T N^-1 B on every nonzero block of the product; "
-                         "two_grid: B^T N_2^-1 B with N_2^-1 on an auxiliary grid (--lmax2, default twice)")
+                         "two_grid: B^T N_2^-1 B with N_2^-1 on an auxiliary grid (--lmax2, default twice); "
+                         "sht: spherical harmonic synthesis + analysis on the grid (L = lmax) and the degrade "
+                         "of Eq. 14 onto a grid of half the band limit")
     ap.add_argument("--lmax2", type=int, default=0, help="band limit of the auxiliary grid for --op two_grid")
     ap.add_argument("--modes", default=None,
                     help="precision modes, the first is reported as value (default fp64,bf16x6,fp32,bf16x3; "
@@ -551,6 +554,120 @@ def run_conv(args):
     print(json.dumps(line), flush=True)
 
 
+def sht_terms(nrings, L):
+    """(degree, order, ring) triples of one Legendre pass: nrings (L+1)(L+2)/2."""
+    return nrings * (L + 1) * (L + 2) // 2
+
+
+def cpu_baseline_sht(budget_s):
+    """The oracle's synthesis and analysis (whole grid, lmax 256, L = 256) until the budget is spent."""
+    from oracle import grid as G
+    from oracle import sht as H
+    info = host_info()
+    threads = blas_threads(info)
+    L = 256
+    og = G.make_grid(L, 8)
+    a = np.random.default_rng(4).standard_normal((L + 1) ** 2)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        H.analysis(og, H.synthesis(og, a, L), L)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n * 2 * sht_terms(og.nrings, L) / dt, "unit": "Legendre terms/s", "cores": int(threads),
+            "kind": "oracle", "sample": f"{n} synthesis + analysis round trips at lmax 256 (whole grid, L = 256), "
+                                       f"{dt:.1f} s wall", "host": info}
+
+
+def run_sht(args):
+    """Spherical harmonic synthesis + analysis (one round trip per step) at L =
+    lmax on the grid, and the degrade of Eq. 14 onto a grid of half the band
+    limit (timed apart)."""
+    import torch
+
+    import paper_1504_04653_amd as sp
+    from workloads import synth as S
+
+    cfg = S.CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    copy_calibration(torch, args.copy_calibration)
+    L = cfg.lmax
+    g = sp.Grid(cfg.lmax, cfg.k)
+    s = sp.Sht(g, L)
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(cfg.seed + 21)
+    ell = np.repeat(np.arange(L + 1), 2 * np.arange(L + 1) + 1)
+    a = torch.as_tensor(rng.standard_normal((L + 1) ** 2) / np.sqrt(ell + 1.0)).cuda()
+    f = torch.empty(g.npix, dtype=torch.float64, device="cuda")
+    back = torch.empty_like(a)
+    for _ in range(args.warmup):
+        s.synthesis(a, f, stream=stream)
+        s.analysis(f, back, stream=stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        s.synthesis(a, f, stream=stream)
+        ev[i][1].record(stream)
+        s.analysis(f, back, stream=stream)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    t_syn = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    t_ana = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    ms_step = wall * 1000.0 / args.steps
+    rt_err = float((back - a).abs().max() / a.abs().max())
+    # degrade onto a grid of half the band limit (L_2 = lmax / 2 on both plans)
+    L2 = cfg.lmax // 2
+    g2 = sp.Grid(L2, cfg.k)
+    so, s2 = sp.Sht(g, L2), sp.Sht(g2, L2)
+    th = torch.as_tensor(S.ninv_for(cfg, *g.pixel_theta_phi())).cuda()
+    th2 = torch.empty(g2.npix, dtype=torch.float64, device="cuda")
+    sp.degrade(so, s2, th, th2, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(3):
+        sp.degrade(so, s2, th, th2, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_deg = e0.elapsed_time(e1) / 3
+    terms = sht_terms(g.nrings, L)
+    flop = 8.0 * (g.nrings // 2) * (L + 1) * (L + 2) / 2        # one Legendre pass (see DESIGN)
+    achieved = flop / (t_syn.mean() * 1e-3) / 1e12
+    print(f"# sht {args.config}: lmax={cfg.lmax} L={L} npix={g.npix} nrings={g.nrings}; synthesis "
+          f"{t_syn.mean():.3f} ms, analysis {t_ana.mean():.3f} ms, round trip error {rt_err:.1e}; degrade "
+          f"lmax {cfg.lmax} -> {L2} (L={L2}) {t_deg:.3f} ms; Legendre part {achieved:.1f} TFLOP/s "
+          f"({achieved / FP64_VECTOR * 100:.1f}% of FP64 vector peak, whole synthesis call)",
+          file=sys.stderr, flush=True)
+    line = {
+        "metric": "spherical harmonic synthesis + analysis, Legendre terms/s",
+        "value": 2 * terms / (ms_step * 1e-3),
+        "unit": "Legendre terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"sympix lmax={cfg.lmax} k={cfg.k}, L={L}, a_lm ~ N(0, 1/(l+1)) seed "
+                               f"{cfg.seed + 21}; degrade of the N^-1 map onto lmax {L2}",
+                   "lmax": cfg.lmax, "L": L, "npix": g.npix, "nrings": g.nrings},
+        "modes": {"synthesis_ms": float(t_syn.mean()), "analysis_ms": float(t_ana.mean()),
+                  "degrade_ms": float(t_deg), "round_trip_error": rt_err},
+        "roofline": {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_VECTOR, "achieved": achieved,
+                     "frac": achieved / FP64_VECTOR, "kernel": "k_leg_syn (whole synthesis call timed)",
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_sht(args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def run_two_hop(args):
     """B^T N^-1 B on the two-hop pattern (every nonzero block of the product)."""
     import torch
@@ -728,6 +845,9 @@ def main():
         return
     if args.op == "two_grid":
         run_two_grid(args)
+        return
+    if args.op == "sht":
+        run_sht(args)
         return
     import torch
 
