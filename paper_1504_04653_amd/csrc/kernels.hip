@@ -721,7 +721,8 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     // W[16 i + lr][8 lk + g] and M[8 lk + g][16 j + lr].
     auto step = [&](const Own &oc, int buf, const SAddr &sa, const OAddr &oa, int sbuf, Stage &stn, Own &on,
                     bool first, bool bar, int nse, int nsh, int noa, int noe, int noh, SAddr &sa_n, OAddr &oa_n,
-                    int stp, DCopy &dprev) {
+                    int stp, DCopy &dprev, auto symt, int ng, int g0, int g1) {
+        constexpr bool S = decltype(symt)::value;
         stage_load(sa, stn);
         own_load(oa, on);
         if constexpr (WD) {
@@ -740,7 +741,8 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
         }
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
-            const int b = 32 * ch + 16 * jj + lr;
+            if (S && jj >= ng) continue;     // symmetric class: this wave's groups of the row
+            const int b = S ? 16 * (jj ? g1 : g0) + lr : 32 * ch + 16 * jj + lr;
             float m[8];
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
@@ -796,40 +798,75 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
     DCopy dpend;                           // D-hat chunks loaded, not yet stored
     dpend.dst[0] = dpend.dst[1] = nullptr;
     __syncthreads();
-    for (int it = 0; it < RPW * nterms; ++it) {
-        next(x, e, x1, e1);
-        const int a = rw + RP * x, a1 = rw + RP * x1;
-        int x2, e2;
-        next(x1, e1, x2, e2);
-        const int ib = 2 * (it & 1), nb = 2 - ib;
-        step(o0, ib, sa, oa, nb, s1, o1, true, false, e1, 1, a1, e1, 0, sa, oa, 2 * it, dpend);
-        step(o1, ib + 1, sa, oa, nb + 1, s0, o0, false, true, e2, 0, a1, e1, 1, sa, oa, 2 * it + 1, dpend);
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
-        if (e == nterms - 1) {           // end of output row a: store, clear
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int blk = sBlk[16 * i + 4 * lk + v];
-                    if (blk >= 0) {
-                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + 32 * ch + lr;
-#pragma unroll
-                        for (int j = 0; j < 2; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
-                    }
+    // Symmetric classes (every term pairs a unique block with itself: the
+    // blocks (J, J), with C[a][b] = C[b][a] bit for bit since the products
+    // B[p][a] B[p][b] are the same numbers either way round): row a needs only
+    // the column groups j >= a / 16 (= x / 4, as a = rw + 4 x); the tiles
+    // below the diagonal are written as mirror images.  The groups a row needs
+    // are shared out so that the two waves of a row phase (column halves 0
+    // and 1) do at most two groups each and one each where two are left:
+    // x / 4 = 0: {0, 1} | {2, 3};  1: {1} | {2, 3};  2: {2} | {3};  3: {} | {3}.
+    auto rows = [&](auto symt) {
+        constexpr bool S = decltype(symt)::value;
+        for (int it = 0; it < RPW * nterms; ++it) {
+            next(x, e, x1, e1);
+            const int a = rw + RP * x, a1 = rw + RP * x1;
+            int x2, e2;
+            next(x1, e1, x2, e2);
+            const int p = x >> 2;
+            int ng = 2, g0 = 2 * ch, g1 = 2 * ch + 1;
+            if constexpr (S) {
+                if (p == 1 && ch == 0) {
+                    ng = 1;
+                    g0 = 1;
+                } else if (p == 2) {
+                    ng = 1;
+                    g0 = 2 + ch;
+                } else if (p == 3) {
+                    ng = ch;
+                    g0 = 3;
                 }
+            }
+            const int ib = 2 * (it & 1), nb = 2 - ib;
+            step(o0, ib, sa, oa, nb, s1, o1, true, false, e1, 1, a1, e1, 0, sa, oa, 2 * it, dpend, symt, ng, g0, g1);
+            step(o1, ib + 1, sa, oa, nb + 1, s0, o0, false, true, e2, 0, a1, e1, 1, sa, oa, 2 * it + 1, dpend, symt,
+                 ng, g0, g1);
 #pragma unroll
             for (int i = 0; i < NI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+                for (int j = 0; j < 2; ++j)
+                    if (!S || j < ng) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
+                    }
+            if (e == nterms - 1) {           // end of output row a: store, clear
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int blk = sBlk[16 * i + 4 * lk + v];
+                        if (blk >= 0) {
+                            double *ob = out + (int64_t)blk * kBlockElems;
+#pragma unroll
+                            for (int j = 0; j < 2; ++j) {
+                                if (S && j >= ng) continue;
+                                const int G = S ? (j ? g1 : g0) : 2 * ch + j;
+                                __builtin_nontemporal_store(acc[i][j][v], &ob[a * 64 + 16 * G + lr]);
+                                if (S && G > p) __builtin_nontemporal_store(acc[i][j][v], &ob[(16 * G + lr) * 64 + a]);
+                            }
+                        }
+                    }
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+            }
+            x = x1;
+            e = e1;
         }
-        x = x1;
-        e = e1;
-    }
+    };
+    if (cl.sym != 0) rows(std::true_type());
+    else rows(std::false_type());
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
         dcopy_store(dpend, lane);
         for (int stp = 2 * RPW * nterms; 2 * NT * stp < kDChunks; ++stp) {
@@ -1075,12 +1112,6 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
     constexpr int NPROD = NP == 3 ? 6 : 3;
-    // One step, in three scheduling regions: (1) the loads of the next step
-    // (addresses read from LDS one step earlier); (2) the MFMAs of this step
-    // from LDS buffer buf (W fragments, and M formed from the staged B_IK
-    // values and this wave's B_IJ values), with the addresses of the step after
-    // next read meanwhile; (3) the next step's staged operands written to the
-    // other buffer, and one barrier.
     // One step, in three scheduling regions: (1) the loads of the staged
     // operands of the step two ahead and of this wave's B_IJ values of the
     // next step; (2) the MFMAs of this step from LDS buffer buf (W fragments,
@@ -1089,7 +1120,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     // operands written to buffer sbuf, and, at the end of a term, a barrier.
     auto step = [&](const Own &oc, int buf, const SAddr &sa, const OAddr &oa, int sbuf, Stage &stn, Own &on,
                     bool first, bool bar, int nse, int nsh, int noa, int noe, int noh, SAddr &sa_n, OAddr &oa_n,
-                    int stp, DCopy &dprev) {
+                    int stp, DCopy &dprev, auto symt, int ng, int g0, int g1) {
+        constexpr bool S = decltype(symt)::value;
         stage_load(sa, stn);
         own_load(oa, on);
         if constexpr (WD) {
@@ -1107,7 +1139,8 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
                 wf[i][k] = __builtin_bit_cast(bf16x8, sW[((buf * NP + k) * 64 + 16 * i + lr) * 4 + (lk ^ wsw(16 * i + lr))]);
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
-            const int b = 32 * ch + 16 * jj + lr;
+            if (S && jj >= ng) continue;     // symmetric class: this wave's groups of the row
+            const int b = S ? 16 * (jj ? g1 : g0) + lr : 32 * ch + 16 * jj + lr;
             const floatx4 u2a = sU[buf * 512 + b * 8 + ((2 * lk) ^ usw(b))];
             const floatx4 u2b = sU[buf * 512 + b * 8 + ((2 * lk + 1) ^ usw(b))];
             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -1185,40 +1218,77 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
     DCopy dpend;                           // D-hat chunks loaded, not yet stored
     dpend.dst[0] = dpend.dst[1] = nullptr;
     __syncthreads();
-    for (int it = 0; it < RPW * nterms; ++it) {
-        next(x, e, x1, e1);
-        const int a = rw + RP * x, a1 = rw + RP * x1;
-        int x2, e2;
-        next(x1, e1, x2, e2);
-        const int ib = 2 * (it & 1), nb = 2 - ib;
-        step(o0, ib, sa, oa, nb, s1, o1, true, false, e1, 1, a1, e1, 0, sa, oa, 2 * it, dpend);
-        step(o1, ib + 1, sa, oa, nb + 1, s0, o0, false, true, e2, 0, a1, e1, 1, sa, oa, 2 * it + 1, dpend);
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
-        if (e == nterms - 1) {           // end of output row a: store, clear
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int blk = sBlk[16 * i + 4 * lk + v];
-                    if (blk >= 0) {
-                        double *o = out + (int64_t)blk * kBlockElems + a * 64 + 32 * ch + lr;
-#pragma unroll
-                        for (int j = 0; j < 2; ++j) __builtin_nontemporal_store(acc[i][j][v], &o[16 * j]);
-                    }
+    // Symmetric classes (every term pairs a unique block with itself: the
+    // blocks (J, J), with C[a][b] = C[b][a] bit for bit since the products
+    // B[p][a] B[p][b] are the same numbers either way round): row a needs only
+    // the column groups j >= a / 16 (= x / 4, as a = rw + 4 x); the tiles
+    // below the diagonal are written as mirror images.  The groups a row needs
+    // are shared out so that the two waves of a row phase (column halves 0
+    // and 1) do at most two groups each and one each where two are left:
+    // x / 4 = 0: {0, 1} | {2, 3};  1: {1} | {2, 3};  2: {2} | {3};  3: {} | {3}.
+    auto rows = [&](auto symt) {
+        constexpr bool S = decltype(symt)::value;
+        for (int it = 0; it < RPW * nterms; ++it) {
+            next(x, e, x1, e1);
+            const int a = rw + RP * x, a1 = rw + RP * x1;
+            int x2, e2;
+            next(x1, e1, x2, e2);
+            const int p = x >> 2;
+            int ng = 2, g0 = 2 * ch, g1 = 2 * ch + 1;
+            if constexpr (S) {
+                if (p == 1 && ch == 0) {
+                    ng = 1;
+                    g0 = 1;
+                } else if (p == 2) {
+                    ng = 1;
+                    g0 = 2 + ch;
+                } else if (p == 3) {
+                    ng = ch;
+                    g0 = 3;
                 }
+            }
+            const int ib = 2 * (it & 1), nb = 2 - ib;
+            step(o0, ib, sa, oa, nb, s1, o1, true, false, e1, 1, a1, e1, 0, sa, oa, 2 * it, dpend, symt, ng, g0, g1);
+            step(o1, ib + 1, sa, oa, nb + 1, s0, o0, false, true, e2, 0, a1, e1, 1, sa, oa, 2 * it + 1, dpend, symt,
+                 ng, g0, g1);
 #pragma unroll
             for (int i = 0; i < NI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+                for (int j = 0; j < 2; ++j)
+                    if (!S || j < ng) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)part[i][j][v];
+                    }
+            if (e == nterms - 1) {           // end of output row a: store, clear
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int blk = sBlk[16 * i + 4 * lk + v];
+                        if (blk >= 0) {
+                            double *ob = out + (int64_t)blk * kBlockElems;
+#pragma unroll
+                            for (int j = 0; j < 2; ++j) {
+                                if (S && j >= ng) continue;
+                                const int G = S ? (j ? g1 : g0) : 2 * ch + j;
+                                __builtin_nontemporal_store(acc[i][j][v], &ob[a * 64 + 16 * G + lr]);
+                                if (S && G > p) __builtin_nontemporal_store(acc[i][j][v], &ob[(16 * G + lr) * 64 + a]);
+                            }
+                        }
+                    }
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+            }
+            x = x1;
+            e = e1;
         }
-        x = x1;
-        e = e1;
-    }
+    };
+    // The symmetric sharing of column groups is not used here: its branches
+    // inside the step cost the split-BF16 form more (the step's scheduling
+    // regions, code size) than the skipped groups save (measured).
+    rows(std::false_type());
     if constexpr (WD) {                  // the last step's chunks, then those past the last step
         dcopy_store(dpend, lane);
         for (int stp = 2 * RPW * nterms; 2 * NT * stp < kDChunks; ++stp) {
