@@ -356,7 +356,10 @@ __device__ __forceinline__ void empty_class_tile(const PD &pd, const DevClass &c
 // (J, J)) give C[a][b] = C[b][a] bit for bit, since the products B[p][a]
 // B[p][b] are the same numbers either way round.  Row a then computes only
 // the column groups j >= a / 16 (10 of the 16 16x16 tiles) and writes the
-// tiles below the diagonal as mirror images.  Wave w's row x is a = w + 4 x,
+// tiles below the diagonal as mirror images (plain stores: a mirrored row
+// gets its 16 values from 16 rows a at different times, and L2 merges them,
+// where streaming stores would send each 8 bytes out as a partial line).
+// Wave w's row x is a = w + 4 x,
 // so a / 16 = x / 4: its rows run in four phases with the first column group
 // JLO fixed at compile time (JLO = 0 for every row of other classes).  A step
 // issues one W load per 16 members whatever the number of column groups, so
@@ -490,8 +493,7 @@ __device__ __forceinline__ void class_f64_tile(const ProblemDesc64 &pd, int item
                         if constexpr (SYM) {
 #pragma unroll
                             for (int j = JLO + 1; j < 4; ++j)
-                                __builtin_nontemporal_store(acc[(r * NJ + j - JLO) * NI + i][v],
-                                                            &ob[(16 * j + lr) * 64 + a]);
+                                ob[(16 * j + lr) * 64 + a] = acc[(r * NJ + j - JLO) * NI + i][v];
                         }
                     }
                 }
@@ -852,7 +854,7 @@ __device__ __forceinline__ void class_f32_tile(const ProblemDesc &pd, int item, 
                                 if (S && j >= ng) continue;
                                 const int G = S ? (j ? g1 : g0) : 2 * ch + j;
                                 __builtin_nontemporal_store(acc[i][j][v], &ob[a * 64 + 16 * G + lr]);
-                                if (S && G > p) __builtin_nontemporal_store(acc[i][j][v], &ob[(16 * G + lr) * 64 + a]);
+                                if (S && G > p) ob[(16 * G + lr) * 64 + a] = acc[i][j][v];
                             }
                         }
                     }
@@ -1272,7 +1274,7 @@ __device__ __forceinline__ void class_bf16_tile(const ProblemDescB &pd, int item
                                 if (S && j >= ng) continue;
                                 const int G = S ? (j ? g1 : g0) : 2 * ch + j;
                                 __builtin_nontemporal_store(acc[i][j][v], &ob[a * 64 + 16 * G + lr]);
-                                if (S && G > p) __builtin_nontemporal_store(acc[i][j][v], &ob[(16 * G + lr) * 64 + a]);
+                                if (S && G > p) ob[(16 * G + lr) * 64 + a] = acc[i][j][v];
                             }
                         }
                     }
