@@ -77,6 +77,42 @@ def lambda_table(lmax: int, theta) -> np.ndarray:
     return out
 
 
+def lambda_m(lmax: int, m: int, theta) -> np.ndarray:
+    """lambda_lm(theta) of one order m for l = m .. lmax: array [lmax+1-m, ntheta].
+    The same steps as lambda_table (the product recurrence in m up to m, then
+    the recurrence in l), for checks at band limits where the full table is
+    too large."""
+    theta = np.atleast_1d(np.asarray(theta, dtype=np.float64))
+    x = np.cos(theta)
+    s = np.sin(theta)
+    mant = np.full(theta.size, np.sqrt(1.0 / (4.0 * np.pi)))
+    e2 = np.zeros(theta.size, dtype=np.int64)
+    for k in range(1, m + 1):
+        mant = mant * np.sqrt((2.0 * k + 1.0) / (2.0 * k)) * s
+        small = np.abs(mant) < 1.0 / _RESCALE
+        mant = np.where(small, mant * _RESCALE, mant)
+        e2 = np.where(small, e2 - 300, e2)
+    out = np.zeros((lmax + 1 - m, theta.size))
+    p_prev = np.zeros(theta.size)
+    p = mant.copy()
+    e = e2.copy()
+    out[0] = np.ldexp(p, e)
+    for l in range(m + 1, lmax + 1):
+        a = np.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+        if l == m + 1:
+            q = a * x * p
+        else:
+            b = np.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+            q = a * (x * p - b * p_prev)
+        big = np.abs(q) > _RESCALE
+        q = np.where(big, q / _RESCALE, q)
+        p = np.where(big, p / _RESCALE, p)
+        e = np.where(big, e + 300, e)
+        p_prev, p = p, q
+        out[l - m] = np.ldexp(p, e)
+    return out
+
+
 def _index(l: int, m: int) -> int:
     return l * l + l + m
 

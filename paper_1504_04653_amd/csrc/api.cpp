@@ -1562,6 +1562,7 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
         max_ring = std::max(max_ring, n);
     }
     if (max_ring > sympix::kShtMaxRing) return fail(SYMPIX_EUNSUPPORTED, "a ring is longer than 8192 pixels");
+    if (nh > sympix::kShtMaxHalfRings) return fail(SYMPIX_EUNSUPPORTED, "more than 4096 rings");
     // lambda_mm of the northern rings: the product recurrence lambda_mm =
     // lambda_{m-1,m-1} sqrt((2m+1)/(2m)) sin(theta) from 1/sqrt(4 pi), kept as
     // mant * 2^exp with mant >= 2^-300
@@ -1584,6 +1585,29 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
             ex[(size_t)m * nh + r] = e;
         }
     }
+    // m-major rows and the monic recurrence's per-degree values (the same
+    // for every ring): b_i = ((l-1)^2 - m^2) / (4 (l-1)^2 - 1), b_0 = -1, and
+    // K_i = prod alpha_j over j in [64 floor(i / 64), i], j >= 1, alpha_j^2 =
+    // (4 l_j^2 - 1) / (l_j^2 - m^2); products and quotients in long double
+    std::vector<int64_t> row_off(L + 1);
+    int64_t nrow = 0;
+    for (int32_t m = 0; m <= L; ++m) {
+        row_off[m] = nrow;
+        nrow += ((int64_t)(L - m + 1) + sympix::kShtRowPad + 3) / 4 * 4;
+    }
+    std::vector<double> rec_b((size_t)nrow, 0.0), rec_k((size_t)nrow, 0.0);
+    for (int32_t m = 0; m <= L; ++m) {
+        double *bb = &rec_b[(size_t)row_off[m]], *kk = &rec_k[(size_t)row_off[m]];
+        const long double mm = (long double)m * m;
+        long double k2 = 1.0L;
+        for (int32_t i = 0; i <= L - m; ++i) {
+            const long double l = (long double)(m + i), l1 = l - 1.0L;
+            bb[i] = i == 0 ? -1.0 : (double)((l1 * l1 - mm) / (4.0L * l1 * l1 - 1.0L));
+            const long double a2 = i == 0 ? 1.0L : (4.0L * l * l - 1.0L) / (l * l - mm);
+            k2 = (i % 64 == 0) ? a2 : k2 * a2;
+            kk[i] = (double)std::sqrt(k2);
+        }
+    }
     sympix_sht *s = injected_alloc_failure() ? nullptr : new (std::nothrow) sympix_sht();
     if (!s) return fail(SYMPIX_ENOMEM, "host allocation failed");
     s->g = g;
@@ -1594,7 +1618,6 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
         return hip_fail(e, "hipGetDevice");
     }
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t nmm = (size_t)(L + 1) * (L + 2) / 2;
     size_t o = 0;
     const size_t o_cos = o;   o += up(sizeof(double) * nh);
     const size_t o_mant = o;  o += up(sizeof(double) * mant.size());
@@ -1604,8 +1627,11 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
     const size_t o_w = o;     o += up(sizeof(double) * nr);
     const size_t o_rad = o;   o += up(rad.size());
     const size_t o_f = o;     o += up(sizeof(double) * 2 * (size_t)nr * (L + 1));
-    const size_t o_ac = o;    o += up(sizeof(double) * nmm);
-    const size_t o_as = o;    o += up(sizeof(double) * nmm);
+    const size_t o_row = o;   o += up(sizeof(int64_t) * (L + 1));
+    const size_t o_b = o;     o += up(sizeof(double) * (size_t)nrow);
+    const size_t o_k = o;     o += up(sizeof(double) * (size_t)nrow);
+    const size_t o_ac = o;    o += up(sizeof(double) * (size_t)nrow);
+    const size_t o_as = o;    o += up(sizeof(double) * (size_t)nrow);
     e = injected_alloc_failure() ? hipErrorOutOfMemory : hipMalloc(&s->block, o);
     if (e != hipSuccess) {
         s->block = nullptr;
@@ -1624,7 +1650,12 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
     put(o_pix, pix0.data(), sizeof(int64_t) * nr);
     put(o_w, rw.data(), sizeof(double) * nr);
     put(o_rad, rad.data(), rad.size());
-    if (e == hipSuccess) e = sympix::sht_prepare(L, max_ring);
+    put(o_row, row_off.data(), sizeof(int64_t) * (L + 1));
+    put(o_b, rec_b.data(), sizeof(double) * (size_t)nrow);
+    put(o_k, rec_k.data(), sizeof(double) * (size_t)nrow);
+    // the rows' padding of ac / as stays zero: the kernels write entries i <= L - m only
+    if (e == hipSuccess) e = hipMemset(base + o_ac, 0, (o_as - o_ac) + sizeof(double) * (size_t)nrow);
+    if (e == hipSuccess) e = sympix::sht_prepare(max_ring);
     if (e != hipSuccess) {
         hipFree(s->block);
         delete s;
@@ -1644,6 +1675,9 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
     d.ring_pix0 = (const int64_t *)(base + o_pix);
     d.ring_w = (const double *)(base + o_w);
     d.ring_rad = (const int8_t *)(base + o_rad);
+    d.row_off = (const int64_t *)(base + o_row);
+    d.rec_b = (const double *)(base + o_b);
+    d.rec_k = (const double *)(base + o_k);
     s->fbuf = (double *)(base + o_f);
     s->ac = (double *)(base + o_ac);
     s->as = (double *)(base + o_as);

@@ -16,28 +16,28 @@
 //   k_leg_adj  one workgroup per m: a_lm = sum_rings lambda_lm G_m(ring),
 //              reduced across the workgroup eight degrees at a time
 //
-// lambda_lm is carried by the three-term recurrence in l from lambda_mm
-// (tabulated on the host), on values scaled by a power of two that changes by
-// 2^300 when they grow past 2^300, so that the far-below-range values near the
-// poles at high m still reach the degrees where they matter.
+// lambda_lm is carried from lambda_mm (tabulated on the host) by the monic
+// form of its three-term recurrence in l, with a per-ring power-of-two scale
+// (the recurrence section below).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "sht.hpp"
 
 namespace sympix {
 namespace {
 
-constexpr int kShtThreads = 512;
+constexpr int kShtThreads = 512;     // ring kernels
+constexpr int kLegThreads = 256;     // Legendre kernels
 constexpr double kSqrt2 = 1.4142135623730951;
 constexpr double kBig = 0x1p300, kSmall = 0x1p-300;
 
-__device__ __forceinline__ int64_t mm_off(int L, int m) {     // m-major layout: rows l = m..L
-    return (int64_t)m * (L + 1) - (int64_t)m * (m - 1) / 2;
-}
-
 // ---------------------------------------------------------------------------
-// Coefficient layout: (L+1)^2 entries at l^2 + l + m  <->  m-major rows of
-// cos (m >= 0) and sin (m >= 1; the m = 0 row is zero) coefficients.
+// Coefficient layout: (L+1)^2 entries at l^2 + l + m  <->  m-major rows (row
+// m from row_off[m], entry i = l - m, zero padding after entry L - m) of cos
+// (m >= 0) and sin (m >= 1; the m = 0 row is zero) coefficients, each held
+// times K_lm, the scale of the monic recurrence below.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void lm_of(int64_t idx, int &l, int &m) {
     int q = (int)sqrt((double)idx);
@@ -47,103 +47,100 @@ __device__ __forceinline__ void lm_of(int64_t idx, int &l, int &m) {
     m = (int)(idx - (int64_t)q * q - q);
 }
 
+// one workgroup per m: row m written in order, its entries read at stride ~2l
 __global__ __launch_bounds__(256) void k_alm_to_mm(const double *__restrict__ alm, int L,
-                                                   double *__restrict__ ac, double *__restrict__ as) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)(L + 1) * (L + 1)) return;
-    int l, m;
-    lm_of(idx, l, m);
-    if (m >= 0) {
-        ac[mm_off(L, m) + l - m] = alm[idx];
-        if (m == 0) as[mm_off(L, 0) + l] = 0.0;
-    } else {
-        as[mm_off(L, -m) + l + m] = alm[idx];
+                                                   const int64_t *__restrict__ row_off,
+                                                   const double *__restrict__ rk, double *__restrict__ ac,
+                                                   double *__restrict__ as) {
+    const int m = blockIdx.x;
+    const int64_t off = row_off[m];
+    for (int i = threadIdx.x; i <= L - m; i += 256) {
+        const int64_t l = m + i, c = l * l + l;
+        const double k = rk[off + i];
+        ac[off + i] = alm[c + m] * k;
+        as[off + i] = m == 0 ? 0.0 : alm[c - m] * k;
     }
 }
 
 __global__ __launch_bounds__(256) void k_mm_to_alm(const double *__restrict__ ac, const double *__restrict__ as,
-                                                   int L, double *__restrict__ alm) {
+                                                   int L, const int64_t *__restrict__ row_off,
+                                                   const double *__restrict__ rk, double *__restrict__ alm) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)(L + 1) * (L + 1)) return;
     int l, m;
     lm_of(idx, l, m);
-    alm[idx] = m >= 0 ? ac[mm_off(L, m) + l - m] : as[mm_off(L, -m) + l + m];
-}
-
-// recurrence factors of degree l (l > m): lambda_l = alpha cos(t) lambda_{l-1}
-// - gamma lambda_{l-2}; gamma = 0 at l = m + 1
-__device__ __forceinline__ void rec_factors(int l, int m, double &alpha, double &gamma) {
-    const double dl = l, dm = m;
-    if (l == m + 1) {
-        alpha = sqrt(2.0 * dm + 3.0);
-        gamma = 0.0;
-        return;
-    }
-    alpha = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
-    const double beta = sqrt(((dl - 1.0) * (dl - 1.0) - dm * dm) / (4.0 * (dl - 1.0) * (dl - 1.0) - 1.0));
-    gamma = alpha * beta;
+    const int64_t o = row_off[m >= 0 ? m : -m] + l - (m >= 0 ? m : -m);
+    alm[idx] = (m >= 0 ? ac[o] : as[o]) / rk[o];
 }
 
 // ---------------------------------------------------------------------------
-// Legendre synthesis.  Workgroup m; thread t takes the ring pairs t + 512 q
-// (R of them at a time, interleaved for latency).  LDS: (alpha, gamma) and
-// (a_cos, a_sin) per degree of this m, padded by kLegPad entries so that the
-// loop reads ahead without a bound check.  Degrees go in pairs (odd i = l -
-// m, then even), so that the parity of each is fixed; the test for the 2^300
-// rescale is made once per pair (two steps of the recurrence grow a value by
-// far less than the 2^723 left to the top of the double range).
+// The recurrence.  lambda_lm = 2^e K_i mu_i (i = l - m), where mu follows the
+// monic recurrence mu_i = cos(theta) mu_{i-1} - b_i mu_{i-2} with b_i =
+// ((l-1)^2 - m^2) / (4 (l-1)^2 - 1); b_0 = -1 starts it from (mu_{-1},
+// mu_{-2}) = (0, lambda_mm 2^-e).  K_i is the product of the factors alpha_j
+// = sqrt((4 l_j^2 - 1) / (l_j^2 - m^2)) of the normalised recurrence over j in
+// [64 c, i], the 64-degree chunk c of i (j >= 1), so that K stays within the
+// double range; at a chunk start mu_{i-1} and mu_{i-2} are multiplied by K of
+// the chunk before's last degree.  A step is then one multiply and one fused
+// multiply-add, and the per-degree values (b_i, the coefficients times K) are
+// the same for every ring: the kernels read them with uniform loads, which go
+// through the scalar cache into scalar registers.
+//
+// When |mu| has grown past 2^300 at a test (one per four or eight degrees),
+// mu is scaled by 2^-300 and e raised by 300, so that the values far below the
+// double range near the poles at high m still reach the degrees where they
+// matter.  Between tests |mu| grows by less than 1.25 per degree (|cos| <= 1,
+// 0 <= b_i < 1/4), and by at most 2^270 at a chunk start, so that it stays
+// below 2^600.
 // ---------------------------------------------------------------------------
-constexpr int kLegPad = 8;
+struct Deg4 { double v[4]; };   // four consecutive degrees of a row (32-byte aligned)
 
-__device__ __forceinline__ void leg_fill(int m, int L, int nl, const double *ac, const double *as, double2 *sF,
-                                         double2 *sA) {
-    const int64_t off = mm_off(L, m);
-    for (int i = threadIdx.x; i < nl + kLegPad; i += kShtThreads) {
-        double al = 0.0, ga = 0.0;
-        if (i > 0 && i < nl) rec_factors(m + i, m, al, ga);
-        sF[i] = double2{al, ga};
-        if (sA) sA[i] = i < nl ? double2{ac[off + i], as[off + i]} : double2{0.0, 0.0};
-    }
-}
+__device__ __forceinline__ Deg4 deg4(const double *p) { return *(const Deg4 *)p; }
 
+// ---------------------------------------------------------------------------
+// Legendre synthesis.  Workgroup m; thread t takes the ring pairs t + 256 q
+// (R of them at a time, interleaved for latency).  Degrees go four at a time
+// (even, odd, even, odd i), the next four read ahead; the rescale test is made
+// once per four degrees (four steps grow |mu| by less than 2.5).
+// ---------------------------------------------------------------------------
 template <int R>
-__global__ __launch_bounds__(kShtThreads) void k_leg_syn(ShtDesc d, const double *__restrict__ ac,
-                                                         const double *__restrict__ as, double *__restrict__ fbuf) {
-    extern __shared__ double2 sh[];
+__global__ __launch_bounds__(kLegThreads) void k_leg_syn(ShtDesc d, const int64_t *__restrict__ row_off,
+                                                         const double *__restrict__ rb,
+                                                         const double *__restrict__ rk,
+                                                         const double *__restrict__ ac,
+                                                         const double *__restrict__ as,
+                                                         double *__restrict__ fbuf) {
     const int m = blockIdx.x, L = d.lmax, nl = L - m + 1;
-    double2 *sF = sh, *sA = sh + nl + kLegPad;        // (alpha, gamma), (a_cos, a_sin)
-    leg_fill(m, L, nl, ac, as, sF, sA);
-    __syncthreads();
-    for (int rp0 = threadIdx.x; rp0 < d.nhalf; rp0 += kShtThreads * R) {
-        double ct[R], x[R], xp[R], ec[R], es[R], oc[R], os[R];
+    const int64_t off = row_off[m];
+    const double *b = rb + off, *kk = rk + off, *cc = ac + off, *cs = as + off;
+    for (int rp0 = threadIdx.x; rp0 < d.nhalf; rp0 += kLegThreads * R) {
+        double ct[R], mu[R], mup[R], ec[R], es[R], oc[R], os[R];
         int e[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const int rp = min(rp0 + kShtThreads * q, d.nhalf - 1);
+            const int rp = min(rp0 + kLegThreads * q, d.nhalf - 1);
             ct[q] = d.ring_cos[rp];
-            x[q] = d.lmm_mant[(int64_t)m * d.nhalf + rp];
+            mu[q] = 0.0;
+            mup[q] = d.lmm_mant[(int64_t)m * d.nhalf + rp];
             e[q] = d.lmm_exp[(int64_t)m * d.nhalf + rp];
-            xp[q] = 0.0;
-            ec[q] = sA[0].x * x[q];
-            es[q] = sA[0].y * x[q];
-            oc[q] = os[q] = 0.0;
+            ec[q] = es[q] = oc[q] = os[q] = 0.0;
         }
-        double2 f1 = sF[1], a1 = sA[1], f2 = sF[2], a2 = sA[2];
-        for (int i = 1; i < nl; i += 2) {
-            const double2 g1 = sF[i + 2], b1 = sA[i + 2], g2 = sF[i + 3], b2 = sA[i + 3];
+        Deg4 gb = deg4(b), gc = deg4(cc), gs = deg4(cs);
+        for (int i0 = 0; i0 < nl; i0 += 4) {
+            const Deg4 nb = deg4(b + i0 + 4), nc = deg4(cc + i0 + 4), ns = deg4(cs + i0 + 4);
+            if (i0 != 0 && (i0 & 63) == 0) {      // chunk start: carry K of the chunk before
+                const double sk = kk[i0 - 1];
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    mu[q] *= sk;
+                    mup[q] *= sk;
+                }
+            }
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const double x1 = fma(f1.x * ct[q], x[q], -f1.y * xp[q]);      // odd degree
-                oc[q] = fma(a1.x, x1, oc[q]);
-                os[q] = fma(a1.y, x1, os[q]);
-                const double x2 = fma(f2.x * ct[q], x1, -f2.y * x[q]);       // even degree (zero past L)
-                ec[q] = fma(a2.x, x2, ec[q]);
-                es[q] = fma(a2.y, x2, es[q]);
-                xp[q] = x1;
-                x[q] = x2;
-                if (fabs(x2) > kBig) {                // rescale the recurrence and its sums
-                    x[q] *= kSmall;
-                    xp[q] *= kSmall;
+                if (fabs(mu[q]) > kBig) {
+                    mu[q] *= kSmall;
+                    mup[q] *= kSmall;
                     ec[q] *= kSmall;
                     es[q] *= kSmall;
                     oc[q] *= kSmall;
@@ -151,14 +148,30 @@ __global__ __launch_bounds__(kShtThreads) void k_leg_syn(ShtDesc d, const double
                     e[q] += 300;
                 }
             }
-            f1 = g1;
-            a1 = b1;
-            f2 = g2;
-            a2 = b2;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const double x0 = fma(ct[q], mu[q], -gb.v[0] * mup[q]);   // even i
+                ec[q] = fma(gc.v[0], x0, ec[q]);
+                es[q] = fma(gs.v[0], x0, es[q]);
+                const double x1 = fma(ct[q], x0, -gb.v[1] * mu[q]);      // odd
+                oc[q] = fma(gc.v[1], x1, oc[q]);
+                os[q] = fma(gs.v[1], x1, os[q]);
+                const double x2 = fma(ct[q], x1, -gb.v[2] * x0);         // even
+                ec[q] = fma(gc.v[2], x2, ec[q]);
+                es[q] = fma(gs.v[2], x2, es[q]);
+                const double x3 = fma(ct[q], x2, -gb.v[3] * x1);         // odd
+                oc[q] = fma(gc.v[3], x3, oc[q]);
+                os[q] = fma(gs.v[3], x3, os[q]);
+                mup[q] = x2;
+                mu[q] = x3;
+            }
+            gb = nb;
+            gc = nc;
+            gs = ns;
         }
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const int rp = rp0 + kShtThreads * q;
+            const int rp = rp0 + kLegThreads * q;
             if (rp >= d.nhalf) continue;
             const int rs = d.nrings - 1 - rp;
             double *fn = fbuf + ((int64_t)rp * (L + 1) + m) * 2;
@@ -172,96 +185,126 @@ __global__ __launch_bounds__(kShtThreads) void k_leg_syn(ShtDesc d, const double
 }
 
 // ---------------------------------------------------------------------------
-// Legendre transpose.  Workgroup m; thread t carries ring pairs t + 512 q (q <
-// R) and adds lambda_lm (G(north) +- G(south)) over them, eight degrees at a
-// time (four pairs, parities fixed as above); the workgroup then sums the
-// 512 partials of each of the 16 values (cos, sin x 8 degrees) through LDS
-// (row w read by 32 threads at consecutive addresses) and wave shuffles.
-// Degrees past L read zero factors and are not written.
+// Legendre transpose.  Workgroup m; thread t carries the ring pairs t + 256 q
+// (q < R, R 256 >= nhalf), with G(north) +- G(south) scaled by 2^e, and adds
+// mu_i times them over its rings, eight degrees at a time; the workgroup then
+// sums the 256 partials of each of the 16 values (cos, sin x 8 degrees)
+// through LDS and wave shuffles, and the result times K_i^2 (K_i for lambda,
+// K_i for the stored scale) is written.  Degrees past L read b = 0 and are
+// not written.
+//
+// While a ring's e is below kEMin its terms are left out: there |lambda| <
+// 2^(e + 573) < 2^-387 (|mu| < 2^303 after a test, K < 2^270), far below the
+// rounding of any sum.  2^e G would underflow there; when a rescale lifts e to
+// kEMin or above, the ring's G is read again and scaled by the new 2^e.
 // ---------------------------------------------------------------------------
+constexpr int kEMin = -960;
+
+struct RingG { double pc, mc, ps, ms; };
+
+// G(north) +- G(south) of mode m on ring pair r, scaled by 2^e (zero below kEMin)
+__device__ __forceinline__ RingG ring_g(const ShtDesc &d, const double *gbuf, int r, int m, int e) {
+    const int L = d.lmax, rs = d.nrings - 1 - r;
+    const double sc = e >= kEMin ? ldexp(1.0, e) : 0.0;
+    const double *gn = gbuf + ((int64_t)r * (L + 1) + m) * 2;
+    const double *gs = gbuf + ((int64_t)rs * (L + 1) + m) * 2;
+    return RingG{(gn[0] + gs[0]) * sc, (gn[0] - gs[0]) * sc, (gn[1] + gs[1]) * sc, (gn[1] - gs[1]) * sc};
+}
+
 template <int R>
-__global__ __launch_bounds__(kShtThreads) void k_leg_adj(ShtDesc d, const double *__restrict__ gbuf,
+__global__ __launch_bounds__(kLegThreads) void k_leg_adj(ShtDesc d, const int64_t *__restrict__ row_off,
+                                                         const double *__restrict__ rb,
+                                                         const double *__restrict__ rk,
+                                                         const double *__restrict__ gbuf,
                                                          double *__restrict__ ac, double *__restrict__ as) {
     constexpr int CH = 8;
-    extern __shared__ double2 sh[];
+    __shared__ double sRed[2 * CH * kLegThreads];
     const int m = blockIdx.x, L = d.lmax, nl = L - m + 1;
-    const int nch = (nl + CH - 1) / CH;
-    double2 *sF = sh;                                  // (alpha, gamma) per degree, zero past L
-    double *sRed = (double *)(sh + nl + kLegPad);      // [2 CH][512]
-    leg_fill(m, L, nl, nullptr, nullptr, sF, nullptr);  // nch CH <= nl + 7 < nl + kLegPad
-    const int64_t off = mm_off(L, m);
-    double ct[R], x[R], xp[R], fsc[R], pc[R], mc[R], ps[R], ms[R];
+    const int64_t off = row_off[m];
+    const double *b = rb + off, *kk = rk + off;
+    double ct[R], mu[R], mup[R];
+    RingG g[R];
     int e[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int rp = threadIdx.x + kShtThreads * q;
+        const int rp = threadIdx.x + kLegThreads * q;
         const bool ok = rp < d.nhalf;
         const int r = ok ? rp : 0;
-        const int rs = d.nrings - 1 - r;
-        ct[q] = d.ring_cos[r];
-        x[q] = ok ? d.lmm_mant[(int64_t)m * d.nhalf + r] : 0.0;
         e[q] = d.lmm_exp[(int64_t)m * d.nhalf + r];
-        fsc[q] = ldexp(1.0, e[q]);
-        xp[q] = 0.0;
-        const double *gn = gbuf + ((int64_t)r * (L + 1) + m) * 2;
-        const double *gs = gbuf + ((int64_t)rs * (L + 1) + m) * 2;
-        pc[q] = gn[0] + gs[0];
-        mc[q] = gn[0] - gs[0];
-        ps[q] = gn[1] + gs[1];
-        ms[q] = gn[1] - gs[1];
+        ct[q] = d.ring_cos[r];
+        mu[q] = 0.0;
+        mup[q] = ok ? d.lmm_mant[(int64_t)m * d.nhalf + r] : 0.0;
+        g[q] = ring_g(d, gbuf, r, m, e[q]);
     }
-    __syncthreads();
-    for (int c = 0; c < nch; ++c) {
-        const int i0 = c * CH;
+    Deg4 b0 = deg4(b), b1 = deg4(b + 4);
+    for (int i0 = 0; i0 < nl; i0 += CH) {
+        const Deg4 n0 = deg4(b + i0 + 8), n1 = deg4(b + i0 + 12);
+        if (i0 != 0 && (i0 & 63) == 0) {
+            const double sk = kk[i0 - 1];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                mu[q] *= sk;
+                mup[q] *= sk;
+            }
+        }
         double vc[CH], vs[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) vc[j] = vs[j] = 0.0;
 #pragma unroll
-        for (int j = 0; j < CH; j += 2) {
-            // degrees i0 + j (even i) and i0 + j + 1 (odd); i = 0 is lambda_mm itself
-            const double2 f0 = sF[i0 + j], f1 = sF[i0 + j + 1];
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                double x0 = x[q];
-                if (i0 + j > 0) x0 = fma(f0.x * ct[q], x[q], -f0.y * xp[q]);
-                const double x1 = fma(f1.x * ct[q], x0, -f1.y * x[q]);
-                const double v0 = x0 * fsc[q], v1 = x1 * fsc[q];
-                vc[j] = fma(v0, pc[q], vc[j]);
-                vs[j] = fma(v0, ps[q], vs[j]);
-                vc[j + 1] = fma(v1, mc[q], vc[j + 1]);
-                vs[j + 1] = fma(v1, ms[q], vs[j + 1]);
-                // carry (x0, x1) as (x_{i-1}, x_i) of the next pair: the next
-                // even degree needs x_{i0+j+1} and x_{i0+j}
-                xp[q] = x0;
-                x[q] = x1;
-                if (fabs(x1) > kBig) {
-                    x[q] *= kSmall;
-                    xp[q] *= kSmall;
-                    e[q] += 300;
-                    fsc[q] = ldexp(1.0, e[q]);
+        for (int q = 0; q < R; ++q) {
+            if (fabs(mu[q]) > kBig) {
+                mu[q] *= kSmall;
+                mup[q] *= kSmall;
+                e[q] += 300;
+                if (e[q] - 300 >= kEMin) {
+                    g[q].pc *= kBig;
+                    g[q].mc *= kBig;
+                    g[q].ps *= kBig;
+                    g[q].ms *= kBig;
+                } else if (e[q] >= kEMin) {       // the ring's terms start to count
+                    // the ring index is made opaque, so that the compiler does not keep
+                    // this rare reload's addresses live across the loop
+                    int rr = min(threadIdx.x + kLegThreads * q, d.nhalf - 1);
+                    asm volatile("" : "+v"(rr));
+                    g[q] = ring_g(d, gbuf, rr, m, e[q]);
                 }
             }
+            double x = mu[q], xp = mup[q];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const double bj = j < 4 ? b0.v[j] : b1.v[j - 4];
+                const double xn = fma(ct[q], x, -bj * xp);
+                vc[j] = fma(xn, (j & 1) ? g[q].mc : g[q].pc, vc[j]);
+                vs[j] = fma(xn, (j & 1) ? g[q].ms : g[q].ps, vs[j]);
+                xp = x;
+                x = xn;
+            }
+            mu[q] = x;
+            mup[q] = xp;
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            sRed[j * kShtThreads + threadIdx.x] = vc[j];
-            sRed[(CH + j) * kShtThreads + threadIdx.x] = vs[j];
+            sRed[j * kLegThreads + threadIdx.x] = vc[j];
+            sRed[(CH + j) * kLegThreads + threadIdx.x] = vs[j];
         }
         __syncthreads();
-        const int row = threadIdx.x >> 5, seg = threadIdx.x & 31;
+        const int row = threadIdx.x >> 4, seg = threadIdx.x & 15;
         double sum = 0.0;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) sum += sRed[row * kShtThreads + t * 32 + seg];   // 32 threads: 32 banks
+        for (int t = 0; t < 16; ++t) sum += sRed[row * kLegThreads + t * 16 + seg];
 #pragma unroll
-        for (int o = 16; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
         if (seg == 0) {
             const int i = i0 + (row & (CH - 1));
             if (i < nl) {
-                if (row < CH) ac[off + i] = sum;
-                else as[off + i] = m == 0 ? 0.0 : sum;
+                const double k2 = kk[i] * kk[i];
+                if (row < CH) ac[off + i] = sum * k2;
+                else as[off + i] = m == 0 ? 0.0 : sum * k2;
             }
         }
         __syncthreads();
+        b0 = n0;
+        b1 = n1;
     }
 }
 
@@ -433,37 +476,33 @@ __global__ __launch_bounds__(kShtThreads) void k_ring_adj(ShtDesc d, const doubl
 
 }  // namespace
 
-hipError_t sht_prepare(int lmax, int max_ring) {
-    const int leg_syn = 2 * (lmax + 1 + kLegPad) * (int)sizeof(double2);
-    const int leg_adj = (lmax + 1 + kLegPad) * (int)sizeof(double2) + 16 * kShtThreads * (int)sizeof(double);
+hipError_t sht_prepare(int max_ring) {
     const int ring = max_ring * (int)sizeof(double2);
-    hipError_t e = hipSuccess;
-    auto set = [&](const void *f, int bytes) {
-        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    };
-    set((const void *)k_leg_syn<1>, leg_syn);
-    set((const void *)k_leg_syn<2>, leg_syn);
-    set((const void *)k_leg_syn<3>, leg_syn);
-    set((const void *)k_leg_adj<1>, leg_adj);
-    set((const void *)k_leg_adj<2>, leg_adj);
-    set((const void *)k_leg_adj<3>, leg_adj);
-    set((const void *)k_ring_syn, ring);
-    set((const void *)k_ring_adj, ring);
+    hipError_t e = hipFuncSetAttribute((const void *)k_ring_syn, hipFuncAttributeMaxDynamicSharedMemorySize, ring);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_ring_adj, hipFuncAttributeMaxDynamicSharedMemorySize, ring);
     return e;
 }
 
 hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double *as, double *fbuf, double *map,
                          bool weighted, hipStream_t st) {
     const int L = d.lmax;
-    const int64_t nalm = (int64_t)(L + 1) * (L + 1);
-    if (alm) hipLaunchKernelGGL(k_alm_to_mm, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, st, alm, L, ac, as);
-    const size_t lds_leg = (size_t)2 * (L + 1 + kLegPad) * sizeof(double2);
-    if (d.nhalf > 2 * kShtThreads)
-        hipLaunchKernelGGL(k_leg_syn<3>, dim3(L + 1), dim3(kShtThreads), lds_leg, st, d, ac, as, fbuf);
-    else if (d.nhalf > kShtThreads)
-        hipLaunchKernelGGL(k_leg_syn<2>, dim3(L + 1), dim3(kShtThreads), lds_leg, st, d, ac, as, fbuf);
-    else
-        hipLaunchKernelGGL(k_leg_syn<1>, dim3(L + 1), dim3(kShtThreads), lds_leg, st, d, ac, as, fbuf);
+    if (alm)
+        hipLaunchKernelGGL(k_alm_to_mm, dim3(L + 1), dim3(256), 0, st, alm, L, d.row_off, d.rec_k, ac, as);
+    const dim3 grid(L + 1), block(kLegThreads);
+    auto syn = [&](auto r) {
+        hipLaunchKernelGGL(k_leg_syn<decltype(r)::value>, grid, block, 0, st, d, d.row_off, d.rec_b, d.rec_k, ac,
+                           as, fbuf);
+    };
+    // ring pairs per thread: the most rings (up to 6) whose passes leave at
+    // most 1/16 of the threads idle, else one ring per thread
+    const int nq = (d.nhalf + kLegThreads - 1) / kLegThreads;
+    auto fits = [&](int r) { return 16L * d.nhalf >= 15L * ((nq + r - 1) / r) * r * kLegThreads; };
+    if (fits(6)) syn(std::integral_constant<int, 6>());
+    else if (fits(4)) syn(std::integral_constant<int, 4>());
+    else if (fits(3)) syn(std::integral_constant<int, 3>());
+    else if (fits(2)) syn(std::integral_constant<int, 2>());
+    else syn(std::integral_constant<int, 1>());
     const size_t lds_ring = (size_t)d.max_ring * sizeof(double2);
     hipLaunchKernelGGL(k_ring_syn, dim3(d.nrings), dim3(kShtThreads), lds_ring, st, d, fbuf, map, weighted ? 1 : 0);
     return hipGetLastError();
@@ -472,17 +511,25 @@ hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double
 hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double *ac, double *as, double *alm,
                        bool weighted, hipStream_t st) {
     const int L = d.lmax;
+    if (d.nhalf > kShtMaxHalfRings) return hipErrorInvalidValue;
     const size_t lds_ring = (size_t)d.max_ring * sizeof(double2);
     hipLaunchKernelGGL(k_ring_adj, dim3(d.nrings), dim3(kShtThreads), lds_ring, st, d, map, gbuf, weighted ? 1 : 0);
-    const size_t lds_leg = (size_t)(L + 1 + kLegPad) * sizeof(double2) + (size_t)16 * kShtThreads * sizeof(double);
-    if (d.nhalf > 2 * kShtThreads)
-        hipLaunchKernelGGL(k_leg_adj<3>, dim3(L + 1), dim3(kShtThreads), lds_leg, st, d, gbuf, ac, as);
-    else if (d.nhalf > kShtThreads)
-        hipLaunchKernelGGL(k_leg_adj<2>, dim3(L + 1), dim3(kShtThreads), lds_leg, st, d, gbuf, ac, as);
-    else
-        hipLaunchKernelGGL(k_leg_adj<1>, dim3(L + 1), dim3(kShtThreads), lds_leg, st, d, gbuf, ac, as);
+    const dim3 grid(L + 1), block(kLegThreads);
+    const int nq = (d.nhalf + kLegThreads - 1) / kLegThreads;   // every ring pair in one pass
+    auto adj = [&](auto r) {
+        hipLaunchKernelGGL(k_leg_adj<decltype(r)::value>, grid, block, 0, st, d, d.row_off, d.rec_b, d.rec_k, gbuf,
+                           ac, as);
+    };
+    if (nq <= 1) adj(std::integral_constant<int, 1>());
+    else if (nq == 2) adj(std::integral_constant<int, 2>());
+    else if (nq == 3) adj(std::integral_constant<int, 3>());
+    else if (nq == 4) adj(std::integral_constant<int, 4>());
+    else if (nq <= 6) adj(std::integral_constant<int, 6>());
+    else adj(std::integral_constant<int, 8>());
     const int64_t nalm = (int64_t)(L + 1) * (L + 1);
-    if (alm) hipLaunchKernelGGL(k_mm_to_alm, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, st, ac, as, L, alm);
+    if (alm)
+        hipLaunchKernelGGL(k_mm_to_alm, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, st, ac, as, L,
+                           d.row_off, d.rec_k, alm);
     return hipGetLastError();
 }
 

@@ -9,7 +9,9 @@
 namespace sympix {
 
 constexpr int kShtMaxRing = 8192;   // longest ring the LDS FFT holds (complex FP64)
-constexpr int kShtMaxL = 4095;      // largest band limit (LDS of the Legendre kernels)
+constexpr int kShtMaxL = 4095;      // largest band limit
+constexpr int kShtMaxHalfRings = 2048;   // northern rings the Legendre transpose holds (8 per thread)
+constexpr int kShtRowPad = 16;      // zero entries after each m-major row (read-ahead of the kernels)
 
 // Device tables of one plan (grid, band limit L).  Rings j = 0 .. nrings-1
 // from the north pole; ring nrings-1-j mirrors ring j, so the Legendre part
@@ -24,17 +26,22 @@ struct ShtDesc {
                                 // + (j / k) k^2 + (j % k) k)
     const double *ring_w;       // [nrings] quadrature weight of each of the ring's pixels
     const int8_t *ring_rad;     // [nrings][16] FFT passes: count, then radices
+    // m-major rows (row m: entries i = l - m = 0 .. L - m, then at least
+    // kShtRowPad zeros; every row starts at a multiple of 4 entries)
+    const int64_t *row_off;     // [L+1] first entry of row m
+    const double *rec_b;        // b_i of the monic recurrence (b_0 = -1)
+    const double *rec_k;        // K_i: the normalised factors' product over i's 64-degree chunk
 };
 
-// map = Y a (alm in the l^2 + l + m layout; nullptr: the m-major ac / as are
-// already filled); with weighted, map = W Y a.  fbuf: nrings (L+1) 2 doubles.
+// map = Y a (alm in the l^2 + l + m layout; nullptr: the m-major ac / as,
+// held times K, are already filled); with weighted, map = W Y a.  fbuf: nrings (L+1) 2 doubles.
 hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double *as, double *fbuf, double *map,
                          bool weighted, hipStream_t st);
 // alm = Y^T map (weighted: Y^T W map); alm == nullptr leaves the result in the
-// m-major ac / as.  gbuf: nrings (L+1) 2 doubles.
+// m-major ac / as (times K).  gbuf: nrings (L+1) 2 doubles.
 hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double *ac, double *as, double *alm,
                        bool weighted, hipStream_t st);
-// Allow the kernels the LDS a plan of band limit L and longest ring max_ring needs.
-hipError_t sht_prepare(int lmax, int max_ring);
+// Allow the ring kernels the LDS a plan whose longest ring is max_ring needs.
+hipError_t sht_prepare(int max_ring);
 
 }  // namespace sympix

@@ -148,6 +148,78 @@ def test_full_size_round_trip_and_transpose(lmax):
     assert e_tr <= 1e-12
 
 
+def test_orders_whose_lambda_mm_is_below_the_double_range():
+    """lmax 2400: on rings with sin(theta) in [m / L, 10^(-323/m)], lambda_mm
+    of order m lies below the smallest double but lambda_lm is of order one
+    before l = L (the turning point m / sin(theta) < L).  Transpose of a map
+    that is nonzero on such rings (and on a polar and an equatorial ring), and
+    synthesis of coefficients of those orders on the same rings, against the
+    oracle's per-order recurrence."""
+    lmax = L = 2400
+    og, g = G.make_grid(lmax, 8), sp.Grid(lmax, 8)
+    s = sp.Sht(g, L)
+    ring, pin, nr, phi = og.pixel_coords()
+    st = np.sin(og.theta[: og.nrings // 2])
+    rings = sorted({0, og.nrings // 2 - 1} | {int(np.argmin(np.abs(st - v))) for v in (0.45, 0.49, 0.52)})
+    orders = [0, 1, 999, 1000, 1100, 1200, 1800, 2400]
+    lam = {m: H.lambda_m(L, m, og.theta[rings]) for m in orders}      # [l - m, ring]
+    rng = np.random.default_rng(2400)
+    # transpose: x nonzero on the chosen rings only
+    x = np.zeros(g.npix)
+    on = np.isin(ring, rings)
+    x[on] = rng.standard_normal(int(on.sum()))
+    yt = torch.empty((L + 1) ** 2, dtype=torch.float64, device="cuda")
+    s.adjoint(dev(x), yt)
+    torch.cuda.synchronize()
+    got = yt.cpu().numpy()
+    worst, scale = 0.0, 0.0
+    for m in orders:
+        ls = np.arange(m, L + 1)
+        gc = np.array([np.sum(x[ring == r] * np.cos(m * phi[ring == r])) for r in rings])
+        gs = np.array([np.sum(x[ring == r] * np.sin(m * phi[ring == r])) for r in rings])
+        ref_c = lam[m] @ gc * (1.0 if m == 0 else np.sqrt(2.0))
+        worst = max(worst, np.abs(got[ls * ls + ls + m] - ref_c).max())
+        scale = max(scale, np.abs(ref_c).max())
+        if m > 0:
+            ref_s = np.sqrt(2.0) * (lam[m] @ gs)
+            worst = max(worst, np.abs(got[ls * ls + ls - m] - ref_s).max())
+    e_adj = worst / scale
+    # synthesis of coefficients of the chosen orders, read on the chosen rings
+    a = np.zeros((L + 1) ** 2)
+    for m in orders:
+        ls = np.arange(m, L + 1)
+        a[ls * ls + ls + m] = rng.standard_normal(ls.size)
+        if m > 0:
+            a[ls * ls + ls - m] = rng.standard_normal(ls.size)
+    out = torch.empty(g.npix, dtype=torch.float64, device="cuda")
+    s.synthesis(dev(a), out)
+    torch.cuda.synchronize()
+    f = out.cpu().numpy()
+    worst, scale = 0.0, 0.0
+    for q, r in enumerate(rings):
+        pix = np.nonzero(ring == r)[0]
+        ref = np.zeros(pix.size)
+        for m in orders:
+            ls = np.arange(m, L + 1)
+            Fc = a[ls * ls + ls + m] @ lam[m][:, q]
+            if m == 0:
+                ref += Fc
+            else:
+                Fs = a[ls * ls + ls - m] @ lam[m][:, q]
+                ref += np.sqrt(2.0) * (Fc * np.cos(m * phi[pix]) + Fs * np.sin(m * phi[pix]))
+        worst = max(worst, np.abs(f[pix] - ref).max())
+        scale = max(scale, np.abs(ref).max())
+    e_syn = worst / scale
+    # Near the pole cos(theta) ~ 1 makes the recurrence's two roots nearly
+    # equal, so a rounding error made at step j grows about linearly over the
+    # steps after it: random roundings leave about eps L^1.5 (1.3e-11 here)
+    # between two orderings of the same FP64 recurrence.  Measured: 1.2-1.7e-12,
+    # the polar ring at m = 0, 1 (every other ring agrees to 2e-14).
+    tol = np.finfo(np.float64).eps * L ** 1.5
+    say(f"[sht lmax=2400] rings {rings}: transpose {e_adj:.2e}, synthesis {e_syn:.2e} (bound {tol:.1e})")
+    assert e_adj <= tol and e_syn <= tol
+
+
 def test_sht_errors():
     g, g2 = sp.Grid(32, 4), sp.Grid(48, 4)
     s, s2, s3 = sp.Sht(g, 20), sp.Sht(g2, 20), sp.Sht(g2, 24)

@@ -169,3 +169,33 @@ def test_degrade_matches_dense_matrices():
     ref = w2 * (Y2 @ (Yo.T @ th))
     got = H.degrade(g_obs, g2, th, L)
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_lambda_m_is_the_tables_column():
+    """One order's column (lambda_m, for band limits where the whole table
+    is too large) takes the same steps as lambda_table: equal bit for bit."""
+    th = np.array([0.003, 0.4, 1.1, 1.5707, 2.9])
+    tab = H.lambda_table(60, th)
+    for m in (0, 1, 7, 31, 60):
+        np.testing.assert_array_equal(H.lambda_m(60, m, th), tab[m:, m, :])
+
+
+def test_lambda_m_where_lambda_mm_is_below_the_double_range():
+    """At m = 1000 and sin(theta) = 0.45, lambda_mm ~ 1e-336 lies below the
+    smallest double, yet lambda_lm is of order one by l = 2400 (past the
+    turning point l ~ m / sin(theta)): against mpmath's Rodrigues series."""
+    m, theta = 1000, math.asin(0.45)
+    col = H.lambda_m(2400, m, np.array([theta]))[:, 0]
+    assert abs(col[0]) == 0.0                          # below 2^-1074
+    for l in (2300, 2400):
+        with mpmath.workdps(3 * l + 50):
+            th = mpmath.mpf(theta)
+            x = mpmath.cos(th)
+            series = mpmath.fsum((-1) ** k * mpmath.binomial(l, k) * mpmath.factorial(2 * l - 2 * k)
+                                 / mpmath.factorial(l - 2 * k - m) * x ** (l - 2 * k - m)
+                                 for k in range((l - m) // 2 + 1))
+            plm = mpmath.sin(th) ** m * series / (mpmath.mpf(2) ** l * mpmath.factorial(l))
+            norm = mpmath.sqrt((2 * l + 1) / (4 * mpmath.pi) * mpmath.factorial(l - m) / mpmath.factorial(l + m))
+            ref = float(norm * plm)
+        assert abs(ref) > 1e-3
+        assert abs(col[l - m] - ref) <= 1e-11 * abs(ref), (l, col[l - m], ref)
