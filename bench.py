@@ -634,7 +634,9 @@ def run_sht(args):
     torch.cuda.synchronize()
     t_deg = e0.elapsed_time(e1) / 3
     terms = sht_terms(g.nrings, L)
-    flop = 8.0 * (g.nrings // 2) * (L + 1) * (L + 2) / 2        # one Legendre pass (see DESIGN)
+    # one Legendre pass: per (degree, order, ring pair) a recurrence step (a
+    # multiply and a fused multiply-add) and two fused multiply-adds, 7 flops
+    flop = 7.0 * (g.nrings // 2) * (L + 1) * (L + 2) / 2
     achieved = flop / (t_syn.mean() * 1e-3) / 1e12
     print(f"# sht {args.config}: lmax={cfg.lmax} L={L} npix={g.npix} nrings={g.nrings}; synthesis "
           f"{t_syn.mean():.3f} ms, analysis {t_ana.mean():.3f} ms, round trip error {rt_err:.1e}; degrade "

@@ -211,14 +211,15 @@ __device__ __forceinline__ RingG ring_g(const ShtDesc &d, const double *gbuf, in
     return RingG{(gn[0] + gs[0]) * sc, (gn[0] - gs[0]) * sc, (gn[1] + gs[1]) * sc, (gn[1] - gs[1]) * sc};
 }
 
-template <int R>
-__global__ __launch_bounds__(kLegThreads) void k_leg_adj(ShtDesc d, const int64_t *__restrict__ row_off,
+template <int T, int R>
+__global__ __launch_bounds__(T) void k_leg_adj(ShtDesc d, const int64_t *__restrict__ row_off,
                                                          const double *__restrict__ rb,
                                                          const double *__restrict__ rk,
                                                          const double *__restrict__ gbuf,
                                                          double *__restrict__ ac, double *__restrict__ as) {
     constexpr int CH = 8;
-    __shared__ double sRed[2 * CH * kLegThreads];
+    constexpr int LPR = T / 16;          // lanes summing one of the 16 values
+    __shared__ double sRed[2 * CH * T];
     const int m = blockIdx.x, L = d.lmax, nl = L - m + 1;
     const int64_t off = row_off[m];
     const double *b = rb + off, *kk = rk + off;
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(kLegThreads) void k_leg_adj(ShtDesc d, const int64_
     int e[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int rp = threadIdx.x + kLegThreads * q;
+        const int rp = threadIdx.x + T * q;
         const bool ok = rp < d.nhalf;
         const int r = ok ? rp : 0;
         e[q] = d.lmm_exp[(int64_t)m * d.nhalf + r];
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(kLegThreads) void k_leg_adj(ShtDesc d, const int64_
                 } else if (e[q] >= kEMin) {       // the ring's terms start to count
                     // the ring index is made opaque, so that the compiler does not keep
                     // this rare reload's addresses live across the loop
-                    int rr = min(threadIdx.x + kLegThreads * q, d.nhalf - 1);
+                    int rr = min(threadIdx.x + T * q, d.nhalf - 1);
                     asm volatile("" : "+v"(rr));
                     g[q] = ring_g(d, gbuf, rr, m, e[q]);
                 }
@@ -284,16 +285,16 @@ __global__ __launch_bounds__(kLegThreads) void k_leg_adj(ShtDesc d, const int64_
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            sRed[j * kLegThreads + threadIdx.x] = vc[j];
-            sRed[(CH + j) * kLegThreads + threadIdx.x] = vs[j];
+            sRed[j * T + threadIdx.x] = vc[j];
+            sRed[(CH + j) * T + threadIdx.x] = vs[j];
         }
         __syncthreads();
-        const int row = threadIdx.x >> 4, seg = threadIdx.x & 15;
+        const int row = threadIdx.x / LPR, seg = threadIdx.x % LPR;
         double sum = 0.0;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) sum += sRed[row * kLegThreads + t * 16 + seg];
+        for (int t = 0; t < 16; ++t) sum += sRed[row * T + t * LPR + seg];
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
         if (seg == 0) {
             const int i = i0 + (row & (CH - 1));
             if (i < nl) {
@@ -312,8 +313,9 @@ __global__ __launch_bounds__(kLegThreads) void k_leg_adj(ShtDesc d, const int64_
 // FFT in LDS: forward DFT z_q <- sum_j z_j exp(-2 pi i j q / n) for n =
 // 2^a 3^b 5^c <= kShtMaxRing, by self-sorting (Stockham) passes of radix 2,
 // 3, 4 and 5.  Pass with radix R over sub-transforms of length Ns: butterfly
-// j takes z[j + r n/R] (r < R), twiddles them by exp(-2 pi i (j mod Ns) r /
-// (Ns R)), applies the R-point DFT and writes output r to (j / Ns) Ns R +
+// j takes z[j + r n/R] (r < R), twiddles them by w^r, w = exp(-2 pi i (j mod
+// Ns) / (Ns R)) (w from one sincospi, its powers by complex products: one or
+// two roundings more), applies the R-point DFT and writes output r to (j / Ns) Ns R +
 // (j mod Ns) + r Ns.  All reads of a pass precede all its writes (the
 // workgroup holds the pass in registers between two barriers), so one buffer
 // serves as input and output.
@@ -382,11 +384,16 @@ __device__ __forceinline__ void fft_pass(double2 *z, int n, int Ns) {
             double2 v[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) v[r] = z[j + r * nb];
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
+            if (Ns > 1) {       // twiddles w^r, w = exp(-2 pi i k / (Ns R)): one sincos, then powers
                 double sn, cs;
-                sincospi(-2.0 * (double)(k * r) / (double)(Ns * R), &sn, &cs);
-                v[r] = cmul(v[r], double2{cs, sn});
+                sincospi(-2.0 * (double)k / (double)(Ns * R), &sn, &cs);
+                const double2 w = double2{cs, sn};
+                double2 wr = w;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    v[r] = cmul(v[r], wr);
+                    if (r + 1 < R) wr = cmul(wr, w);
+                }
             }
             dft_small<R>(v);
 #pragma unroll
@@ -514,18 +521,24 @@ hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double
     if (d.nhalf > kShtMaxHalfRings) return hipErrorInvalidValue;
     const size_t lds_ring = (size_t)d.max_ring * sizeof(double2);
     hipLaunchKernelGGL(k_ring_adj, dim3(d.nrings), dim3(kShtThreads), lds_ring, st, d, map, gbuf, weighted ? 1 : 0);
-    const dim3 grid(L + 1), block(kLegThreads);
-    const int nq = (d.nhalf + kLegThreads - 1) / kLegThreads;   // every ring pair in one pass
-    auto adj = [&](auto r) {
-        hipLaunchKernelGGL(k_leg_adj<decltype(r)::value>, grid, block, 0, st, d, d.row_off, d.rec_b, d.rec_k, gbuf,
-                           ac, as);
+    // every ring pair in one pass: 128 threads with up to 8 ring pairs each
+    // (half the partial sums of 256 threads), else 256 threads with 6 or 8
+    auto adj = [&](auto t, auto r) {
+        constexpr int T = decltype(t)::value, R = decltype(r)::value;
+        hipLaunchKernelGGL((k_leg_adj<T, R>), dim3(L + 1), dim3(T), 0, st, d, d.row_off, d.rec_b, d.rec_k, gbuf, ac,
+                           as);
     };
-    if (nq <= 1) adj(std::integral_constant<int, 1>());
-    else if (nq == 2) adj(std::integral_constant<int, 2>());
-    else if (nq == 3) adj(std::integral_constant<int, 3>());
-    else if (nq == 4) adj(std::integral_constant<int, 4>());
-    else if (nq <= 6) adj(std::integral_constant<int, 6>());
-    else adj(std::integral_constant<int, 8>());
+    using T128 = std::integral_constant<int, 128>;
+    using T256 = std::integral_constant<int, 256>;
+    const int nq = (d.nhalf + 127) / 128;
+    if (nq <= 1) adj(T128(), std::integral_constant<int, 1>());
+    else if (nq == 2) adj(T128(), std::integral_constant<int, 2>());
+    else if (nq == 3) adj(T128(), std::integral_constant<int, 3>());
+    else if (nq == 4) adj(T128(), std::integral_constant<int, 4>());
+    else if (nq <= 6) adj(T128(), std::integral_constant<int, 6>());
+    else if (nq <= 8) adj(T128(), std::integral_constant<int, 8>());
+    else if (nq <= 12) adj(T256(), std::integral_constant<int, 6>());
+    else adj(T256(), std::integral_constant<int, 8>());
     const int64_t nalm = (int64_t)(L + 1) * (L + 1);
     if (alm)
         hipLaunchKernelGGL(k_mm_to_alm, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, st, ac, as, L,
