@@ -39,38 +39,60 @@ constexpr double kBig = 0x1p300, kSmall = 0x1p-300;
 // (m >= 0) and sin (m >= 1; the m = 0 row is zero) coefficients, each held
 // times K_lm, the scale of the monic recurrence below.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void lm_of(int64_t idx, int &l, int &m) {
-    int q = (int)sqrt((double)idx);
-    while ((int64_t)q * q > idx) --q;
-    while ((int64_t)(q + 1) * (q + 1) <= idx) ++q;
-    l = q;
-    m = (int)(idx - (int64_t)q * q - q);
-}
+// Layout changes between the two orders, tiled (32 orders x 32 degrees per
+// workgroup of 256 threads) and transposed through LDS, so that the vector
+// (consecutive m at one l) and the rows (consecutive l at one m) are both read
+// and written in runs.  Tiles holding no l >= m exit at once.
+constexpr int kMmTile = 32;
 
-// one workgroup per m: row m written in order, its entries read at stride ~2l
-__global__ __launch_bounds__(256) void k_alm_to_mm(const double *__restrict__ alm, int L,
-                                                   const int64_t *__restrict__ row_off,
-                                                   const double *__restrict__ rk, double *__restrict__ ac,
-                                                   double *__restrict__ as) {
-    const int m = blockIdx.x;
-    const int64_t off = row_off[m];
-    for (int i = threadIdx.x; i <= L - m; i += 256) {
-        const int64_t l = m + i, c = l * l + l;
-        const double k = rk[off + i];
-        ac[off + i] = alm[c + m] * k;
-        as[off + i] = m == 0 ? 0.0 : alm[c - m] * k;
+template <bool TO_MM>
+__global__ __launch_bounds__(256) void k_alm_mm(const double *__restrict__ src, int L,
+                                                const int64_t *__restrict__ row_off,
+                                                const double *__restrict__ rk, double *__restrict__ ac,
+                                                double *__restrict__ as, double *__restrict__ dst) {
+    __shared__ double tc[kMmTile][kMmTile + 1], ts[kMmTile][kMmTile + 1];   // [m - m0][l - l0]
+    const int m0 = blockIdx.y * kMmTile, l0 = blockIdx.x * kMmTile;
+    if (l0 + kMmTile - 1 < m0) return;
+    const int fast = threadIdx.x & 31, slow = threadIdx.x >> 5;
+    if constexpr (TO_MM) {
+        for (int q = slow; q < kMmTile; q += 8) {        // one degree per pass, consecutive m
+            const int l = l0 + q, m = m0 + fast;
+            if (l <= L && m <= l) {
+                const int64_t c = (int64_t)l * l + l;
+                tc[fast][q] = src[c + m];
+                ts[fast][q] = m == 0 ? 0.0 : src[c - m];
+            }
+        }
+        __syncthreads();
+        for (int q = slow; q < kMmTile; q += 8) {        // one order per pass, consecutive l, times K
+            const int m = m0 + q, l = l0 + fast;
+            if (l <= L && m <= l) {
+                const int64_t o = row_off[m] + l - m;
+                const double k = rk[o];
+                ac[o] = tc[q][fast] * k;
+                as[o] = ts[q][fast] * k;
+            }
+        }
+    } else {
+        for (int q = slow; q < kMmTile; q += 8) {        // one order per pass, consecutive l, over K
+            const int m = m0 + q, l = l0 + fast;
+            if (l <= L && m <= l) {
+                const int64_t o = row_off[m] + l - m;
+                const double k = rk[o];
+                tc[q][fast] = ac[o] / k;
+                ts[q][fast] = as[o] / k;
+            }
+        }
+        __syncthreads();
+        for (int q = slow; q < kMmTile; q += 8) {        // one degree per pass, consecutive m
+            const int l = l0 + q, m = m0 + fast;
+            if (l <= L && m <= l) {
+                const int64_t c = (int64_t)l * l + l;
+                dst[c + m] = tc[fast][q];
+                if (m > 0) dst[c - m] = ts[fast][q];
+            }
+        }
     }
-}
-
-__global__ __launch_bounds__(256) void k_mm_to_alm(const double *__restrict__ ac, const double *__restrict__ as,
-                                                   int L, const int64_t *__restrict__ row_off,
-                                                   const double *__restrict__ rk, double *__restrict__ alm) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)(L + 1) * (L + 1)) return;
-    int l, m;
-    lm_of(idx, l, m);
-    const int64_t o = row_off[m >= 0 ? m : -m] + l - (m >= 0 ? m : -m);
-    alm[idx] = (m >= 0 ? ac[o] : as[o]) / rk[o];
 }
 
 // ---------------------------------------------------------------------------
@@ -211,8 +233,11 @@ __device__ __forceinline__ RingG ring_g(const ShtDesc &d, const double *gbuf, in
     return RingG{(gn[0] + gs[0]) * sc, (gn[0] - gs[0]) * sc, (gn[1] + gs[1]) * sc, (gn[1] - gs[1]) * sc};
 }
 
+// up to six ring pairs per thread fit in 128 VGPRs (four waves per SIMD; the
+// few values the compiler then keeps in scratch are read only on the rare
+// reload path)
 template <int T, int R>
-__global__ __launch_bounds__(T) void k_leg_adj(ShtDesc d, const int64_t *__restrict__ row_off,
+__global__ __launch_bounds__(T, R <= 6 ? 4 : 1) void k_leg_adj(ShtDesc d, const int64_t *__restrict__ row_off,
                                                          const double *__restrict__ rb,
                                                          const double *__restrict__ rk,
                                                          const double *__restrict__ gbuf,
@@ -494,8 +519,10 @@ hipError_t sht_prepare(int max_ring) {
 hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double *as, double *fbuf, double *map,
                          bool weighted, hipStream_t st) {
     const int L = d.lmax;
+    const int nt = (L + kMmTile) / kMmTile;
     if (alm)
-        hipLaunchKernelGGL(k_alm_to_mm, dim3(L + 1), dim3(256), 0, st, alm, L, d.row_off, d.rec_k, ac, as);
+        hipLaunchKernelGGL(k_alm_mm<true>, dim3(nt, nt), dim3(256), 0, st, alm, L, d.row_off, d.rec_k, ac, as,
+                           nullptr);
     const dim3 grid(L + 1), block(kLegThreads);
     auto syn = [&](auto r) {
         hipLaunchKernelGGL(k_leg_syn<decltype(r)::value>, grid, block, 0, st, d, d.row_off, d.rec_b, d.rec_k, ac,
@@ -539,10 +566,10 @@ hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double
     else if (nq <= 8) adj(T128(), std::integral_constant<int, 8>());
     else if (nq <= 12) adj(T256(), std::integral_constant<int, 6>());
     else adj(T256(), std::integral_constant<int, 8>());
-    const int64_t nalm = (int64_t)(L + 1) * (L + 1);
+    const int nt = (L + kMmTile) / kMmTile;
     if (alm)
-        hipLaunchKernelGGL(k_mm_to_alm, dim3((unsigned)((nalm + 255) / 256)), dim3(256), 0, st, ac, as, L,
-                           d.row_off, d.rec_k, alm);
+        hipLaunchKernelGGL(k_alm_mm<false>, dim3(nt, nt), dim3(256), 0, st, nullptr, L, d.row_off, d.rec_k, ac,
+                           as, alm);
     return hipGetLastError();
 }
 
