@@ -1548,7 +1548,7 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
     std::vector<int64_t> pix0(nr, 0);
     std::vector<double> rw(nr, 0.0);
     std::vector<int8_t> rad((size_t)nr * 16, 0);
-    int32_t max_ring = 0;
+    int32_t max_ring = 0, max_fft = 0;
     for (size_t b = 0; b < geo.band_tiles.size(); ++b) {
         const int32_t n = k * geo.band_tiles[b];
         for (int32_t r = 0; r < k; ++r) {
@@ -1556,10 +1556,12 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
             rn[j] = n;
             pix0[j] = geo.band_tile0[b] * (int64_t)k * k + r;
             rw[j] = geo.weight[j] * 2.0 * kPi / (double)n;
-            if (!ring_radices(n, &rad[(size_t)j * 16]))
+            // an even ring takes an FFT of half its length (its values paired as complex)
+            if (!ring_radices(n % 2 == 0 ? n / 2 : n, &rad[(size_t)j * 16]))
                 return fail(SYMPIX_EUNSUPPORTED, "a ring length is not of the form 2^a 3^b 5^c");
         }
         max_ring = std::max(max_ring, n);
+        max_fft = std::max(max_fft, n % 2 == 0 ? n / 2 : n);
     }
     if (max_ring > sympix::kShtMaxRing) return fail(SYMPIX_EUNSUPPORTED, "a ring is longer than 8192 pixels");
     if (nh > sympix::kShtMaxHalfRings) return fail(SYMPIX_EUNSUPPORTED, "more than 4096 rings");
@@ -1655,7 +1657,7 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
     put(o_k, rec_k.data(), sizeof(double) * (size_t)nrow);
     // the rows' padding of ac / as stays zero: the kernels write entries i <= L - m only
     if (e == hipSuccess) e = hipMemset(base + o_ac, 0, (o_as - o_ac) + sizeof(double) * (size_t)nrow);
-    if (e == hipSuccess) e = sympix::sht_prepare(max_ring);
+    if (e == hipSuccess) e = sympix::sht_prepare(max_fft);
     if (e != hipSuccess) {
         hipFree(s->block);
         delete s;
@@ -1667,7 +1669,7 @@ sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sh
     d.nhalf = nh;
     d.k = k;
     d.max_ring = max_ring;
-    d.pad = 0;
+    d.max_fft = max_fft;
     d.ring_cos = (const double *)(base + o_cos);
     d.lmm_mant = (const double *)(base + o_mant);
     d.lmm_exp = (const int32_t *)(base + o_exp);

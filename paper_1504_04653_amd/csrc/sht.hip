@@ -28,7 +28,7 @@
 namespace sympix {
 namespace {
 
-constexpr int kShtThreads = 512;     // ring kernels
+constexpr int kRingThreads = 1024;   // ring kernels: one workgroup of 16 waves per ring
 constexpr int kLegThreads = 256;     // Legendre kernels
 constexpr double kSqrt2 = 1.4142135623730951;
 constexpr double kBig = 0x1p300, kSmall = 0x1p-300;
@@ -394,15 +394,15 @@ __device__ __forceinline__ void dft_small(double2 *v) {
     }
 }
 
-template <int R>
+template <int R, int MAXN>
 __device__ __forceinline__ void fft_pass(double2 *z, int n, int Ns) {
-    constexpr int MB = (kShtMaxRing / R + kShtThreads - 1) / kShtThreads;
+    constexpr int MB = (MAXN / R + kRingThreads - 1) / kRingThreads;
     const int nb = n / R;
     double2 out[MB][R];
     int dst[MB];
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
-        const int j = threadIdx.x + kShtThreads * b;
+        const int j = threadIdx.x + kRingThreads * b;
         dst[b] = -1;
         if (j < nb) {
             const int k = j % Ns;
@@ -436,15 +436,16 @@ __device__ __forceinline__ void fft_pass(double2 *z, int n, int Ns) {
     __syncthreads();
 }
 
+template <int MAXN>
 __device__ void fft_forward(double2 *z, int n, const int8_t *rad) {
     int Ns = 1;
     const int np = rad[0];
     for (int p = 1; p <= np; ++p) {
         const int R = rad[p];
-        if (R == 4) fft_pass<4>(z, n, Ns);
-        else if (R == 2) fft_pass<2>(z, n, Ns);
-        else if (R == 3) fft_pass<3>(z, n, Ns);
-        else fft_pass<5>(z, n, Ns);
+        if (R == 4) fft_pass<4, MAXN>(z, n, Ns);
+        else if (R == 2) fft_pass<2, MAXN>(z, n, Ns);
+        else if (R == 3) fft_pass<3, MAXN>(z, n, Ns);
+        else fft_pass<5, MAXN>(z, n, Ns);
         Ns *= R;
     }
 }
@@ -455,48 +456,112 @@ __device__ __forceinline__ int64_t ring_pixel(const ShtDesc &d, int r, int j) {
     return d.ring_pix0[r] + (int64_t)(j / d.k) * d.k * d.k + (int64_t)(j % d.k) * d.k;
 }
 
-// f_j = Re sum_m H_m exp(i m phi_j), phi_j = 2 pi (j + 1/2) / n, with H_0 =
-// F_0 and H_m = sqrt(2) (F_m^cos - i F_m^sin): fold m onto k = m mod n with the
-// half-pixel phase exp(i pi m / n), then f = Re DFT(conj Z).  With wmul the
-// ring is scaled by its pixel weight (W_2 of Eq. 14).
-__global__ __launch_bounds__(kShtThreads) void k_ring_syn(ShtDesc d, const double *__restrict__ fbuf,
+// Ring transforms.  A ring of even length n = 2N takes an FFT of length N
+// (the ring's FFT length nf, whose radices the plan holds): its n real values
+// pair up as N complex ones (x_2r + i x_2r+1), which halves the LDS and the
+// butterflies.  A ring of odd length (odd tile sizes k) takes the FFT of
+// length n.  MAXN bounds nf (the plan's longest), and sizes the registers one
+// FFT pass holds.
+
+// y_q = conj(sum_{m = q mod n, m <= L} H_m exp(i pi m / n)): the ring's modes
+// H_0 = F_0, H_m = sqrt(2) (F_m^cos - i F_m^sin) folded onto frequency q with
+// the half-pixel phase
+__device__ __forceinline__ double2 fold_mode(const double *F, int L, int n, int q) {
+    double zr = 0.0, zi = 0.0;
+    for (int m = q; m <= L; m += n) {
+        const double hc = m == 0 ? F[0] : kSqrt2 * F[2 * m];
+        const double hs = m == 0 ? 0.0 : -kSqrt2 * F[2 * m + 1];
+        double sn, cs;
+        sincospi((double)m / (double)n, &sn, &cs);
+        zr += hc * cs - hs * sn;
+        zi += hc * sn + hs * cs;
+    }
+    return double2{zr, -zi};
+}
+
+// f_j = Re sum_m H_m exp(i m phi_j), phi_j = 2 pi (j + 1/2) / n, that is f =
+// Re DFT_n(y).  Even n = 2N: with A_k = y_k + y_k+N and B_k = (y_k - y_k+N)
+// w^k (w = exp(-2 pi i / n)), f_2r = Re DFT_N(A)_r and f_2r+1 = Re DFT_N(B)_r;
+// taking the conjugate-even part of each, A'_k = (A_k + conj A_N-k) / 2 (and
+// B'), makes both transforms real, so one FFT of C = A' + i B' gives f_2r +
+// i f_2r+1.  A thread builds C_k and C_N-k together from y at k, k + N, N - k
+// and n - k.  With wmul the ring is scaled by its pixel weight (W_2 of Eq. 14).
+template <int MAXN>
+__global__ __launch_bounds__(kRingThreads) void k_ring_syn(ShtDesc d, const double *__restrict__ fbuf,
                                                           double *__restrict__ map, int wmul) {
     extern __shared__ double2 z[];
     const int r = blockIdx.x, L = d.lmax, n = d.ring_n[r];
     const double *F = fbuf + (int64_t)r * (L + 1) * 2;
-    for (int k = threadIdx.x; k < n; k += kShtThreads) {
-        double zr = 0.0, zi = 0.0;
-        for (int m = k; m <= L; m += n) {
-            const double hc = m == 0 ? F[0] : kSqrt2 * F[2 * m];
-            const double hs = m == 0 ? 0.0 : -kSqrt2 * F[2 * m + 1];
-            double sn, cs;
-            sincospi((double)m / (double)n, &sn, &cs);
-            zr += hc * cs - hs * sn;
-            zi += hc * sn + hs * cs;
-        }
-        z[k] = double2{zr, -zi};
+    const double w = wmul ? d.ring_w[r] : 1.0;
+    if (n & 1) {
+        for (int k = threadIdx.x; k < n; k += kRingThreads) z[k] = fold_mode(F, L, n, k);
+        __syncthreads();
+        fft_forward<MAXN>(z, n, d.ring_rad + 16 * r);
+        for (int j = threadIdx.x; j < n; j += kRingThreads) map[ring_pixel(d, r, j)] = w * z[j].x;
+        return;
+    }
+    const int N = n >> 1;
+    for (int k = threadIdx.x; 2 * k <= N; k += kRingThreads) {
+        const int kp = k == 0 ? 0 : N - k;
+        const double2 y0 = fold_mode(F, L, n, k), y1 = fold_mode(F, L, n, k + N);
+        const double2 y2 = fold_mode(F, L, n, kp), y3 = fold_mode(F, L, n, kp + N);
+        double sk, ck, sp, cp;
+        sincospi(-2.0 * (double)k / (double)n, &sk, &ck);
+        sincospi(-2.0 * (double)kp / (double)n, &sp, &cp);
+        const double2 a = double2{y0.x + y1.x, y0.y + y1.y}, ap = double2{y2.x + y3.x, y2.y + y3.y};
+        const double2 b = cmul(double2{y0.x - y1.x, y0.y - y1.y}, double2{ck, sk});
+        const double2 bp = cmul(double2{y2.x - y3.x, y2.y - y3.y}, double2{cp, sp});
+        // C_k = (a + conj ap) / 2 + i (b + conj bp) / 2, C_kp likewise with the roles swapped
+        z[k] = double2{0.5 * (a.x + ap.x) - 0.5 * (b.y - bp.y), 0.5 * (a.y - ap.y) + 0.5 * (b.x + bp.x)};
+        if (kp != k)
+            z[kp] = double2{0.5 * (ap.x + a.x) - 0.5 * (bp.y - b.y), 0.5 * (ap.y - a.y) + 0.5 * (bp.x + b.x)};
     }
     __syncthreads();
-    fft_forward(z, n, d.ring_rad + 16 * r);
-    const double w = wmul ? d.ring_w[r] : 1.0;
-    for (int j = threadIdx.x; j < n; j += kShtThreads) map[ring_pixel(d, r, j)] = w * z[j].x;
+    fft_forward<MAXN>(z, N, d.ring_rad + 16 * r);
+    for (int j = threadIdx.x; j < N; j += kRingThreads) {
+        map[ring_pixel(d, r, 2 * j)] = w * z[j].x;
+        map[ring_pixel(d, r, 2 * j + 1)] = w * z[j].y;
+    }
 }
 
 // The transpose: G_m^cos = c_m sum_j f_j cos(m phi_j), G_m^sin = sqrt(2)
-// sum_j f_j sin(m phi_j) (c_0 = 1, c_m = sqrt(2)), from D = DFT(f) as
-// exp(-i pi m / n) D_(m mod n).  With wmul the ring is first scaled by its
+// sum_j f_j sin(m phi_j) (c_0 = 1, c_m = sqrt(2)), from D = DFT_n(f) as
+// exp(-i pi m / n) D_(m mod n).  Even n = 2N: Z = DFT_N(f_2r + i f_2r+1) gives
+// D_q = E_q + w^q O_q with E_q = (Z_q + conj Z_N-q) / 2 and O_q = (Z_q - conj
+// Z_N-q) / (2 i) (indices mod N).  With wmul the ring is first scaled by its
 // pixel weight (the W of analysis).
-__global__ __launch_bounds__(kShtThreads) void k_ring_adj(ShtDesc d, const double *__restrict__ map,
+template <int MAXN>
+__global__ __launch_bounds__(kRingThreads) void k_ring_adj(ShtDesc d, const double *__restrict__ map,
                                                           double *__restrict__ gbuf, int wmul) {
     extern __shared__ double2 z[];
     const int r = blockIdx.x, L = d.lmax, n = d.ring_n[r];
     const double w = wmul ? d.ring_w[r] : 1.0;
-    for (int j = threadIdx.x; j < n; j += kShtThreads) z[j] = double2{w * map[ring_pixel(d, r, j)], 0.0};
+    const bool half = (n & 1) == 0;
+    const int nf = half ? n >> 1 : n;
+    if (half) {
+        for (int j = threadIdx.x; j < nf; j += kRingThreads)
+            z[j] = double2{w * map[ring_pixel(d, r, 2 * j)], w * map[ring_pixel(d, r, 2 * j + 1)]};
+    } else {
+        for (int j = threadIdx.x; j < n; j += kRingThreads) z[j] = double2{w * map[ring_pixel(d, r, j)], 0.0};
+    }
     __syncthreads();
-    fft_forward(z, n, d.ring_rad + 16 * r);
+    fft_forward<MAXN>(z, nf, d.ring_rad + 16 * r);
     double *G = gbuf + (int64_t)r * (L + 1) * 2;
-    for (int m = threadIdx.x; m <= L; m += kShtThreads) {
-        const double2 v = z[m % n];
+    for (int m = threadIdx.x; m <= L; m += kRingThreads) {
+        const int q = m % n;
+        double2 v;
+        if (half) {
+            const int qq = q < nf ? q : q - nf, qp = qq == 0 ? 0 : nf - qq;
+            const double2 zq = z[qq], zc = double2{z[qp].x, -z[qp].y};
+            const double2 e = double2{0.5 * (zq.x + zc.x), 0.5 * (zq.y + zc.y)};
+            const double2 o = double2{0.5 * (zq.y - zc.y), -0.5 * (zq.x - zc.x)};   // (zq - zc) / (2 i)
+            double sq, cq;
+            sincospi(-2.0 * (double)q / (double)n, &sq, &cq);
+            const double2 wo = cmul(o, double2{cq, sq});
+            v = double2{e.x + wo.x, e.y + wo.y};
+        } else {
+            v = z[q];
+        }
         double sn, cs;
         sincospi((double)m / (double)n, &sn, &cs);
         const double re = v.x * cs + v.y * sn;          // Re(exp(-i pi m / n) v)
@@ -508,11 +573,24 @@ __global__ __launch_bounds__(kShtThreads) void k_ring_adj(ShtDesc d, const doubl
 
 }  // namespace
 
-hipError_t sht_prepare(int max_ring) {
-    const int ring = max_ring * (int)sizeof(double2);
-    hipError_t e = hipFuncSetAttribute((const void *)k_ring_syn, hipFuncAttributeMaxDynamicSharedMemorySize, ring);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_ring_adj, hipFuncAttributeMaxDynamicSharedMemorySize, ring);
+// ring kernels for the plan's longest FFT length max_fft (<= kShtMaxRing)
+template <typename F>
+static void ring_dispatch(int max_fft, F &&f) {
+    if (max_fft <= 1024) f(std::integral_constant<int, 1024>());
+    else if (max_fft <= 2048) f(std::integral_constant<int, 2048>());
+    else if (max_fft <= 4096) f(std::integral_constant<int, 4096>());
+    else f(std::integral_constant<int, kShtMaxRing>());
+}
+
+hipError_t sht_prepare(int max_fft) {
+    const int bytes = max_fft * (int)sizeof(double2);
+    hipError_t e = hipSuccess;
+    ring_dispatch(max_fft, [&](auto mx) {
+        constexpr int M = decltype(mx)::value;
+        e = hipFuncSetAttribute((const void *)k_ring_syn<M>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_ring_adj<M>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    });
     return e;
 }
 
@@ -537,8 +615,11 @@ hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double
     else if (fits(3)) syn(std::integral_constant<int, 3>());
     else if (fits(2)) syn(std::integral_constant<int, 2>());
     else syn(std::integral_constant<int, 1>());
-    const size_t lds_ring = (size_t)d.max_ring * sizeof(double2);
-    hipLaunchKernelGGL(k_ring_syn, dim3(d.nrings), dim3(kShtThreads), lds_ring, st, d, fbuf, map, weighted ? 1 : 0);
+    const size_t lds_ring = (size_t)d.max_fft * sizeof(double2);
+    ring_dispatch(d.max_fft, [&](auto mx) {
+        hipLaunchKernelGGL(k_ring_syn<decltype(mx)::value>, dim3(d.nrings), dim3(kRingThreads), lds_ring, st, d, fbuf,
+                           map, weighted ? 1 : 0);
+    });
     return hipGetLastError();
 }
 
@@ -546,8 +627,11 @@ hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double
                        bool weighted, hipStream_t st) {
     const int L = d.lmax;
     if (d.nhalf > kShtMaxHalfRings) return hipErrorInvalidValue;
-    const size_t lds_ring = (size_t)d.max_ring * sizeof(double2);
-    hipLaunchKernelGGL(k_ring_adj, dim3(d.nrings), dim3(kShtThreads), lds_ring, st, d, map, gbuf, weighted ? 1 : 0);
+    const size_t lds_ring = (size_t)d.max_fft * sizeof(double2);
+    ring_dispatch(d.max_fft, [&](auto mx) {
+        hipLaunchKernelGGL(k_ring_adj<decltype(mx)::value>, dim3(d.nrings), dim3(kRingThreads), lds_ring, st, d, map,
+                           gbuf, weighted ? 1 : 0);
+    });
     // every ring pair in one pass: 128 threads with up to 8 ring pairs each
     // (half the partial sums of 256 threads), else 256 threads with 6 or 8
     auto adj = [&](auto t, auto r) {

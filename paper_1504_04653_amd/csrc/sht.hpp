@@ -17,7 +17,7 @@ constexpr int kShtRowPad = 16;      // zero entries after each m-major row (read
 // from the north pole; ring nrings-1-j mirrors ring j, so the Legendre part
 // runs over the nhalf = nrings/2 northern rings.
 struct ShtDesc {
-    int32_t lmax, nrings, nhalf, k, max_ring, pad;
+    int32_t lmax, nrings, nhalf, k, max_ring, max_fft;   // max_fft: longest ring FFT (n / 2 for even n, else n)
     const double *ring_cos;     // [nhalf] cos(theta) of the northern rings
     const double *lmm_mant;     // [L+1][nhalf] lambda_mm = mant * 2^exp
     const int32_t *lmm_exp;     // [L+1][nhalf]
@@ -25,7 +25,8 @@ struct ShtDesc {
     const int64_t *ring_pix0;   // [nrings] pixel of ring position 0 (ring position j:
                                 // + (j / k) k^2 + (j % k) k)
     const double *ring_w;       // [nrings] quadrature weight of each of the ring's pixels
-    const int8_t *ring_rad;     // [nrings][16] FFT passes: count, then radices
+    const int8_t *ring_rad;     // [nrings][16] passes of the ring's FFT (length n / 2 for even n, else n):
+                                // count, then radices
     // m-major rows (row m: entries i = l - m = 0 .. L - m, then at least
     // kShtRowPad zeros; every row starts at a multiple of 4 entries)
     const int64_t *row_off;     // [L+1] first entry of row m
@@ -41,7 +42,7 @@ hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double
 // m-major ac / as (times K).  gbuf: nrings (L+1) 2 doubles.
 hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double *ac, double *as, double *alm,
                        bool weighted, hipStream_t st);
-// Allow the ring kernels the LDS a plan whose longest ring is max_ring needs.
-hipError_t sht_prepare(int max_ring);
+// Allow the ring kernels the LDS a plan whose longest ring FFT is max_fft needs.
+hipError_t sht_prepare(int max_fft);
 
 }  // namespace sympix
