@@ -28,12 +28,15 @@ def test_host_abi_under_address_and_undefined_behaviour_sanitizers(tmp_path):
         pytest.skip("hipcc not available")
     srcs = [os.path.join(CSRC, "geometry.cpp"), os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "sht.hip"),
             os.path.join(ROOT, "tests", "sanitize", "abi_host_check.cpp")]
-    objs = []
-    for src in srcs:
+    objs, procs = [], []
+    for src in srcs:                     # the five compilations run side by side
         obj = str(tmp_path / (os.path.basename(src) + ".o"))
-        res = subprocess.run([HIPCC, *FLAGS, *SAN, "-c", src, "-o", obj], capture_output=True, text=True)
-        assert res.returncode == 0, res.stderr[-3000:]
+        procs.append(subprocess.Popen([HIPCC, *FLAGS, *SAN, "-c", src, "-o", obj], stdout=subprocess.PIPE,
+                                      stderr=subprocess.PIPE, text=True))
         objs.append(obj)
+    for pr in procs:
+        _, err = pr.communicate()
+        assert pr.returncode == 0, err[-3000:]
     exe = str(tmp_path / "abi_host_check")
     res = subprocess.run([HIPCC, "--offload-arch=gfx950", *SAN, *objs, "-o", exe], capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-3000:]
