@@ -46,7 +46,8 @@ def rel(got, ref):
 
 # (lmax, k, L); k = 3 at lmax 38 gives rings of odd length (81 pixels), which
 # take the ring FFT at full length, every other ring at half length
-CASES = [(16, 2, 16), (40, 4, 30), (64, 8, 64), (128, 8, 128), (100, 8, 60), (38, 3, 38)]
+CASES = [(16, 2, 16), (40, 4, 30), (64, 8, 64), (128, 8, 128), (100, 8, 60), (38, 3, 38),
+         (16, 2, 0), (32, 4, 48)]                         # L = 0; L above the grid's lmax (modes alias)
 
 
 @pytest.mark.parametrize("lmax,k,L", CASES)
@@ -150,22 +151,31 @@ def test_full_size_round_trip_and_transpose(lmax):
     assert e_tr <= 1e-12
 
 
-def test_orders_whose_lambda_mm_is_below_the_double_range():
-    """lmax 2400: on rings with sin(theta) in [m / L, 10^(-323/m)], lambda_mm
-    of order m lies below the smallest double but lambda_lm is of order one
-    before l = L (the turning point m / sin(theta) < L).  Transpose of a map
-    that is nonzero on such rings (and on a polar and an equatorial ring), and
-    synthesis of coefficients of those orders on the same rings, against the
-    oracle's per-order recurrence."""
-    lmax = L = 2400
+# (L, orders m whose window [m / L, 10^(-323/m)] of sin(theta) is not empty)
+FULL_ORDERS = {2400: (1000, 1100, 1200), 3000: (1200, 1500, 2000)}
+
+
+@pytest.mark.parametrize("L", [2400, 3000])
+def test_orders_whose_lambda_mm_is_below_the_double_range(L):
+    """On rings with sin(theta) in [m / L, 10^(-323/m)], lambda_mm of order m
+    lies below the smallest double but lambda_lm is of order one before l = L
+    (the turning point m / sin(theta) < L).  Transpose of a map that is nonzero
+    on such rings (and on a polar and an equatorial ring), and synthesis of
+    coefficients of those orders (and of m = 0, 1, L) on the same rings,
+    against the oracle's per-order recurrence; at L = 3000 this is the
+    workload the SHT bench times (lmax 3000 grid, L = lmax)."""
+    lmax = L
     og, g = G.make_grid(lmax, 8), sp.Grid(lmax, 8)
     s = sp.Sht(g, L)
     ring, pin, nr, phi = og.pixel_coords()
     st = np.sin(og.theta[: og.nrings // 2])
-    rings = sorted({0, og.nrings // 2 - 1} | {int(np.argmin(np.abs(st - v))) for v in (0.45, 0.49, 0.52)})
-    orders = [0, 1, 999, 1000, 1100, 1200, 1800, 2400]
+    windows = [(m / L + 10.0 ** (-323.0 / m)) / 2 for m in FULL_ORDERS[L]]
+    rings = sorted({0, og.nrings // 2 - 1} | {int(np.argmin(np.abs(st - v))) for v in windows})
+    orders = sorted({0, 1, L // 2, L} | set(FULL_ORDERS[L]) | {FULL_ORDERS[L][0] - 1})
     lam = {m: H.lambda_m(L, m, og.theta[rings]) for m in orders}      # [l - m, ring]
-    rng = np.random.default_rng(2400)
+    for m in FULL_ORDERS[L]:       # the case: some chosen ring has lambda_mm = 0 yet |lambda_lm| ~ 1
+        assert any(lam[m][0, q] == 0.0 and np.abs(lam[m][:, q]).max() > 0.1 for q in range(len(rings)))
+    rng = np.random.default_rng(L)
     # transpose: x nonzero on the chosen rings only
     x = np.zeros(g.npix)
     on = np.isin(ring, rings)
@@ -214,11 +224,13 @@ def test_orders_whose_lambda_mm_is_below_the_double_range():
     e_syn = worst / scale
     # Near the pole cos(theta) ~ 1 makes the recurrence's two roots nearly
     # equal, so a rounding error made at step j grows about linearly over the
-    # steps after it: random roundings leave about eps L^1.5 (1.3e-11 here)
-    # between two orderings of the same FP64 recurrence.  Measured: 1.2-1.7e-12,
-    # the polar ring at m = 0, 1 (every other ring agrees to 2e-14).
+    # steps after it: random roundings leave about eps L^1.5 (2.6e-11 at L =
+    # 2400, 3.6e-11 at 3000; eps = 2^-52) between two orderings of the same FP64
+    # recurrence.  Measured: 1.2-1.7e-12 at L = 2400, 2.6-3.6e-12 at 3000, the
+    # polar ring at m = 0, 1 (every other ring agrees to 2e-14).
     tol = np.finfo(np.float64).eps * L ** 1.5
-    say(f"[sht lmax=2400] rings {rings}: transpose {e_adj:.2e}, synthesis {e_syn:.2e} (bound {tol:.1e})")
+    say(f"[sht lmax={L}] rings {rings} orders {orders}: transpose {e_adj:.2e}, synthesis {e_syn:.2e} "
+        f"(bound {tol:.1e})")
     assert e_adj <= tol and e_syn <= tol
 
 
