@@ -115,6 +115,25 @@ __global__ __launch_bounds__(256) void k_alm_mm(const double *__restrict__ src, 
 // 0 <= b_i < 1/4), and by at most 2^270 at a chunk start, so that it stays
 // below 2^600.
 // ---------------------------------------------------------------------------
+// Workgroups go to the 8 XCDs in turn (workgroup w on XCD w mod 8).  The
+// Legendre kernels' ring buffer holds, per ring, the orders m in 16-byte
+// entries, so one 128-byte line holds 8 consecutive orders; the workgroups of
+// those orders are put on one XCD, whose L2 then merges their entries:
+// w = 8 (8 (g / 8) + m mod 8) + g mod 8 for m = 8 g + (m mod 8), the orders in
+// increasing m (largest rows first) on every XCD; -1 past L.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int order_of_workgroup(int L) {
+    const int w = blockIdx.x, x = w % kXcds, s = w / kXcds;
+    const int m = kXcds * (x + kXcds * (s / kXcds)) + s % kXcds;
+    return m <= L ? m : -1;
+}
+
+__host__ __forceinline__ int order_workgroups(int L) {
+    const int g = kXcds * kXcds;
+    return (L + 1 + g - 1) / g * g;
+}
+
 struct Deg4 { double v[4]; };   // four consecutive degrees of a row (32-byte aligned)
 
 __device__ __forceinline__ Deg4 deg4(const double *p) { return *(const Deg4 *)p; }
@@ -132,7 +151,9 @@ __global__ __launch_bounds__(kLegThreads) void k_leg_syn(ShtDesc d, const int64_
                                                          const double *__restrict__ ac,
                                                          const double *__restrict__ as,
                                                          double *__restrict__ fbuf) {
-    const int m = blockIdx.x, L = d.lmax, nl = L - m + 1;
+    const int m = order_of_workgroup(d.lmax);
+    if (m < 0) return;
+    const int L = d.lmax, nl = L - m + 1;
     const int64_t off = row_off[m];
     const double *b = rb + off, *kk = rk + off, *cc = ac + off, *cs = as + off;
     for (int rp0 = threadIdx.x; rp0 < d.nhalf; rp0 += kLegThreads * R) {
@@ -245,7 +266,9 @@ __global__ __launch_bounds__(T, R <= 6 ? 4 : 1) void k_leg_adj(ShtDesc d, const 
     constexpr int CH = 8;
     constexpr int LPR = T / 16;          // lanes summing one of the 16 values
     __shared__ double sRed[2 * CH * T];
-    const int m = blockIdx.x, L = d.lmax, nl = L - m + 1;
+    const int m = order_of_workgroup(d.lmax);
+    if (m < 0) return;
+    const int L = d.lmax, nl = L - m + 1;
     const int64_t off = row_off[m];
     const double *b = rb + off, *kk = rk + off;
     double ct[R], mu[R], mup[R];
@@ -463,20 +486,37 @@ __device__ __forceinline__ int64_t ring_pixel(const ShtDesc &d, int r, int j) {
 // length n.  MAXN bounds nf (the plan's longest), and sizes the registers one
 // FFT pass holds.
 
+// As for the orders above, and the k rings of a band interleave their pixels at a stride of k (one 128-byte line
+// holds pixels of every ring of the band).  A band's rings are therefore given
+// to workgroups on one XCD, w = 8 (k (band / 8) + row) + band mod 8, so that
+// its L2 serves the shared lines; -1 past the last band.
+
+__device__ __forceinline__ int ring_of_workgroup(const ShtDesc &d) {
+    const int w = blockIdx.x, x = w % kXcds, s = w / kXcds;
+    const int band = x + kXcds * (s / d.k), row = s % d.k;
+    return band * d.k < d.nrings ? band * d.k + row : -1;
+}
+
+__host__ __forceinline__ int ring_workgroups(const ShtDesc &d) {
+    const int nbands = d.nrings / d.k;
+    return (nbands + kXcds - 1) / kXcds * kXcds * d.k;
+}
+
 // y_q = conj(sum_{m = q mod n, m <= L} H_m exp(i pi m / n)): the ring's modes
 // H_0 = F_0, H_m = sqrt(2) (F_m^cos - i F_m^sin) folded onto frequency q with
-// the half-pixel phase
-__device__ __forceinline__ double2 fold_mode(const double *F, int L, int n, int q) {
-    double zr = 0.0, zi = 0.0;
+// the half-pixel phase.  exp(i pi (q + j n) / n) = (-1)^j exp(i pi q / n), so
+// the phase ph = exp(i pi q / n) is applied once, after the sum.
+__device__ __forceinline__ double2 fold_mode(const double *F, int L, int n, int q, double2 ph) {
+    double hr = 0.0, hi = 0.0, sg = 1.0;
     for (int m = q; m <= L; m += n) {
         const double hc = m == 0 ? F[0] : kSqrt2 * F[2 * m];
         const double hs = m == 0 ? 0.0 : -kSqrt2 * F[2 * m + 1];
-        double sn, cs;
-        sincospi((double)m / (double)n, &sn, &cs);
-        zr += hc * cs - hs * sn;
-        zi += hc * sn + hs * cs;
+        hr += sg * hc;
+        hi += sg * hs;
+        sg = -sg;
     }
-    return double2{zr, -zi};
+    const double2 z = cmul(double2{hr, hi}, ph);
+    return double2{z.x, -z.y};
 }
 
 // f_j = Re sum_m H_m exp(i m phi_j), phi_j = 2 pi (j + 1/2) / n, that is f =
@@ -490,11 +530,17 @@ template <int MAXN>
 __global__ __launch_bounds__(kRingThreads) void k_ring_syn(ShtDesc d, const double *__restrict__ fbuf,
                                                           double *__restrict__ map, int wmul) {
     extern __shared__ double2 z[];
-    const int r = blockIdx.x, L = d.lmax, n = d.ring_n[r];
+    const int r = ring_of_workgroup(d);
+    if (r < 0) return;
+    const int L = d.lmax, n = d.ring_n[r];
     const double *F = fbuf + (int64_t)r * (L + 1) * 2;
     const double w = wmul ? d.ring_w[r] : 1.0;
     if (n & 1) {
-        for (int k = threadIdx.x; k < n; k += kRingThreads) z[k] = fold_mode(F, L, n, k);
+        for (int k = threadIdx.x; k < n; k += kRingThreads) {
+            double sn, cs;
+            sincospi((double)k / (double)n, &sn, &cs);
+            z[k] = fold_mode(F, L, n, k, double2{cs, sn});
+        }
         __syncthreads();
         fft_forward<MAXN>(z, n, d.ring_rad + 16 * r);
         for (int j = threadIdx.x; j < n; j += kRingThreads) map[ring_pixel(d, r, j)] = w * z[j].x;
@@ -503,14 +549,17 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_syn(ShtDesc d, const doub
     const int N = n >> 1;
     for (int k = threadIdx.x; 2 * k <= N; k += kRingThreads) {
         const int kp = k == 0 ? 0 : N - k;
-        const double2 y0 = fold_mode(F, L, n, k), y1 = fold_mode(F, L, n, k + N);
-        const double2 y2 = fold_mode(F, L, n, kp), y3 = fold_mode(F, L, n, kp + N);
-        double sk, ck, sp, cp;
-        sincospi(-2.0 * (double)k / (double)n, &sk, &ck);
-        sincospi(-2.0 * (double)kp / (double)n, &sp, &cp);
+        // p = exp(i pi k / n) gives every phase of the pair: at k + N it is i p,
+        // at N - k i conj(p), at n - k -conj(p); w^k = conj(p)^2, w^(N-k) = -p^2
+        double s, c;
+        sincospi((double)k / (double)n, &s, &c);
+        const double2 y0 = fold_mode(F, L, n, k, double2{c, s}), y1 = fold_mode(F, L, n, k + N, double2{-s, c});
+        const double2 y2 = kp == k ? y0 : fold_mode(F, L, n, kp, double2{s, c});
+        const double2 y3 = kp == k ? y1 : fold_mode(F, L, n, kp + N, double2{-c, s});
+        const double c2 = c * c - s * s, s2 = 2.0 * c * s;
         const double2 a = double2{y0.x + y1.x, y0.y + y1.y}, ap = double2{y2.x + y3.x, y2.y + y3.y};
-        const double2 b = cmul(double2{y0.x - y1.x, y0.y - y1.y}, double2{ck, sk});
-        const double2 bp = cmul(double2{y2.x - y3.x, y2.y - y3.y}, double2{cp, sp});
+        const double2 b = cmul(double2{y0.x - y1.x, y0.y - y1.y}, double2{c2, -s2});
+        const double2 bp = kp == k ? b : cmul(double2{y2.x - y3.x, y2.y - y3.y}, double2{-c2, -s2});
         // C_k = (a + conj ap) / 2 + i (b + conj bp) / 2, C_kp likewise with the roles swapped
         z[k] = double2{0.5 * (a.x + ap.x) - 0.5 * (b.y - bp.y), 0.5 * (a.y - ap.y) + 0.5 * (b.x + bp.x)};
         if (kp != k)
@@ -534,7 +583,9 @@ template <int MAXN>
 __global__ __launch_bounds__(kRingThreads) void k_ring_adj(ShtDesc d, const double *__restrict__ map,
                                                           double *__restrict__ gbuf, int wmul) {
     extern __shared__ double2 z[];
-    const int r = blockIdx.x, L = d.lmax, n = d.ring_n[r];
+    const int r = ring_of_workgroup(d);
+    if (r < 0) return;
+    const int L = d.lmax, n = d.ring_n[r];
     const double w = wmul ? d.ring_w[r] : 1.0;
     const bool half = (n & 1) == 0;
     const int nf = half ? n >> 1 : n;
@@ -549,21 +600,20 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_adj(ShtDesc d, const doub
     double *G = gbuf + (int64_t)r * (L + 1) * 2;
     for (int m = threadIdx.x; m <= L; m += kRingThreads) {
         const int q = m % n;
+        double sn, cs;
+        sincospi((double)m / (double)n, &sn, &cs);
         double2 v;
         if (half) {
             const int qq = q < nf ? q : q - nf, qp = qq == 0 ? 0 : nf - qq;
             const double2 zq = z[qq], zc = double2{z[qp].x, -z[qp].y};
             const double2 e = double2{0.5 * (zq.x + zc.x), 0.5 * (zq.y + zc.y)};
             const double2 o = double2{0.5 * (zq.y - zc.y), -0.5 * (zq.x - zc.x)};   // (zq - zc) / (2 i)
-            double sq, cq;
-            sincospi(-2.0 * (double)q / (double)n, &sq, &cq);
-            const double2 wo = cmul(o, double2{cq, sq});
+            // w^q = exp(-2 pi i m / n) = conj(exp(i pi m / n))^2
+            const double2 wo = cmul(o, double2{cs * cs - sn * sn, -2.0 * cs * sn});
             v = double2{e.x + wo.x, e.y + wo.y};
         } else {
             v = z[q];
         }
-        double sn, cs;
-        sincospi((double)m / (double)n, &sn, &cs);
         const double re = v.x * cs + v.y * sn;          // Re(exp(-i pi m / n) v)
         const double im = v.y * cs - v.x * sn;
         G[2 * m] = m == 0 ? re : kSqrt2 * re;
@@ -601,7 +651,7 @@ hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double
     if (alm)
         hipLaunchKernelGGL(k_alm_mm<true>, dim3(nt, nt), dim3(256), 0, st, alm, L, d.row_off, d.rec_k, ac, as,
                            nullptr);
-    const dim3 grid(L + 1), block(kLegThreads);
+    const dim3 grid(order_workgroups(L)), block(kLegThreads);
     auto syn = [&](auto r) {
         hipLaunchKernelGGL(k_leg_syn<decltype(r)::value>, grid, block, 0, st, d, d.row_off, d.rec_b, d.rec_k, ac,
                            as, fbuf);
@@ -617,7 +667,7 @@ hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double
     else syn(std::integral_constant<int, 1>());
     const size_t lds_ring = (size_t)d.max_fft * sizeof(double2);
     ring_dispatch(d.max_fft, [&](auto mx) {
-        hipLaunchKernelGGL(k_ring_syn<decltype(mx)::value>, dim3(d.nrings), dim3(kRingThreads), lds_ring, st, d, fbuf,
+        hipLaunchKernelGGL(k_ring_syn<decltype(mx)::value>, dim3(ring_workgroups(d)), dim3(kRingThreads), lds_ring, st, d, fbuf,
                            map, weighted ? 1 : 0);
     });
     return hipGetLastError();
@@ -629,14 +679,14 @@ hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double
     if (d.nhalf > kShtMaxHalfRings) return hipErrorInvalidValue;
     const size_t lds_ring = (size_t)d.max_fft * sizeof(double2);
     ring_dispatch(d.max_fft, [&](auto mx) {
-        hipLaunchKernelGGL(k_ring_adj<decltype(mx)::value>, dim3(d.nrings), dim3(kRingThreads), lds_ring, st, d, map,
+        hipLaunchKernelGGL(k_ring_adj<decltype(mx)::value>, dim3(ring_workgroups(d)), dim3(kRingThreads), lds_ring, st, d, map,
                            gbuf, weighted ? 1 : 0);
     });
     // every ring pair in one pass: 128 threads with up to 8 ring pairs each
     // (half the partial sums of 256 threads), else 256 threads with 6 or 8
     auto adj = [&](auto t, auto r) {
         constexpr int T = decltype(t)::value, R = decltype(r)::value;
-        hipLaunchKernelGGL((k_leg_adj<T, R>), dim3(L + 1), dim3(T), 0, st, d, d.row_off, d.rec_b, d.rec_k, gbuf, ac,
+        hipLaunchKernelGGL((k_leg_adj<T, R>), dim3(order_workgroups(L)), dim3(T), 0, st, d, d.row_off, d.rec_b, d.rec_k, gbuf, ac,
                            as);
     };
     using T128 = std::integral_constant<int, 128>;
