@@ -179,16 +179,23 @@ __global__ __launch_bounds__(kLegThreads) void k_leg_syn(ShtDesc d, const int64_
                     mup[q] *= sk;
                 }
             }
+            // the test of all rings at once, one wave-uniform branch: short
+            // per-ring branches would be executed under a mask every time
+            bool grow = false;
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                if (fabs(mu[q]) > kBig) {
-                    mu[q] *= kSmall;
-                    mup[q] *= kSmall;
-                    ec[q] *= kSmall;
-                    es[q] *= kSmall;
-                    oc[q] *= kSmall;
-                    os[q] *= kSmall;
-                    e[q] += 300;
+            for (int q = 0; q < R; ++q) grow |= fabs(mu[q]) > kBig;
+            if (__builtin_expect(__any(grow), 0)) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    if (fabs(mu[q]) > kBig) {
+                        mu[q] *= kSmall;
+                        mup[q] *= kSmall;
+                        ec[q] *= kSmall;
+                        es[q] *= kSmall;
+                        oc[q] *= kSmall;
+                        os[q] *= kSmall;
+                        e[q] += 300;
+                    }
                 }
             }
 #pragma unroll
@@ -299,9 +306,13 @@ __global__ __launch_bounds__(T, R <= 6 ? 4 : 1) void k_leg_adj(ShtDesc d, const 
         double vc[CH], vs[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) vc[j] = vs[j] = 0.0;
+        bool grow = false;                 // as in the synthesis: one uniform branch
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            if (fabs(mu[q]) > kBig) {
+        for (int q = 0; q < R; ++q) grow |= fabs(mu[q]) > kBig;
+        if (__builtin_expect(__any(grow), 0)) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                if (fabs(mu[q]) <= kBig) continue;
                 mu[q] *= kSmall;
                 mup[q] *= kSmall;
                 e[q] += 300;
@@ -318,6 +329,9 @@ __global__ __launch_bounds__(T, R <= 6 ? 4 : 1) void k_leg_adj(ShtDesc d, const 
                     g[q] = ring_g(d, gbuf, rr, m, e[q]);
                 }
             }
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
             double x = mu[q], xp = mup[q];
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
