@@ -7,11 +7,13 @@
 // splits into a Legendre part per m (over all rings, O(L^2 N_ring)) and a
 // Fourier part per ring (O(n log n)):
 //
+//   k_alm_mm   the coefficient vector to m-major rows (and back)
 //   k_leg_syn  one workgroup per m: F_m(ring) = sum_l a_lm lambda_lm(theta),
 //              north and south rings of a pair together (lambda_lm(pi - t) =
 //              (-1)^(l-m) lambda_lm(t): even and odd l - m summed apart)
 //   k_ring_syn one workgroup per ring: the modes folded onto the ring's n
-//              frequencies, an FFT in LDS, the ring scattered to SymPix order
+//              frequencies, an FFT in LDS (of length n / 2 for even n: the
+//              ring's real values in pairs), the ring scattered to SymPix order
 //   k_ring_adj the transpose: gather, FFT, unfold to the modes m <= L
 //   k_leg_adj  one workgroup per m: a_lm = sum_rings lambda_lm G_m(ring),
 //              reduced across the workgroup eight degrees at a time
