@@ -459,13 +459,15 @@ void sympix_batch_destroy(sympix_batch *bt);
 typedef struct sympix_sht sympix_sht;
 
 /* Plan for the transforms of band limit lmax_sh on grid g, on the current
- * device: ring tables, lambda_mm per ring and m, and the plan's work buffers
- * (about 16 nrings (L+1) + 16 (L+1)(L+2)/2 + 12 (nrings/2)(L+1) bytes).  The
+ * device: ring tables, lambda_mm per ring and m, the recurrence's per-degree
+ * values and the plan's work buffers (about 16 nrings (L+1) + 32 (L+1)(L+2)/2
+ * + 12 (nrings/2)(L+1) bytes).  The
  * grid must outlive the plan.  Calls that use one plan (the transforms below,
  * and a degrade naming it) share its work buffers and must not overlap in
  * time: issue them on one stream, or order the streams.
- * Errors: EINVAL (NULL, lmax_sh < 0), EUNSUPPORTED (lmax_sh > 4095, a ring
- * longer than 8192 pixels or not of the form 2^a 3^b 5^c), ENOMEM, EHIP. */
+ * Errors: EINVAL (NULL, lmax_sh < 0), EUNSUPPORTED (lmax_sh > 4095, more
+ * than 4096 rings, a ring longer than 8192 pixels or not of the form
+ * 2^a 3^b 5^c), ENOMEM, EHIP. */
 sympix_status sympix_sht_create(const sympix_grid *g, int32_t lmax_sh, sympix_sht **out);
 
 /* Free a plan (after its last call has completed). NULL is ignored. */
