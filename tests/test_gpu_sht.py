@@ -234,6 +234,31 @@ def test_orders_whose_lambda_mm_is_below_the_double_range(L):
     assert e_adj <= tol and e_syn <= tol
 
 
+@pytest.mark.parametrize("lmax,k", [(300, 16), (1000, 4), (700, 5)])
+def test_round_trip_and_transpose_other_tile_sizes(lmax, k):
+    """Tile sizes other than 8 at larger band limits (k = 5 gives rings of odd
+    length, taking the full-length ring FFT): analysis inverts synthesis and
+    <Y a, x> = <a, Y^T x>, as at k = 8."""
+    L = lmax
+    g = sp.Grid(lmax, k)
+    s = sp.Sht(g, L)
+    rng = np.random.default_rng(lmax + k)
+    ell = np.repeat(np.arange(L + 1), 2 * np.arange(L + 1) + 1)
+    a = dev(rng.standard_normal((L + 1) ** 2) / np.sqrt(ell + 1.0))
+    f = torch.empty(g.npix, dtype=torch.float64, device="cuda")
+    back = torch.empty_like(a)
+    s.synthesis(a, f)
+    s.analysis(f, back)
+    x = dev(rng.standard_normal(g.npix))
+    yt = torch.empty_like(a)
+    s.adjoint(x, yt)
+    torch.cuda.synchronize()
+    e_rt = float((back - a).abs().max() / a.abs().max())
+    e_tr = abs(float(f @ x) - float(a @ yt)) / (float(f.abs().sum()) * float(x.abs().max()))
+    say(f"[sht lmax={lmax} k={k}] npix={g.npix}: analysis of synthesis {e_rt:.2e}; <Ya,x> vs <a,Y^T x> {e_tr:.2e}")
+    assert e_rt <= 1e-10 and e_tr <= 1e-12
+
+
 @pytest.mark.parametrize("lmax", [511, 639, 767])
 def test_table1_round_trip_on_this_grid(lmax):
     """Table 1's experiment (Section 3.3) on this build's grids: 100 draws of
