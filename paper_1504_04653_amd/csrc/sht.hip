@@ -648,11 +648,14 @@ static void ring_dispatch(int max_fft, F &&f) {
     else f(std::integral_constant<int, kShtMaxRing>());
 }
 
+// The attribute is set to the instantiation's own bound (MAXN complex values),
+// not to this plan's longest FFT: plans of other sizes that use the same
+// instantiation then never lower it below what one of them launches with.
 hipError_t sht_prepare(int max_fft) {
-    const int bytes = max_fft * (int)sizeof(double2);
     hipError_t e = hipSuccess;
     ring_dispatch(max_fft, [&](auto mx) {
         constexpr int M = decltype(mx)::value;
+        const int bytes = M * (int)sizeof(double2);
         e = hipFuncSetAttribute((const void *)k_ring_syn<M>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void *)k_ring_adj<M>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

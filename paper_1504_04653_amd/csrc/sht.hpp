@@ -42,7 +42,8 @@ hipError_t sht_synthesis(const ShtDesc &d, const double *alm, double *ac, double
 // m-major ac / as (times K).  gbuf: nrings (L+1) 2 doubles.
 hipError_t sht_adjoint(const ShtDesc &d, const double *map, double *gbuf, double *ac, double *as, double *alm,
                        bool weighted, hipStream_t st);
-// Allow the ring kernels the LDS a plan whose longest ring FFT is max_fft needs.
+// Allow the ring kernels (the instantiation for FFTs up to max_fft) their
+// largest LDS.
 hipError_t sht_prepare(int max_fft);
 
 }  // namespace sympix

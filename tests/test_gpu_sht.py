@@ -259,6 +259,28 @@ def test_round_trip_and_transpose_other_tile_sizes(lmax, k):
     assert e_rt <= 1e-10 and e_tr <= 1e-12
 
 
+def test_plans_sharing_a_ring_kernel():
+    """Two plans whose ring FFTs take the same kernel instantiation but need
+    different LDS (odd rings of 6075 and 5625 pixels at k = 5: 97 and 90 KB):
+    creating the second plan must not lower the first one's LDS allowance, so
+    the first plan's transforms still run after the second exists."""
+    ga, gb = sp.Grid(3000, 5), sp.Grid(2700, 5)
+    sa = sp.Sht(ga, 3000)
+    sb = sp.Sht(gb, 2700)
+    for g, s, L in ((ga, sa, 3000), (gb, sb, 2700)):
+        rng = np.random.default_rng(L)
+        ell = np.repeat(np.arange(L + 1), 2 * np.arange(L + 1) + 1)
+        a = dev(rng.standard_normal((L + 1) ** 2) / np.sqrt(ell + 1.0))
+        f = torch.empty(g.npix, dtype=torch.float64, device="cuda")
+        back = torch.empty_like(a)
+        s.synthesis(a, f)
+        s.analysis(f, back)
+        torch.cuda.synchronize()
+        e_rt = float((back - a).abs().max() / a.abs().max())
+        say(f"[sht lmax={L} k=5] npix={g.npix}: analysis of synthesis {e_rt:.2e}")
+        assert e_rt <= 1e-10
+
+
 @pytest.mark.parametrize("lmax", [511, 639, 767])
 def test_table1_round_trip_on_this_grid(lmax):
     """Table 1's experiment (Section 3.3) on this build's grids: 100 draws of
