@@ -1063,8 +1063,8 @@ def main():
     roof["kernel"] = KERNEL_NAME[head]
     if hr["D_and_btnb_one_launch"]:
         roof["kernel"] = roof["kernel"].replace("false", "true")   # the instantiation that also writes D-hat
-        roof["note"] = ("one launch writes B^T N^-1 B and D-hat (66.4 GB); its lower bound is the larger of "
-                        "the MFMA time and the HBM write time")
+        roof["note"] = (f"one launch writes B^T N^-1 B and D-hat ({2 * nelem * 8 / 1e9:.1f} GB); its lower bound "
+                        "is the larger of the MFMA time and the HBM write time")
     roof["traffic"] = traffic
     line = {
         "metric": METRIC,

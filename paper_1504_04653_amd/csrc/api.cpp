@@ -81,8 +81,10 @@ struct DevGrid {
     int32_t *class_terms = nullptr;
     int32_t *class_blk = nullptr;
     int32_t *class_itab = nullptr;
-    int32_t *mtiles = nullptr;
+    int32_t *mtiles = nullptr;          // member tiles, class order (batch work items)
     int32_t *mtiles32 = nullptr;
+    int32_t *gtiles = nullptr;          // the same as the class-grid launch's dispatch tables
+    int32_t *gtiles32 = nullptr;
     int32_t *conv_chunks = nullptr;
     int32_t *conv_slots = nullptr;
 };
@@ -109,6 +111,8 @@ void free_dev(DevGrid &d) {
     hipFree(d.class_itab);
     hipFree(d.mtiles);
     hipFree(d.mtiles32);
+    hipFree(d.gtiles);
+    hipFree(d.gtiles32);
     hipFree(d.conv_chunks);
     hipFree(d.conv_slots);
     d = DevGrid();
@@ -120,7 +124,7 @@ struct DevClasses {
     int32_t *class_terms = nullptr;
     int32_t *class_blk = nullptr;
     int32_t *class_itab = nullptr;
-    int32_t *mtiles = nullptr;
+    int32_t *gtiles = nullptr;          // dispatch table of the class-grid launch
 };
 
 void free_dev_classes(DevClasses &d) {
@@ -128,7 +132,7 @@ void free_dev_classes(DevClasses &d) {
     hipFree(d.class_terms);
     hipFree(d.class_blk);
     hipFree(d.class_itab);
-    hipFree(d.mtiles);
+    hipFree(d.gtiles);
     d = DevClasses();
 }
 
@@ -203,6 +207,8 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.class_itab, geo.cls.class_itab.data(), geo.cls.class_itab.size());
     if (e == hipSuccess) e = upload(&d.mtiles, geo.cls.mtiles.data(), geo.cls.mtiles.size());
     if (e == hipSuccess) e = upload(&d.mtiles32, geo.cls.mtiles32.data(), geo.cls.mtiles32.size());
+    if (e == hipSuccess) e = upload(&d.gtiles, geo.cls.gtiles.data(), geo.cls.gtiles.size());
+    if (e == hipSuccess) e = upload(&d.gtiles32, geo.cls.gtiles32.data(), geo.cls.gtiles32.size());
     if (e == hipSuccess) e = upload(&d.conv_chunks, geo.conv_chunks.data(), geo.conv_chunks.size());
     if (e == hipSuccess) e = upload(&d.conv_slots, geo.conv_slots.data(), geo.conv_slots.size());
     if (e != hipSuccess) {
@@ -241,7 +247,7 @@ sympix_status two_hop_tables(const sympix_grid *g, int device, const sympix::Pat
     if (e == hipSuccess) e = upload(&d.class_terms, ct.class_terms.data(), ct.class_terms.size());
     if (e == hipSuccess) e = upload(&d.class_blk, ct.class_blk.data(), ct.class_blk.size());
     if (e == hipSuccess) e = upload(&d.class_itab, ct.class_itab.data(), ct.class_itab.size());
-    if (e == hipSuccess) e = upload(&d.mtiles, ct.mtiles.data(), ct.mtiles.size());
+    if (e == hipSuccess) e = upload(&d.gtiles, ct.gtiles.data(), ct.gtiles.size());
     if (e != hipSuccess) {
         free_dev_classes(d);
         return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for the two-hop tables failed")
@@ -440,15 +446,15 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
         a.class_terms = dc->class_terms;
         a.class_blk = dc->class_blk;
         a.class_itab = dc->class_itab;
-        a.mtiles = dc->mtiles;
+        a.mtiles = dc->gtiles;
     } else {
         a.classes = dg->classes;
         a.class_terms = dg->class_terms;
         a.class_blk = dg->class_blk;
         a.class_itab = dg->class_itab;
-        a.mtiles = dg->mtiles;
+        a.mtiles = dg->gtiles;
     }
-    a.nmtiles = (int64_t)ct.mtiles.size() / 4;
+    a.nmtiles = (int64_t)ct.gtiles.size() / 4;
     a.nblocks = nblocks;
     a.npix = geo.npix;
     a.ninv = ninv_dev;
@@ -790,12 +796,13 @@ struct sympix_batch {
     int32_t schedule = SYMPIX_SCHED_XCD_QUEUES;
     int32_t tiling = SYMPIX_TILES_64;
     int32_t nworkgroups = 0;
-    // per tile shape (sympix_tiling): problem descriptors, tile counts, work
-    // items in natural order
+    // per tile shape (sympix_tiling): problem descriptors, dispatch tables,
+    // work items in natural order
     std::vector<sympix::ProblemDesc64> hdesc64[SYMPIX_NTILINGS]; // FP64
     std::vector<sympix::ProblemDesc> hdesc[SYMPIX_NTILINGS];     // FP32
     std::vector<sympix::ProblemDescB> hdescb[SYMPIX_NTILINGS];   // split BF16
-    std::vector<int64_t> nmtiles[SYMPIX_NTILINGS];
+    std::vector<const int32_t *> gtiles[SYMPIX_NTILINGS];   // per problem: the class-grid dispatch table
+    std::vector<int64_t> ngtiles[SYMPIX_NTILINGS];
     std::vector<int32_t> item_prob[SYMPIX_NTILINGS], item_tile[SYMPIX_NTILINGS], item_cost[SYMPIX_NTILINGS];
     std::vector<uint16_t *> wsplit;                // split BF16: 3 N^-1 parts per problem
     std::vector<const double *> ninv;
@@ -947,7 +954,8 @@ sympix_status capture_batch(sympix_batch *bt, int32_t s, int32_t t) {
     bl.descb = bt->d_descb[t];
     bl.ninv = bt->ninv.data();
     bl.npix = bt->npix.data();
-    bl.nmtiles = bt->nmtiles[t].data();
+    bl.gtiles = bt->gtiles[t].data();
+    bl.ngtiles = bt->ngtiles[t].data();
     bl.desc = bt->d_desc[t];
     bl.items = bt->d_items;
     bl.nitems = nitems;
@@ -1063,7 +1071,9 @@ sympix_status sympix_batch_create(const sympix_problem *p, int32_t n, int32_t pr
                                     p[i].b->ut32, {nullptr, nullptr, nullptr}, p[i].out_dev, nullptr, nullptr, nullptr};
             bt->hdescb[t].push_back(db);
             const int64_t nmt = (int64_t)tiles.size() / 4;
-            bt->nmtiles[t].push_back(nmt);
+            const std::vector<int32_t> &gt = t == SYMPIX_TILES_64 ? geo.cls.gtiles : geo.cls.gtiles32;
+            bt->gtiles[t].push_back(t == SYMPIX_TILES_64 ? dg->gtiles : dg->gtiles32);
+            bt->ngtiles[t].push_back((int64_t)gt.size() / 4);
             for (int64_t k = 0; k < nmt; ++k) {
                 bt->item_prob[t].push_back(i);
                 bt->item_tile[t].push_back((int32_t)k);
@@ -1258,7 +1268,7 @@ struct DevCross {
     int32_t *class_terms = nullptr;
     int32_t *class_blk = nullptr;
     int32_t *class_itab = nullptr;
-    int32_t *mtiles = nullptr;
+    int32_t *gtiles = nullptr;          // dispatch table of the class-grid launch
     int32_t *exp_items = nullptr;
     int32_t *exp_blk = nullptr;
 };
@@ -1271,7 +1281,7 @@ void free_dev_cross(DevCross &d) {
     hipFree(d.class_terms);
     hipFree(d.class_blk);
     hipFree(d.class_itab);
-    hipFree(d.mtiles);
+    hipFree(d.gtiles);
     hipFree(d.exp_items);
     hipFree(d.exp_blk);
     d = DevCross();
@@ -1324,7 +1334,7 @@ sympix_status cross_tables(const sympix_cross *c, int device, const DevCross **o
     if (e == hipSuccess) e = upload(&d.class_terms, x.cls.class_terms.data(), x.cls.class_terms.size());
     if (e == hipSuccess) e = upload(&d.class_blk, x.cls.class_blk.data(), x.cls.class_blk.size());
     if (e == hipSuccess) e = upload(&d.class_itab, x.cls.class_itab.data(), x.cls.class_itab.size());
-    if (e == hipSuccess) e = upload(&d.mtiles, x.cls.mtiles.data(), x.cls.mtiles.size());
+    if (e == hipSuccess) e = upload(&d.gtiles, x.cls.gtiles.data(), x.cls.gtiles.size());
     if (e == hipSuccess) e = upload(&d.exp_items, x.exp_items.data(), x.exp_items.size());
     if (e == hipSuccess) e = upload(&d.exp_blk, x.exp_blk.data(), x.exp_blk.size());
     if (e != hipSuccess) {
@@ -1475,8 +1485,8 @@ sympix_status sympix_sample_BtNB_cross(const sympix_cross *c, const sympix_kerne
     a.class_terms = dx->class_terms;
     a.class_blk = dx->class_blk;
     a.class_itab = dx->class_itab;
-    a.mtiles = dx->mtiles;
-    a.nmtiles = (int64_t)x.cls.mtiles.size() / 4;
+    a.mtiles = dx->gtiles;
+    a.nmtiles = (int64_t)x.cls.gtiles.size() / 4;
     a.nblocks = nblocks;
     a.npix = g2.npix;
     a.ninv = ninv2_dev;

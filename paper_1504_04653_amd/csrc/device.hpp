@@ -62,8 +62,9 @@ struct BtnbArgs {
     const double *u64t;
     const float *ut32;
     const DevClass *classes;
-    const int32_t *class_terms, *class_blk, *class_itab, *mtiles;
-    int64_t nmtiles;
+    const int32_t *class_terms, *class_blk, *class_itab;
+    const int32_t *mtiles;    // the class-grid dispatch table: one slot per workgroup,
+    int64_t nmtiles;          // 4 ints as a member tile, groups 0 an empty slot
     uint16_t *wsplit[3];      // scratch: N^-1 split into BF16 parts, npix each
     float *wf32;              // scratch: N^-1 rounded to FP32, npix
     int64_t npix;
@@ -118,8 +119,11 @@ struct ProblemDesc {
 };
 
 // a10: one batched launch.  host_desc / host_descb / host_desc64 / ninv /
-// npix / nmtiles / wsplit are host arrays of nprob entries (wsplit: 3 per
-// problem); desc, descb, desc64, items, qb and counters live on the device.
+// npix / gtiles / ngtiles / wsplit are host arrays of nprob entries (wsplit: 3
+// per problem; gtiles: device pointers to each problem's class-grid dispatch
+// table of ngtiles slots, used by the one-launch-per-problem schedule in place
+// of the descriptors' member tiles); desc, descb, desc64, items, qb and
+// counters live on the device.
 // prec: 0 FP64 (desc64, host_desc64; N^-1 read as given), 1 FP32 (desc,
 // host_desc), 2 or 3 split BF16 with that many parts (descb, host_descb, and
 // the N^-1 parts in wsplit).
@@ -134,7 +138,8 @@ struct BatchLaunch {
     const ProblemDescB *descb;
     const double *const *ninv;
     const int64_t *npix;
-    const int64_t *nmtiles;
+    const int32_t *const *gtiles;
+    const int64_t *ngtiles;
     const ProblemDesc *desc;
     const int32_t *items;     // 2 per item: problem, member tile
     int64_t nitems;

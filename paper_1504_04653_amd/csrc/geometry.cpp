@@ -161,6 +161,53 @@ int64_t pos_mod(int64_t a, int64_t m) {
     return r < 0 ? r + m : r;
 }
 
+// Dispatch table of a launch with one workgroup per member tile.  Workgroup w
+// runs on XCD w mod 8, whose CUs take that XCD's workgroups in order as they
+// free up.  The tiles, in class order, are cut into 8 contiguous ranges of
+// equal count: a class's tiles, which read the same unique blocks, stay on one
+// XCD and in its L2, and heavy and light tiles stay mixed, so that MFMA work
+// and output stores overlap on every CU.  Each range runs in class order except
+// its smallest tiles (by (nterms + 1) x groups, the 1 for the stores) that
+// hold kTailPercent of its work: they run last, largest first, and fill the
+// CUs that finish early, so that no large tile starts when the rest are done.
+// Slot 8 i + x holds the i-th tile of range x; ranges shorter than the first
+// end in an empty slot (groups 0).
+std::vector<int32_t> xcd_dispatch_table(const std::vector<BlockClass> &classes, const std::vector<int32_t> &tiles) {
+    constexpr int kX = 8;
+    constexpr int64_t kTailPercent = 15;
+    const int64_t n = (int64_t)tiles.size() / 4, per = n / kX, rem = n % kX;
+    auto cost = [&](int64_t i) { return (int64_t)(classes[tiles[4 * i]].nterms + 1) * tiles[4 * i + 2]; };
+    const int64_t len = per + (rem > 0);
+    std::vector<int32_t> out(4 * kX * len, 0);
+    std::vector<int64_t> order, seq;
+    for (int64_t x = 0; x < kX; ++x) {
+        const int64_t b = x * per + std::min(x, rem), e = b + per + (x < rem);
+        int64_t work = 0;
+        order.clear();
+        for (int64_t i = b; i < e; ++i) {
+            work += cost(i);
+            order.push_back(i);
+        }
+        // the tail: the first tiles of the range ordered by cost, until they hold the share
+        std::stable_sort(order.begin(), order.end(), [&](int64_t u, int64_t v) { return cost(u) < cost(v); });
+        std::vector<char> tail(e - b, 0);
+        int64_t acc = 0, ntail = 0;
+        for (; ntail < (int64_t)order.size() && 100 * acc < kTailPercent * work; ++ntail) {
+            tail[order[ntail] - b] = 1;
+            acc += cost(order[ntail]);
+        }
+        seq.clear();
+        for (int64_t i = b; i < e; ++i)
+            if (!tail[i - b]) seq.push_back(i);
+        const size_t head = seq.size();
+        seq.insert(seq.end(), order.begin(), order.begin() + ntail);
+        std::stable_sort(seq.begin() + head, seq.end(), [&](int64_t u, int64_t v) { return cost(u) > cost(v); });
+        for (size_t j = 0; j < seq.size(); ++j)
+            std::copy_n(tiles.begin() + 4 * seq[j], 4, out.begin() + 4 * (kX * (int64_t)j + x));
+    }
+    return out;
+}
+
 // Block classes of a stored-block pattern: key = the sorted (uid_a, uid_b)
 // pairs of a block's terms; member tiles of 64 rows (a tail of at most 48
 // members in tiles of 32 and / or 16) and, as a second tile shape, of 32.
@@ -236,6 +283,8 @@ void build_classes(const std::vector<int64_t> &term_ptr, const std::vector<Term>
         if (bc.nblocks - mb > 0) ct.mtiles32.insert(ct.mtiles32.end(), {(int32_t)c, mb, 1, 0});
         ct.classes.push_back(bc);
     }
+    ct.gtiles = xcd_dispatch_table(ct.classes, ct.mtiles);
+    ct.gtiles32 = xcd_dispatch_table(ct.classes, ct.mtiles32);
 }
 
 }  // namespace

@@ -41,6 +41,9 @@ struct ClassTables {
                                         // 16-row groups (1, 2 or 4), 0
     std::vector<int32_t> mtiles32;      // the same with tiles of at most 32 rows
                                         // (groups 1 or 2): a tile shape for batches
+    std::vector<int32_t> gtiles;        // mtiles in the order of a one-workgroup-per-tile
+    std::vector<int32_t> gtiles32;      // launch (slot 8 i + x: the i-th tile run on
+                                        // XCD x; groups 0: an empty slot), and mtiles32
     int32_t max_class_terms = 0;
 };
 

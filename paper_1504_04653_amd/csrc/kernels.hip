@@ -567,8 +567,9 @@ void k_class_f64(ProblemDesc64 pd) {
     __shared__ int32_t sTile[64 * kTileStride];
     __shared__ int32_t sBlk[128];                    // stored block per member row; D-hat source block
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
-    const int item = xcd_contiguous_index();
+    const int item = blockIdx.x;        // pd.mtiles: a dispatch table, slot per workgroup
     const int groups = pd.mtiles[4 * item + 2];
+    if (groups == 0) return;            // an empty slot
     if (groups == 4) class_f64_tile<4, WD>(pd, item, sTile, sBlk, sTerm);
     else if (groups == 2) class_f64_tile<2, WD>(pd, item, sTile, sBlk, sTerm);
     else class_f64_tile<1, WD>(pd, item, sTile, sBlk, sTerm);
@@ -883,6 +884,7 @@ template <bool WD>
 __device__ __forceinline__ void class_f32_item(const ProblemDesc &pd, int item, int32_t *sTile, int32_t *sBlk,
                                                int32_t *sTerm, floatx4 *sW, floatx4 *sU) {
     const int groups = pd.mtiles[4 * item + 2];
+    if (groups == 0) return;            // an empty slot of a dispatch table
     if (groups == 4) class_f32_tile<4, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
     else if (groups == 2) class_f32_tile<2, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
     else class_f32_tile<1, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
@@ -896,7 +898,7 @@ void k_class_f32(ProblemDesc pd) {
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ floatx4 sW[4 * 512];                  // staged W, four buffers
     __shared__ floatx4 sU[4 * 512];                  // staged B_IK values, four buffers
-    class_f32_item<WD>(pd, xcd_contiguous_index(), sTile, sBlk, sTerm, sW, sU);
+    class_f32_item<WD>(pd, blockIdx.x, sTile, sBlk, sTerm, sW, sU);
 }
 
 // ---------------------------------------------------------------------------
@@ -1307,6 +1309,7 @@ template <int NP, bool WD>
 __device__ __forceinline__ void class_bf16_item(const ProblemDescB &pd, int item, int32_t *sTile, int32_t *sBlk,
                                                 int32_t *sTerm, u16x8 *sW, floatx4 *sU) {
     const int groups = pd.mtiles[4 * item + 2];
+    if (groups == 0) return;            // an empty slot of a dispatch table
     if (groups == 4) class_bf16_tile<NP, 4, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
     else if (groups == 2) class_bf16_tile<NP, 2, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
     else class_bf16_tile<NP, 1, WD>(pd, item, sTile, sBlk, sTerm, sW, sU);
@@ -1320,7 +1323,7 @@ void k_class_bf16(ProblemDescB pd) {
     __shared__ int32_t sTerm[2 * kMaxClassTerms];     // unique-block pairs of the class
     __shared__ u16x8 sW[4 * NP * 64 * 4];            // staged W, four buffers
     __shared__ floatx4 sU[4 * 512];                  // staged B_IK values, four buffers
-    class_bf16_item<NP, WD>(pd, xcd_contiguous_index(), sTile, sBlk, sTerm, sW, sU);
+    class_bf16_item<NP, WD>(pd, blockIdx.x, sTile, sBlk, sTerm, sW, sU);
 }
 
 // Many problems in one persistent launch, split BF16 (the queues and their
@@ -1448,10 +1451,12 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
                 hipLaunchKernelGGL(k_batch_f64, dim3((unsigned)b.nworkgroups), dim3(256), 0, st, b.desc64, b.items,
                                    b.qb, b.nq, b.counters);
         } else {
-            for (int p = 0; p < b.nprob; ++p)
-                if (b.nmtiles[p] > 0)
-                    hipLaunchKernelGGL(k_class_f64<false>, dim3((unsigned)b.nmtiles[p]), dim3(256), 0, st,
-                                       b.host_desc64[p]);
+            for (int p = 0; p < b.nprob; ++p) {
+                if (b.ngtiles[p] == 0) continue;
+                ProblemDesc64 d = b.host_desc64[p];
+                d.mtiles = b.gtiles[p];
+                hipLaunchKernelGGL(k_class_f64<false>, dim3((unsigned)b.ngtiles[p]), dim3(256), 0, st, d);
+            }
         }
         return hipGetLastError();
     }
@@ -1478,14 +1483,18 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
         }
     } else {
         for (int p = 0; p < b.nprob; ++p) {
-            if (b.nmtiles[p] == 0) continue;
-            const dim3 g((unsigned)b.nmtiles[p]);
-            if (!bf16)
-                hipLaunchKernelGGL(k_class_f32<false>, g, dim3(512), 0, st, b.host_desc[p]);
-            else if (b.prec == 2)
-                hipLaunchKernelGGL((k_class_bf16<2, false>), g, dim3(512), 0, st, b.host_descb[p]);
-            else
-                hipLaunchKernelGGL((k_class_bf16<3, false>), g, dim3(512), 0, st, b.host_descb[p]);
+            if (b.ngtiles[p] == 0) continue;
+            const dim3 g((unsigned)b.ngtiles[p]);
+            if (!bf16) {
+                ProblemDesc d = b.host_desc[p];
+                d.mtiles = b.gtiles[p];
+                hipLaunchKernelGGL(k_class_f32<false>, g, dim3(512), 0, st, d);
+            } else {
+                ProblemDescB d = b.host_descb[p];
+                d.mtiles = b.gtiles[p];
+                if (b.prec == 2) hipLaunchKernelGGL((k_class_bf16<2, false>), g, dim3(512), 0, st, d);
+                else hipLaunchKernelGGL((k_class_bf16<3, false>), g, dim3(512), 0, st, d);
+            }
         }
     }
     return hipGetLastError();
