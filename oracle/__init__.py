@@ -20,6 +20,9 @@ twogrid    B-hat = Y_2 B Y_1^T between an auxiliary grid and the grid of the
 sht        spherical harmonic synthesis, its transpose and the quadrature
            analysis of Eq. 1 on the SymPix geometry (real orthonormal basis),
            and the N^-1 degrade theta_2 = W_2 Y_2 Y_obs^T theta of Eq. 14.
+precond    the block-Jacobi factor of the system matrix of Section 4.2:
+           Cholesky of every tile's diagonal block of D-hat + B-hat^T N^-1
+           B-hat, and its solve.
 brute      pattern-level brute force without any symmetry reuse (tests only).
 
 Every function is plain and slow on purpose: the point is that a reader can
