@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="lmax3000")
-    ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop", "two_grid", "sht"],
+    ap.add_argument("--op", default="btnb", choices=["btnb", "conv", "two_hop", "two_grid", "sht", "factor"],
                     help="btnb: the D-hat / B-hat^T N^-1 B-hat step (default); conv: the pixel-domain "
                          "convolution g = B-hat f; two_hop: B^T N^-1 B on every nonzero block of the product; "
                          "two_grid: B^T N_2^-1 B with N_2^-1 on an auxiliary grid (--lmax2, default twice); "
@@ -105,18 +105,18 @@ def parse():
     return args
 
 
-def kernels_hash():
-    src = os.path.join(ROOT, "paper_1504_04653_amd", "csrc", "kernels.hip")
+def kernels_hash(source="kernels.hip"):
+    src = os.path.join(ROOT, "paper_1504_04653_amd", "csrc", source)
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def recorded_traffic(mode, config):
+def recorded_traffic(mode, config, source="kernels.hip"):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
-    was taken on the current kernel source (else None)."""
+    was taken on the current source of the kernel (else None)."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
     if not os.path.exists(path):
         return None
-    h = kernels_hash()
+    h = kernels_hash(source)
     for line in open(path):
         m = re.match(r"\|\s*(\S+)\s*\|\s*(\S+)\s*\|\s*(\S+)\s*\|\s*([0-9.eE+]+)\s*\|\s*([0-9.eE+]+)\s*\|", line)
         if m and m.group(1) == mode and m.group(2) == config and m.group(3) == h:
@@ -554,6 +554,114 @@ def run_conv(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_baseline_factor(A, budget_s):
+    """The oracle's Cholesky and solve on host copies of sampled diagonal blocks until the budget is spent."""
+    from oracle import precond as P
+    info = host_info()
+    threads = blas_threads(info)
+    rng = np.random.default_rng(5)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        U, _ = P.cholesky_upper(A[n % len(A)])
+        P.solve_upper_factor(U, rng.standard_normal(A.shape[1]))
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "tiles/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} Cholesky factorisations and solves of 64x64 diagonal blocks A_J = D_JJ + C_JJ "
+                      f"({len(A)} random tiles of the workload, copied from the device), {dt:.1f} s wall",
+            "host": info}
+
+
+def run_factor(args):
+    """Block-Jacobi preconditioner of D-hat + B-hat^T N^-1 B-hat (Section 4.2): a step is one
+    factorisation of every tile's diagonal block and one application to a vector."""
+    import torch
+
+    import paper_1504_04653_amd as sp
+    from workloads import synth as S
+
+    cfg = S.CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    copy_calibration(torch, args.copy_calibration)
+    g = sp.Grid(cfg.lmax, cfg.k)
+    th, ph = g.pixel_theta_phi()
+    ninv = S.ninv_for(cfg, th, ph)
+    b_l, R = S.gaussian_beam(cfg.lmax, g.npix, cfg.fwhm_pix)
+    stream = torch.cuda.current_stream()
+    kb = sp.Kernel(g, b_l, R, stream=stream)
+    kd = sp.Kernel(g, S.prior(cfg.lmax), 0.0, stream=stream)
+    D = torch.empty(g.out_len, dtype=torch.float64, device="cuda")
+    C = torch.empty(g.out_len, dtype=torch.float64, device="cuda")
+    sp.sample_D_BtNB(g, kd, kb, torch.as_tensor(ninv).cuda(), D, C, "fp64", stream=stream)
+    U = torch.empty(g.ntiles * 4096, dtype=torch.float64, device="cuda")
+    info = torch.empty(g.ntiles, dtype=torch.int32, device="cuda")
+    r = torch.as_tensor(np.random.default_rng(2).standard_normal(g.npix)).cuda()
+    x = torch.empty(g.npix, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        sp.factor_diag(g, D, C, U, info, stream=stream)
+        sp.solve_diag(g, U, r, x, stream=stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
+    t_start = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        sp.factor_diag(g, D, C, U, info, stream=stream)
+        ev[2 * i + 1].record(stream)
+        sp.solve_diag(g, U, r, x, stream=stream)
+        ev[2 * i + 2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    f_ms = np.array([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)])
+    s_ms = np.array([ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(args.steps)])
+    ms_step = wall * 1000.0 / args.steps
+    f_bytes = g.ntiles * (3 * 4096 * 8 + 4)            # D_JJ and C_JJ read, U_J written, info
+    s_bytes = g.ntiles * 4096 * 8 + 2 * 8 * g.npix      # U read, r read, x written
+    f_gbs = f_bytes / (f_ms.mean() * 1e-3) / 1e9
+    s_gbs = s_bytes / (s_ms.mean() * 1e-3) / 1e9
+    info_h = info.cpu().numpy()
+    tiles_b, _, _ = g.bands()
+    band_of = np.repeat(np.arange(len(tiles_b)), tiles_b)
+    failed_bands = sorted(set(band_of[info_h > 0].tolist()))
+    print(f"# factor {args.config}: lmax={cfg.lmax} tiles={g.ntiles}; factor {f_ms.mean():.3f} ms "
+          f"({f_gbs:.0f} GB/s), solve {s_ms.mean():.3f} ms ({s_gbs:.0f} GB/s); step {ms_step:.3f} ms; "
+          f"failed pivots {int((info_h > 0).sum())} in bands {failed_bands[:10]}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "block-Jacobi factor and solve of D-hat + B-hat^T N^-1 B-hat, tiles/s",
+        "value": g.ntiles / (ms_step * 1e-3),
+        "unit": "tiles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"sympix lmax={cfg.lmax} k={cfg.k}: FP64 D-hat (prior (l+1)^2) and B-hat^T N^-1 "
+                               f"B-hat (beam FWHM {cfg.fwhm_pix:g} px, N^-1 {cfg.ninv_kind} seed {cfg.seed}) "
+                               f"diagonal blocks; r ~ N(0,1) seed 2",
+                   "lmax": cfg.lmax, "ntiles": g.ntiles, "npix": g.npix},
+        "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK, "achieved": f_gbs,
+                     "frac": f_gbs / HBM_PEAK, "kernel": "k_factor_diag",
+                     "traffic": recorded_traffic("factor", args.config, "precond.hip")},
+        "factor_ms": float(f_ms.mean()),
+        "solve": {"ms": float(s_ms.mean()), "kernel": "k_solve_diag", "achieved_GBs": s_gbs,
+                  "frac": s_gbs / HBM_PEAK, "traffic": recorded_traffic("solve", args.config, "precond.hip")},
+        "failed_pivots": int((info_h > 0).sum()),
+        "failed_bands": failed_bands,
+    }
+    if not args.no_cpu_baseline:
+        brp, _ = g.blocks()
+        pick = np.random.default_rng(4).choice(g.ntiles, 256, replace=False)
+        pick = pick[info_h[pick] == 0]
+        idx = torch.as_tensor(brp[pick], device="cuda")
+        A = (D.view(-1, 64, 64)[idx] + C.view(-1, 64, 64)[idx]).cpu().numpy()
+        line["cpu_baseline"] = cpu_baseline_factor(A, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def sht_terms(nrings, L):
     """(degree, order, ring) triples of one Legendre pass: nrings (L+1)(L+2)/2."""
     return nrings * (L + 1) * (L + 2) // 2
@@ -850,6 +958,9 @@ def main():
         return
     if args.op == "sht":
         run_sht(args)
+        return
+    if args.op == "factor":
+        run_factor(args)
         return
     import torch
 

@@ -271,6 +271,40 @@ sympix_status sympix_sample_D_BtNB(const sympix_grid *g, const sympix_kernel *d,
                                    const double *ninv_dev, int64_t ninv_len, int32_t prec, double *outD_dev,
                                    int64_t outD_len, double *outC_dev, int64_t outC_len, void *stream);
 
+/* ---- Block-Jacobi factor of the system matrix (Section 4.2) --------------------
+ * Section 4.2 solves with the matrix D-hat + B-hat^T N^-1 B-hat, and the local
+ * blocks exist to build preconditioners or smoothers for its iterative
+ * solution.  These two calls build and apply the block-Jacobi one: per tile
+ * J the diagonal block A_J = D_JJ + C_JJ, its Cholesky factor, and
+ * x_J = A_J^-1 r_J.  Device kernels for k = 8. */
+
+/* For every tile J: A_J = D_JJ + C_JJ from the stored blocks (J, J) of D_dev
+ * (sympix_sample_D layout) and C_dev (sympix_sample_BtNB layout; NULL with
+ * C_len 0 factors D_JJ alone), both device float64 of nblocks k^4 values.
+ * Only the upper triangle of A_J is read.  U_dev (device float64, ntiles k^4
+ * values, tile J's block at J k^4) receives the upper triangular U_J with
+ * A_J = U_J^T U_J, row-major, zeros below the diagonal; info_dev (device
+ * int32, ntiles values) receives 0, or j + 1 when the pivot of row j is not
+ * positive (A_J is not numerically positive definite; U_J is then
+ * unspecified).  Pivots are scaled by their reciprocal.  Buffers 16-byte
+ * aligned (info 4-byte), outputs not overlapping any other buffer.
+ * Errors: EINVAL (NULL, misalignment, overlap), ESIZE (lengths), EUNSUPPORTED
+ * (k != 8), EHIP. */
+sympix_status sympix_factor_diag(const sympix_grid *g, const double *D_dev, int64_t D_len, const double *C_dev,
+                                 int64_t C_len, double *U_dev, int64_t U_len, int32_t *info_dev, int64_t info_len,
+                                 void *stream);
+
+/* x_J = A_J^-1 r_J = (U_J^T U_J)^-1 r_J for every tile J (forward then back
+ * substitution), with U_dev from sympix_factor_diag (ntiles k^4 values) and
+ * r_dev, x_dev device float64 of npix values in pixel order (tile J owns
+ * pixels [J k^2, (J+1) k^2)).  x_dev may be r_dev itself (in place) but may
+ * not overlap it otherwise, nor U_dev.  Tiles whose factor failed give
+ * unspecified values.
+ * Errors: EINVAL (NULL, misalignment, overlap), ESIZE (lengths), EUNSUPPORTED
+ * (k != 8), EHIP. */
+sympix_status sympix_solve_diag(const sympix_grid *g, const double *U_dev, int64_t U_len, const double *r_dev,
+                                int64_t r_len, double *x_dev, int64_t x_len, void *stream);
+
 /* ---- Two grids: B-hat = Y_2 B Y_1^T (Eqs. 13 and 16) --------------------------
  * Eq. 13 moves N^-1 onto an auxiliary SymPix grid Y_2, which may differ from
  * the grid Y_1 of the unknowns (Section 4.2: with Y_2 at twice the band limit

@@ -84,6 +84,8 @@ _sample_BtNB_noalloc = _sig("sympix_sample_BtNB_noalloc", [_vp, _vp, _vp, _i64, 
 _sample_BtNB_pattern = _sig("sympix_sample_BtNB_pattern", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _i64, _vp])
 _sample_D_BtNB = _sig("sympix_sample_D_BtNB", [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp, _i64, _vp])
 _convolve = _sig("sympix_convolve", [_vp, _vp, _vp, _i64, _vp, _i64, _vp])
+_factor_diag = _sig("sympix_factor_diag", [_vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp])
+_solve_diag = _sig("sympix_solve_diag", [_vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp])
 _last_error = _sig("sympix_last_error", [], ctypes.c_char_p)
 
 
@@ -138,7 +140,7 @@ def plan_name(plan):
 EXPORTED = ("sympix_grid_create", "sympix_grid_destroy", "sympix_grid_dims", "sympix_grid_rings",
             "sympix_grid_bands", "sympix_grid_pixels", "sympix_grid_neighbours", "sympix_grid_blocks", "sympix_grid_pattern_blocks", "sympix_grid_unique",
             "sympix_kernel_tabulate", "sympix_kernel_destroy", "sympix_kernel_eval", "sympix_sample_D",
-            "sympix_sample_BtNB", "sympix_sample_BtNB_noalloc", "sympix_sample_BtNB_pattern", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
+            "sympix_sample_BtNB", "sympix_sample_BtNB_noalloc", "sympix_sample_BtNB_pattern", "sympix_sample_D_BtNB", "sympix_convolve", "sympix_factor_diag", "sympix_solve_diag", "sympix_batch_create", "sympix_batch_set_schedule", "sympix_batch_set_tiling", "sympix_batch_tune",
             "sympix_batch_launch", "sympix_batch_plan", "sympix_batch_destroy", "sympix_last_error",
             "sympix_cross_create", "sympix_cross_destroy", "sympix_cross_dims", "sympix_cross_neighbours",
             "sympix_cross_unique", "sympix_kernel_tabulate_cross", "sympix_sample_B_cross", "sympix_sample_BtNB_cross",
@@ -368,6 +370,31 @@ def convolve(grid: Grid, kernel: Kernel, f, out, stream=None):
     _require_f64_device(out, "out")
     _check(_convolve(grid.handle, kernel.handle, _ptr(f), _numel(f), _ptr(out), _numel(out), _stream(stream)))
     return out
+
+
+def factor_diag(grid: Grid, D, C, U, info, stream=None):
+    """U_J with U_J^T U_J = D_JJ + C_JJ for every tile J (C None: D_JJ alone),
+    into U (ntiles k^4 float64) and info (ntiles int32: 0, or the failing
+    pivot row + 1)."""
+    import torch
+    _require_f64_device(D, "D")
+    if C is not None:
+        _require_f64_device(C, "C")
+    _require_f64_device(U, "U")
+    if not (isinstance(info, torch.Tensor) and info.is_cuda and info.dtype == torch.int32 and info.is_contiguous()):
+        raise TypeError("info must be a contiguous int32 CUDA tensor")
+    _check(_factor_diag(grid.handle, _ptr(D), _numel(D), None if C is None else _ptr(C), 0 if C is None else _numel(C),
+                        _ptr(U), _numel(U), _ptr(info), _numel(info), _stream(stream)))
+    return U, info
+
+
+def solve_diag(grid: Grid, U, r, x, stream=None):
+    """x_J = (U_J^T U_J)^-1 r_J for every tile (x may be r)."""
+    _require_f64_device(U, "U")
+    _require_f64_device(r, "r")
+    _require_f64_device(x, "x")
+    _check(_solve_diag(grid.handle, _ptr(U), _numel(U), _ptr(r), _numel(r), _ptr(x), _numel(x), _stream(stream)))
+    return x
 
 
 class Cross:

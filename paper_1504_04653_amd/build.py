@@ -34,14 +34,16 @@ def build(verbose: bool = False) -> str:
     geo_o = os.path.join(BUILD, "geometry.o")
     ker_o = os.path.join(BUILD, "kernels.o")
     sht_o = os.path.join(BUILD, "sht.o")
+    pre_o = os.path.join(BUILD, "precond.o")
     api_o = os.path.join(BUILD, "api.o")
     _run(["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra",
           "-c", os.path.join(CSRC, "geometry.cpp"), "-o", geo_o], verbose)
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", ker_o], verbose)
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "sht.hip"), "-o", sht_o], verbose)
+    _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "precond.hip"), "-o", pre_o], verbose)
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "api.cpp"), "-o", api_o], verbose)
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, geo_o, ker_o, sht_o, api_o], verbose)
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, geo_o, ker_o, sht_o, pre_o, api_o], verbose)
     shutil.move(tmp, LIB)
     return LIB
 

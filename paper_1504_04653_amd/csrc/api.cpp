@@ -20,6 +20,7 @@
 #include "../../include/sympix.h"
 #include "device.hpp"
 #include "geometry.hpp"
+#include "precond.hpp"
 #include "sht.hpp"
 
 using sympix::Geometry;
@@ -87,6 +88,7 @@ struct DevGrid {
     int32_t *gtiles32 = nullptr;
     int32_t *conv_chunks = nullptr;
     int32_t *conv_slots = nullptr;
+    int32_t *diag_blk = nullptr;        // per tile: its stored block (J, J)
 };
 
 template <class T>
@@ -115,6 +117,7 @@ void free_dev(DevGrid &d) {
     hipFree(d.gtiles32);
     hipFree(d.conv_chunks);
     hipFree(d.conv_slots);
+    hipFree(d.diag_blk);
     d = DevGrid();
 }
 
@@ -211,6 +214,9 @@ sympix_status device_tables(const sympix_grid *g, int device, const DevGrid **ou
     if (e == hipSuccess) e = upload(&d.gtiles32, geo.cls.gtiles32.data(), geo.cls.gtiles32.size());
     if (e == hipSuccess) e = upload(&d.conv_chunks, geo.conv_chunks.data(), geo.conv_chunks.size());
     if (e == hipSuccess) e = upload(&d.conv_slots, geo.conv_slots.data(), geo.conv_slots.size());
+    std::vector<int32_t> diag(geo.ntiles);
+    for (int64_t J = 0; J < geo.ntiles; ++J) diag[J] = (int32_t)geo.blk_ptr[J];   // K ascending from K = J
+    if (e == hipSuccess) e = upload(&d.diag_blk, diag.data(), diag.size());
     if (e != hipSuccess) {
         free_dev(d);
         return e == hipErrorOutOfMemory ? fail(SYMPIX_ENOMEM, "device allocation for grid tables failed")
@@ -732,6 +738,56 @@ sympix_status sympix_sample_D(const sympix_grid *g, const sympix_kernel *d, doub
     hipStream_t st = (hipStream_t)stream;
     return after_launch(sympix::launch_expand(d->u64, dg->exp_items, (int64_t)geo.exp_items.size() / 4, dg->exp_blk, out_dev, st), st,
                         "sample_D");
+}
+
+sympix_status sympix_factor_diag(const sympix_grid *g, const double *D_dev, int64_t D_len, const double *C_dev,
+                                 int64_t C_len, double *U_dev, int64_t U_len, int32_t *info_dev, int64_t info_len,
+                                 void *stream) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const Geometry &geo = g->geo;
+    if (geo.k != 8) return fail(SYMPIX_EUNSUPPORTED, "device kernels are built for k = 8");
+    const int64_t nb = geo.nblocks() * sympix::kBlockElems, nu = geo.ntiles * sympix::kBlockElems;
+    if (D_len != nb || (C_dev ? C_len != nb : C_len != 0) || U_len != nu || info_len != geo.ntiles)
+        return fail(SYMPIX_ESIZE, "D_len and C_len must be nblocks * k^4 (C_len 0 without C), U_len ntiles * k^4, "
+                                  "info_len ntiles");
+    if (geo.ntiles > 0 && (!D_dev || !U_dev || !info_dev)) return fail(SYMPIX_EINVAL, "NULL device buffer");
+    if (((uintptr_t)D_dev) % 16 || ((uintptr_t)C_dev) % 16 || ((uintptr_t)U_dev) % 16 || ((uintptr_t)info_dev) % 4)
+        return fail(SYMPIX_EINVAL, "misaligned device buffer");
+    auto overlaps = [](const void *a, int64_t na, const void *b, int64_t nb2) {
+        return a && b && (const char *)a < (const char *)b + nb2 && (const char *)b < (const char *)a + na;
+    };
+    const int64_t bU = U_len * 8, bI = info_len * 4;
+    if (overlaps(U_dev, bU, D_dev, D_len * 8) || overlaps(U_dev, bU, C_dev, C_len * 8) ||
+        overlaps(info_dev, bI, D_dev, D_len * 8) || overlaps(info_dev, bI, C_dev, C_len * 8) ||
+        overlaps(info_dev, bI, U_dev, bU))
+        return fail(SYMPIX_EINVAL, "an output overlaps another buffer");
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const DevGrid *dg = nullptr;
+    sympix_status s = device_tables(g, device, &dg);
+    if (s != SYMPIX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    return after_launch(sympix::launch_factor_diag(D_dev, C_dev, dg->diag_blk, geo.ntiles, U_dev, info_dev, st), st,
+                        "factor_diag");
+}
+
+sympix_status sympix_solve_diag(const sympix_grid *g, const double *U_dev, int64_t U_len, const double *r_dev,
+                                int64_t r_len, double *x_dev, int64_t x_len, void *stream) {
+    if (!g) return fail(SYMPIX_EINVAL, "NULL grid");
+    const Geometry &geo = g->geo;
+    if (geo.k != 8) return fail(SYMPIX_EUNSUPPORTED, "device kernels are built for k = 8");
+    if (U_len != geo.ntiles * sympix::kBlockElems || r_len != geo.npix || x_len != geo.npix)
+        return fail(SYMPIX_ESIZE, "U_len must be ntiles * k^4, r_len and x_len npix");
+    if (geo.ntiles > 0 && (!U_dev || !r_dev || !x_dev)) return fail(SYMPIX_EINVAL, "NULL device buffer");
+    if (((uintptr_t)U_dev) % 16 || ((uintptr_t)r_dev) % 16 || ((uintptr_t)x_dev) % 16)
+        return fail(SYMPIX_EINVAL, "misaligned device buffer");
+    if (x_dev != r_dev && x_dev && r_dev && r_dev < x_dev + x_len && x_dev < r_dev + r_len)
+        return fail(SYMPIX_EINVAL, "x_dev overlaps r_dev without being it");
+    if (x_dev && U_dev && (const double *)x_dev < U_dev + U_len && U_dev < (const double *)x_dev + x_len)
+        return fail(SYMPIX_EINVAL, "x_dev overlaps U_dev");
+    hipStream_t st = (hipStream_t)stream;
+    return after_launch(sympix::launch_solve_diag(U_dev, r_dev, x_dev, geo.ntiles, st), st, "solve_diag");
 }
 
 sympix_status sympix_convolve(const sympix_grid *g, const sympix_kernel *b, const double *f_dev,

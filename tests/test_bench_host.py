@@ -44,7 +44,7 @@ def test_traffic_rows_count_only_for_the_current_kernel_source(tmp_path, monkeyp
         f"| bf16x6 | lmax3000 | {h} | 1.0e+08 | 2.0e+09 |\n"
         f"| fp64 | lmax3000 | 0000000000000000 | 5.0e+08 | 6.0e+09 |\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernels_hash", lambda: h)
+    monkeypatch.setattr(bench, "kernels_hash", lambda source="kernels.hip": h)
     assert bench.recorded_traffic("bf16x6", "lmax3000") == pytest.approx(2.1e9)
     assert bench.recorded_traffic("fp64", "lmax3000") is None        # taken on another source
     assert bench.recorded_traffic("bf16x6", "batch32") is None      # no row

@@ -26,10 +26,10 @@ FLAGS = ["-std=c++17", "-O1", "-g", "-fPIC", "--offload-arch=gfx950",
 def test_host_abi_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     if not (os.path.exists(HIPCC) or shutil.which("hipcc")):
         pytest.skip("hipcc not available")
-    srcs = [os.path.join(CSRC, "geometry.cpp"), os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "sht.hip"),
+    srcs = [os.path.join(CSRC, "geometry.cpp"), os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "sht.hip"), os.path.join(CSRC, "precond.hip"),
             os.path.join(ROOT, "tests", "sanitize", "abi_host_check.cpp")]
     objs, procs = [], []
-    for src in srcs:                     # the five compilations run side by side
+    for src in srcs:                     # the compilations run side by side
         obj = str(tmp_path / (os.path.basename(src) + ".o"))
         procs.append(subprocess.Popen([HIPCC, *FLAGS, *SAN, "-c", src, "-o", obj], stdout=subprocess.PIPE,
                                       stderr=subprocess.PIPE, text=True))
