@@ -142,6 +142,24 @@ int main() {
     unsetenv("SYMPIX_FAIL_ALLOC");
     CHECK(sympix_sht_synthesis(nullptr, nullptr, 0, nullptr, 0, nullptr) == SYMPIX_EINVAL);
     CHECK(sympix_sht_degrade(nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr) == SYMPIX_EINVAL);
+    // block-Jacobi factor and solve: argument checks come before any device call
+    {
+        sympix_dims da;
+        CHECK(sympix_grid_dims(a, &da) == SYMPIX_OK);
+        const int64_t nb = da.nblocks * 4096, nu = da.ntiles * 4096;
+        double *fake = (double *)0x1000;   // never dereferenced: every call below fails its checks
+        int32_t *ifake = (int32_t *)0x1000;
+        CHECK(sympix_factor_diag(nullptr, fake, nb, nullptr, 0, fake, nu, ifake, da.ntiles, nullptr) == SYMPIX_EINVAL);
+        CHECK(sympix_factor_diag(a, fake, nb - 1, nullptr, 0, fake, nu, ifake, da.ntiles, nullptr) == SYMPIX_ESIZE);
+        CHECK(sympix_factor_diag(a, fake, nb, nullptr, nb, fake, nu, ifake, da.ntiles, nullptr) == SYMPIX_ESIZE);
+        CHECK(sympix_factor_diag(a, fake, nb, fake, nb, fake, nu, ifake, da.ntiles + 1, nullptr) == SYMPIX_ESIZE);
+        CHECK(sympix_factor_diag(a, nullptr, nb, nullptr, 0, fake, nu, ifake, da.ntiles, nullptr) == SYMPIX_EINVAL);
+        CHECK(sympix_factor_diag(b, fake, 0, nullptr, 0, fake, 0, ifake, 0, nullptr) == SYMPIX_EUNSUPPORTED);
+        CHECK(sympix_solve_diag(nullptr, fake, nu, fake, da.npix, fake, da.npix, nullptr) == SYMPIX_EINVAL);
+        CHECK(sympix_solve_diag(a, fake, nu, fake, da.npix - 1, fake, da.npix, nullptr) == SYMPIX_ESIZE);
+        CHECK(sympix_solve_diag(a, fake, nu, fake, da.npix, fake + 8, da.npix, nullptr) == SYMPIX_EINVAL);
+        CHECK(sympix_solve_diag(b, fake, 0, fake, 0, fake, 0, nullptr) == SYMPIX_EUNSUPPORTED);
+    }
     sympix_sht_destroy(nullptr);
     sympix_grid_destroy(a);
     sympix_grid_destroy(b);
