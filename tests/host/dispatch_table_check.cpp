@@ -1,6 +1,7 @@
 // Host check of the class-grid dispatch tables (geometry only, no device):
 // for grids of several sizes, the two-hop pattern and a two-grid pair, each
-// table holds every member tile exactly once plus empty slots; slot 8 i + x is
+// table holds every member tile exactly once.  Below 32 tiles per CU it is all
+// tiles largest first; above, plus empty slots: slot 8 i + x is
 // XCD x's i-th tile; XCD x runs the x-th of 8 contiguous class-order ranges of
 // equal count (the first n mod 8 one longer); each range runs in class order
 // but for its smallest tiles by (nterms + 1) x groups, the fewest that hold 15%
@@ -31,7 +32,6 @@ static int failures = 0;
 static void check_table(const char *what, const ClassTables &ct, const std::vector<int32_t> &tiles,
                         const std::vector<int32_t> &table) {
     const int64_t n = (int64_t)tiles.size() / 4;
-    CHECK(table.size() % 32 == 0);
     std::map<std::array<int32_t, 4>, int64_t> pos;   // tile -> index in class order
     for (int64_t i = 0; i < n; ++i) {
         std::array<int32_t, 4> t{tiles[4 * i], tiles[4 * i + 1], tiles[4 * i + 2], tiles[4 * i + 3]};
@@ -41,6 +41,23 @@ static void check_table(const char *what, const ClassTables &ct, const std::vect
     auto cost = [&](int64_t i) { return (int64_t)(ct.classes[tiles[4 * i]].nterms + 1) * tiles[4 * i + 2]; };
     const int64_t slots = (int64_t)table.size() / 4;
     std::vector<int> seen(n, 0);
+    if (n < 32 * 256) {                  // short launches: every tile once, largest first, ties in class order
+        CHECK(slots == n);
+        int64_t prev = -1;
+        for (int64_t s = 0; s < slots; ++s) {
+            std::array<int32_t, 4> t{table[4 * s], table[4 * s + 1], table[4 * s + 2], table[4 * s + 3]};
+            auto it = pos.find(t);
+            CHECK(it != pos.end());
+            if (it == pos.end()) return;
+            const int64_t i = it->second;
+            ++seen[i];
+            if (prev >= 0) CHECK(cost(prev) > cost(i) || (cost(prev) == cost(i) && prev < i));
+            prev = i;
+        }
+        for (int64_t i = 0; i < n; ++i) CHECK(seen[i] == 1);
+        return;
+    }
+    CHECK(table.size() % 32 == 0);
     const int64_t per = n / 8, rem = n % 8;
     CHECK(slots == 8 * (per + (rem > 0)));
     int64_t next = 0;                    // first class-order index of the next range
@@ -107,7 +124,9 @@ static void check_classes(const char *what, const ClassTables &ct) {
 }
 
 int main() {
-    const int sizes[][2] = {{1, 8}, {7, 8}, {16, 8}, {64, 8}, {256, 8}, {512, 8}, {1500, 8}, {40, 4}, {30, 3}};
+    const int sizes[][2] = {{1, 8}, {7, 8}, {16, 8}, {64, 8}, {256, 8}, {512, 8}, {1500, 8}, {2048, 8}, {3000, 8},
+                            {40, 4}, {30, 3}};
+    int64_t long_tables = 0;
     for (auto &sz : sizes) {
         Geometry g;
         std::string err;
@@ -117,6 +136,7 @@ int main() {
             return 1;
         }
         check_classes(what.c_str(), g.cls);
+        long_tables += (g.cls.mtiles.size() / 4 >= 32 * 256) + (g.cls.mtiles32.size() / 4 >= 32 * 256);
         if (sz[0] == 64 || sz[0] == 256) {
             Pattern p;
             if (build_two_hop(g, p, err) != 0) return 1;
@@ -127,6 +147,10 @@ int main() {
             if (build_cross(g2, g, x, err) != 0) return 1;
             check_classes((what + " cross").c_str(), x.cls);
         }
+    }
+    if (long_tables < 2) {
+        std::fprintf(stderr, "dispatch_table_check: the per-XCD layout was not exercised\n");
+        ++failures;
     }
     if (failures) {
         std::fprintf(stderr, "dispatch_table_check: %d failed checks\n", failures);
