@@ -33,9 +33,14 @@ kernel and samples B^T N^-1 B on the two-hop pattern (every nonzero block of
 the product), in the first of --modes.  With --op two_grid a step tabulates
 the beam kernel between the configuration's grid Y_1 and an auxiliary grid Y_2
 (--lmax2, default twice lmax) and samples B^T N_2^-1 B with N_2^-1 on Y_2.
+With --op sht a step is one synthesis and one analysis at L = lmax.  With
+--op factor the FP64 operators come from one combined call before the timed
+region, and a step factors every tile's diagonal block of
+D-hat + B^T N^-1 B (Cholesky) and applies the block-Jacobi solve once.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config lmax3000|batch32]
-                       [--op btnb|conv|two_hop|two_grid] [--lmax2 L] [--modes fp64,bf16x6,fp32,bf16x3]
+                       [--op btnb|conv|two_hop|two_grid|sht|factor] [--lmax2 L]
+                       [--modes fp64,bf16x6,fp32,bf16x3]
                        [--no-cpu-baseline] [--no-batch-compare]
 """
 from __future__ import annotations
