@@ -49,7 +49,7 @@ typedef enum {
     SYMPIX_ENOMEM = -3,      /* host or device allocation failed */
     SYMPIX_EHIP = -4,        /* a HIP runtime call or kernel launch failed */
     SYMPIX_ESIZE = -5,       /* an output or input length does not match the grid */
-    SYMPIX_EUNSUPPORTED = -6 /* valid request this build does not implement (see message) */
+    SYMPIX_EUNSUPPORTED = -6 /* valid request this library does not implement (see message) */
 } sympix_status;
 
 typedef enum {

@@ -3,7 +3,7 @@
 (oracle.sht): every pixel and coefficient on small grids (several tile sizes,
 band limits below and at the grid's lmax), the degrade between two grids,
 sampled rings at lmax 512, and at the full sizes (lmax 1500 and 3000) the
-properties that hold at any size: analysis inverts synthesis on this build's
+properties that hold at any size: analysis inverts synthesis on this library's
 grids (to the level the oracle shows at lmax 128 and 512) and Y^T is the
 transpose of Y (<Y a, f> = <a, Y^T f>)."""
 import sys
@@ -283,7 +283,7 @@ def test_plans_sharing_a_ring_kernel():
 
 @pytest.mark.parametrize("lmax", [511, 639, 767])
 def test_table1_round_trip_on_this_grid(lmax):
-    """Table 1's experiment (Section 3.3) on this build's grids: 100 draws of
+    """Table 1's experiment (Section 3.3) on this library's grids: 100 draws of
     unit-Gaussian a_lm at L = lmax, synthesis then analysis, max and mean
     |a_hat - a|.  These grids keep every polar sample the analysis needs (7-15%
     more pixels than Table 1 prints), so the round trip is exact to rounding,

@@ -222,7 +222,7 @@ def test_grid_readings_record_is_reproduced():
     """tests/golden/table1_npix.txt is what make_grid_readings.py (oracle only)
     writes: every reading's grid size at the paper's margin for the five
     printed cases (Table 1, Sections 3.1 and 3.2), recomputed here in full;
-    the margin scan recomputed for the build's reading and three others; and
+    the margin scan recomputed for the reading used here and three others; and
     its conclusion: no reading reproduces Table 1 at any one margin."""
     mod = _readings_script()
     rec = mod.parse(mod.OUT)
@@ -244,7 +244,7 @@ def test_grid_readings_record_is_reproduced():
 
 
 def test_build_reading_overshoots_every_printed_grid_size():
-    """The build's reading (Fig. 3 literally, band 1 free) gives grids 13.2%,
+    """The reading used here (Fig. 3 literally, band 1 free) gives grids 13.2%,
     10.5% and 9.6% larger than Table 1's, 7.2% larger than Section 3.1's 5.6e6
     and 11.5% larger than Section 3.2's 780,000; these are recorded, not
     pinned (parity unpinned for the tile programme against the printed

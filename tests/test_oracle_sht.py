@@ -144,7 +144,7 @@ def test_adjoint_is_the_transpose_of_synthesis():
 
 def test_polar_cut_keeps_the_round_trip_exact():
     """The polar rings of a SymPix grid hold fewer than 2 L + 1 pixels, but the
-    cut of Eq. 3 only drops modes that are negligible there: on this build's
+    cut of Eq. 3 only drops modes that are negligible there: on this library's
     grid analysis after synthesis still returns the coefficients to ~1e-13 at
     L = lmax (the paper's Table 1 reports 7.8e-3 for its own, smaller grids)."""
     g = G.make_grid(128, 8)
