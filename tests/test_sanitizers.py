@@ -1,7 +1,7 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only):
 the library's sources are compiled with the sanitizers on their host part
-(device code is built as usual and never launched), linked with the driver
-tests/sanitize/abi_host_check.cpp, and run with leak detection on.  The driver
+(device code is built as usual and never launched), linked with the test program
+tests/sanitize/abi_host_check.cpp, and run with leak detection on.  The program
 creates grids of many sizes and tile sizes, fills every layout query into
 buffers of exactly the reported sizes, builds the two-hop pattern and
 two-grid pairs, and walks the argument-error and injected allocation-failure
