@@ -532,6 +532,21 @@ int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::str
                     g.conv_chunks.insert(g.conv_chunks.end(), {J0, n, slot0, (int32_t)(slots.size() / (1 + kConvTiles))});
                 }
             }
+            // The launch gives workgroup w the chunk (w mod 8) per + min(w mod 8, rem) + w / 8
+            // (an XCD-contiguous map); place the chunks so that the workgroups, dispatched in
+            // order, take them largest first (slots, stable): the last chunks of every CU are
+            // then the small ones
+            const int64_t nc = (int64_t)g.conv_chunks.size() / 4, per = nc / 8, rem = nc % 8;
+            std::vector<int64_t> order(nc);
+            for (int64_t i = 0; i < nc; ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int64_t a, int64_t b) { return g.conv_chunks[4 * a + 3] > g.conv_chunks[4 * b + 3]; });
+            std::vector<int32_t> placed(g.conv_chunks.size());
+            for (int64_t w = 0; w < nc; ++w) {
+                const int64_t x = w & 7, i = w >> 3, ch = x * per + std::min(x, rem) + i;
+                std::copy_n(g.conv_chunks.begin() + 4 * order[w], 4, placed.begin() + 4 * ch);
+            }
+            g.conv_chunks.swap(placed);
         }
 
         build_classes(g.term_ptr, g.terms, g.cls);

@@ -107,7 +107,8 @@ struct Geometry {
     // convolution g = B-hat f: chunks of up to kConvTiles consecutive output
     // tiles of one band {first tile, tiles, first slot, slots}; per slot a
     // unique block and, for each tile, the input tile K it multiplies (-1: none)
-    std::vector<int32_t> conv_chunks;   // 4 per chunk
+    std::vector<int32_t> conv_chunks;   // 4 per chunk, placed so that the launch's
+                                        // workgroups take them largest first
     std::vector<int32_t> conv_slots;    // 1 + kConvTiles per slot: uid, K[]
 
     double y_pattern_max = 0.0;   // max 1 - cos(gamma) over all pattern pairs

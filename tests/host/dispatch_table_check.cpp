@@ -136,6 +136,25 @@ int main() {
             return 1;
         }
         check_classes(what.c_str(), g.cls);
+        {   // convolution chunks: every tile in exactly one chunk of its band; workgroups in
+            // dispatch order take them largest first
+            const char *w = what.c_str();
+            const int64_t nc = (int64_t)g.conv_chunks.size() / 4, per = nc / 8, rem = nc % 8;
+            std::vector<int> covered(g.ntiles, 0);
+            int64_t prev = -1;
+            for (int64_t wg = 0; wg < nc; ++wg) {
+                const int64_t x = wg & 7, i = wg >> 3, ch = x * per + std::min(x, rem) + i;
+                const int32_t *c = &g.conv_chunks[4 * ch];
+                for (int32_t t = 0; t < c[1]; ++t) ++covered[c[0] + t];
+                if (prev >= 0) {
+                    const char *what = w;
+                    CHECK(c[3] <= prev);
+                }
+                prev = c[3];
+            }
+            const char *what = w;
+            for (int64_t J = 0; J < g.ntiles; ++J) CHECK(covered[J] == 1);
+        }
         long_tables += (g.cls.mtiles.size() / 4 >= 32 * 256) + (g.cls.mtiles32.size() / 4 >= 32 * 256);
         if (sz[0] == 64 || sz[0] == 256) {
             Pattern p;

@@ -3,7 +3,8 @@ geometry sources are compiled with g++ together with
 tests/host/dispatch_table_check.cpp, which builds grids, a two-hop pattern
 and a two-grid pair and checks every table: each member tile once, slot
 8 i + x the i-th tile of XCD x, contiguous class-order ranges of equal work
-run largest first, empty slots only at the ends."""
+run largest first, empty slots only at the ends; and the convolution chunks,
+which cover every tile once and reach the workgroups largest first."""
 import os
 import shutil
 import subprocess
