@@ -9,7 +9,13 @@
  *   - the local part of D-hat = Y D Y^T and B-hat = Y B Y^T (Eq. 16): elements
  *     between pixels in the same or in neighbouring tiles (Section 4.2);
  *   - the matching blocks of B-hat^T N^-1 B-hat for a diagonal pixel-space N^-1
- *     (Eq. 15).
+ *     (Eq. 15), also on the two-hop pattern and with N^-1 on a second grid
+ *     (Eq. 13);
+ *   - the pixel-domain convolution B-hat f (Section 4.1);
+ *   - spherical harmonic synthesis, its transpose, analysis (Eq. 1) and the
+ *     N^-1 degrade of Eq. 14 on the SymPix geometry;
+ *   - the block-Jacobi factor of D-hat + B-hat^T N^-1 B-hat and its solve
+ *     (Section 4.2's system matrix).
  *
  * Conventions shared by every call
  * --------------------------------
