@@ -664,6 +664,26 @@ def run_factor(args):
         idx = torch.as_tensor(brp[pick], device="cuda")
         A = (D.view(-1, 64, 64)[idx] + C.view(-1, 64, 64)[idx]).cpu().numpy()
         line["cpu_baseline"] = cpu_baseline_factor(A, args.cpu_seconds)
+        # the last timed outputs of the same tiles against the oracle (outside the timed region):
+        # the GPU factor's backward error, and both factors and solves relative to kappa(A_J)
+        from oracle import precond as P
+        Ug = U.view(-1, 64, 64)[torch.as_tensor(pick, device="cuda")].cpu().numpy()
+        xg = x.view(-1, 64)[torch.as_tensor(pick, device="cuda")].cpu().numpy()
+        rh = r.view(-1, 64)[torch.as_tensor(pick, device="cuda")].cpu().numpy()
+        back = fwd = sol = 0.0
+        for n in range(len(pick)):
+            a = np.triu(A[n]) + np.triu(A[n], 1).T
+            ev = np.linalg.eigvalsh(a)
+            kappa = ev[-1] / ev[0]
+            Uo, _ = P.cholesky_upper(A[n])
+            back = max(back, np.abs(Ug[n].T @ Ug[n] - a).max() / np.abs(a).max())
+            fwd = max(fwd, np.abs(Ug[n] - Uo).max() / np.abs(Uo).max() / kappa)
+            xo = P.solve_upper_factor(Uo, rh[n])
+            sol = max(sol, np.abs(xg[n] - xo).max() / np.abs(xo).max() / kappa)
+        line["error_vs_oracle"] = {"tiles": int(len(pick)), "factor_backward": back, "factor_forward_over_kappa": fwd,
+                                   "solve_over_kappa": sol, "bound_backward": 4 * 64 * 2.0 ** -52}
+        print(f"# factor gate on {len(pick)} tiles: backward {back:.2e} (bound {4 * 64 * 2.0 ** -52:.1e}), "
+              f"factor/kappa {fwd:.2e}, solve/kappa {sol:.2e}", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
