@@ -487,16 +487,18 @@ def cpu_baseline_conv(cfg, budget_s):
     t0 = time.perf_counter()
     ntiles = 0
     k2 = og.k ** 2
+    refs = {}                            # output tile -> the oracle's g_J, for the comparison
     while time.perf_counter() - t0 < budget_s:
         J = int(rng.integers(og.ntiles))
         acc = np.zeros(k2)
         for K in op.neighbours(J):
             acc += op.block(J, K) @ f[K * k2:(K + 1) * k2]
+        refs[J] = acc
         ntiles += 1
     dt = time.perf_counter() - t0
     return {"value": ntiles * k2 / dt, "unit": "pixels/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{ntiles} random output tiles of the lmax={cfg.lmax} convolution, "
-                      f"unique blocks evaluated on first use, {dt:.1f} s wall", "host": info}
+                      f"unique blocks evaluated on first use, {dt:.1f} s wall", "host": info}, refs
 
 
 def run_conv(args):
@@ -555,7 +557,12 @@ def run_conv(args):
                      "traffic": recorded_traffic("conv", args.config)},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_conv(cfg, args.cpu_seconds)
+        line["cpu_baseline"], refs = cpu_baseline_conv(cfg, args.cpu_seconds)
+        # the last timed output on the oracle's tiles (outside the timed region)
+        got = out.view(-1, 64).cpu().numpy()
+        gate = max(np.abs(got[J] - ref).max() / np.abs(ref).max() for J, ref in refs.items())
+        line["error_vs_oracle"] = {"tiles": len(refs), "gate": float(gate), "bound": 1e-10}
+        print(f"# conv gate on {len(refs)} tiles: {gate:.2e} (bound 1e-10)", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
