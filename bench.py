@@ -810,6 +810,31 @@ def run_sht(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_baseline_two_hop(cfg, ninv, b_l, R, rp, col, budget_s):
+    """The oracle's B^T N^-1 B blocks of random two-hop block-rows until the budget is spent; returns
+    the baseline and, per block computed, its position in the pattern and the oracle's values."""
+    from oracle import grid as G
+    from oracle import operators as O
+    info = host_info()
+    threads = blas_threads(info)
+    og = G.make_grid(cfg.lmax, cfg.k)
+    op = O.LocalOperator(og, b_l, R)
+    rng = np.random.default_rng(cfg.seed + 13)
+    idx, rows, refs = [], [], []
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        J = int(rng.integers(og.ntiles))
+        for n in range(int(rp[J]), int(rp[J + 1])):
+            refs.append(O.btnb_block(op, ninv, J, int(col[n])))
+            idx.append(n)
+            rows.append(J)
+    dt = time.perf_counter() - t0
+    return ({"value": len(idx) * 4096 / dt, "unit": "elements/s", "cores": int(threads), "kind": "oracle",
+             "sample": f"{len(set(rows))} random block-rows ({len(idx)} blocks) of the lmax={cfg.lmax} two-hop "
+                       f"pattern, unique blocks evaluated on first use, {dt:.1f} s wall", "host": info},
+            idx, rows, np.stack(refs) if refs else np.zeros((0, 64, 64)))
+
+
 def run_two_hop(args):
     """B^T N^-1 B on the two-hop pattern (every nonzero block of the product)."""
     import torch
@@ -825,7 +850,8 @@ def run_two_hop(args):
     nblk, nterms = g.pattern_size("two_hop")
     setup = time.perf_counter() - t0
     th, ph = g.pixel_theta_phi()
-    ninv_dev = torch.as_tensor(S.ninv_for(cfg, th, ph)).cuda()
+    ninv = S.ninv_for(cfg, th, ph)
+    ninv_dev = torch.as_tensor(ninv).cuda()
     b_l, R = S.gaussian_beam(cfg.lmax, g.npix, cfg.fwhm_pix)
     out = torch.empty(nblk * 4096, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -890,6 +916,15 @@ def run_two_hop(args):
                    "lmax": cfg.lmax, "nblocks": nblk, "nterms": nterms, "precision": prec},
         "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        rp, col = g.pattern_blocks("two_hop")
+        base, idx, rows, ref = cpu_baseline_two_hop(cfg, ninv, b_l, R, rp, col, args.cpu_seconds)
+        line["cpu_baseline"] = base
+        # the last timed output on the oracle's blocks (outside the timed region)
+        got = out.view(-1, 64, 64)[torch.as_tensor(np.asarray(idx, dtype=np.int64), device="cuda")].cpu().numpy()
+        gr = gate(got, ref, rows)
+        line["error_vs_oracle"] = {"blocks": len(idx), "gate": gr, "bound": BOUND[prec]}
+        print(f"# two-hop gate on {len(idx)} blocks: {gr:.2e} (bound {BOUND[prec]:g})", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
