@@ -928,6 +928,32 @@ def run_two_hop(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_baseline_two_grid(cfg, lmax2, ninv2, b_l, R, rp, col, budget_s):
+    """The oracle's B^T N_2^-1 B blocks of random block-rows of Y_1 until the budget is spent; returns
+    the baseline and, per block computed, its position in the stored-block order and its values."""
+    from oracle import grid as G
+    from oracle import twogrid as X
+    info = host_info()
+    threads = blas_threads(info)
+    og1, og2 = G.make_grid(cfg.lmax, cfg.k), G.make_grid(lmax2, cfg.k)
+    op = X.CrossOperator(og2, og1, b_l, R)
+    rng = np.random.default_rng(cfg.seed + 17)
+    idx, rows, refs = [], [], []
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        J = int(rng.integers(og1.ntiles))
+        for n in range(int(rp[J]), int(rp[J + 1])):
+            refs.append(X.btnb_cross_block(op, ninv2, J, int(col[n])))
+            idx.append(n)
+            rows.append(J)
+    dt = time.perf_counter() - t0
+    return ({"value": len(idx) * 4096 / dt, "unit": "elements/s", "cores": int(threads), "kind": "oracle",
+             "sample": f"{len(set(rows))} random block-rows ({len(idx)} blocks) of Y_1 (lmax {cfg.lmax}) with "
+                       f"N_2^-1 on Y_2 (lmax {lmax2}), unique blocks evaluated on first use, {dt:.1f} s wall",
+             "host": info},
+            idx, rows, np.stack(refs) if refs else np.zeros((0, 64, 64)))
+
+
 def run_two_grid(args):
     """B^T N_2^-1 B with N_2^-1 on an auxiliary grid Y_2 of twice the band limit
     (Eq. 13; Section 4.2's "twice that of Y_1"): a step tabulates the two-grid
@@ -946,7 +972,8 @@ def run_two_grid(args):
     x = sp.Cross(g2, g1)
     setup = time.perf_counter() - t0
     th2, ph2 = g2.pixel_theta_phi()
-    ninv2 = torch.as_tensor(S.ninv_for(cfg, th2, ph2)).cuda()
+    ninv2_h = S.ninv_for(cfg, th2, ph2)
+    ninv2 = torch.as_tensor(ninv2_h).cuda()
     b_l, R = S.gaussian_beam(cfg.lmax, g1.npix, cfg.fwhm_pix)
     out = torch.empty(x.out_len, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -1002,6 +1029,15 @@ def run_two_grid(args):
         "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec], "achieved": mfma,
                      "frac": mfma / PEAK[prec], "kernel": KERNEL_NAME[prec], "traffic": None},
     }
+    if not args.no_cpu_baseline:
+        rp, col = g1.blocks()
+        base, idx, rows, ref = cpu_baseline_two_grid(cfg, lmax2, ninv2_h, b_l, R, rp, col, args.cpu_seconds)
+        line["cpu_baseline"] = base
+        # the last timed output on the oracle's blocks (outside the timed region)
+        got = out.view(-1, 64, 64)[torch.as_tensor(np.asarray(idx, dtype=np.int64), device="cuda")].cpu().numpy()
+        gr = gate(got, ref, rows)
+        line["error_vs_oracle"] = {"blocks": len(idx), "gate": gr, "bound": BOUND[prec]}
+        print(f"# two-grid gate on {len(idx)} blocks: {gr:.2e} (bound {BOUND[prec]:g})", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
