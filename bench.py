@@ -807,6 +807,22 @@ def run_sht(args):
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_sht(args.cpu_seconds)
+        # the last timed synthesis on the equator ring against the oracle's sums there
+        # (outside the timed region; the oracle takes about 25 s for one ring at L = 3000)
+        from oracle import grid as G
+        from oracle import sht as H
+        og = G.make_grid(cfg.lmax, cfg.k)
+        r_eq = og.nrings // 2
+        ring_of, _, _, _ = og.pixel_coords()
+        t0 = time.perf_counter()
+        f_ref = H.synthesis(og, a.cpu().numpy(), L, rings=[r_eq])
+        dt = time.perf_counter() - t0
+        f_got = f.cpu().numpy()[ring_of == r_eq]
+        gr = float(np.abs(f_got - f_ref).max() / np.abs(f_ref).max())
+        line["error_vs_oracle"] = {"ring": int(r_eq), "pixels": int(f_ref.size), "synthesis_gate": gr,
+                                   "oracle_s": dt}
+        print(f"# sht gate on ring {r_eq} ({f_ref.size} pixels): {gr:.2e}, oracle {dt:.0f} s", file=sys.stderr,
+              flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -122,15 +122,24 @@ def _ring_tables(g: Grid):
     return ring, phi
 
 
-def synthesis(g: Grid, a, lmax: int) -> np.ndarray:
-    """f = Y a on every pixel of g (Eq. 1 as a sum over modes)."""
+def synthesis(g: Grid, a, lmax: int, rings=None) -> np.ndarray:
+    """f = Y a on every pixel of g (Eq. 1 as a sum over modes); with rings
+    (a list of ring indices), f on the pixels of those rings only, in pixel
+    order (the same sums, so the same values)."""
     a = np.asarray(a, dtype=np.float64)
     if a.shape != ((lmax + 1) ** 2,):
         raise ValueError("a must have (lmax+1)^2 entries")
     ring, phi = _ring_tables(g)
-    lam = lambda_table(lmax, g.theta)                       # [l, m, ring]
+    if rings is None:
+        lam = lambda_table(lmax, g.theta)                   # [l, m, ring]
+    else:
+        rings = list(rings)
+        keep = np.isin(ring, rings)
+        ring = np.searchsorted(np.asarray(sorted(rings)), ring[keep])   # position among the chosen rings
+        phi = phi[keep]
+        lam = lambda_table(lmax, np.asarray(g.theta)[sorted(rings)])
     ls = np.arange(lmax + 1)
-    f = np.zeros(g.npix)
+    f = np.zeros(len(ring))
     for m in range(lmax + 1):
         l_m = ls[m:]
         cm = a[l_m * l_m + l_m + m]

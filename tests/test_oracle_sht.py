@@ -199,3 +199,16 @@ def test_lambda_m_where_lambda_mm_is_below_the_double_range():
             ref = float(norm * plm)
         assert abs(ref) > 1e-3
         assert abs(col[l - m] - ref) <= 1e-11 * abs(ref), (l, col[l - m], ref)
+
+
+def test_synthesis_on_chosen_rings_is_the_full_maps_restriction():
+    """The ring-restricted synthesis (used to check the device transform at
+    full size on a few rings) gives exactly the full map's values there."""
+    g = G.make_grid(40, 4)
+    L = 40
+    a = np.random.default_rng(12).standard_normal((L + 1) ** 2)
+    full = H.synthesis(g, a, L)
+    ring, _, _, _ = g.pixel_coords()
+    rings = [0, 7, g.nrings // 2, g.nrings - 1]
+    part = H.synthesis(g, a, L, rings=rings)
+    assert np.array_equal(part, full[np.isin(ring, rings)])
