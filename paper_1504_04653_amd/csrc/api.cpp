@@ -461,6 +461,12 @@ sympix_status sample_btnb(const sympix_grid *g, const sympix_kernel *d, const sy
         a.mtiles = dg->gtiles;
     }
     a.nmtiles = (int64_t)ct.gtiles.size() / 4;
+    // A short FP64 launch runs faster on tiles of at most 32 rows: twice the tiles to
+    // balance over the CUs, and the FP64 kernel keeps its full speed on half tiles
+    if (!pat && prec == SYMPIX_FP64 && (int64_t)ct.mtiles.size() / 4 < sympix::kShortLaunchTiles) {
+        a.mtiles = dg->gtiles32;
+        a.nmtiles = (int64_t)ct.gtiles32.size() / 4;
+    }
     a.nblocks = nblocks;
     a.npix = geo.npix;
     a.ninv = ninv_dev;

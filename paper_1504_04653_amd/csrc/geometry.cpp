@@ -171,15 +171,15 @@ int64_t pos_mod(int64_t a, int64_t m) {
 // hold kTailPercent of its work: they run last, largest first, and fill the
 // CUs that finish early, so that no large tile starts when the rest are done.
 // Slot 8 i + x holds the i-th tile of range x; ranges shorter than the first
-// end in an empty slot (groups 0).  A launch of fewer than kGlobalBelow
-// tiles per CU (256 CUs) is too short for that: there the last few tiles of
-// every CU set the time, and the table is all tiles largest first (stable).
+// end in an empty slot (groups 0).  A launch of fewer than kShortLaunchTiles
+// tiles (32 per CU) is too short for that: there the last few tiles of every
+// CU set the time, and the table is all tiles largest first (stable).
 std::vector<int32_t> xcd_dispatch_table(const std::vector<BlockClass> &classes, const std::vector<int32_t> &tiles) {
     constexpr int kX = 8;
-    constexpr int64_t kTailPercent = 15, kGlobalBelow = 32, kCUs = 256;
+    constexpr int64_t kTailPercent = 15;
     const int64_t n = (int64_t)tiles.size() / 4, per = n / kX, rem = n % kX;
     auto cost = [&](int64_t i) { return (int64_t)(classes[tiles[4 * i]].nterms + 1) * tiles[4 * i + 2]; };
-    if (n < kGlobalBelow * kCUs) {
+    if (n < kShortLaunchTiles) {
         std::vector<int64_t> order(n);
         for (int64_t i = 0; i < n; ++i) order[i] = i;
         std::stable_sort(order.begin(), order.end(), [&](int64_t u, int64_t v) { return cost(u) > cost(v); });

@@ -142,6 +142,10 @@ struct CrossGeometry {
     int64_t nunique() const { return (int64_t)key_delta.size(); }
 };
 
+// A class-grid launch of fewer member tiles than this (32 per CU of the 256)
+// takes them from a table in one global largest-first order (geometry.cpp).
+constexpr int64_t kShortLaunchTiles = 32 * 256;
+
 // Status codes follow sympix_status. On failure err holds a message.
 int build_geometry(int32_t lmax, int32_t k, double margin, Geometry &g, std::string &err);
 
